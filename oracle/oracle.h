@@ -1,0 +1,130 @@
+/*
+ * oracle.h -- plain CPU reference of the non-episodic neuroevolution world
+ * step (arXiv 2302.09334, App. B).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library includes, links
+ * or calls this code; only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark load liboracle.so.  It shares no header,
+ * helper, table or constant generator with the GPU path: both sides are
+ * written independently against the same written semantics.
+ *
+ * Everything here is deliberately slow and literal: floating point for the
+ * controller is IEEE double, loops follow the definitions, and no step is
+ * blocked, fused or reordered.
+ */
+#ifndef ECO_ORACLE_H
+#define ECO_ORACLE_H
+
+#include <stdint.h>
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Parameters of one world.  Field meanings follow App. B.4 (hyperparameters)
+ * in the parameterisation of the benchmark workloads (integer energies). */
+typedef struct oracle_config {
+    int32_t H, W;          /* grid rows x cols; row 0 is the top (lowest regrowth) */
+    int32_t cap;           /* maximum number of live agents                       */
+    int32_t n_init;        /* agents placed at step 0                              */
+    int32_t obs_radius;    /* rho: observation window is (2 rho + 1)^2             */
+    int32_t hidden;        /* GRU hidden size                                      */
+    double  res_init_p;    /* initial Bernoulli resource probability               */
+    double  rate_bottom;   /* regrowth rate at row H-1                             */
+    double  rate_top;      /* regrowth rate at row 0                               */
+    double  rate_scale;    /* multiplier on the latitude rate                      */
+    double  spont;         /* spontaneous growth probability (the constant c)      */
+    int32_t E0;            /* energy at birth                                      */
+    int32_t decay;         /* energy lost per step                                 */
+    int32_t gain;          /* energy gained per resource eaten                     */
+    int32_t E_repr;        /* reproduction energy threshold                        */
+    int32_t T_repr;        /* consecutive steps at or above E_repr to reproduce    */
+    int32_t L_max;         /* age at which an agent dies                           */
+    double  sigma_mut;     /* std of the Gaussian weight mutation                  */
+    double  w_init_gain;   /* initial weight std = gain / sqrt(fan_in)             */
+} oracle_config;
+
+/* Result of one oracle step. */
+typedef struct oracle_stepinfo {
+    int32_t n_live;      /* live agents after the step                         */
+    int32_t births;      /* children created                                   */
+    int32_t deaths;      /* agents removed                                     */
+    int32_t eaten;       /* resources consumed                                 */
+    int32_t resources;   /* resources on the grid after regrowth               */
+    int32_t resyncs;     /* near-tie actions adopted from the supplied hints   */
+    int32_t mismatches;  /* hints that disagreed outside the near-tie band     */
+    int32_t claim_wins;  /* birth-claim winners before the slot cap            */
+} oracle_stepinfo;
+
+/* Random stream identifiers of the counter-based generator. */
+enum {
+    ORACLE_S_INIT_RES = 1,
+    ORACLE_S_INIT_PLACE = 2,
+    ORACLE_S_INIT_W = 3,
+    ORACLE_S_MOVE = 4,
+    ORACLE_S_BIRTH = 5,
+    ORACLE_S_MUTATE = 6,
+    ORACLE_S_REGROW = 7
+};
+
+/* ---- primitives (exposed so that tests can pin them one by one) ---------- */
+
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) on n counters.
+ * ctr: n x 4 words, key: 2 words, out: n x 4 words. */
+void oracle_philox4x32_10(const uint32_t *ctr, const uint32_t *key, uint32_t *out, size_t n);
+
+/* Natural log of u in (0, 1] in single precision (project definition). */
+void oracle_ln_unit(const float *u, float *out, size_t n);
+/* sin and cos of 2*pi*u for dyadic u in [0, 1) (project definition). */
+void oracle_sincos_2pi(const float *u, float *s, float *c, size_t n);
+/* Box-Muller: two standard normals from two 32-bit words, n pairs. */
+void oracle_gauss_pair(const uint32_t *a, const uint32_t *b, float *z0, float *z1, size_t n);
+
+/* Number of inputs, parameters, and the parameter offsets of the genome. */
+int32_t oracle_n_inputs(int32_t obs_radius);
+int32_t oracle_n_params(int32_t obs_radius, int32_t hidden);
+
+/* Regrowth threshold table, H x 25 entries: grow iff draw < table[row*25+n]. */
+int oracle_threshold_table(const oracle_config *cfg, uint64_t *out);
+
+/* One GRU controller evaluation in double (used to pin the gate convention).
+ * theta: genome (n_params floats), x: inputs, h: hidden (float),
+ * h_out: new hidden (double), logits: 5 doubles. */
+void oracle_gru_eval(int32_t n_in, int32_t hidden, const float *theta, const double *x,
+                     const float *h, double *h_out, double *logits);
+
+/* ---- the world ------------------------------------------------------------ */
+
+void *oracle_create(const oracle_config *cfg, uint64_t seed, char *err, size_t errlen);
+void  oracle_destroy(void *w);
+
+/* Force actions by uid: act[u] in 0..4 forces agent u; -1 (or uid >= n) uses
+ * `dflt`; dflt = -1 means the controller decides. Pass n = 0 to clear. */
+void oracle_set_forced(void *w, const int32_t *act, int32_t n, int32_t dflt);
+
+/* Advance one step.  hint_uid/hint_act (sorted by uid, may be NULL) are the
+ * actions another implementation took; where this oracle's own top logits are
+ * closer than 1e-5 * max(1, |top|) the hinted action is adopted (resync). */
+int oracle_step(void *w, const uint32_t *hint_uid, const uint8_t *hint_act, int32_t n_hint,
+                oracle_stepinfo *info);
+
+int64_t  oracle_t(const void *w);
+int32_t  oracle_n_live(const void *w);
+uint32_t oracle_next_uid(const void *w);
+
+/* Copy out the state.  Agents are in uid order.  Any pointer may be NULL. */
+void oracle_get_grid(const void *w, uint8_t *R);
+void oracle_get_agents(const void *w, uint32_t *uid, int32_t *row, int32_t *col,
+                       int32_t *energy, int32_t *age, int32_t *streak);
+void oracle_get_hidden(const void *w, float *h);          /* n_live x hidden        */
+void oracle_get_theta(const void *w, float *theta);       /* n_live x n_params      */
+/* Controller outputs of the last step, for the agents that acted in it (uid
+ * order, the population at the start of that step). */
+int32_t oracle_last_n_acted(const void *w);
+void oracle_get_last_logits(const void *w, uint32_t *uid, double *logits, uint8_t *action);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
