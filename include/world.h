@@ -1,0 +1,184 @@
+/*
+ * world.h -- C-ABI of the MI355X (gfx950) world-step library libworld.so.
+ *
+ * The library advances worlds of the non-episodic neuroevolution simulator of
+ * arXiv 2302.09334 on the GPU.  One step of a world is the method of App. B:
+ * latitude-dependent resource regrowth (App. B.1, Eq. (1)), per-agent local
+ * observation and recurrent controller with individual weights (App. B.2,
+ * B.5), moves, eating and the energy update (App. B.2), minimal-criterion
+ * reproduction with Gaussian mutation and death (App. B.3), here in the
+ * parameterisation of the benchmark workloads (integer energies, a GRU cell
+ * with a linear head, one agent per cell).
+ *
+ * Conventions
+ *  - Plain C; every function returns an int status: WORLD_OK (0) or a
+ *    negative WORLD_E_* code.  No exceptions cross the ABI and nothing aborts.
+ *  - Memory: the caller owns the device arena (device memory of at least
+ *    world_required_bytes, 256-byte aligned) and the HIP stream; the library
+ *    owns only the small host handle.  Host buffers passed to snapshot/load
+ *    are owned by the caller and only used during the call.
+ *  - Asynchrony: world_create, world_step and world_step_many enqueue work on
+ *    the world's stream and return; errors raised by the device surface at
+ *    the next synchronising call (world_sync, world_snapshot, ...).
+ *  - After a HIP error the handle is poisoned: every later call except
+ *    world_destroy returns WORLD_E_POISONED.
+ *  - A handle is not thread-safe; distinct handles are.
+ */
+#ifndef ECO_WORLD_H
+#define ECO_WORLD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WORLD_OK 0
+#define WORLD_E_INVALID_ARG (-1)       /* NULL pointer, bad K, mismatched worlds */
+#define WORLD_E_INVALID_CONFIG (-2)    /* world_config outside the supported range */
+#define WORLD_E_BUFFER_TOO_SMALL (-3)  /* arena or host buffer too small */
+#define WORLD_E_HIP (-4)               /* HIP runtime or device-side failure */
+#define WORLD_E_POISONED (-5)          /* an earlier call failed on the device */
+#define WORLD_E_STATE (-6)             /* request outside what the world holds */
+
+/* Execution modes of world_step / world_step_many. */
+#define WORLD_MODE_KERNELS 0      /* one launch per phase per step            */
+#define WORLD_MODE_GRAPH 1        /* K steps of phase launches in a HIP graph */
+#define WORLD_MODE_PERSISTENT 2   /* one cooperative launch runs all K steps  */
+
+/* Parameters of one world (App. B.4 hyperparameters, benchmark form).
+ * Supported: H >= 2, W >= 1, H*W <= 2^26, 1 <= cap <= 2^20,
+ * 0 <= n_init <= min(cap, H*W), obs_radius in 1..3, hidden in {16, 32},
+ * E0 > 0, decay >= 0, gain >= 0, T_repr >= 1, L_max >= 1, log_steps >= 0. */
+typedef struct world_config {
+    uint32_t struct_size;   /* sizeof(world_config)                               */
+    int32_t H, W;           /* grid rows x cols; row 0 = top = slowest regrowth    */
+    int32_t cap;            /* agent slots (maximum population)                    */
+    int32_t n_init;         /* agents placed at step 0                              */
+    int32_t obs_radius;     /* rho: observation window (2 rho + 1)^2 x 2 + energy    */
+    int32_t hidden;         /* GRU hidden size                                      */
+    double res_init_p;      /* initial resource probability per cell               */
+    double rate_bottom;     /* latitude regrowth rate at row H-1                    */
+    double rate_top;        /* latitude regrowth rate at row 0                      */
+    double rate_scale;      /* multiplier of the latitude rate                      */
+    double spont;           /* spontaneous growth probability                       */
+    int32_t E0;             /* energy at birth                                      */
+    int32_t decay;          /* energy lost per step                                 */
+    int32_t gain;           /* energy per resource eaten                            */
+    int32_t E_repr;         /* reproduction energy threshold                        */
+    int32_t T_repr;         /* consecutive steps at/above E_repr needed to reproduce*/
+    int32_t L_max;          /* age of death                                         */
+    double sigma_mut;       /* mutation std                                          */
+    double w_init_gain;     /* initial weight std = w_init_gain / sqrt(fan_in)       */
+    int32_t log_steps;      /* steps of controller log kept on device (0 = none)     */
+    uint32_t flags;         /* reserved, must be 0                                    */
+} world_config;
+
+typedef struct world world_t;
+
+/* Per-step counters kept on device for the last 1024 steps. */
+typedef struct world_counters {
+    int32_t n_live;      /* live agents after the step          */
+    int32_t births;      /* children created in the step        */
+    int32_t deaths;      /* agents that died in the step        */
+    int32_t eaten;       /* resources eaten in the step         */
+    int32_t resources;   /* resources on the grid after regrowth*/
+    int32_t claim_wins;  /* birth claims won before the slot cap */
+    int32_t reserved[2];
+} world_counters;
+
+#define WORLD_SNAP_HIDDEN 1u   /* fill h (agent_capacity x hidden)          */
+#define WORLD_SNAP_THETA 2u    /* fill theta (agent_capacity x n_params)    */
+
+/* Canonical host image of a world.  Agents are listed in increasing uid.
+ * theta uses the genome order: W_ih[i][k][g] (inputs x hidden x gates r,z,n),
+ * W_hh[j][k][g], b_ih[k][g], b_hh[k][g], W_o[a][k] (5 x hidden), b_o[a]. */
+typedef struct world_image {
+    uint32_t struct_size;    /* sizeof(world_image)                             */
+    uint32_t flags;          /* WORLD_SNAP_* bits                               */
+    int64_t step;            /* steps taken                                      */
+    int32_t n_live;          /* agents listed                                    */
+    uint32_t next_uid;       /* uid the next child receives                      */
+    int32_t agent_capacity;  /* length of the per-agent arrays (>= n_live)       */
+    int32_t reserved;
+    uint8_t *R;              /* H*W resource bits, row-major                     */
+    uint32_t *uid;
+    int32_t *row, *col, *energy, *age, *streak;
+    float *h;
+    float *theta;
+} world_image;
+
+/* Device bytes a world with this configuration needs.  Pure host function. */
+int world_required_bytes(const world_config *cfg, size_t *device_bytes);
+
+/* Inputs and parameters per agent for this configuration.  Pure host. */
+int world_dims(const world_config *cfg, int32_t *n_inputs, int32_t *n_params);
+
+/* Lay out a world in `device_arena` (>= world_required_bytes, 256-byte aligned,
+ * owned by the caller and kept alive until world_destroy), initialise it from
+ * `seed` (resources, placement and genomes from the counter-based generator)
+ * on `hip_stream` (a hipStream_t; NULL = default stream).  Synchronises the
+ * stream before returning.  *out receives the handle. */
+int world_create(const world_config *cfg, uint64_t seed, void *device_arena, size_t arena_bytes,
+                 void *hip_stream, world_t **out);
+
+/* Enqueue K >= 1 steps of the world step on the world's stream. */
+int world_step(world_t *w, int32_t K);
+
+/* Enqueue K steps of n worlds in shared launches.  All worlds must use the
+ * same stream; the result of every world is bit-identical to stepping it alone. */
+int world_step_many(world_t *const *ws, int32_t n, int32_t K);
+
+/* Select WORLD_MODE_* for later steps. */
+int world_set_mode(world_t *w, int32_t mode);
+
+/* Wait for the world's stream; report device-side failures. */
+int world_sync(world_t *w);
+
+/* Synchronise and copy the canonical state into caller buffers.  If
+ * agent_capacity < n_live, returns WORLD_E_BUFFER_TOO_SMALL with n_live set. */
+int world_snapshot(world_t *w, world_image *out);
+
+/* Overwrite the world's state from a canonical image (both WORLD_SNAP_HIDDEN
+ * and WORLD_SNAP_THETA must be set).  Validates positions, uids and sizes. */
+int world_load(world_t *w, const world_image *in);
+
+/* Synchronise and copy counters of steps [first_step, first_step + n). */
+int world_counters_get(world_t *w, int64_t first_step, int32_t n, world_counters *out);
+
+/* Synchronise and release the handle.  The arena is not freed. */
+int world_destroy(world_t *w);
+
+/* Message of the last failure of `w` (or of the calling thread if w is NULL). */
+const char *world_last_error(const world_t *w);
+
+/* ---- test hooks ----------------------------------------------------------- */
+
+/* Force every agent's action (0 = N, 1 = S, 2 = E, 3 = W, 4 = stay); -1
+ * returns control to the controller. */
+int world_set_forced_action(world_t *w, int32_t action);
+
+/* Synchronise and copy the controller log of `step` (needs log_steps > 0 and
+ * the step among the last log_steps): per acting agent in uid order its uid,
+ * action and 5 logits.  *n receives the number of agents. */
+int world_action_log(world_t *w, int64_t step, int32_t capacity, uint32_t *uid, uint8_t *action,
+                     float *logits, int32_t *n);
+
+/* Philox4x32-10 on the device: n counters (device, n x 4 words) under key
+ * (k0, k1) into out (device, n x 4 words), on hip_stream. */
+int world_test_philox(const uint32_t *d_ctr, size_t n, uint32_t k0, uint32_t k1, uint32_t *d_out,
+                      void *hip_stream);
+
+/* Box-Muller normals on the device from n word pairs (device buffers). */
+int world_test_gauss(const uint32_t *d_a, const uint32_t *d_b, size_t n, float *d_z0, float *d_z1,
+                     void *hip_stream);
+
+/* Regrowth threshold table of a configuration, as the library builds it
+ * (host memory, H x 25 entries; grow iff draw < entry). */
+int world_threshold_table(const world_config *cfg, uint64_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

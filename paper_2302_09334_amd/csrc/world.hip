@@ -1,0 +1,854 @@
+// world.hip -- host side of libworld.so: configuration checks, arena layout,
+// initialisation, step launches (per-phase kernels, HIP graphs, persistent
+// cooperative kernel), snapshots and the C-ABI of include/world.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/world.h"
+#include "kernels.h"
+#include "persistent.h"
+
+using namespace eco;
+
+namespace {
+
+thread_local std::string g_thread_err;
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
+
+int n_inputs_of(int rho) {
+    const int w = 2 * rho + 1;
+    return 2 * w * w + 1;
+}
+
+struct Dims {
+    int n_in, P, Ppad, off_hh, off_bih, off_bhh, off_wo, off_bo, nblk;
+};
+
+Dims dims_of(const world_config& c) {
+    Dims d;
+    d.n_in = n_inputs_of(c.obs_radius);
+    const int hd = c.hidden;
+    d.off_hh = d.n_in * hd * 3;
+    d.off_bih = d.off_hh + hd * hd * 3;
+    d.off_bhh = d.off_bih + hd * 3;
+    d.off_wo = d.off_bhh + hd * 3;
+    d.off_bo = d.off_wo + 5 * hd;
+    d.P = d.off_bo + 5;
+    d.Ppad = int(align_up(size_t(d.P), 64));   // 256-byte rows
+    d.nblk = (d.P + 3) / 4;
+    return d;
+}
+
+const char* check_config(const world_config* c) {
+    if (!c) return "config is NULL";
+    if (c->struct_size != sizeof(world_config)) return "world_config.struct_size mismatch";
+    if (c->H < 2 || c->W < 1) return "grid must be at least 2 x 1";
+    if (int64_t(c->H) * c->W > (int64_t(1) << 26)) return "grid larger than 2^26 cells";
+    if (c->cap < 1 || c->cap > (1 << 20)) return "cap must be in 1..2^20";
+    if (c->n_init < 0 || c->n_init > c->cap || int64_t(c->n_init) > int64_t(c->H) * c->W)
+        return "n_init must be in 0..min(cap, H*W)";
+    if (c->obs_radius < 1 || c->obs_radius > 3) return "obs_radius must be 1..3";
+    if (c->hidden != 16 && c->hidden != 32) return "hidden must be 16 or 32";
+    if (c->E0 <= 0 || c->decay < 0 || c->gain < 0) return "E0 > 0, decay >= 0, gain >= 0 required";
+    if (c->T_repr < 1 || c->L_max < 1) return "T_repr and L_max must be positive";
+    if (c->log_steps < 0) return "log_steps must be >= 0";
+    if (c->flags != 0) return "flags must be 0";
+    if (!std::isfinite(c->res_init_p) || !std::isfinite(c->rate_bottom) || !std::isfinite(c->rate_top) ||
+        !std::isfinite(c->rate_scale) || !std::isfinite(c->spont) || !std::isfinite(c->sigma_mut) ||
+        !std::isfinite(c->w_init_gain))
+        return "non-finite parameter";
+    return nullptr;
+}
+
+// Byte offsets of every array inside the arena.
+struct Layout {
+    size_t desc, scal, ring, batch, thr, R0, R1, occA, occB;
+    size_t uid, cell, prev_cell, energy, age, streak, action, alive, win, claim;
+    size_t live0, live1, freeq, child, h, theta;
+    size_t log_uid, log_act, log_logits, log_n, barrier;
+    size_t total;
+};
+
+Layout layout_of(const world_config& c) {
+    const Dims dm = dims_of(c);
+    const size_t HW = size_t(c.H) * c.W;
+    const size_t cap = size_t(c.cap);
+    const size_t L = size_t(c.log_steps);
+    Layout l;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    l.desc = take(sizeof(WorldDev));
+    l.scal = take(sizeof(WorldScal));
+    l.ring = take(sizeof(int32_t) * kRing * kCtrWords);
+    l.batch = take(256);   // single-world launch table
+    l.barrier = take(64);
+    l.thr = take(sizeof(uint64_t) * size_t(c.H) * 25);
+    l.R0 = take(HW);
+    l.R1 = take(HW);
+    l.occA = take(4 * HW);
+    l.occB = take(4 * HW);
+    l.uid = take(4 * cap);
+    l.cell = take(4 * cap);
+    l.prev_cell = take(4 * cap);
+    l.energy = take(4 * cap);
+    l.age = take(4 * cap);
+    l.streak = take(4 * cap);
+    l.action = take(cap);
+    l.alive = take(cap);
+    l.win = take(cap);
+    l.claim = take(4 * cap);
+    l.live0 = take(4 * cap);
+    l.live1 = take(4 * cap);
+    l.freeq = take(4 * cap);
+    l.child = take(16 * cap);
+    l.h = take(4 * cap * size_t(c.hidden));
+    l.theta = take(4 * cap * size_t(dm.Ppad));
+    l.log_uid = take(4 * L * cap);
+    l.log_act = take(L * cap);
+    l.log_logits = take(4 * 5 * L * cap);
+    l.log_n = take(4 * L);
+    l.total = o;
+    return l;
+}
+
+// Regrowth thresholds (App. B.1, Eq. (1) in the workload parameterisation):
+// p(row, n) = (rate_top + (rate_bottom - rate_top) * row / (H - 1)) * scale
+//             * n / 24 + spont, grow iff draw < floor(p * 2^32), IEEE double.
+uint64_t threshold_of(double p) {
+    if (!(p > 0.0)) return 0;
+    if (p >= 1.0) return uint64_t(1) << 32;
+    return uint64_t(std::floor(p * 4294967296.0));
+}
+
+void build_thresholds(const world_config& c, uint64_t* out) {
+    for (int row = 0; row < c.H; ++row) {
+        const double span = c.rate_bottom - c.rate_top;
+        const double lat = (span * double(row)) / double(c.H - 1);
+        const double rate = (c.rate_top + lat) * c.rate_scale;
+        for (int n = 0; n <= 24; ++n) {
+            const double q = (rate * double(n)) / 24.0;
+            out[row * 25 + n] = threshold_of(q + c.spont);
+        }
+    }
+}
+
+}  // namespace
+
+struct world {
+    world_config cfg;
+    Dims dm;
+    Layout lay;
+    uint64_t seed;
+    char* base;            // device arena
+    WorldDev dev;          // host copy of the descriptor
+    WorldDev* d_dev;       // device address of the descriptor
+    struct {
+        const WorldDev* const* w;
+        const int* block_pre;
+        const int* item_pre;
+    } tv;                  // single-world launch table (inside the arena)
+    std::vector<int> host_bp;
+    int max_useful = 1;
+    hipStream_t stream;
+    int mode = WORLD_MODE_KERNELS;
+    bool poisoned = false;
+    std::string err;
+    std::map<int, hipGraphExec_t> graphs;
+    std::map<int, hipGraph_t> graph_defs;
+};
+
+namespace {
+
+int fail(world* w, int code, const std::string& msg) {
+    if (w) {
+        w->err = msg;
+        if (code == WORLD_E_HIP) w->poisoned = true;
+    } else {
+        g_thread_err = msg;
+    }
+    return code;
+}
+
+#define HIP_TRY(w, expr)                                                              \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return fail((w), WORLD_E_HIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+int blocks_act(const world_config& c) { return (c.cap + kBlock / 64 - 1) / (kBlock / 64); }
+int blocks_agent(const world_config& c) { return (c.cap + kBlock - 1) / kBlock; }
+int tiles_of(const world_config& c) {
+    return ((c.H + kTile - 1) / kTile) * ((c.W + kTile - 1) / kTile);
+}
+
+// Host table of block prefixes for a batch of worlds (kPreKinds x (n + 1)).
+std::vector<int> batch_prefix(const std::vector<const world*>& ws) {
+    const int n = int(ws.size());
+    std::vector<int> pre(size_t(kPreKinds) * (n + 1), 0);
+    for (int i = 0; i < n; ++i) {
+        const world_config& c = ws[i]->cfg;
+        pre[kPreAct * (n + 1) + i + 1] = pre[kPreAct * (n + 1) + i] + blocks_act(c);
+        pre[kPreAgent * (n + 1) + i + 1] = pre[kPreAgent * (n + 1) + i] + blocks_agent(c);
+        pre[kPreTile * (n + 1) + i + 1] = pre[kPreTile * (n + 1) + i] + tiles_of(c);
+        pre[kPreSpawn * (n + 1) + i + 1] = pre[kPreSpawn * (n + 1) + i] + kSpawnBlocksPerWorld;
+    }
+    return pre;
+}
+
+// Enqueue one step of the per-phase kernels for a batch.
+hipError_t launch_step(const Batch& b, const int* host_pre, int n, hipStream_t s) {
+    const int np = n + 1;
+    hipLaunchKernelGGL(k_act, dim3(host_pre[kPreAct * np + n]), dim3(kBlock), 0, s, b);
+    hipLaunchKernelGGL(k_move, dim3(host_pre[kPreAgent * np + n]), dim3(kBlock), 0, s, b);
+    hipLaunchKernelGGL(k_claim, dim3(host_pre[kPreAgent * np + n]), dim3(kBlock), 0, s, b);
+    hipLaunchKernelGGL(k_regrow, dim3(host_pre[kPreTile * np + n]), dim3(kBlock), 0, s, b);
+    hipLaunchKernelGGL(k_scan, dim3(n), dim3(kBlock), 0, s, b);
+    hipLaunchKernelGGL(k_spawn, dim3(host_pre[kPreSpawn * np + n]), dim3(kBlock), 0, s, b);
+    return hipGetLastError();
+}
+
+int device_cus() {
+    static int cus = 0;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess)
+            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (cus <= 0) cus = 1;
+    });
+    return cus;
+}
+
+int check_device_error(world* w) {
+    WorldScal sc;
+    HIP_TRY(w, hipMemcpyAsync(&sc, w->base + w->lay.scal, sizeof(sc), hipMemcpyDeviceToHost, w->stream));
+    HIP_TRY(w, hipStreamSynchronize(w->stream));
+    if (sc.err != 0) return fail(w, WORLD_E_HIP, "grid barrier timed out on the device (err=" + std::to_string(sc.err) + ")");
+    return WORLD_OK;
+}
+
+int wall_rate_khz() {
+    static int rate = 0;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess)
+            (void)hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, dev);
+        if (rate <= 0) rate = 100000;
+    });
+    return rate;
+}
+
+int persistent_blocks_per_cu() {
+    static int nb = 0;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_persistent), kBlock,
+                                                          0) != hipSuccess || nb < 1)
+            nb = 1;
+    });
+    return nb;
+}
+
+// Device table of a batch: world pointers, block prefixes (per-phase kernels)
+// and item prefixes (persistent kernel).
+struct TableView {
+    const WorldDev* const* w;
+    const int* block_pre;
+    const int* item_pre;
+};
+
+std::vector<char> build_table(const std::vector<const world*>& ws, char* dev_base, TableView* view,
+                              std::vector<int>* host_block_pre, int* max_useful) {
+    const int n = int(ws.size());
+    const std::vector<int> bp = batch_prefix(ws);
+    std::vector<int> ip(size_t(3) * (n + 1), 0);
+    int useful = 1;
+    for (int i = 0; i < n; ++i) {
+        const world_config& c = ws[i]->cfg;
+        ip[0 * (n + 1) + i + 1] = ip[0 * (n + 1) + i] + c.cap;
+        ip[1 * (n + 1) + i + 1] = ip[1 * (n + 1) + i] + int(align_up(size_t(c.cap), 64));
+        ip[2 * (n + 1) + i + 1] = ip[2 * (n + 1) + i] + tiles_of(c);
+    }
+    useful = std::max({ (ip[n] + 3) / 4, ip[2 * (n + 1) + n], (ip[(n + 1) + n] + kBlock - 1) / kBlock, 1 });
+    const size_t ptr_bytes = align_up(sizeof(void*) * size_t(n), 16);
+    const size_t bp_bytes = sizeof(int) * bp.size();
+    std::vector<char> host(ptr_bytes + bp_bytes + sizeof(int) * ip.size());
+    for (int i = 0; i < n; ++i) {
+        const WorldDev* p = ws[i]->d_dev;
+        std::memcpy(host.data() + sizeof(void*) * i, &p, sizeof(p));
+    }
+    std::memcpy(host.data() + ptr_bytes, bp.data(), bp_bytes);
+    std::memcpy(host.data() + ptr_bytes + bp_bytes, ip.data(), sizeof(int) * ip.size());
+    view->w = reinterpret_cast<const WorldDev* const*>(dev_base);
+    view->block_pre = reinterpret_cast<const int*>(dev_base + ptr_bytes);
+    view->item_pre = reinterpret_cast<const int*>(dev_base + ptr_bytes + bp_bytes);
+    *host_block_pre = bp;
+    *max_useful = useful;
+    return host;
+}
+
+size_t table_bytes(int n) {
+    return align_up(sizeof(void*) * size_t(n), 16) + sizeof(int) * size_t(kPreKinds + 3) * (n + 1);
+}
+
+// K steps of a batch in the given mode.  `graphs` caches captured graphs.
+int run_steps(world* w0, int mode, const TableView& tv, const std::vector<int>& host_bp, int n, int max_useful,
+              int K, std::map<int, hipGraphExec_t>& graphs, std::map<int, hipGraph_t>& defs) {
+    hipStream_t s = w0->stream;
+    Batch b{tv.w, tv.block_pre, n};
+    if (mode == WORLD_MODE_KERNELS) {
+        for (int k = 0; k < K; ++k) HIP_TRY(w0, launch_step(b, host_bp.data(), n, s));
+        return WORLD_OK;
+    }
+    if (mode == WORLD_MODE_GRAPH) {
+        auto it = graphs.find(K);
+        if (it == graphs.end()) {
+            hipGraph_t g = nullptr;
+            hipGraphExec_t ge = nullptr;
+            HIP_TRY(w0, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            hipError_t le = hipSuccess;
+            for (int k = 0; k < K && le == hipSuccess; ++k) le = launch_step(b, host_bp.data(), n, s);
+            const hipError_t ce = hipStreamEndCapture(s, &g);
+            if (le != hipSuccess) return fail(w0, WORLD_E_HIP, std::string("graph capture: ") + hipGetErrorString(le));
+            if (ce != hipSuccess) return fail(w0, WORLD_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
+            HIP_TRY(w0, hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+            defs[K] = g;
+            it = graphs.emplace(K, ge).first;
+        }
+        HIP_TRY(w0, hipGraphLaunch(it->second, s));
+        return WORLD_OK;
+    }
+    const int grid = std::max(1, std::min(persistent_blocks_per_cu() * device_cus(), max_useful));
+    PersistArgs pa;
+    pa.w = tv.w;
+    pa.pre = tv.item_pre;
+    pa.n = n;
+    pa.barrier = reinterpret_cast<uint32_t*>(w0->base + w0->lay.barrier);
+    pa.err = reinterpret_cast<int32_t*>(w0->base + w0->lay.scal + offsetof(WorldScal, err));
+    pa.spin_ticks = uint64_t(wall_rate_khz()) * 1000ull * 2ull;   // 2 s
+    pa.max_useful_blocks = max_useful;
+    for (int done = 0; done < K;) {
+        const int chunk = std::min(K - done, 1024);
+        pa.K = chunk;
+        hipLaunchKernelGGL(k_zero_barrier, dim3(1), dim3(64), 0, s, pa.barrier);
+        HIP_TRY(w0, hipGetLastError());
+        void* args[] = {&pa};
+        HIP_TRY(w0, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_persistent), dim3(grid), dim3(kBlock),
+                                               args, 0, s));
+        done += chunk;
+    }
+    return WORLD_OK;
+}
+
+}  // namespace
+
+// =========================================================================
+// C-ABI
+// =========================================================================
+
+extern "C" {
+
+int world_required_bytes(const world_config* cfg, size_t* device_bytes) {
+    if (!device_bytes) return fail(nullptr, WORLD_E_INVALID_ARG, "device_bytes is NULL");
+    if (const char* m = check_config(cfg)) return fail(nullptr, WORLD_E_INVALID_CONFIG, m);
+    *device_bytes = layout_of(*cfg).total;
+    return WORLD_OK;
+}
+
+int world_dims(const world_config* cfg, int32_t* n_in, int32_t* n_params) {
+    if (const char* m = check_config(cfg)) return fail(nullptr, WORLD_E_INVALID_CONFIG, m);
+    const Dims d = dims_of(*cfg);
+    if (n_in) *n_in = d.n_in;
+    if (n_params) *n_params = d.P;
+    return WORLD_OK;
+}
+
+int world_threshold_table(const world_config* cfg, uint64_t* out) {
+    if (!out) return fail(nullptr, WORLD_E_INVALID_ARG, "out is NULL");
+    if (const char* m = check_config(cfg)) return fail(nullptr, WORLD_E_INVALID_CONFIG, m);
+    build_thresholds(*cfg, out);
+    return WORLD_OK;
+}
+
+int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t arena_bytes, void* hip_stream,
+                 world_t** out) {
+    if (!out || !arena) return fail(nullptr, WORLD_E_INVALID_ARG, "arena and out must be non-NULL");
+    *out = nullptr;
+    if (const char* m = check_config(cfg)) return fail(nullptr, WORLD_E_INVALID_CONFIG, m);
+    if (reinterpret_cast<uintptr_t>(arena) % kAlign != 0)
+        return fail(nullptr, WORLD_E_INVALID_ARG, "arena must be 256-byte aligned");
+    const Layout lay = layout_of(*cfg);
+    if (arena_bytes < lay.total) return fail(nullptr, WORLD_E_BUFFER_TOO_SMALL, "arena smaller than world_required_bytes");
+
+    world* w = new world();
+    w->cfg = *cfg;
+    w->dm = dims_of(*cfg);
+    w->lay = lay;
+    w->seed = seed;
+    w->base = static_cast<char*>(arena);
+    w->stream = static_cast<hipStream_t>(hip_stream);
+    const world_config& c = *cfg;
+    const Dims& dm = w->dm;
+    char* b = w->base;
+
+    WorldDev& d = w->dev;
+    std::memset(&d, 0, sizeof(d));
+    d.H = c.H; d.W = c.W; d.cap = c.cap; d.rho = c.obs_radius; d.hd = c.hidden;
+    d.n_in = dm.n_in; d.P = dm.P; d.Ppad = dm.Ppad;
+    d.E0 = c.E0; d.decay = c.decay; d.gain = c.gain; d.E_repr = c.E_repr; d.T_repr = c.T_repr; d.L_max = c.L_max;
+    d.sigma = float(c.sigma_mut);
+    d.seed_lo = uint32_t(seed); d.seed_hi = uint32_t(seed >> 32);
+    d.forced = -1;
+    d.log_steps = c.log_steps;
+    d.off_hh = dm.off_hh; d.off_bih = dm.off_bih; d.off_bhh = dm.off_bhh; d.off_wo = dm.off_wo; d.off_bo = dm.off_bo;
+    d.nblk = dm.nblk;
+    d.R[0] = reinterpret_cast<uint8_t*>(b + lay.R0);
+    d.R[1] = reinterpret_cast<uint8_t*>(b + lay.R1);
+    d.occA = reinterpret_cast<int32_t*>(b + lay.occA);
+    d.occB = reinterpret_cast<int32_t*>(b + lay.occB);
+    d.thr = reinterpret_cast<const uint64_t*>(b + lay.thr);
+    d.uid = reinterpret_cast<uint32_t*>(b + lay.uid);
+    d.cell = reinterpret_cast<int32_t*>(b + lay.cell);
+    d.prev_cell = reinterpret_cast<int32_t*>(b + lay.prev_cell);
+    d.energy = reinterpret_cast<int32_t*>(b + lay.energy);
+    d.age = reinterpret_cast<int32_t*>(b + lay.age);
+    d.streak = reinterpret_cast<int32_t*>(b + lay.streak);
+    d.action = reinterpret_cast<uint8_t*>(b + lay.action);
+    d.alive = reinterpret_cast<uint8_t*>(b + lay.alive);
+    d.win = reinterpret_cast<uint8_t*>(b + lay.win);
+    d.claim = reinterpret_cast<int32_t*>(b + lay.claim);
+    d.h = reinterpret_cast<float*>(b + lay.h);
+    d.theta = reinterpret_cast<float*>(b + lay.theta);
+    d.live[0] = reinterpret_cast<int32_t*>(b + lay.live0);
+    d.live[1] = reinterpret_cast<int32_t*>(b + lay.live1);
+    d.freeq = reinterpret_cast<int32_t*>(b + lay.freeq);
+    d.child = reinterpret_cast<int4*>(b + lay.child);
+    d.scal = reinterpret_cast<WorldScal*>(b + lay.scal);
+    d.ring = reinterpret_cast<int32_t*>(b + lay.ring);
+    d.log_uid = reinterpret_cast<uint32_t*>(b + lay.log_uid);
+    d.log_act = reinterpret_cast<uint8_t*>(b + lay.log_act);
+    d.log_logits = reinterpret_cast<float*>(b + lay.log_logits);
+    d.log_n = reinterpret_cast<int32_t*>(b + lay.log_n);
+    d.barrier = reinterpret_cast<uint32_t*>(b + lay.barrier);
+    w->d_dev = reinterpret_cast<WorldDev*>(b + lay.desc);
+
+    // Host initialisation (not timed): resources, placement, lists.
+    const size_t HW = size_t(c.H) * c.W;
+    std::vector<uint8_t> R(HW);
+    const uint64_t res_thr = threshold_of(c.res_init_p);
+    std::vector<uint64_t> keys(HW);
+    for (size_t i = 0; i < HW; ++i) {
+        R[i] = uint64_t(philox(uint32_t(i), 0, kInitRes, 0, d.seed_lo, d.seed_hi).x) < res_thr ? 1 : 0;
+        keys[i] = (uint64_t(philox(uint32_t(i), 0, kInitPlace, 0, d.seed_lo, d.seed_hi).x) << 32) | i;
+    }
+    const size_t n0 = size_t(c.n_init);
+    std::partial_sort(keys.begin(), keys.begin() + n0, keys.end());
+    std::vector<int32_t> occ(HW, -1);
+    std::vector<int32_t> cells(c.cap, 0), energy(c.cap, 0), zeros(c.cap, 0), live(c.cap, 0), freeq(c.cap, 0);
+    std::vector<uint32_t> uid(c.cap, 0);
+    std::vector<uint8_t> alive(c.cap, 0);
+    for (size_t a = 0; a < n0; ++a) {
+        const int32_t cell = int32_t(keys[a] & 0xFFFFFFFFu);
+        occ[cell] = int32_t(a);
+        cells[a] = cell;
+        energy[a] = c.E0;
+        uid[a] = uint32_t(a);
+        alive[a] = 1;
+        live[a] = int32_t(a);
+    }
+    for (int s = int(n0); s < c.cap; ++s) freeq[s - int(n0)] = s;
+    std::vector<uint64_t> thr(size_t(c.H) * 25);
+    build_thresholds(c, thr.data());
+    WorldScal sc;
+    std::memset(&sc, 0, sizeof(sc));
+    sc.n_live = int32_t(n0);
+    sc.next_uid = uint32_t(n0);
+    sc.free_head = 0;
+    sc.free_tail = (c.cap - int(n0)) % c.cap;
+    // Single-world launch table.
+    TableView tv;
+    std::vector<const world*> one{w};
+    const std::vector<char> table = build_table(one, b + lay.batch, &tv, &w->host_bp, &w->max_useful);
+    w->tv.w = tv.w;
+    w->tv.block_pre = tv.block_pre;
+    w->tv.item_pre = tv.item_pre;
+
+    hipStream_t s = w->stream;
+    auto up = [&](size_t off, const void* src, size_t bytes) {
+        return hipMemcpyAsync(b + off, src, bytes, hipMemcpyHostToDevice, s);
+    };
+    hipError_t e = hipSuccess;
+#define UP(off, src, bytes) \
+    if (e == hipSuccess) e = up(off, src, bytes)
+    UP(lay.desc, &d, sizeof(d));
+    UP(lay.scal, &sc, sizeof(sc));
+    UP(lay.batch, table.data(), table.size());
+    UP(lay.thr, thr.data(), thr.size() * sizeof(uint64_t));
+    UP(lay.R0, R.data(), HW);
+    UP(lay.R1, R.data(), HW);
+    UP(lay.occA, occ.data(), HW * 4);
+    UP(lay.occB, occ.data(), HW * 4);
+    UP(lay.uid, uid.data(), size_t(c.cap) * 4);
+    UP(lay.cell, cells.data(), size_t(c.cap) * 4);
+    UP(lay.prev_cell, cells.data(), size_t(c.cap) * 4);
+    UP(lay.energy, energy.data(), size_t(c.cap) * 4);
+    UP(lay.age, zeros.data(), size_t(c.cap) * 4);
+    UP(lay.streak, zeros.data(), size_t(c.cap) * 4);
+    UP(lay.claim, zeros.data(), size_t(c.cap) * 4);
+    UP(lay.alive, alive.data(), size_t(c.cap));
+    UP(lay.live0, live.data(), size_t(c.cap) * 4);
+    UP(lay.live1, live.data(), size_t(c.cap) * 4);
+    UP(lay.freeq, freeq.data(), size_t(c.cap) * 4);
+#undef UP
+    if (e == hipSuccess) e = hipMemsetAsync(b + lay.ring, 0, sizeof(int32_t) * kRing * kCtrWords, s);
+    if (e == hipSuccess) e = hipMemsetAsync(b + lay.barrier, 0, 64, s);
+    if (e == hipSuccess) e = hipMemsetAsync(b + lay.h, 0, 4 * size_t(c.cap) * c.hidden, s);
+    if (e == hipSuccess) e = hipMemsetAsync(b + lay.action, 4, size_t(c.cap), s);
+    if (e == hipSuccess) e = hipMemsetAsync(b + lay.win, 0, size_t(c.cap), s);
+    if (e == hipSuccess) e = hipMemsetAsync(b + lay.theta, 0, 4 * size_t(c.cap) * dm.Ppad, s);
+    if (e == hipSuccess && c.log_steps > 0) e = hipMemsetAsync(b + lay.log_n, 0, 4 * size_t(c.log_steps), s);
+    if (e == hipSuccess && n0 > 0) {
+        const float std_ih = float(c.w_init_gain / std::sqrt(double(dm.n_in)));
+        const float std_hd = float(c.w_init_gain / std::sqrt(double(c.hidden)));
+        const int64_t items = int64_t(n0) * dm.nblk;
+        const int grid = int(std::min<int64_t>((items + kBlock - 1) / kBlock, 65536));
+        hipLaunchKernelGGL(k_init_theta, dim3(grid), dim3(kBlock), 0, s, w->d_dev, int(n0), std_ih, std_hd);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        fail(nullptr, WORLD_E_HIP, std::string("world_create: ") + hipGetErrorString(e));
+        delete w;
+        return WORLD_E_HIP;
+    }
+    *out = w;
+    return WORLD_OK;
+}
+
+int world_set_mode(world_t* w, int32_t mode) {
+    if (!w) return fail(nullptr, WORLD_E_INVALID_ARG, "world is NULL");
+    if (mode != WORLD_MODE_KERNELS && mode != WORLD_MODE_GRAPH && mode != WORLD_MODE_PERSISTENT)
+        return fail(w, WORLD_E_INVALID_ARG, "unknown mode");
+    w->mode = mode;
+    return WORLD_OK;
+}
+
+static int step_single(world* w, int K) {
+    TableView tv{w->tv.w, w->tv.block_pre, w->tv.item_pre};
+    return run_steps(w, w->mode, tv, w->host_bp, 1, w->max_useful, K, w->graphs, w->graph_defs);
+}
+
+// Launch tables of batches (device memory owned by the library, one per
+// distinct list of worlds), with their captured graphs.
+struct BatchEntry {
+    void* dev = nullptr;
+    TableView tv;
+    std::vector<int> host_bp;
+    int max_useful = 1;
+    std::map<int, hipGraphExec_t> graphs;
+    std::map<int, hipGraph_t> defs;
+};
+
+static std::mutex g_batch_mu;
+static std::map<std::vector<uintptr_t>, BatchEntry*> g_batches;
+
+static std::vector<uintptr_t> batch_key(world_t* const* ws, int n) {
+    std::vector<uintptr_t> key;
+    for (int i = 0; i < n; ++i) {
+        key.push_back(reinterpret_cast<uintptr_t>(ws[i]));
+        key.push_back(reinterpret_cast<uintptr_t>(ws[i]->d_dev));
+        key.push_back(uintptr_t(ws[i]->cfg.cap));
+        key.push_back(uintptr_t(ws[i]->cfg.H) << 32 | uintptr_t(ws[i]->cfg.W));
+        key.push_back(uintptr_t(ws[i]->cfg.hidden));
+    }
+    return key;
+}
+
+static int batch_step(world_t* const* ws, int n, int K) {
+    world* w0 = ws[0];
+    BatchEntry* be = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_batch_mu);
+        auto key = batch_key(ws, n);
+        auto it = g_batches.find(key);
+        if (it == g_batches.end()) {
+            be = new BatchEntry();
+            hipError_t e = hipMalloc(&be->dev, table_bytes(n));
+            if (e != hipSuccess) {
+                delete be;
+                return fail(w0, WORLD_E_HIP, std::string("hipMalloc(batch table): ") + hipGetErrorString(e));
+            }
+            std::vector<const world*> list(ws, ws + n);
+            const std::vector<char> host = build_table(list, static_cast<char*>(be->dev), &be->tv, &be->host_bp,
+                                                       &be->max_useful);
+            e = hipMemcpy(be->dev, host.data(), host.size(), hipMemcpyHostToDevice);
+            if (e != hipSuccess) {
+                (void)hipFree(be->dev);
+                delete be;
+                return fail(w0, WORLD_E_HIP, std::string("batch table upload: ") + hipGetErrorString(e));
+            }
+            g_batches.emplace(std::move(key), be);
+        } else {
+            be = it->second;
+        }
+    }
+    return run_steps(w0, w0->mode, be->tv, be->host_bp, n, be->max_useful, K, be->graphs, be->defs);
+}
+
+int world_step(world_t* w, int32_t K) {
+    if (!w) return fail(nullptr, WORLD_E_INVALID_ARG, "world is NULL");
+    if (w->poisoned) return WORLD_E_POISONED;
+    if (K < 1) return fail(w, WORLD_E_INVALID_ARG, "K must be >= 1");
+    return step_single(w, K);
+}
+
+int world_sync(world_t* w) {
+    if (!w) return fail(nullptr, WORLD_E_INVALID_ARG, "world is NULL");
+    if (w->poisoned) return WORLD_E_POISONED;
+    HIP_TRY(w, hipStreamSynchronize(w->stream));
+    return check_device_error(w);
+}
+
+int world_snapshot(world_t* w, world_image* out) {
+    if (!w || !out) return fail(w, WORLD_E_INVALID_ARG, "NULL argument");
+    if (w->poisoned) return WORLD_E_POISONED;
+    if (out->struct_size != sizeof(world_image)) return fail(w, WORLD_E_INVALID_ARG, "world_image.struct_size mismatch");
+    if (int rc = world_sync(w)) return rc;
+    const world_config& c = w->cfg;
+    const Layout& l = w->lay;
+    WorldScal sc;
+    HIP_TRY(w, hipMemcpy(&sc, w->base + l.scal, sizeof(sc), hipMemcpyDeviceToHost));
+    out->step = sc.t;
+    out->n_live = sc.n_live;
+    out->next_uid = sc.next_uid;
+    if (out->agent_capacity < sc.n_live) return fail(w, WORLD_E_BUFFER_TOO_SMALL, "agent_capacity < n_live");
+    const size_t HW = size_t(c.H) * c.W;
+    if (out->R) HIP_TRY(w, hipMemcpy(out->R, w->base + (sc.t & 1 ? l.R1 : l.R0), HW, hipMemcpyDeviceToHost));
+    const int n = sc.n_live;
+    std::vector<int32_t> live(std::max(n, 1));
+    HIP_TRY(w, hipMemcpy(live.data(), w->base + (sc.live_sel ? l.live1 : l.live0), 4 * size_t(n), hipMemcpyDeviceToHost));
+    auto gather_i32 = [&](size_t off, int32_t* dst) -> int {
+        if (!dst) return WORLD_OK;
+        std::vector<int32_t> all(c.cap);
+        HIP_TRY(w, hipMemcpy(all.data(), w->base + off, 4 * size_t(c.cap), hipMemcpyDeviceToHost));
+        for (int i = 0; i < n; ++i) dst[i] = all[live[i]];
+        return WORLD_OK;
+    };
+    if (int rc = gather_i32(l.uid, reinterpret_cast<int32_t*>(out->uid))) return rc;
+    if (out->row || out->col) {
+        std::vector<int32_t> cells(std::max(n, 1));
+        if (int rc = gather_i32(l.cell, cells.data())) return rc;
+        for (int i = 0; i < n; ++i) {
+            if (out->row) out->row[i] = cells[i] / c.W;
+            if (out->col) out->col[i] = cells[i] % c.W;
+        }
+    }
+    if (int rc = gather_i32(l.energy, out->energy)) return rc;
+    if (int rc = gather_i32(l.age, out->age)) return rc;
+    if (int rc = gather_i32(l.streak, out->streak)) return rc;
+    if ((out->flags & WORLD_SNAP_HIDDEN) && out->h) {
+        std::vector<float> hs(size_t(c.cap) * c.hidden);
+        HIP_TRY(w, hipMemcpy(hs.data(), w->base + l.h, 4 * hs.size(), hipMemcpyDeviceToHost));
+        for (int i = 0; i < n; ++i)
+            std::memcpy(out->h + size_t(i) * c.hidden, hs.data() + size_t(live[i]) * c.hidden, 4 * size_t(c.hidden));
+    }
+    if ((out->flags & WORLD_SNAP_THETA) && out->theta) {
+        const size_t P = size_t(w->dm.P), Pp = size_t(w->dm.Ppad);
+        for (int i = 0; i < n; ++i)
+            HIP_TRY(w, hipMemcpy(out->theta + size_t(i) * P, w->base + l.theta + 4 * Pp * size_t(live[i]), 4 * P,
+                                 hipMemcpyDeviceToHost));
+    }
+    return WORLD_OK;
+}
+
+int world_load(world_t* w, const world_image* in) {
+    if (!w || !in) return fail(w, WORLD_E_INVALID_ARG, "NULL argument");
+    if (w->poisoned) return WORLD_E_POISONED;
+    if (in->struct_size != sizeof(world_image)) return fail(w, WORLD_E_INVALID_ARG, "world_image.struct_size mismatch");
+    const world_config& c = w->cfg;
+    const int n = in->n_live;
+    if (n < 0 || n > c.cap) return fail(w, WORLD_E_INVALID_ARG, "n_live out of range");
+    if (!(in->flags & WORLD_SNAP_HIDDEN) || !(in->flags & WORLD_SNAP_THETA) || !in->R || !in->uid || !in->row ||
+        !in->col || !in->energy || !in->age || !in->streak || (n > 0 && (!in->h || !in->theta)))
+        return fail(w, WORLD_E_INVALID_ARG, "world_load needs the full state");
+    if (in->step < 0) return fail(w, WORLD_E_INVALID_ARG, "negative step");
+    const size_t HW = size_t(c.H) * c.W;
+    std::vector<int32_t> occ(HW, -1), cells(c.cap, 0), live(c.cap, 0), freeq(c.cap, 0);
+    for (int i = 0; i < n; ++i) {
+        if (in->row[i] < 0 || in->row[i] >= c.H || in->col[i] < 0 || in->col[i] >= c.W)
+            return fail(w, WORLD_E_INVALID_ARG, "agent outside the grid");
+        if (i > 0 && in->uid[i] <= in->uid[i - 1]) return fail(w, WORLD_E_INVALID_ARG, "uids must increase");
+        if (in->uid[i] >= in->next_uid) return fail(w, WORLD_E_INVALID_ARG, "uid >= next_uid");
+        const int cell = in->row[i] * c.W + in->col[i];
+        if (occ[cell] != -1) return fail(w, WORLD_E_INVALID_ARG, "two agents in one cell");
+        occ[cell] = i;
+        cells[i] = cell;
+        live[i] = i;
+    }
+    for (int s = n; s < c.cap; ++s) freeq[s - n] = s;
+    std::vector<uint8_t> alive(c.cap, 0);
+    for (int i = 0; i < n; ++i) alive[i] = 1;
+    WorldScal sc;
+    std::memset(&sc, 0, sizeof(sc));
+    sc.t = in->step;
+    sc.n_live = n;
+    sc.next_uid = in->next_uid;
+    sc.free_tail = (c.cap - n) % c.cap;
+    const Layout& l = w->lay;
+    char* b = w->base;
+    const size_t P = size_t(w->dm.P), Pp = size_t(w->dm.Ppad);
+    std::vector<float> th(size_t(std::max(n, 1)) * Pp, 0.f);
+    for (int i = 0; i < n; ++i) std::memcpy(th.data() + size_t(i) * Pp, in->theta + size_t(i) * P, 4 * P);
+    std::vector<int32_t> ages(c.cap, 0), streaks(c.cap, 0), energies(c.cap, 0);
+    std::vector<uint32_t> uids(c.cap, 0);
+    for (int i = 0; i < n; ++i) {
+        ages[i] = in->age[i];
+        streaks[i] = in->streak[i];
+        energies[i] = in->energy[i];
+        uids[i] = in->uid[i];
+    }
+    HIP_TRY(w, hipStreamSynchronize(w->stream));
+    HIP_TRY(w, hipMemcpy(b + l.scal, &sc, sizeof(sc), hipMemcpyHostToDevice));
+    HIP_TRY(w, hipMemcpy(b + (in->step & 1 ? l.R1 : l.R0), in->R, HW, hipMemcpyHostToDevice));
+    HIP_TRY(w, hipMemcpy(b + l.occA, occ.data(), 4 * HW, hipMemcpyHostToDevice));
+    HIP_TRY(w, hipMemcpy(b + l.occB, occ.data(), 4 * HW, hipMemcpyHostToDevice));
+    HIP_TRY(w, hipMemcpy(b + l.uid, uids.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
+    HIP_TRY(w, hipMemcpy(b + l.cell, cells.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
+    HIP_TRY(w, hipMemcpy(b + l.prev_cell, cells.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
+    HIP_TRY(w, hipMemcpy(b + l.energy, energies.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
+    HIP_TRY(w, hipMemcpy(b + l.age, ages.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
+    HIP_TRY(w, hipMemcpy(b + l.streak, streaks.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
+    HIP_TRY(w, hipMemcpy(b + l.alive, alive.data(), size_t(c.cap), hipMemcpyHostToDevice));
+    HIP_TRY(w, hipMemcpy(b + l.live0, live.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
+    HIP_TRY(w, hipMemcpy(b + l.freeq, freeq.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
+    if (n > 0) {
+        std::vector<float> hs(size_t(c.cap) * c.hidden, 0.f);
+        std::memcpy(hs.data(), in->h, 4 * size_t(n) * c.hidden);
+        HIP_TRY(w, hipMemcpy(b + l.h, hs.data(), 4 * hs.size(), hipMemcpyHostToDevice));
+        HIP_TRY(w, hipMemcpy(b + l.theta, th.data(), 4 * size_t(n) * Pp, hipMemcpyHostToDevice));
+    }
+    return WORLD_OK;
+}
+
+int world_counters_get(world_t* w, int64_t first, int32_t n, world_counters* out) {
+    if (!w || (!out && n > 0)) return fail(w, WORLD_E_INVALID_ARG, "NULL argument");
+    if (w->poisoned) return WORLD_E_POISONED;
+    if (int rc = world_sync(w)) return rc;
+    WorldScal sc;
+    HIP_TRY(w, hipMemcpy(&sc, w->base + w->lay.scal, sizeof(sc), hipMemcpyDeviceToHost));
+    if (n < 0 || first < 0 || first + n > sc.t || first < sc.t - kRing)
+        return fail(w, WORLD_E_STATE, "requested steps are not held in the counter ring");
+    std::vector<int32_t> ring(size_t(kRing) * kCtrWords);
+    HIP_TRY(w, hipMemcpy(ring.data(), w->base + w->lay.ring, 4 * ring.size(), hipMemcpyDeviceToHost));
+    for (int i = 0; i < n; ++i) {
+        const int32_t* r = ring.data() + ((first + i) % kRing) * kCtrWords;
+        out[i].n_live = r[kCtrLive];
+        out[i].births = r[kCtrBirths];
+        out[i].deaths = r[kCtrDeaths];
+        out[i].eaten = r[kCtrEaten];
+        out[i].resources = r[kCtrRes];
+        out[i].claim_wins = r[kCtrWins];
+        out[i].reserved[0] = out[i].reserved[1] = 0;
+    }
+    return WORLD_OK;
+}
+
+int world_destroy(world_t* w) {
+    if (!w) return WORLD_OK;
+    (void)hipStreamSynchronize(w->stream);
+    for (auto& kv : w->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto& kv : w->graph_defs) (void)hipGraphDestroy(kv.second);
+    delete w;
+    return WORLD_OK;
+}
+
+const char* world_last_error(const world_t* w) {
+    if (w) return w->err.c_str();
+    return g_thread_err.c_str();
+}
+
+int world_set_forced_action(world_t* w, int32_t action) {
+    if (!w) return fail(nullptr, WORLD_E_INVALID_ARG, "world is NULL");
+    if (w->poisoned) return WORLD_E_POISONED;
+    if (action < -1 || action > 4) return fail(w, WORLD_E_INVALID_ARG, "action must be -1..4");
+    w->dev.forced = action;
+    HIP_TRY(w, hipStreamSynchronize(w->stream));
+    HIP_TRY(w, hipMemcpy(w->base + w->lay.desc + offsetof(WorldDev, forced), &action, sizeof(action),
+                         hipMemcpyHostToDevice));
+    return WORLD_OK;
+}
+
+int world_action_log(world_t* w, int64_t step, int32_t capacity, uint32_t* uid, uint8_t* action, float* logits,
+                     int32_t* n) {
+    if (!w || !n) return fail(w, WORLD_E_INVALID_ARG, "NULL argument");
+    if (w->poisoned) return WORLD_E_POISONED;
+    const world_config& c = w->cfg;
+    if (c.log_steps <= 0) return fail(w, WORLD_E_STATE, "world created without a controller log");
+    if (int rc = world_sync(w)) return rc;
+    WorldScal sc;
+    HIP_TRY(w, hipMemcpy(&sc, w->base + w->lay.scal, sizeof(sc), hipMemcpyDeviceToHost));
+    if (step < 0 || step >= sc.t || step < sc.t - c.log_steps) return fail(w, WORLD_E_STATE, "step not held in the log");
+    const size_t row = size_t(step % c.log_steps);
+    int32_t cnt = 0;
+    HIP_TRY(w, hipMemcpy(&cnt, w->base + w->lay.log_n + 4 * row, 4, hipMemcpyDeviceToHost));
+    *n = cnt;
+    if (capacity < cnt) return fail(w, WORLD_E_BUFFER_TOO_SMALL, "capacity < agents in the step");
+    const size_t base = row * size_t(c.cap);
+    if (uid) HIP_TRY(w, hipMemcpy(uid, w->base + w->lay.log_uid + 4 * base, 4 * size_t(cnt), hipMemcpyDeviceToHost));
+    if (action) HIP_TRY(w, hipMemcpy(action, w->base + w->lay.log_act + base, size_t(cnt), hipMemcpyDeviceToHost));
+    if (logits)
+        HIP_TRY(w, hipMemcpy(logits, w->base + w->lay.log_logits + 4 * 5 * base, 4 * 5 * size_t(cnt), hipMemcpyDeviceToHost));
+    return WORLD_OK;
+}
+
+int world_test_philox(const uint32_t* d_ctr, size_t n, uint32_t k0, uint32_t k1, uint32_t* d_out, void* stream) {
+    if (!d_ctr || !d_out) return fail(nullptr, WORLD_E_INVALID_ARG, "NULL argument");
+    if (n == 0) return WORLD_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_test_philox, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, d_ctr, n, k0, k1, d_out);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(nullptr, WORLD_E_HIP, hipGetErrorString(e));
+    return WORLD_OK;
+}
+
+int world_test_gauss(const uint32_t* d_a, const uint32_t* d_b, size_t n, float* d_z0, float* d_z1, void* stream) {
+    if (!d_a || !d_b || !d_z0 || !d_z1) return fail(nullptr, WORLD_E_INVALID_ARG, "NULL argument");
+    if (n == 0) return WORLD_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_test_gauss, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, d_a, d_b, n, d_z0, d_z1);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(nullptr, WORLD_E_HIP, hipGetErrorString(e));
+    return WORLD_OK;
+}
+
+int world_step_many(world_t* const* ws, int32_t n, int32_t K) {
+    if (!ws || n < 1) return fail(nullptr, WORLD_E_INVALID_ARG, "empty world list");
+    if (K < 1) return fail(nullptr, WORLD_E_INVALID_ARG, "K must be >= 1");
+    for (int i = 0; i < n; ++i) {
+        if (!ws[i]) return fail(nullptr, WORLD_E_INVALID_ARG, "NULL world in list");
+        if (ws[i]->poisoned) return WORLD_E_POISONED;
+        if (ws[i]->stream != ws[0]->stream) return fail(nullptr, WORLD_E_INVALID_ARG, "worlds must share one stream");
+    }
+    return batch_step(ws, n, K);
+}
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+// world_dev.h -- device-side description of one world and its arena layout.
+//
+// Everything a kernel needs about a world is reachable from one WorldDev
+// record that lives in the world's own arena, so a launch over one or many
+// worlds only passes pointers to these records.
+//
+// HBM layout (structure of arrays, every array 256-byte aligned):
+//   grid      R[2] (u8, double-buffered for the synchronous regrowth),
+//             occA/occB (i32 slot or -1; occA = state at the step start,
+//             occB = state after moves and deaths, mirrored back each step),
+//             thr (u64 H x 25 regrowth thresholds)
+//   agents    uid, cell, prev_cell, energy, age, streak (i32 per slot),
+//             action, alive, win (u8), claim (i32), h (f32 slot x hidden),
+//             theta (f32 slot x Ppad, the genome order with each input's
+//             3*hidden gate weights contiguous so that skipping a zero input
+//             skips one contiguous row)
+//   lists     live[2] (slots in uid order), freeq (ring of free slots),
+//             child (per step: child slot, parent slot, cell, uid)
+//   scalars   WorldScal, counters ring (1024 steps), optional controller log
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+namespace eco {
+
+constexpr int kRing = 1024;     // steps of counters kept on device
+constexpr int kCtrWords = 8;    // words per counter record
+constexpr int kBlock = 256;     // threads per block in every kernel
+constexpr int kTile = 16;       // regrowth tile edge (16 x 16 cells per block)
+
+// Counter record fields (match world_counters in world.h).
+enum : int { kCtrLive = 0, kCtrBirths, kCtrDeaths, kCtrEaten, kCtrRes, kCtrWins };
+
+struct WorldScal {
+    int64_t t;          // steps taken
+    int32_t n_live;
+    uint32_t next_uid;
+    int32_t free_head;  // ring of free slots: [head, head + n_free) mod cap
+    int32_t free_tail;
+    int32_t live_sel;   // which live[] buffer is current
+    int32_t n_child;    // children created by the last scan
+    int64_t spawn_t;    // step of the pending children
+    int32_t err;        // device-side failure code (barrier time-out)
+    int32_t pad[5];
+};
+
+struct WorldDev {
+    // configuration
+    int32_t H, W, cap, rho, hd, n_in, P, Ppad;
+    int32_t E0, decay, gain, E_repr, T_repr, L_max;
+    float sigma;
+    uint32_t seed_lo, seed_hi;
+    int32_t forced;     // forced action or -1
+    int32_t log_steps;
+    int32_t off_hh, off_bih, off_bhh, off_wo, off_bo;  // genome offsets (floats)
+    int32_t nblk;       // float4 blocks per genome, ceil(P / 4)
+    int32_t pad0;
+    // grid
+    uint8_t* R[2];
+    int32_t* occA;
+    int32_t* occB;
+    const uint64_t* thr;
+    // agents
+    uint32_t* uid;
+    int32_t* cell;
+    int32_t* prev_cell;
+    int32_t* energy;
+    int32_t* age;
+    int32_t* streak;
+    uint8_t* action;
+    uint8_t* alive;
+    uint8_t* win;
+    int32_t* claim;
+    float* h;
+    float* theta;
+    // lists
+    int32_t* live[2];
+    int32_t* freeq;
+    int4* child;
+    // scalars and logs
+    WorldScal* scal;
+    int32_t* ring;        // kRing x kCtrWords
+    uint32_t* log_uid;    // log_steps x cap
+    uint8_t* log_act;     // log_steps x cap
+    float* log_logits;    // log_steps x cap x 5
+    int32_t* log_n;       // log_steps
+    uint32_t* barrier;    // grid barrier counter of the persistent kernel
+};
+
+}  // namespace eco
