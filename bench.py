@@ -1,0 +1,309 @@
+#!/usr/bin/env python
+"""Benchmark of the fused world step on one MI355X.
+
+Metric: agent-steps/s on the 200 x 400 world with ~4k agents (every agent of
+the population acts once per step).  The workload (``m1_4k``): 200 x 400 grid,
+4608 agent slots, 4096 initial agents, Bernoulli(0.3) resources, regrowth
+rates x5, 7x7x2+1 observation, GRU hidden 32, seed 0.  W warm-up steps, then
+exactly K timed steps (world_step in chunks of --chunk steps) between two
+device synchronisations.  Inputs are resident in HBM before timing starts.
+
+Also reported:
+* ``roofline``: the dominant kernel (the act phase: observation + GRU) timed
+  with HIP events on the world's stream in a separate per-phase pass, its
+  algorithmic bytes per launch (live agents x bytes each agent must read and
+  write + the grid) against the 8 TB/s HBM peak; ``traffic`` from the
+  committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary when the kernel source
+  still matches it.
+* ``cpu_baseline``: the oracle (plain C, one thread) on a bounded sample of
+  the same workload on the host cores.
+
+``--gpus N`` with N > 1 is refused: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "act_m1_4k_traffic.txt")
+KERNEL_SOURCES = ["rng.h", "world_dev.h", "phases.h", "kernels.h"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2302_09334_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def observed_inputs(snap: dict, cfg: dict) -> np.ndarray:
+    """Non-zero binary inputs per agent (resource and occupancy windows; outside
+    cells read as no resource and occupied)."""
+    H, W, rho = cfg["H"], cfg["W"], cfg["obs_radius"]
+    R = np.zeros((H + 2 * rho, W + 2 * rho), np.int32)
+    R[rho:rho + H, rho:rho + W] = snap["R"]
+    O = np.ones((H + 2 * rho, W + 2 * rho), np.int32)
+    O[rho:rho + H, rho:rho + W] = 0
+    O[snap["row"] + rho, snap["col"] + rho] = 1
+    nnz = np.zeros(snap["n_live"], np.int64)
+    for dy in range(-rho, rho + 1):
+        for dx in range(-rho, rho + 1):
+            r = snap["row"] + rho + dy
+            c = snap["col"] + rho + dx
+            nnz += R[r, c] + O[r, c]
+    return nnz
+
+
+def act_bytes_per_agent(cfg: dict, nnz_mean: float) -> float:
+    """Bytes the act phase must move per agent: the recurrent weights, both
+    bias vectors, the head, the energy row, one 3*hidden row per non-zero
+    binary input, the hidden state in and out, and the agent's scalars."""
+    hd = cfg["hidden"]
+    rw = 3 * hd * 4
+    return (3 * hd * hd * 4 + 2 * rw + (5 * hd + 5) * 4 + rw + nnz_mean * rw + 2 * hd * 4 + 21)
+
+
+def read_traffic(src_hash: str):
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != src_hash:
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(cfg: dict, seed: int, seconds: float) -> dict:
+    import oracle
+    ow = oracle.OracleWorld(oracle.OracleConfig.from_dict(cfg), seed)
+    acted = 0
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        n = ow.n_live
+        ow.step()
+        acted += n
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds and steps >= 3:
+            break
+    ow.close()
+    return {"value": acted / el, "unit": "agent-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"steps 0..{steps - 1} of the same workload from its seed ({acted} agent-steps, "
+                      f"{el:.1f} s, plain C oracle, one thread; initialisation excluded)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=1000)
+    ap.add_argument("--workload", default="m1_4k")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--mode", default="auto", choices=["auto", "kernels", "graph", "persistent"])
+    ap.add_argument("--chunk", type=int, default=100, help="steps per world_step call")
+    ap.add_argument("--phase-steps", type=int, default=200, help="steps of the per-phase event pass")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run the plain copy kernel on 1 GiB (memory-counter calibration)")
+    args = ap.parse_args()
+
+    world_size = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world_size != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    if args.steps < 1 or args.steps > 8000:
+        sys.exit("--steps must be in 1..8000 (the per-step counter ring holds 8192 steps)")
+
+    import torch
+    from paper_2302_09334_amd import workloads, world
+
+    cfg = workloads.WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    w = world.World(cfg, args.seed, stream=stream, mode="graph")
+    log(f"[bench] {args.workload}: H={cfg['H']} W={cfg['W']} cap={cfg['cap']} n_init={cfg['n_init']} "
+        f"hidden={cfg['hidden']} P={w.n_params}")
+
+    def run(nsteps, mode):
+        w.set_mode(mode)
+        done = 0
+        while done < nsteps:
+            k = min(args.chunk, nsteps - done)
+            w.step(k)
+            done += k
+
+    # warm-up (graph mode; every mode reaches the same state)
+    run(args.warmup, "graph")
+    w.sync()
+    start = w.snapshot(hidden=True, theta=True)
+    log(f"[bench] warm-up done: t={start['t']} n_live={start['n_live']}")
+
+    # pick the launch mode on a short calibration from the same state
+    modes = ["graph", "persistent", "kernels"] if args.mode == "auto" else [args.mode]
+    calib = {}
+    for m in modes:
+        w.load(start)
+        run(min(args.chunk, args.steps), m)   # capture / first launch
+        w.sync()
+        w.load(start)
+        n_cal = min(2 * args.chunk, args.steps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run(n_cal, m)
+        w.sync()
+        calib[m] = (time.perf_counter() - t0) / n_cal * 1e3
+        log(f"[bench] mode {m}: {calib[m] * 1e3:.1f} us/step")
+    best = min(calib, key=calib.get)
+
+    # the timed region: exactly K steps from the warmed-up state
+    w.load(start)
+    run(min(args.chunk, args.steps), best)
+    w.sync()
+    w.load(start)
+    w.set_mode(best)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range((args.steps + args.chunk - 1) // args.chunk + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        ev[0].record(stream)
+        done = 0
+        i = 0
+        while done < args.steps:
+            k = min(args.chunk, args.steps - done)
+            w.step(k)
+            done += k
+            i += 1
+            ev[i].record(stream)
+    w.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    chunk_ms = np.array([ev[j].elapsed_time(ev[j + 1]) for j in range(i)])
+    chunk_steps = np.array([min(args.chunk, args.steps - j * args.chunk) for j in range(i)])
+    per_step_ms = chunk_ms / chunk_steps
+    t_first = start["t"]
+    ctr_prev = w.counters(t_first - 1, 1)["n_live"][0] if t_first > 0 else start["n_live"]
+    ctr = w.counters(t_first, args.steps)
+    acting = np.concatenate([[ctr_prev], ctr["n_live"][:-1]])
+    agent_steps = int(acting.sum())
+    value = agent_steps / wall
+    end = w.snapshot()
+    log(f"[bench] timed {args.steps} steps in {wall * 1e3:.2f} ms ({best}); agent-steps {agent_steps}; "
+        f"N_live mean {acting.mean():.1f} min {acting.min()} max {acting.max()}; births {int(ctr['births'].sum())} "
+        f"deaths {int(ctr['deaths'].sum())}")
+
+    # roofline of the dominant kernel: act phase in per-phase mode with events
+    w.load(start)
+    nnz0 = observed_inputs(start, cfg)
+    ph_ms = w.phase_times(args.phase_steps)
+    mid = w.snapshot()
+    nnz1 = observed_inputs(mid, cfg)
+    nnz_mean = float(np.concatenate([nnz0, nnz1]).mean())
+    pc = w.counters(t_first, args.phase_steps)
+    n_act = float(np.concatenate([[start["n_live"]], pc["n_live"][:-1]]).mean())
+    per_agent = act_bytes_per_agent(cfg, nnz_mean)
+    grid_bytes = cfg["H"] * cfg["W"] * 5
+    act_bytes = n_act * per_agent + grid_bytes
+    act_ms = float(ph_ms[0])
+    achieved = act_bytes / (act_ms * 1e-3) / 1e9
+    src_hash = kernel_source_hash()
+    traffic = read_traffic(src_hash)
+    dense_per_agent = 4 * w.n_params + 2 * cfg["hidden"] * 4 + 21
+    log(f"[bench] phases ms/step act {ph_ms[0]:.4f} move {ph_ms[1]:.4f} claim+regrow {ph_ms[2]:.4f}; "
+        f"nnz mean {nnz_mean:.2f}; act bytes {act_bytes / 1e6:.2f} MB")
+
+    if args.calib_copy:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            world.test_copy(src, dst, stream)
+        torch.cuda.synchronize()
+        log("[bench] copy calibration: 3 x 1 GiB device copies done")
+
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] oracle CPU baseline ...")
+        cpu = cpu_baseline(cfg, args.seed, args.cpu_seconds)
+        log(f"[bench] oracle: {cpu['value']:.0f} agent-steps/s")
+
+    ms_per_step = wall / args.steps * 1e3
+    out = {
+        "metric": "agent-steps/s @200x400, ~4k agents; batched/served p50/p99 step latency",
+        "value": value,
+        "unit": "agent-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded counter-based generator: resources, placement, genomes)",
+        "config": {
+            "workload": f"{args.workload}: {cfg['H']}x{cfg['W']} grid, cap {cfg['cap']}, {cfg['n_init']} initial "
+                        f"agents, resources Bernoulli({cfg['res_init_p']}), regrowth x{cfg['rate_scale']}, "
+                        f"obs {2 * cfg['obs_radius'] + 1}x{2 * cfg['obs_radius'] + 1}x2+1, GRU {cfg['hidden']}, "
+                        f"seed {args.seed}",
+            "launch_mode": best,
+            "steps_per_launch": args.chunk,
+            "n_live_mean": float(acting.mean()),
+            "n_live_min": int(acting.min()),
+            "n_live_max": int(acting.max()),
+            "births": int(ctr["births"].sum()),
+            "deaths": int(ctr["deaths"].sum()),
+            "parallelism": "single GPU",
+        },
+        "latency_ms_per_step": {"p50": float(np.percentile(per_step_ms, 50)),
+                                "p99": float(np.percentile(per_step_ms, 99)),
+                                "window": f"per {args.chunk}-step launch"},
+        "modes_us_per_step": {m: v * 1e3 for m, v in calib.items()},
+        "phases_ms_per_step": {"act": float(ph_ms[0]), "move": float(ph_ms[1]),
+                               "claim_regrow": float(ph_ms[2])},
+        "roofline": {
+            "kernel": "k_act (observation + GRU + head, one wave per agent)",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": act_bytes,
+            "per_agent_bytes": per_agent,
+            "agents_per_launch": n_act,
+            "nnz_binary_inputs_mean": nnz_mean,
+            "dense_equivalent_bytes_per_launch": n_act * dense_per_agent + grid_bytes,
+            "act_ms": act_ms,
+            "kernel_source_sha256_16": src_hash,
+        },
+        "cpu_baseline": cpu,
+    }
+    w.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

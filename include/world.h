@@ -77,7 +77,7 @@ typedef struct world_config {
 
 typedef struct world world_t;
 
-/* Per-step counters kept on device for the last 1024 steps. */
+/* Per-step counters kept on device for the last 8192 steps. */
 typedef struct world_counters {
     int32_t n_live;      /* live agents after the step          */
     int32_t births;      /* children created in the step        */
@@ -173,6 +173,18 @@ int world_test_philox(const uint32_t *d_ctr, size_t n, uint32_t k0, uint32_t k1,
 /* Box-Muller normals on the device from n word pairs (device buffers). */
 int world_test_gauss(const uint32_t *d_a, const uint32_t *d_b, size_t n, float *d_z0, float *d_z1,
                      void *hip_stream);
+
+/* Run K steps as per-phase kernels with HIP events between the phases (on
+ * the world's stream) and return the mean milliseconds per step of each phase
+ * in ms[0..2] = act (child genomes of the previous step, observation and
+ * controller), move (moves, energy, death, survivor scan), claim (birth
+ * claims, birth scan, regrowth).  The steps are real: the world advances by
+ * K.  Synchronises. */
+int world_phase_times(world_t *w, int32_t K, float *ms);
+
+/* Plain device-to-device copy kernel (16-byte vector loads/stores) of `bytes`
+ * (multiple of 16) on hip_stream; a known-size reference for memory counters. */
+int world_test_copy(const void *d_src, void *d_dst, size_t bytes, void *hip_stream);
 
 /* Regrowth threshold table of a configuration, as the library builds it
  * (host memory, H x 25 entries; grow iff draw < entry). */

@@ -36,16 +36,19 @@ def flags() -> list[str]:
     ]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = [hipcc()] + flags() + SOURCES + ["-o", tmp]
+def build(verbose: bool = False, out: str = LIB, defines: dict | None = None) -> str:
+    """Compile the library to `out`; `defines` are extra -D tuning macros
+    (ECO_ACT_ROWS, ECO_ACT_WAVES)."""
+    tmp = out + ".tmp"
+    extra = [f"-D{k}={v}" for k, v in (defines or {}).items()]
+    cmd = [hipcc()] + flags() + extra + SOURCES + ["-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)
     if verbose and (res.stdout or res.stderr):
         print(res.stdout + res.stderr)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -13,8 +13,8 @@
 
 namespace eco {
 
-enum : int { kPreAct = 0, kPreAgent = 1, kPreTile = 2, kPreSpawn = 3, kPreKinds = 4 };
-constexpr int kSpawnBlocksPerWorld = 32;
+enum : int { kPreAct = 0, kPreMove = 1, kPreClaim = 2, kPreKinds = 3 };
+constexpr int kNewbornBlocks = 64;   // leading act blocks that create children
 
 struct Batch {
     const WorldDev* const* w;   // n descriptors
@@ -32,65 +32,139 @@ __device__ __forceinline__ int find_world(const int* pre, int n, int b) {
     return lo;
 }
 
-__global__ __launch_bounds__(kBlock) void k_act(Batch bt) {
+// Block bodies, shared by the per-phase kernels and the persistent kernel.
+// `vb` is the block's index in the batch-wide numbering of its phase.
+
+// Act blocks of a world: kNewbornBlocks leading blocks create the children of
+// the previous step (rank r, r + kNewbornBlocks, ...) and run their first
+// controller step (they are the last n_child entries of the live list); the
+// remaining blocks run the controller of the other agents, four per block.
+__device__ __forceinline__ void act_body(const Batch& bt, int vb, int tid, StepShared& sh) {
     const int* pre = bt.pre + kPreAct * (bt.n + 1);
-    const int wi = find_world(pre, bt.n, blockIdx.x);
+    const int wi = find_world(pre, bt.n, vb);
     const WorldDev& d = *bt.w[wi];
-    const int lb = blockIdx.x - pre[wi];
-    const int64_t t = d.scal->t;
-    const int n = d.scal->n_live;
-    if (lb == 0 && threadIdx.x == 0) step_open(d, t);
-    const int li = lb * (kBlock / 64) + int(threadIdx.x >> 6);
-    if (li >= n) return;
-    const int slot = d.live[d.scal->live_sel][li];
-    const int lane = threadIdx.x & 63;
-    if (d.hd == 32) act_agent<32>(d, slot, li, t, lane);
-    else act_agent<16>(d, slot, li, t, lane);
+    const int lb = vb - pre[wi];
+    const WorldScal* S = d.scal;
+    const int64_t t = S->t;
+    const int n = S->n_live;
+    const int nc = S->n_child;
+    const int sel = S->live_sel;
+    if (lb < kNewbornBlocks) {
+        if (lb == 0) {
+            if (tid == 0) step_open(d, t);
+            close_counters_in_step(d, tid, sh);
+        }
+        for (int rk = lb; rk < nc; rk += kNewbornBlocks) {
+            spawn_child(d, rk, tid);
+            __syncthreads();
+            spawn_proj(d, rk, tid);
+            __syncthreads();
+            if (tid < 64) {
+                const int li = n - nc + rk;
+                const int slot = d.live[sel][li];
+                if (d.hd == 32) act_agent<32>(d, slot, li, t, tid);
+                else act_agent<16>(d, slot, li, t, tid);
+            }
+            __syncthreads();
+        }
+        return;
+    }
+    const int li = (lb - kNewbornBlocks) * (kBlock / 64) + (tid >> 6);
+    if (li >= n - nc) return;
+    const int slot = d.live[sel][li];
+    if (d.hd == 32) act_agent<32>(d, slot, li, t, tid & 63);
+    else act_agent<16>(d, slot, li, t, tid & 63);
+}
+
+__device__ __forceinline__ void move_body(const Batch& bt, int vb, int tid, StepShared& sh) {
+    const int* pre = bt.pre + kPreMove * (bt.n + 1);
+    const int wi = find_world(pre, bt.n, vb);
+    move_block(*bt.w[wi], vb - pre[wi], tid, sh);
+}
+
+// Claim blocks of a world: the claim tiles (look-back order), the regrowth
+// tiles, then one wave per survivor computing the recurrent projection for
+// the next act phase (the survivors are the first entries of the next live
+// list, whose count the move look-back has fixed).
+__device__ __forceinline__ void claim_body(const Batch& bt, int vb, int tid, StepShared& sh) {
+    const int* pre = bt.pre + kPreClaim * (bt.n + 1);
+    const int wi = find_world(pre, bt.n, vb);
+    const WorldDev& d = *bt.w[wi];
+    const int lb = vb - pre[wi];
+    const int ntile = (d.cap + kBlock - 1) / kBlock;
+    if (lb < ntile) {
+        claim_block(d, lb, tid, sh);
+        return;
+    }
+    if (lb < ntile + d.ntiles) {
+        regrow_tile(d, lb - ntile, tid, sh);
+        return;
+    }
+    const int li = (lb - ntile - d.ntiles) * (kBlock / 64) + (tid >> 6);
+    const int surv = int(unpack_a(lookback_total(d.lb_move, ntile)));
+    if (li >= surv) return;
+    const int slot = d.live[d.scal->live_sel ^ 1][li];
+    if (d.hd == 32) proj_agent<32>(d, slot, tid & 63);
+    else proj_agent<16>(d, slot, tid & 63);
+}
+
+#ifndef ECO_ACT_WAVES
+#define ECO_ACT_WAVES 0   // waves per SIMD the act kernel is compiled for (0 = compiler's choice)
+#endif
+#if ECO_ACT_WAVES > 0
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(ECO_ACT_WAVES, ECO_ACT_WAVES)))
+#else
+__global__ __launch_bounds__(kBlock)
+#endif
+void k_act(Batch bt) {
+    __shared__ StepShared sh;
+    act_body(bt, blockIdx.x, threadIdx.x, sh);
+}
+
+// Creates the pending children of a world's last step now (before its state
+// is read by the host); k_clear_pending then marks them as created, so the
+// next act phase treats them as ordinary agents.
+__global__ __launch_bounds__(kBlock) void k_materialize(const WorldDev* dp) {
+    const WorldDev& d = *dp;
+    const int nc = d.scal->n_child;
+    for (int rk = blockIdx.x; rk < nc; rk += gridDim.x) {
+        spawn_child(d, rk, threadIdx.x);
+        __syncthreads();
+        spawn_proj(d, rk, threadIdx.x);
+        __syncthreads();
+    }
+}
+
+// Recurrent projections of every live agent of a world (after creation or a
+// load, when no move phase has produced them).
+__global__ __launch_bounds__(kBlock) void k_proj_all(const WorldDev* dp) {
+    const WorldDev& d = *dp;
+    const WorldScal* S = d.scal;
+    const int li = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (li >= S->n_live) return;
+    const int slot = d.live[S->live_sel][li];
+    if (d.hd == 32) proj_agent<32>(d, slot, threadIdx.x & 63);
+    else proj_agent<16>(d, slot, threadIdx.x & 63);
+}
+
+__global__ void k_clear_pending(const WorldDev* dp) {
+    if (threadIdx.x == 0) dp->scal->n_child = 0;
+}
+
+// Sums the eaten / resource partials of a world's last step if still open.
+__global__ __launch_bounds__(kBlock) void k_close_counters(const WorldDev* dp) {
+    __shared__ StepShared sh;
+    close_counters_in_step(*dp, threadIdx.x, sh);
 }
 
 __global__ __launch_bounds__(kBlock) void k_move(Batch bt) {
-    const int* pre = bt.pre + kPreAgent * (bt.n + 1);
-    const int wi = find_world(pre, bt.n, blockIdx.x);
-    const WorldDev& d = *bt.w[wi];
-    const int i = (blockIdx.x - pre[wi]) * kBlock + threadIdx.x;
-    const int64_t t = d.scal->t;
-    int ate = 0;
-    if (i < d.scal->n_live) ate = move_agent(d, d.live[d.scal->live_sel][i], t);
-    const int cnt = __popcll(__ballot(ate != 0));
-    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(d.ring + (t % kRing) * kCtrWords + kCtrEaten, cnt);
+    __shared__ StepShared sh;
+    move_body(bt, blockIdx.x, threadIdx.x, sh);
 }
 
 __global__ __launch_bounds__(kBlock) void k_claim(Batch bt) {
-    const int* pre = bt.pre + kPreAgent * (bt.n + 1);
-    const int wi = find_world(pre, bt.n, blockIdx.x);
-    const WorldDev& d = *bt.w[wi];
-    const int i = (blockIdx.x - pre[wi]) * kBlock + threadIdx.x;
-    if (i < d.scal->n_live) claim_agent(d, d.live[d.scal->live_sel][i], d.scal->t);
-}
-
-__global__ __launch_bounds__(kBlock) void k_regrow(Batch bt) {
-    __shared__ uint8_t s[(kTile + 4) * (kTile + 4)];
-    const int* pre = bt.pre + kPreTile * (bt.n + 1);
-    const int wi = find_world(pre, bt.n, blockIdx.x);
-    const WorldDev& d = *bt.w[wi];
-    const int64_t t = d.scal->t;
-    const int cnt = regrow_tile(d, blockIdx.x - pre[wi], t, threadIdx.x, s);
-    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(d.ring + (t % kRing) * kCtrWords + kCtrRes, cnt);
-}
-
-__global__ __launch_bounds__(kBlock) void k_scan(Batch bt) {
-    __shared__ int sm[3 * (kBlock / 64)];
-    scan_world(*bt.w[blockIdx.x], threadIdx.x, sm);
-}
-
-__global__ __launch_bounds__(kBlock) void k_spawn(Batch bt) {
-    const int* pre = bt.pre + kPreSpawn * (bt.n + 1);
-    const int wi = find_world(pre, bt.n, blockIdx.x);
-    const WorldDev& d = *bt.w[wi];
-    const int nchunks = (d.nblk + kBlock - 1) / kBlock;
-    const int items = d.scal->n_child * nchunks;
-    const int nb = pre[wi + 1] - pre[wi];
-    for (int it = blockIdx.x - pre[wi]; it < items; it += nb) spawn_item(d, it, nchunks, threadIdx.x);
+    __shared__ StepShared sh;
+    claim_body(bt, blockIdx.x, threadIdx.x, sh);
 }
 
 // Initial genomes: agent slots [0, n_init) hold uids 0..n_init-1; parameter p
@@ -121,6 +195,10 @@ __global__ __launch_bounds__(kBlock) void k_init_theta(const WorldDev* dp, int n
         *reinterpret_cast<float4*>(d.theta + size_t(a) * size_t(d.Ppad) + 4 * blk) =
             make_float4(o[0], o[1], o[2], o[3]);
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy16(const int4* __restrict__ src, int4* __restrict__ dst, size_t n) {
+    for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += size_t(gridDim.x) * kBlock) dst[i] = src[i];
 }
 
 __global__ void k_test_philox(const uint32_t* ctr, size_t n, uint32_t k0, uint32_t k1, uint32_t* out) {

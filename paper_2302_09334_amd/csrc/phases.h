@@ -1,15 +1,21 @@
 // phases.h -- device code of one world step (gfx950, wave64).
 //
-// A step is split into five phases separated by device-wide ordering points
-// (kernel boundaries or grid barriers):
-//   P1 act     observe + GRU controller + arg-max, one wave per agent
-//   P2 move    move resolution, eating, energy, age, death, streak
-//   P3 claim   birth claims and their resolution; regrowth of the grid
-//   P4 scan    one block per world: survivors, deaths and winners in uid
-//              order, slot allocation for children, live-list compaction
-//   P5 spawn   child genomes (parent + sigma * N(0, 1)) and child records
+// A step is three phases separated by device-wide ordering points (kernel
+// boundaries or grid barriers):
+//   P1 act     observe + GRU controller + arg-max, one wave per agent; the
+//              children born in the previous step are first created (genome =
+//              parent + sigma * N(0, 1), record, occB) by leading blocks,
+//              which then run their first controller step
+//   P2 move    move resolution, eating, energy, age, death, streak; a
+//              decoupled look-back scan over the live list (uid order)
+//              compacts the survivors and ranks the dead
+//   P3 claim   birth claims and their resolution, ranked by a second
+//              look-back scan (born = rank < cap - survivors, so every
+//              winner knows its child slot at once); regrowth tiles; the
+//              last claim block to finish closes the step's bookkeeping
 // Every decision is a gather: an agent reads its neighbours' state and
-// decides on its own, so no phase needs atomics except the integer counters.
+// decides on its own; cross-block communication is limited to the look-back
+// status words and one completion counter per world.
 //
 // Paper mapping: observation and controller App. B.2/B.5, moves and energy
 // App. B.2, reproduction/mutation/death App. B.3, regrowth App. B.1 Eq. (1).
@@ -21,6 +27,11 @@
 #include "world_dev.h"
 
 namespace eco {
+
+// occB word of a live agent after P2: slot | eligible << 30 | birth dir << 28.
+constexpr int kOccElig = 1 << 30;
+constexpr int kOccDirShift = 28;
+constexpr int kOccSlotMask = (1 << 28) - 1;
 
 // Action deltas: 0 = N (row - 1), 1 = S (row + 1), 2 = E (col + 1),
 // 3 = W (col - 1), 4 = stay.
@@ -46,27 +57,26 @@ __device__ __forceinline__ float sigmoidf_(float v) { return 1.0f / (1.0f + expf
 // tree.  The summation order therefore depends only on the agent's own
 // observation, never on the launch shape or on other worlds in the launch.
 // ---------------------------------------------------------------------------
+#ifndef ECO_ACT_ROWS
+#define ECO_ACT_ROWS 16   // input rows fetched per wave per batch
+#endif
+
+// ---------------------------------------------------------------------------
+// Recurrent projection gh = W_hh h + b_hh of the agent in `slot` (one wave),
+// written to gh[slot] (3 * HD floats, gate-interleaved per hidden unit).  It
+// depends only on the hidden state left by the last act phase, so it is
+// computed ahead of the next act phase, off its critical path.  Group g sums
+// the recurrent rows j = jj * G + g in increasing jj, then the groups combine
+// by a fixed xor tree: the order depends on nothing but the agent.
+// ---------------------------------------------------------------------------
 template <int HD>
-__device__ __forceinline__ void act_agent(const WorldDev& d, int slot, int li, int64_t t, int lane) {
+__device__ __forceinline__ void proj_agent(const WorldDev& d, int slot, int lane) {
     constexpr int G = 64 / HD;
-    constexpr int RW = 3 * HD;   // floats per input row
-    constexpr int JJ = HD / G;   // recurrent rows per group
-    constexpr int B = 8;         // input rows per group per batch
+    constexpr int RW = 3 * HD;
+    constexpr int JJ = HD / G;
     const int g = lane / HD;
     const int k = lane - g * HD;
-    const int H = d.H, W = d.W;
-    const int cell = d.cell[slot];
-    const int r = cell / W;
-    const int c = cell - r * W;
-    const int e = d.energy[slot];
     const float* th = d.theta + size_t(slot) * size_t(d.Ppad);
-
-    // A child created in the previous step is entered into occB here, where
-    // no phase reads occB.
-    if (lane == 0 && d.age[slot] == 0) d.occB[cell] = slot;
-
-    // Recurrent weights and hidden state do not depend on the observation:
-    // issue them first.
     const float hk = d.h[size_t(slot) * HD + k];
     float whr[JJ], whz[JJ], whn[JJ];
 #pragma unroll
@@ -76,11 +86,93 @@ __device__ __forceinline__ void act_agent(const WorldDev& d, int slot, int li, i
         whz[jj] = p[1];
         whn[jj] = p[2];
     }
+    const float* pbh = th + d.off_bhh + 3 * k;
+    const float bhr = pbh[0], bhz = pbh[1], bhn = pbh[2];
+    float hr = 0.f, hz = 0.f, hn = 0.f;
+#pragma unroll
+    for (int jj = 0; jj < JJ; ++jj) {
+        const float hj = __shfl(hk, jj * G + g);
+        hr = fmaf(hj, whr[jj], hr);
+        hz = fmaf(hj, whz[jj], hz);
+        hn = fmaf(hj, whn[jj], hn);
+    }
+#pragma unroll
+    for (int off = HD; off < 64; off <<= 1) {
+        hr += __shfl_xor(hr, off);
+        hz += __shfl_xor(hz, off);
+        hn += __shfl_xor(hn, off);
+    }
+    if (g == 0) {
+        float* o = d.gh + size_t(slot) * RW + 3 * k;
+        o[0] = hr + bhr;
+        o[1] = hz + bhz;
+        o[2] = hn + bhn;
+    }
+}
 
-    // Observation: lane q < w^2 looks at window cell (q / w - rho, q % w - rho).
+// A zero hidden state (new agents) projects to b_hh.
+template <int HD>
+__device__ __forceinline__ void proj_zero(const WorldDev& d, int slot, int lane) {
+    constexpr int RW = 3 * HD;
+    if (lane < HD) {
+        const float* pbh = d.theta + size_t(slot) * size_t(d.Ppad) + d.off_bhh + 3 * lane;
+        float* o = d.gh + size_t(slot) * RW + 3 * lane;
+        // 0 * W_hh summed from +0 is +0, and +0 + b = b: the same bits as the
+        // full projection of a zero hidden state.
+        o[0] = 0.f + pbh[0];
+        o[1] = 0.f + pbh[1];
+        o[2] = 0.f + pbh[2];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// P1: observation + GRU + head + arg-max for the agent in `slot` (one wave).
+//
+// Lane layout: G = 64 / HD groups of HD lanes; lane (g, k) owns hidden unit k
+// of group g.  Each input row of W_ih holds the 3 gate weights of every
+// hidden unit contiguously (3 * HD floats), so a group reads one row with one
+// 12-byte load per lane.  Inputs are binary except the energy, so the input
+// projection is a sum of the rows whose input is 1: the set bits of two wave
+// ballots are dealt round-robin to the groups, each group sums its rows in
+// increasing input order, and the group partials are combined by a fixed xor
+// tree.  The summation order therefore depends only on the agent's own
+// observation, never on the launch shape or on other worlds in the launch.
+// The recurrent projection comes precomputed from gh[slot].
+// ---------------------------------------------------------------------------
+template <int HD>
+__device__ __forceinline__ void act_agent(const WorldDev& d, int slot, int li, int64_t t, int lane) {
+    constexpr int G = 64 / HD;
+    constexpr int RW = 3 * HD;   // floats per input row
+    constexpr int B = ECO_ACT_ROWS / G;   // input rows per group per batch
+    const int g = lane / HD;
+    const int k = lane - g * HD;
+    const int H = d.H, W = d.W;
+    const int cell = d.cell[slot];
+    const int r = cell / W;
+    const int c = cell - r * W;
+    const int e = d.energy[slot];
+    const float* th = d.theta + size_t(slot) * size_t(d.Ppad);
     const int rho = d.rho;
     const int win = 2 * rho + 1;
     const int w2 = win * win;
+    const int erow = 2 * w2;   // energy input row
+
+    // Round trip 1: everything that does not depend on the observation (the
+    // hidden state, the recurrent projection, the input biases, the energy
+    // row, the head) together with the observation window itself.
+    const float hk = d.h[size_t(slot) * HD + k];
+    const float* pg = d.gh + size_t(slot) * RW + 3 * k;
+    const float ghr = pg[0], ghz = pg[1], ghn = pg[2];
+    const float* pe = th + erow * RW + 3 * k;
+    const float* pbi = th + d.off_bih + 3 * k;
+    const float er = pe[0], ez = pe[1], en = pe[2];
+    const float bir = pbi[0], biz = pbi[1], bin = pbi[2];
+    float wo[5], bo[5];
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+        wo[a] = th[d.off_wo + a * HD + k];
+        bo[a] = th[d.off_bo + a];
+    }
     const uint8_t* R = d.R[t & 1];
     bool rb = false, ob = false;
     if (lane < w2) {
@@ -97,8 +189,9 @@ __device__ __forceinline__ void act_agent(const WorldDev& d, int slot, int li, i
     }
     uint64_t mR = __ballot(rb);
     uint64_t mO = __ballot(ob);
+    const uint64_t occ_bits = mO;
 
-    const int erow = 2 * w2;   // energy input row
+    // Round trip 2 (usually the last): every input row whose input is 1.
     float ar = 0.f, az = 0.f, an = 0.f;
     while (mR | mO) {
         int rows[G * B];
@@ -135,35 +228,17 @@ __device__ __forceinline__ void act_agent(const WorldDev& d, int slot, int li, i
             an += vn[b];
         }
     }
-
-    float hr = 0.f, hz = 0.f, hn = 0.f;
-#pragma unroll
-    for (int jj = 0; jj < JJ; ++jj) {
-        const float hj = __shfl(hk, jj * G + g);
-        hr = fmaf(hj, whr[jj], hr);
-        hz = fmaf(hj, whz[jj], hz);
-        hn = fmaf(hj, whn[jj], hn);
-    }
 #pragma unroll
     for (int off = HD; off < 64; off <<= 1) {
         ar += __shfl_xor(ar, off);
         az += __shfl_xor(az, off);
         an += __shfl_xor(an, off);
-        hr += __shfl_xor(hr, off);
-        hz += __shfl_xor(hz, off);
-        hn += __shfl_xor(hn, off);
     }
 
     const float xe = float(e) / float(d.E0);
-    const float* pe = th + erow * RW + 3 * k;
-    const float* pbi = th + d.off_bih + 3 * k;
-    const float* pbh = th + d.off_bhh + 3 * k;
-    const float gir = fmaf(xe, pe[0], ar) + pbi[0];
-    const float giz = fmaf(xe, pe[1], az) + pbi[1];
-    const float gin = fmaf(xe, pe[2], an) + pbi[2];
-    const float ghr = hr + pbh[0];
-    const float ghz = hz + pbh[1];
-    const float ghn = hn + pbh[2];
+    const float gir = fmaf(xe, er, ar) + bir;
+    const float giz = fmaf(xe, ez, az) + biz;
+    const float gin = fmaf(xe, en, an) + bin;
     const float rg = sigmoidf_(gir + ghr);
     const float zg = sigmoidf_(giz + ghz);
     const float ng = tanhf(fmaf(rg, ghn, gin));
@@ -172,10 +247,10 @@ __device__ __forceinline__ void act_agent(const WorldDev& d, int slot, int li, i
     float lg[5];
 #pragma unroll
     for (int a = 0; a < 5; ++a) {
-        float v = hnew * th[d.off_wo + a * HD + k];
+        float v = hnew * wo[a];
 #pragma unroll
         for (int off = HD / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        lg[a] = v + th[d.off_bo + a];
+        lg[a] = v + bo[a];
     }
     int best = 0;
 #pragma unroll
@@ -184,7 +259,23 @@ __device__ __forceinline__ void act_agent(const WorldDev& d, int slot, int li, i
     if (d.forced >= 0) best = d.forced;
 
     if (g == 0) d.h[size_t(slot) * HD + k] = hnew;
-    if (lane == 0) d.action[slot] = uint8_t(best);
+    if (lane == 0) {
+        d.action[slot] = uint8_t(best);
+        // Move claim (resolved by the next phase): a move targets the window
+        // cell one step away, which must be inside the grid and empty at the
+        // step start (its occupancy bit, outside cells reading occupied, is 0).
+        // The smallest (MOVE draw, uid) among a cell's claimants wins; an
+        // atomic minimum is independent of the order of the claims.
+        if (best < 4) {
+            const int q = (rho + act_dr(best)) * win + (rho + act_dc(best));
+            if (!((occ_bits >> q) & 1ull)) {
+                const uint32_t u = d.uid[slot];
+                const uint64_t key = claim_key(philox(u, uint32_t(t), kMove, 0, d.seed_lo, d.seed_hi).x, u);
+                const int Y = (r + act_dr(best)) * W + (c + act_dc(best));
+                atomicMin(reinterpret_cast<unsigned long long*>(d.mclaim + Y), (unsigned long long)key);
+            }
+        }
+    }
     if (d.log_steps > 0) {
         const size_t row = size_t(t % d.log_steps) * size_t(d.cap) + size_t(li);
         if (lane == 0) {
@@ -203,21 +294,111 @@ __device__ __forceinline__ void act_agent(const WorldDev& d, int slot, int li, i
 
 // Step-start bookkeeping done once per world per step by one thread.
 __device__ __forceinline__ void step_open(const WorldDev& d, int64_t t) {
-    int32_t* rec = d.ring + (t % kRing) * kCtrWords;
-    rec[kCtrEaten] = 0;
-    rec[kCtrRes] = 0;
     if (d.log_steps > 0) d.log_n[t % d.log_steps] = d.scal->n_live;
 }
 
 // ---------------------------------------------------------------------------
-// P2: moves (one thread per live agent).  A move is claimed only into an
-// in-grid cell empty at the step start; the neighbours N of the target that
-// claim it are exactly those whose action points from N to the target, and
-// the smallest (MOVE draw, uid) among them wins.  Each agent evaluates the
-// competition for its own target, so no claim grid is needed.  Then: eat the
+// Decoupled look-back prefix sum over the tiles of one phase (tile = one
+// block of kBlock live-list entries).  A status word packs
+//   [epoch 20 | flag 2 | a 21 | b 21]   flag 1 = tile total, 2 = inclusive
+// where epoch = step mod 2^20, so words from earlier steps are ignored and the
+// arrays never need clearing between steps.  Returns the exclusive prefix of
+// the packed (a, b) pair; waits are bounded (2 s) and a time-out sets the
+// world's error word.
+// ---------------------------------------------------------------------------
+constexpr int kCntBits = 21;
+constexpr uint64_t kCntMask = (uint64_t(1) << kCntBits) - 1;
+constexpr uint64_t kValMask = (uint64_t(1) << (2 * kCntBits)) - 1;
+
+__device__ __forceinline__ uint64_t pack2(uint32_t a, uint32_t b) { return (uint64_t(a) << kCntBits) | b; }
+__device__ __forceinline__ uint32_t unpack_a(uint64_t v) { return uint32_t((v >> kCntBits) & kCntMask); }
+__device__ __forceinline__ uint32_t unpack_b(uint64_t v) { return uint32_t(v & kCntMask); }
+
+__device__ __forceinline__ uint64_t lookback(const WorldDev& d, uint64_t* st, int tile, uint32_t epoch,
+                                             uint64_t local, int tid, uint64_t* s_bcast) {
+    if (tid == 0) {
+        const uint64_t tag = uint64_t(epoch & 0xFFFFFu) << 44;
+        uint64_t excl = 0;
+        if (tile == 0) {
+            __hip_atomic_store(st, tag | (uint64_t(2) << 42) | local, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            __hip_atomic_store(st + tile, tag | (uint64_t(1) << 42) | local, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            int k = tile - 1;
+            const uint64_t t0 = wall_clock64();
+            while (k >= 0) {
+                const uint64_t v = __hip_atomic_load(st + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t flag = uint32_t(v >> 42) & 3u;
+                if ((v >> 44) != (tag >> 44) || flag == 0) {
+                    if (wall_clock64() - t0 > 200000000ull) {   // 2 s at the 100 MHz wall clock
+                        __hip_atomic_store(&d.scal->err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                excl += v & kValMask;
+                if (flag == 2) break;
+                --k;
+            }
+            __hip_atomic_store(st + tile, tag | (uint64_t(2) << 42) | (excl + local), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        *s_bcast = excl;
+    }
+    __syncthreads();
+    const uint64_t r = *s_bcast;
+    __syncthreads();
+    return r;
+}
+
+// Inclusive total of the last tile of a completed look-back.
+__device__ __forceinline__ uint64_t lookback_total(const uint64_t* st, int ntile) {
+    return __hip_atomic_load(st + ntile - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kValMask;
+}
+
+// Block-local exclusive ranks of two predicates and the block totals.
+struct BlockRank {
+    int ra, rb;   // this thread's exclusive rank among the block's a / b
+    int ta, tb;   // block totals
+};
+
+__device__ __forceinline__ BlockRank block_rank2(bool a, bool b, int tid, int* sw) {
+    const int lane = tid & 63, wv = tid >> 6;
+    constexpr int NW = kBlock / 64;
+    const uint64_t ma = __ballot(a), mb = __ballot(b);
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    if (lane == 0) {
+        sw[wv] = __popcll(ma);
+        sw[NW + wv] = __popcll(mb);
+    }
+    __syncthreads();
+    BlockRank r;
+    r.ra = __popcll(ma & lt);
+    r.rb = __popcll(mb & lt);
+    r.ta = r.tb = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        if (w < wv) {
+            r.ra += sw[w];
+            r.rb += sw[NW + w];
+        }
+        r.ta += sw[w];
+        r.tb += sw[NW + w];
+    }
+    __syncthreads();
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// P2: moves (one thread per live agent).  A move was claimed in P1 only into
+// an in-grid cell empty at the step start, and the cell's claim word holds
+// the smallest (MOVE draw, uid) of its claimants: the agent moves iff that is
+// its own key.  Then: eat the
 // resource of the final cell, energy += gain * ate - decay, age += 1, death
 // at energy <= 0 or age >= L_max, streak of survivors.  occB receives the
 // moves and deaths; occA (read by every agent in this phase) is untouched.
+// Returns bit 0 = ate, bit 1 = died.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int move_agent(const WorldDev& d, int slot, int64_t t) {
     const int W = d.W, H = d.H;
@@ -230,20 +411,8 @@ __device__ __forceinline__ int move_agent(const WorldDev& d, int slot, int64_t t
         const int tr = r + act_dr(a), tc = c + act_dc(a);
         if (tr >= 0 && tr < H && tc >= 0 && tc < W) {
             const int Y = tr * W + tc;
-            if (d.occA[Y] == -1) {
-                const uint64_t key = claim_key(philox(u, uint32_t(t), kMove, 0, d.seed_lo, d.seed_hi).x, u);
-                bool won = true;
-                for (int d2 = 0; d2 < 4; ++d2) {
-                    const int nr = tr - act_dr(d2), nc = tc - act_dc(d2);
-                    if ((nr == r && nc == c) || nr < 0 || nr >= H || nc < 0 || nc >= W) continue;
-                    const int o = d.occA[nr * W + nc];
-                    if (o < 0 || d.action[o] != d2) continue;
-                    const uint32_t uo = d.uid[o];
-                    const uint64_t ko = claim_key(philox(uo, uint32_t(t), kMove, 0, d.seed_lo, d.seed_hi).x, uo);
-                    if (ko < key) won = false;
-                }
-                if (won) newX = Y;
-            }
+            const uint64_t key = claim_key(philox(u, uint32_t(t), kMove, 0, d.seed_lo, d.seed_hi).x, u);
+            if (d.mclaim[Y] == key) newX = Y;
         }
     }
     uint8_t* Rc = d.R[t & 1];
@@ -260,42 +429,103 @@ __device__ __forceinline__ int move_agent(const WorldDev& d, int slot, int64_t t
     d.cell[slot] = newX;
     d.prev_cell[slot] = X;
     d.alive[slot] = dead ? 0 : 1;
-    if (newX != X) {
-        d.occB[X] = -1;
-        if (!dead) d.occB[newX] = slot;
-    } else if (dead) {
-        d.occB[X] = -1;
+    // Both occupancy grids take the moves and deaths (neither is read in this
+    // phase): occA is the next step's start state, occB is read by P3.  A
+    // survivor's occB word also says whether it is eligible to reproduce and
+    // from which direction its birth scan starts; its birth key is stored per
+    // slot, so P3 learns a neighbour's claim from occupancy reads alone.
+    int word = -1;
+    if (!dead) {
+        word = slot;
+        if (st >= d.T_repr) {
+            const Draw4 b = philox(u, uint32_t(t), kBirth, 0, d.seed_lo, d.seed_hi);
+            word |= kOccElig | int((b.x & 3u) << kOccDirShift);
+            d.bkey[slot] = claim_key(b.y, u);
+        }
     }
-    return ate;
+    if (newX != X) {
+        d.occA[X] = -1;
+        d.occB[X] = -1;
+        if (!dead) d.occA[newX] = slot;
+    } else if (dead) {
+        d.occA[X] = -1;
+    }
+    d.occB[newX] = word;
+    return ate | (dead ? 2 : 0);
+}
+
+struct StepShared {
+    uint8_t tile[(kTile + 4) * (kTile + 4)];
+    int sw[2 * (kBlock / 64)];
+    uint64_t bcast;
+    int flag;
+};
+
+// P2 for tile `j` (kBlock live-list entries) of one world.  Survivors keep
+// their uid order in the next live list; dead slots are listed in uid order.
+__device__ __forceinline__ void move_block(const WorldDev& d, int j, int tid, StepShared& sh) {
+    const WorldScal* S = d.scal;
+    const int n = S->n_live;
+    const int sel = S->live_sel;
+    const int64_t t = S->t;
+    const int i = j * kBlock + tid;
+    int slot = -1, res = 0;
+    if (i < n) {
+        slot = d.live[sel][i];
+        res = move_agent(d, slot, t);
+    }
+    const bool alive = i < n && !(res & 2);
+    const bool dead = i < n && (res & 2);
+    const int cnt = __popcll(__ballot((res & 1) != 0));
+    if ((tid & 63) == 0) d.eat_part[i >> 6] = cnt;
+    const BlockRank br = block_rank2(alive, dead, tid, sh.sw);
+    const uint64_t ex = lookback(d, d.lb_move, j, uint32_t(t), pack2(br.ta, br.tb), tid, &sh.bcast);
+    if (alive) d.live[sel ^ 1][unpack_a(ex) + br.ra] = slot;
+    if (dead) d.deadlist[unpack_b(ex) + br.rb] = slot;
 }
 
 // First free in-grid 4-neighbour of `cell` (order N, S, E, W cyclically from
-// `d0`) in the post-move, post-death occupancy; -1 if none.
+// `d0`) in the post-move, post-death occupancy; -1 if none.  The four
+// occupancy words are loaded together.
 __device__ __forceinline__ int birth_target(const WorldDev& d, int cell, int d0) {
     const int W = d.W, H = d.H;
     const int r = cell / W, c = cell - (cell / W) * W;
-    for (int k = 0; k < 4; ++k) {
-        const int dd = (d0 + k) & 3;
+    int nb[4];
+    bool freec[4];
+#pragma unroll
+    for (int dd = 0; dd < 4; ++dd) {
         const int nr = r + act_dr(dd), nc = c + act_dc(dd);
-        if (nr >= 0 && nr < H && nc >= 0 && nc < W && d.occB[nr * W + nc] == -1) return nr * W + nc;
+        const bool in = nr >= 0 && nr < H && nc >= 0 && nc < W;
+        nb[dd] = nr * W + nc;
+        freec[dd] = in && d.occB[in ? nb[dd] : cell] == -1;
     }
-    return -1;
+    int C = -1;
+#pragma unroll
+    for (int k = 3; k >= 0; --k) {
+        const int dd = (d0 + k) & 3;
+        if (freec[dd]) C = nb[dd];
+    }
+    return C;
 }
 
 // ---------------------------------------------------------------------------
-// P3a: mirror this agent's move/death into occA, then, for an eligible
-// survivor, compute its birth claim and resolve it against the other eligible
-// agents next to the claimed cell (their claims are recomputed from occB).
+// P3a: clear this agent's move-claim word, then, for an eligible survivor,
+// compute its birth claim and resolve it against the other eligible agents
+// next to the claimed cell: their occB words give eligibility and scan start,
+// their claims are recomputed from occB, their keys come from bkey.
+// Returns true for a claim winner.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void claim_agent(const WorldDev& d, int slot, int64_t t) {
+__device__ __forceinline__ bool claim_agent(const WorldDev& d, int slot, int64_t t) {
     const int X = d.prev_cell[slot];
     const int X2 = d.cell[slot];
     const bool alive = d.alive[slot] != 0;
-    if (!alive) {
-        d.occA[X] = -1;
-    } else if (X2 != X) {
-        d.occA[X] = -1;
-        d.occA[X2] = slot;
+    {
+        // clear the move-claim word this agent may have written in P1
+        const int a = d.action[slot];
+        if (a < 4) {
+            const int tr = X / d.W + act_dr(a), tc = X - (X / d.W) * d.W + act_dc(a);
+            if (tr >= 0 && tr < d.H && tc >= 0 && tc < d.W) d.mclaim[tr * d.W + tc] = ~0ull;
+        }
     }
     int C = -1;
     bool won = false;
@@ -308,34 +538,124 @@ __device__ __forceinline__ void claim_agent(const WorldDev& d, int slot, int64_t
             won = true;
             const int W = d.W, H = d.H;
             const int cr = C / W, cc = C - (C / W) * W;
+            int M[4], v[4];
+#pragma unroll
             for (int dd = 0; dd < 4; ++dd) {
                 const int mr = cr + act_dr(dd), mc = cc + act_dc(dd);
-                if (mr < 0 || mr >= H || mc < 0 || mc >= W) continue;
-                const int M = mr * W + mc;
-                if (M == X2) continue;
-                const int o = d.occB[M];
-                if (o < 0 || d.streak[o] < d.T_repr) continue;
-                const uint32_t uo = d.uid[o];
-                const Draw4 bo = philox(uo, uint32_t(t), kBirth, 0, d.seed_lo, d.seed_hi);
-                if (birth_target(d, M, int(bo.x & 3u)) != C) continue;
-                if (claim_key(bo.y, uo) < key) won = false;
+                const bool in = mr >= 0 && mr < H && mc >= 0 && mc < W;
+                M[dd] = mr * W + mc;
+                v[dd] = (in && M[dd] != X2) ? d.occB[M[dd]] : -1;
+            }
+#pragma unroll
+            for (int dd = 0; dd < 4; ++dd) {
+                if (v[dd] < 0 || !(v[dd] & kOccElig)) continue;
+                const int o = v[dd] & kOccSlotMask;
+                const uint64_t ko = d.bkey[o];
+                if (birth_target(d, M[dd], (v[dd] >> kOccDirShift) & 3) != C) continue;
+                if (ko < key) won = false;
             }
         }
     }
     d.claim[slot] = C;
-    d.win[slot] = won ? 1 : 0;
+    return won;
+}
+
+// P3a for tile `j` of one world.  The winner of global rank r (uid order) is
+// born iff r < cap - survivors; its child takes free slot r of the ring if the
+// ring holds more than r slots, else the (r - free)-th slot freed this step.
+// The last claim tile to finish closes the step (counts, free ring, scalars).
+__device__ __forceinline__ void claim_block(const WorldDev& d, int j, int tid, StepShared& sh) {
+    WorldScal* S = d.scal;
+    const int n = S->n_live;
+    const int sel = S->live_sel;
+    const int64_t t = S->t;
+    const int cap = d.cap;
+    const int ntile = (cap + kBlock - 1) / kBlock;
+    const int i = j * kBlock + tid;
+    int slot = -1;
+    bool win = false;
+    if (i < n) {
+        slot = d.live[sel][i];
+        win = claim_agent(d, slot, t);
+    }
+    const BlockRank br = block_rank2(win, false, tid, sh.sw);
+    const uint64_t ex = lookback(d, d.lb_claim, j, uint32_t(t), pack2(br.ta, 0), tid, &sh.bcast);
+    const int surv = int(unpack_a(lookback_total(d.lb_move, ntile)));
+    const int nfree = cap - n;
+    if (win) {
+        const int rk = int(unpack_a(ex)) + br.ra;
+        if (rk < cap - surv) {
+            int cs;
+            if (rk < nfree) {
+                int q = S->free_head + rk;
+                if (q >= cap) q -= cap;
+                cs = d.freeq[q];
+            } else {
+                cs = d.deadlist[rk - nfree];
+            }
+            const int cell = d.claim[slot];
+            d.child[rk] = make_int4(cs, slot, cell, int(S->next_uid + uint32_t(rk)));
+            d.live[sel ^ 1][surv + rk] = cs;
+            d.occA[cell] = cs;   // occA is neither read nor written by others in this phase
+        }
+    }
+    // completion: the last tile to get here closes the step
+    __syncthreads();
+    if (tid == 0) {
+        // Relaxed: the closing block reads only look-back words (atomics) and
+        // data of earlier phases; the counter orders its writes of the
+        // scalars after every tile's reads of them.
+        const uint32_t prev = __hip_atomic_fetch_add(d.done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        sh.flag = (prev == uint32_t(ntile - 1)) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!sh.flag) return;
+    const int wins = int(unpack_a(lookback_total(d.lb_claim, ntile)));
+    const int dead = n - surv;
+    const int nb = min(wins, cap - surv);
+    const int consumed = max(0, nb - nfree);
+    const int ft = S->free_tail;
+    for (int q = consumed + tid; q < dead; q += kBlock) {
+        int pos = ft + q - consumed;
+        if (pos >= cap) pos -= cap;
+        d.freeq[pos] = d.deadlist[q];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        __hip_atomic_store(d.done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int nfh = S->free_head + min(nb, nfree);
+        if (nfh >= cap) nfh -= cap;
+        int nft = ft + (dead - consumed);
+        if (nft >= cap) nft -= cap;
+        int32_t* rec = d.ring + (t % kRing) * kCtrWords;
+        rec[kCtrLive] = surv + nb;
+        rec[kCtrBirths] = nb;
+        rec[kCtrDeaths] = dead;
+        rec[kCtrWins] = wins;
+        S->n_prev = n;
+        S->free_head = nfh;
+        S->free_tail = nft;
+        S->n_live = surv + nb;
+        S->next_uid = S->next_uid + uint32_t(nb);
+        S->live_sel = sel ^ 1;
+        S->n_child = nb;
+        S->spawn_t = t;
+        S->ctr_open = 1;
+        S->t = t + 1;
+    }
 }
 
 // ---------------------------------------------------------------------------
 // P3b: regrowth of one kTile x kTile tile (one block).  The tile plus a
 // 2-cell halo of the post-eating grid is staged in LDS; an empty cell counts
 // the resources among its 24 neighbours and grows iff its REGROW draw is
-// below thr[row][count].  Writes the other grid buffer (synchronous update).
-// Returns the number of resources in the tile after regrowth (lane 0 of each
-// wave holds its wave's count).
+// below thr[row][count].  Writes the other grid buffer (synchronous update)
+// and the tile's resource count.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int regrow_tile(const WorldDev& d, int tile, int64_t t, int tid, uint8_t* s) {
+__device__ __forceinline__ void regrow_tile(const WorldDev& d, int tile, int tid, StepShared& sh) {
     constexpr int E = kTile + 4;
+    const int64_t t = d.scal->t;
+    uint8_t* s = sh.tile;
     const int ntx = (d.W + kTile - 1) / kTile;
     const int ty0 = (tile / ntx) * kTile;
     const int tx0 = (tile - (tile / ntx) * ntx) * kTile;
@@ -354,185 +674,112 @@ __device__ __forceinline__ int regrow_tile(const WorldDev& d, int tile, int64_t 
         const int q = gy * d.W + gx;
         v = s[(ly + 2) * E + lx + 2];
         if (!v) {
-            int n = 0;
+            int cnt = 0;
 #pragma unroll
             for (int dy = 0; dy < 5; ++dy)
 #pragma unroll
-                for (int dx = 0; dx < 5; ++dx) n += s[(ly + dy) * E + lx + dx];
+                for (int dx = 0; dx < 5; ++dx) cnt += s[(ly + dy) * E + lx + dx];
             const Draw4 dr = philox(uint32_t(q), uint32_t(t), kRegrow, 0, d.seed_lo, d.seed_hi);
-            v = uint64_t(dr.x) < d.thr[gy * 25 + n] ? 1 : 0;
+            v = uint64_t(dr.x) < d.thr[gy * 25 + cnt] ? 1 : 0;
         }
         Rn[q] = uint8_t(v);
     }
-    const int cnt = __popcll(__ballot(v != 0));
-    __syncthreads();   // the tile buffer is reused by the next tile
-    return cnt;
-}
-
-// Exclusive prefix sums of three per-thread counts over a block of kBlock
-// threads; also returns the block totals.  `sm` holds 3 * (kBlock / 64) ints.
-__device__ __forceinline__ void block_scan3(int a, int b, int c, int& ea, int& eb, int& ec, int& ta,
-                                            int& tb, int& tc, int tid, int* sm) {
-    const int lane = tid & 63, wv = tid >> 6;
-    int ia = a, ib = b, ic = c;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int xa = __shfl_up(ia, off), xb = __shfl_up(ib, off), xc = __shfl_up(ic, off);
-        if (lane >= off) {
-            ia += xa;
-            ib += xb;
-            ic += xc;
-        }
-    }
-    constexpr int NW = kBlock / 64;
-    if (lane == 63) {
-        sm[wv] = ia;
-        sm[NW + wv] = ib;
-        sm[2 * NW + wv] = ic;
-    }
-    __syncthreads();
-    int pa = 0, pb = 0, pc = 0;
-    ta = tb = tc = 0;
-    for (int w = 0; w < NW; ++w) {
-        if (w < wv) {
-            pa += sm[w];
-            pb += sm[NW + w];
-            pc += sm[2 * NW + w];
-        }
-        ta += sm[w];
-        tb += sm[NW + w];
-        tc += sm[2 * NW + w];
-    }
-    ea = pa + ia - a;
-    eb = pb + ib - b;
-    ec = pc + ic - c;
-    __syncthreads();
+    const BlockRank br = block_rank2(v != 0, false, tid, sh.sw);
+    if (tid == 0) d.res_part[tile] = br.ta;
 }
 
 // ---------------------------------------------------------------------------
-// P4: one block per world.  In uid order (the live list): survivors are
-// compacted into the other live buffer, dead slots are appended to the free
-// ring, and birth-claim winners are ranked; the first min(winners, cap -
-// survivors) are born, taking free slots from the head of the ring (pushes
-// happen before pops, so a slot freed by a death this step can be reused).
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void scan_world(const WorldDev& d, int tid, int* sm) {
-    WorldScal* S = d.scal;
-    const int n = S->n_live;
-    const int sel = S->live_sel;
-    const int64_t t = S->t;
-    const uint32_t next_uid = S->next_uid;
-    const int fh = S->free_head, ft = S->free_tail;
-    const int cap = d.cap;
-    const int* L = d.live[sel];
-    int* Ln = d.live[sel ^ 1];
-    const int per = (n + kBlock - 1) / kBlock;
-    const int beg = min(n, tid * per);
-    const int end = min(n, beg + per);
-    int cs = 0, cd = 0, cw = 0;
-    for (int i = beg; i < end; ++i) {
-        const int s = L[i];
-        if (d.alive[s]) {
-            ++cs;
-            cw += d.win[s];
-        } else {
-            ++cd;
-        }
-    }
-    int os, od, ow, ns, nd, nw;
-    block_scan3(cs, cd, cw, os, od, ow, ns, nd, nw, tid, sm);
-    const int nb = min(nw, cap - ns);
-    for (int i = beg; i < end; ++i) {
-        const int s = L[i];
-        if (d.alive[s]) {
-            Ln[os++] = s;
-        } else {
-            int q = ft + od++;
-            if (q >= cap) q -= cap;
-            d.freeq[q] = s;
-        }
-    }
-    __syncthreads();
-    for (int i = beg; i < end; ++i) {
-        const int s = L[i];
-        if (d.alive[s] && d.win[s]) {
-            const int rk = ow++;
-            if (rk < nb) {
-                int q = fh + rk;
-                if (q >= cap) q -= cap;
-                const int cslot = d.freeq[q];
-                Ln[ns + rk] = cslot;
-                d.child[rk] = make_int4(cslot, s, d.claim[s], int(next_uid + uint32_t(rk)));
-                d.streak[s] = 0;
-            }
-        }
-    }
-    __syncthreads();
-    if (tid == 0) {
-        int nfh = fh + nb;
-        if (nfh >= cap) nfh -= cap;
-        int nft = ft + nd;
-        if (nft >= cap) nft -= cap;
-        S->free_head = nfh;
-        S->free_tail = nft;
-        S->n_live = ns + nb;
-        S->next_uid = next_uid + uint32_t(nb);
-        S->live_sel = sel ^ 1;
-        S->n_child = nb;
-        S->spawn_t = t;
-        S->t = t + 1;
-        int32_t* rec = d.ring + (t % kRing) * kCtrWords;
-        rec[kCtrLive] = ns + nb;
-        rec[kCtrBirths] = nb;
-        rec[kCtrDeaths] = nd;
-        rec[kCtrWins] = nw;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// P5: one (child, chunk) item; a chunk is kBlock float4 blocks of the genome.
+// Child creation (start of P1, one block per child): the genome is
 // theta_child[p] = fmaf(sigma, z_p, theta_parent[p]) with z_p lane p % 4 of
-// the MUTATE draw (child uid, step, block p / 4).  Chunk 0 also writes the
-// child's record (energy E0, age 0, streak 0, zero hidden state) and its occA
-// cell; occB receives it in the next P1.
+// the MUTATE draw (child uid, birth step, block p / 4); the record gets
+// energy E0, age 0, streak 0 and a zero hidden state; the child enters occB
+// (occA received it when it was born) and the parent's streak restarts.
+// Every store is complete when this returns, so the same block can run the
+// child's controller right after a block barrier.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void spawn_item(const WorldDev& d, int item, int nchunks, int tid) {
-    const int rk = item / nchunks;
-    const int q = item - rk * nchunks;
+__device__ __forceinline__ void spawn_child(const WorldDev& d, int rk, int tid) {
     const int4 rec = d.child[rk];   // child slot, parent slot, cell, uid
     const uint32_t ts = uint32_t(d.scal->spawn_t);
-    const int blk = q * kBlock + tid;
-    if (blk < d.nblk) {
+    const float* par = d.theta + size_t(rec.y) * size_t(d.Ppad);
+    float* out = d.theta + size_t(rec.x) * size_t(d.Ppad);
+    for (int blk = tid; blk < d.nblk; blk += kBlock) {
         const int p0 = 4 * blk;
-        const float4 par = *reinterpret_cast<const float4*>(d.theta + size_t(rec.y) * size_t(d.Ppad) + p0);
+        const float4 pv = *reinterpret_cast<const float4*>(par + p0);
         const Draw4 dr = philox(uint32_t(rec.w), ts, kMutate, uint32_t(blk), d.seed_lo, d.seed_hi);
         float z0, z1, z2, z3;
         box_muller(dr.x, dr.y, z0, z1);
         box_muller(dr.z, dr.w, z2, z3);
         float4 o;
-        o.x = fmaf(d.sigma, z0, par.x);
-        o.y = p0 + 1 < d.P ? fmaf(d.sigma, z1, par.y) : 0.f;
-        o.z = p0 + 2 < d.P ? fmaf(d.sigma, z2, par.z) : 0.f;
-        o.w = p0 + 3 < d.P ? fmaf(d.sigma, z3, par.w) : 0.f;
-        *reinterpret_cast<float4*>(d.theta + size_t(rec.x) * size_t(d.Ppad) + p0) = o;
+        o.x = fmaf(d.sigma, z0, pv.x);
+        o.y = p0 + 1 < d.P ? fmaf(d.sigma, z1, pv.y) : 0.f;
+        o.z = p0 + 2 < d.P ? fmaf(d.sigma, z2, pv.z) : 0.f;
+        o.w = p0 + 3 < d.P ? fmaf(d.sigma, z3, pv.w) : 0.f;
+        *reinterpret_cast<float4*>(out + p0) = o;
     }
-    if (q == 0) {
-        const int cs = rec.x;
-        if (tid == 0) {
-            d.uid[cs] = uint32_t(rec.w);
-            d.cell[cs] = rec.z;
-            d.prev_cell[cs] = rec.z;
-            d.energy[cs] = d.E0;
-            d.age[cs] = 0;
-            d.streak[cs] = 0;
-            d.alive[cs] = 1;
-            d.win[cs] = 0;
-            d.claim[cs] = -1;
-            d.action[cs] = 4;
-            d.occA[rec.z] = cs;
+    const int cs = rec.x;
+    if (tid == 0) {
+        d.uid[cs] = uint32_t(rec.w);
+        d.cell[cs] = rec.z;
+        d.prev_cell[cs] = rec.z;
+        d.energy[cs] = d.E0;
+        d.age[cs] = 0;
+        d.streak[cs] = 0;
+        d.alive[cs] = 1;
+        d.claim[cs] = -1;
+        d.action[cs] = 4;
+        d.occB[rec.z] = cs;
+        d.streak[rec.y] = 0;
+    }
+    if (tid < d.hd) d.h[size_t(cs) * d.hd + tid] = 0.f;
+    __builtin_amdgcn_s_waitcnt(0);   // this thread's stores have completed
+}
+
+// Recurrent projection of a new agent (after spawn_child and a barrier).
+__device__ __forceinline__ void spawn_proj(const WorldDev& d, int rk, int tid) {
+    if (tid < 64) {
+        const int cs = d.child[rk].x;
+        if (d.hd == 32) proj_zero<32>(d, cs, tid);
+        else proj_zero<16>(d, cs, tid);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+}
+
+// Eaten and resource totals of the step just closed (one block per world).
+__device__ __forceinline__ void close_counters(const WorldDev& d, int tid, StepShared& sh) {
+    WorldScal* S = d.scal;
+    if (!S->ctr_open) return;
+    const int nwv = (S->n_prev + 63) / 64;
+    int pe = 0, pr = 0;
+    for (int i = tid; i < nwv; i += kBlock) pe += d.eat_part[i];
+    for (int i = tid; i < d.ntiles; i += kBlock) pr += d.res_part[i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        pe += __shfl_xor(pe, off);
+        pr += __shfl_xor(pr, off);
+    }
+    if ((tid & 63) == 0) {
+        sh.sw[tid >> 6] = pe;
+        sh.sw[(kBlock / 64) + (tid >> 6)] = pr;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int te = 0, tr = 0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            te += sh.sw[w];
+            tr += sh.sw[(kBlock / 64) + w];
         }
-        if (tid < d.hd) d.h[size_t(cs) * d.hd + tid] = 0.f;
+        int32_t* rec = d.ring + (S->spawn_t % kRing) * kCtrWords;
+        rec[kCtrEaten] = te;
+        rec[kCtrRes] = tr;
     }
+    __syncthreads();
+}
+
+// P1 bookkeeping by the first block of a world: sum the eaten / resource
+// partials of the previous step (written by its P2 and P3).
+__device__ __forceinline__ void close_counters_in_step(const WorldDev& d, int tid, StepShared& sh) {
+    close_counters(d, tid, sh);
+    if (tid == 0) d.scal->ctr_open = 0;
 }
 
 }  // namespace eco

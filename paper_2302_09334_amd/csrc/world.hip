@@ -73,10 +73,10 @@ const char* check_config(const world_config* c) {
 
 // Byte offsets of every array inside the arena.
 struct Layout {
-    size_t desc, scal, ring, batch, thr, R0, R1, occA, occB;
-    size_t uid, cell, prev_cell, energy, age, streak, action, alive, win, claim;
-    size_t live0, live1, freeq, child, h, theta;
-    size_t log_uid, log_act, log_logits, log_n, barrier;
+    size_t desc, scal, ring, batch, thr, R0, R1, occA, occB, mclaim;
+    size_t uid, cell, prev_cell, energy, age, streak, action, alive, win, claim, bkey;
+    size_t live0, live1, freeq, child, h, gh, theta;
+    size_t log_uid, log_act, log_logits, log_n, barrier, eat_part, res_part, deadlist, lb_move, lb_claim, done;
     size_t total;
 };
 
@@ -102,6 +102,7 @@ Layout layout_of(const world_config& c) {
     l.R1 = take(HW);
     l.occA = take(4 * HW);
     l.occB = take(4 * HW);
+    l.mclaim = take(8 * HW);
     l.uid = take(4 * cap);
     l.cell = take(4 * cap);
     l.prev_cell = take(4 * cap);
@@ -112,16 +113,24 @@ Layout layout_of(const world_config& c) {
     l.alive = take(cap);
     l.win = take(cap);
     l.claim = take(4 * cap);
+    l.bkey = take(8 * cap);
     l.live0 = take(4 * cap);
     l.live1 = take(4 * cap);
     l.freeq = take(4 * cap);
     l.child = take(16 * cap);
     l.h = take(4 * cap * size_t(c.hidden));
+    l.gh = take(4 * cap * 3 * size_t(c.hidden));
     l.theta = take(4 * cap * size_t(dm.Ppad));
     l.log_uid = take(4 * L * cap);
     l.log_act = take(L * cap);
     l.log_logits = take(4 * 5 * L * cap);
     l.log_n = take(4 * L);
+    l.eat_part = take(4 * (cap / 64 + 1));
+    l.deadlist = take(4 * cap);
+    l.lb_move = take(8 * ((cap + kBlock - 1) / kBlock));
+    l.lb_claim = take(8 * ((cap + kBlock - 1) / kBlock));
+    l.done = take(64);
+    l.res_part = take(4 * size_t(((c.H + kTile - 1) / kTile) * ((c.W + kTile - 1) / kTile)));
     l.total = o;
     return l;
 }
@@ -160,7 +169,6 @@ struct world {
     struct {
         const WorldDev* const* w;
         const int* block_pre;
-        const int* item_pre;
     } tv;                  // single-world launch table (inside the arena)
     std::vector<int> host_bp;
     int max_useful = 1;
@@ -203,10 +211,9 @@ std::vector<int> batch_prefix(const std::vector<const world*>& ws) {
     std::vector<int> pre(size_t(kPreKinds) * (n + 1), 0);
     for (int i = 0; i < n; ++i) {
         const world_config& c = ws[i]->cfg;
-        pre[kPreAct * (n + 1) + i + 1] = pre[kPreAct * (n + 1) + i] + blocks_act(c);
-        pre[kPreAgent * (n + 1) + i + 1] = pre[kPreAgent * (n + 1) + i] + blocks_agent(c);
-        pre[kPreTile * (n + 1) + i + 1] = pre[kPreTile * (n + 1) + i] + tiles_of(c);
-        pre[kPreSpawn * (n + 1) + i + 1] = pre[kPreSpawn * (n + 1) + i] + kSpawnBlocksPerWorld;
+        pre[kPreAct * (n + 1) + i + 1] = pre[kPreAct * (n + 1) + i] + kNewbornBlocks + blocks_act(c);
+        pre[kPreMove * (n + 1) + i + 1] = pre[kPreMove * (n + 1) + i] + blocks_agent(c);
+        pre[kPreClaim * (n + 1) + i + 1] = pre[kPreClaim * (n + 1) + i] + blocks_agent(c) + tiles_of(c) + blocks_act(c);
     }
     return pre;
 }
@@ -215,11 +222,8 @@ std::vector<int> batch_prefix(const std::vector<const world*>& ws) {
 hipError_t launch_step(const Batch& b, const int* host_pre, int n, hipStream_t s) {
     const int np = n + 1;
     hipLaunchKernelGGL(k_act, dim3(host_pre[kPreAct * np + n]), dim3(kBlock), 0, s, b);
-    hipLaunchKernelGGL(k_move, dim3(host_pre[kPreAgent * np + n]), dim3(kBlock), 0, s, b);
-    hipLaunchKernelGGL(k_claim, dim3(host_pre[kPreAgent * np + n]), dim3(kBlock), 0, s, b);
-    hipLaunchKernelGGL(k_regrow, dim3(host_pre[kPreTile * np + n]), dim3(kBlock), 0, s, b);
-    hipLaunchKernelGGL(k_scan, dim3(n), dim3(kBlock), 0, s, b);
-    hipLaunchKernelGGL(k_spawn, dim3(host_pre[kPreSpawn * np + n]), dim3(kBlock), 0, s, b);
+    hipLaunchKernelGGL(k_move, dim3(host_pre[kPreMove * np + n]), dim3(kBlock), 0, s, b);
+    hipLaunchKernelGGL(k_claim, dim3(host_pre[kPreClaim * np + n]), dim3(kBlock), 0, s, b);
     return hipGetLastError();
 }
 
@@ -239,7 +243,9 @@ int check_device_error(world* w) {
     WorldScal sc;
     HIP_TRY(w, hipMemcpyAsync(&sc, w->base + w->lay.scal, sizeof(sc), hipMemcpyDeviceToHost, w->stream));
     HIP_TRY(w, hipStreamSynchronize(w->stream));
-    if (sc.err != 0) return fail(w, WORLD_E_HIP, "grid barrier timed out on the device (err=" + std::to_string(sc.err) + ")");
+    if (sc.err != 0)
+        return fail(w, WORLD_E_HIP, std::string(sc.err == 1 ? "grid barrier" : "look-back scan") +
+                                        " wait timed out on the device");
     return WORLD_OK;
 }
 
@@ -266,46 +272,32 @@ int persistent_blocks_per_cu() {
     return nb;
 }
 
-// Device table of a batch: world pointers, block prefixes (per-phase kernels)
-// and item prefixes (persistent kernel).
+// Device table of a batch: world pointers and per-phase block prefixes.
 struct TableView {
     const WorldDev* const* w;
     const int* block_pre;
-    const int* item_pre;
 };
+
+size_t table_bytes(int n) { return align_up(sizeof(void*) * size_t(n), 16) + sizeof(int) * size_t(kPreKinds) * (n + 1); }
 
 std::vector<char> build_table(const std::vector<const world*>& ws, char* dev_base, TableView* view,
                               std::vector<int>* host_block_pre, int* max_useful) {
     const int n = int(ws.size());
     const std::vector<int> bp = batch_prefix(ws);
-    std::vector<int> ip(size_t(3) * (n + 1), 0);
     int useful = 1;
-    for (int i = 0; i < n; ++i) {
-        const world_config& c = ws[i]->cfg;
-        ip[0 * (n + 1) + i + 1] = ip[0 * (n + 1) + i] + c.cap;
-        ip[1 * (n + 1) + i + 1] = ip[1 * (n + 1) + i] + int(align_up(size_t(c.cap), 64));
-        ip[2 * (n + 1) + i + 1] = ip[2 * (n + 1) + i] + tiles_of(c);
-    }
-    useful = std::max({ (ip[n] + 3) / 4, ip[2 * (n + 1) + n], (ip[(n + 1) + n] + kBlock - 1) / kBlock, 1 });
+    for (int k = 0; k < kPreKinds; ++k) useful = std::max(useful, bp[size_t(k) * (n + 1) + n]);
     const size_t ptr_bytes = align_up(sizeof(void*) * size_t(n), 16);
-    const size_t bp_bytes = sizeof(int) * bp.size();
-    std::vector<char> host(ptr_bytes + bp_bytes + sizeof(int) * ip.size());
+    std::vector<char> host(ptr_bytes + sizeof(int) * bp.size());
     for (int i = 0; i < n; ++i) {
         const WorldDev* p = ws[i]->d_dev;
         std::memcpy(host.data() + sizeof(void*) * i, &p, sizeof(p));
     }
-    std::memcpy(host.data() + ptr_bytes, bp.data(), bp_bytes);
-    std::memcpy(host.data() + ptr_bytes + bp_bytes, ip.data(), sizeof(int) * ip.size());
+    std::memcpy(host.data() + ptr_bytes, bp.data(), sizeof(int) * bp.size());
     view->w = reinterpret_cast<const WorldDev* const*>(dev_base);
     view->block_pre = reinterpret_cast<const int*>(dev_base + ptr_bytes);
-    view->item_pre = reinterpret_cast<const int*>(dev_base + ptr_bytes + bp_bytes);
     *host_block_pre = bp;
     *max_useful = useful;
     return host;
-}
-
-size_t table_bytes(int n) {
-    return align_up(sizeof(void*) * size_t(n), 16) + sizeof(int) * size_t(kPreKinds + 3) * (n + 1);
 }
 
 // K steps of a batch in the given mode.  `graphs` caches captured graphs.
@@ -337,13 +329,10 @@ int run_steps(world* w0, int mode, const TableView& tv, const std::vector<int>& 
     }
     const int grid = std::max(1, std::min(persistent_blocks_per_cu() * device_cus(), max_useful));
     PersistArgs pa;
-    pa.w = tv.w;
-    pa.pre = tv.item_pre;
-    pa.n = n;
+    pa.bt = b;
     pa.barrier = reinterpret_cast<uint32_t*>(w0->base + w0->lay.barrier);
     pa.err = reinterpret_cast<int32_t*>(w0->base + w0->lay.scal + offsetof(WorldScal, err));
     pa.spin_ticks = uint64_t(wall_rate_khz()) * 1000ull * 2ull;   // 2 s
-    pa.max_useful_blocks = max_useful;
     for (int done = 0; done < K;) {
         const int chunk = std::min(K - done, 1024);
         pa.K = chunk;
@@ -424,6 +413,7 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
     d.occA = reinterpret_cast<int32_t*>(b + lay.occA);
     d.occB = reinterpret_cast<int32_t*>(b + lay.occB);
     d.thr = reinterpret_cast<const uint64_t*>(b + lay.thr);
+    d.mclaim = reinterpret_cast<uint64_t*>(b + lay.mclaim);
     d.uid = reinterpret_cast<uint32_t*>(b + lay.uid);
     d.cell = reinterpret_cast<int32_t*>(b + lay.cell);
     d.prev_cell = reinterpret_cast<int32_t*>(b + lay.prev_cell);
@@ -434,7 +424,9 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
     d.alive = reinterpret_cast<uint8_t*>(b + lay.alive);
     d.win = reinterpret_cast<uint8_t*>(b + lay.win);
     d.claim = reinterpret_cast<int32_t*>(b + lay.claim);
+    d.bkey = reinterpret_cast<uint64_t*>(b + lay.bkey);
     d.h = reinterpret_cast<float*>(b + lay.h);
+    d.gh = reinterpret_cast<float*>(b + lay.gh);
     d.theta = reinterpret_cast<float*>(b + lay.theta);
     d.live[0] = reinterpret_cast<int32_t*>(b + lay.live0);
     d.live[1] = reinterpret_cast<int32_t*>(b + lay.live1);
@@ -447,6 +439,13 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
     d.log_logits = reinterpret_cast<float*>(b + lay.log_logits);
     d.log_n = reinterpret_cast<int32_t*>(b + lay.log_n);
     d.barrier = reinterpret_cast<uint32_t*>(b + lay.barrier);
+    d.eat_part = reinterpret_cast<int32_t*>(b + lay.eat_part);
+    d.deadlist = reinterpret_cast<int32_t*>(b + lay.deadlist);
+    d.lb_move = reinterpret_cast<uint64_t*>(b + lay.lb_move);
+    d.lb_claim = reinterpret_cast<uint64_t*>(b + lay.lb_claim);
+    d.done = reinterpret_cast<uint32_t*>(b + lay.done);
+    d.res_part = reinterpret_cast<int32_t*>(b + lay.res_part);
+    d.ntiles = ((c.H + kTile - 1) / kTile) * ((c.W + kTile - 1) / kTile);
     w->d_dev = reinterpret_cast<WorldDev*>(b + lay.desc);
 
     // Host initialisation (not timed): resources, placement, lists.
@@ -488,7 +487,6 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
     const std::vector<char> table = build_table(one, b + lay.batch, &tv, &w->host_bp, &w->max_useful);
     w->tv.w = tv.w;
     w->tv.block_pre = tv.block_pre;
-    w->tv.item_pre = tv.item_pre;
 
     hipStream_t s = w->stream;
     auto up = [&](size_t off, const void* src, size_t bytes) {
@@ -519,6 +517,10 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
 #undef UP
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.ring, 0, sizeof(int32_t) * kRing * kCtrWords, s);
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.barrier, 0, 64, s);
+    if (e == hipSuccess) e = hipMemsetAsync(b + lay.done, 0, 64, s);
+    if (e == hipSuccess) e = hipMemsetAsync(b + lay.mclaim, 0xFF, 8 * HW, s);
+    if (e == hipSuccess) e = hipMemsetAsync(b + lay.lb_move, 0, 8 * size_t(blocks_agent(c)), s);
+    if (e == hipSuccess) e = hipMemsetAsync(b + lay.lb_claim, 0, 8 * size_t(blocks_agent(c)), s);
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.h, 0, 4 * size_t(c.cap) * c.hidden, s);
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.action, 4, size_t(c.cap), s);
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.win, 0, size_t(c.cap), s);
@@ -530,6 +532,10 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
         const int64_t items = int64_t(n0) * dm.nblk;
         const int grid = int(std::min<int64_t>((items + kBlock - 1) / kBlock, 65536));
         hipLaunchKernelGGL(k_init_theta, dim3(grid), dim3(kBlock), 0, s, w->d_dev, int(n0), std_ih, std_hd);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && n0 > 0) {
+        hipLaunchKernelGGL(k_proj_all, dim3(blocks_act(c)), dim3(kBlock), 0, s, static_cast<const WorldDev*>(w->d_dev));
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -551,7 +557,7 @@ int world_set_mode(world_t* w, int32_t mode) {
 }
 
 static int step_single(world* w, int K) {
-    TableView tv{w->tv.w, w->tv.block_pre, w->tv.item_pre};
+    TableView tv{w->tv.w, w->tv.block_pre};
     return run_steps(w, w->mode, tv, w->host_bp, 1, w->max_useful, K, w->graphs, w->graph_defs);
 }
 
@@ -635,6 +641,16 @@ int world_snapshot(world_t* w, world_image* out) {
     const Layout& l = w->lay;
     WorldScal sc;
     HIP_TRY(w, hipMemcpy(&sc, w->base + l.scal, sizeof(sc), hipMemcpyDeviceToHost));
+    if (sc.n_child > 0) {
+        // children of the last step are created at the start of the next
+        // one; create them now so that the image is complete
+        const WorldDev* dp = w->d_dev;
+        hipLaunchKernelGGL(k_materialize, dim3(std::min(sc.n_child, 1024)), dim3(kBlock), 0, w->stream, dp);
+        hipLaunchKernelGGL(k_clear_pending, dim3(1), dim3(64), 0, w->stream, dp);
+        HIP_TRY(w, hipGetLastError());
+        HIP_TRY(w, hipStreamSynchronize(w->stream));
+        HIP_TRY(w, hipMemcpy(&sc, w->base + l.scal, sizeof(sc), hipMemcpyDeviceToHost));
+    }
     out->step = sc.t;
     out->n_live = sc.n_live;
     out->next_uid = sc.next_uid;
@@ -738,11 +754,19 @@ int world_load(world_t* w, const world_image* in) {
     HIP_TRY(w, hipMemcpy(b + l.alive, alive.data(), size_t(c.cap), hipMemcpyHostToDevice));
     HIP_TRY(w, hipMemcpy(b + l.live0, live.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
     HIP_TRY(w, hipMemcpy(b + l.freeq, freeq.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
+    HIP_TRY(w, hipMemset(b + l.lb_move, 0, 8 * size_t(blocks_agent(c))));
+    HIP_TRY(w, hipMemset(b + l.lb_claim, 0, 8 * size_t(blocks_agent(c))));
+    HIP_TRY(w, hipMemset(b + l.done, 0, 64));
+    HIP_TRY(w, hipMemset(b + l.mclaim, 0xFF, 8 * HW));
     if (n > 0) {
         std::vector<float> hs(size_t(c.cap) * c.hidden, 0.f);
         std::memcpy(hs.data(), in->h, 4 * size_t(n) * c.hidden);
         HIP_TRY(w, hipMemcpy(b + l.h, hs.data(), 4 * hs.size(), hipMemcpyHostToDevice));
         HIP_TRY(w, hipMemcpy(b + l.theta, th.data(), 4 * size_t(n) * Pp, hipMemcpyHostToDevice));
+        hipLaunchKernelGGL(k_proj_all, dim3(blocks_act(c)), dim3(kBlock), 0, w->stream,
+                           static_cast<const WorldDev*>(w->d_dev));
+        HIP_TRY(w, hipGetLastError());
+        HIP_TRY(w, hipStreamSynchronize(w->stream));
     }
     return WORLD_OK;
 }
@@ -750,6 +774,10 @@ int world_load(world_t* w, const world_image* in) {
 int world_counters_get(world_t* w, int64_t first, int32_t n, world_counters* out) {
     if (!w || (!out && n > 0)) return fail(w, WORLD_E_INVALID_ARG, "NULL argument");
     if (w->poisoned) return WORLD_E_POISONED;
+    // the eaten / resource totals of the last step are summed at the start of
+    // the next step; sum them now if that has not happened yet
+    hipLaunchKernelGGL(k_close_counters, dim3(1), dim3(kBlock), 0, w->stream, static_cast<const WorldDev*>(w->d_dev));
+    HIP_TRY(w, hipGetLastError());
     if (int rc = world_sync(w)) return rc;
     WorldScal sc;
     HIP_TRY(w, hipMemcpy(&sc, w->base + w->lay.scal, sizeof(sc), hipMemcpyDeviceToHost));
@@ -834,6 +862,57 @@ int world_test_gauss(const uint32_t* d_a, const uint32_t* d_b, size_t n, float* 
     if (n == 0) return WORLD_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipLaunchKernelGGL(k_test_gauss, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, d_a, d_b, n, d_z0, d_z1);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(nullptr, WORLD_E_HIP, hipGetErrorString(e));
+    return WORLD_OK;
+}
+
+int world_phase_times(world_t* w, int32_t K, float* ms) {
+    if (!w || !ms) return fail(w, WORLD_E_INVALID_ARG, "NULL argument");
+    if (w->poisoned) return WORLD_E_POISONED;
+    if (K < 1) return fail(w, WORLD_E_INVALID_ARG, "K must be >= 1");
+    const int np = 2;
+    const int* hp = w->host_bp.data();
+    Batch b{w->tv.w, w->tv.block_pre, 1};
+    hipStream_t s = w->stream;
+    std::vector<hipEvent_t> ev(size_t(K) * 4);
+    for (auto& e : ev) HIP_TRY(w, hipEventCreate(&e));
+    hipError_t le = hipSuccess;
+    for (int k = 0; k < K && le == hipSuccess; ++k) {
+        hipEvent_t* e = ev.data() + size_t(k) * 4;
+        (void)hipEventRecord(e[0], s);
+        hipLaunchKernelGGL(k_act, dim3(hp[kPreAct * np + 1]), dim3(kBlock), 0, s, b);
+        (void)hipEventRecord(e[1], s);
+        hipLaunchKernelGGL(k_move, dim3(hp[kPreMove * np + 1]), dim3(kBlock), 0, s, b);
+        (void)hipEventRecord(e[2], s);
+        hipLaunchKernelGGL(k_claim, dim3(hp[kPreClaim * np + 1]), dim3(kBlock), 0, s, b);
+        (void)hipEventRecord(e[3], s);
+        le = hipGetLastError();
+    }
+    hipError_t se = hipStreamSynchronize(s);
+    double acc[3] = {0, 0, 0};
+    for (int k = 0; k < K && le == hipSuccess && se == hipSuccess; ++k) {
+        hipEvent_t* e = ev.data() + size_t(k) * 4;
+        for (int p = 0; p < 3; ++p) {
+            float v = 0.f;
+            if (hipEventElapsedTime(&v, e[p], e[p + 1]) == hipSuccess) acc[p] += v;
+        }
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    if (le != hipSuccess) return fail(w, WORLD_E_HIP, std::string("phase launch: ") + hipGetErrorString(le));
+    if (se != hipSuccess) return fail(w, WORLD_E_HIP, std::string("phase sync: ") + hipGetErrorString(se));
+    for (int p = 0; p < 3; ++p) ms[p] = float(acc[p] / K);
+    return check_device_error(w);
+}
+
+int world_test_copy(const void* src, void* dst, size_t bytes, void* stream) {
+    if (!src || !dst || bytes % 16 != 0) return fail(nullptr, WORLD_E_INVALID_ARG, "bad copy arguments");
+    if (bytes == 0) return WORLD_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t n = bytes / 16;
+    const int grid = int(std::min<size_t>((n + kBlock - 1) / kBlock, size_t(device_cus()) * 16));
+    hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(kBlock), 0, s, static_cast<const int4*>(src), static_cast<int4*>(dst), n);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(nullptr, WORLD_E_HIP, hipGetErrorString(e));

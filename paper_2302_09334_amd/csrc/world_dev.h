@@ -7,7 +7,9 @@
 // HBM layout (structure of arrays, every array 256-byte aligned):
 //   grid      R[2] (u8, double-buffered for the synchronous regrowth),
 //             occA/occB (i32 slot or -1; occA = state at the step start,
-//             occB = state after moves and deaths, mirrored back each step),
+//             read by the act phase; occB = state after moves and deaths,
+//             read by the claim phase; children enter occA when they are
+//             born and occB when they are created),
 //             thr (u64 H x 25 regrowth thresholds)
 //   agents    uid, cell, prev_cell, energy, age, streak (i32 per slot),
 //             action, alive, win (u8), claim (i32), h (f32 slot x hidden),
@@ -16,7 +18,7 @@
 //             skips one contiguous row)
 //   lists     live[2] (slots in uid order), freeq (ring of free slots),
 //             child (per step: child slot, parent slot, cell, uid)
-//   scalars   WorldScal, counters ring (1024 steps), optional controller log
+//   scalars   WorldScal, counters ring (8192 steps), optional controller log
 #pragma once
 
 #include <stddef.h>
@@ -24,7 +26,7 @@
 
 namespace eco {
 
-constexpr int kRing = 1024;     // steps of counters kept on device
+constexpr int kRing = 8192;     // steps of counters kept on device
 constexpr int kCtrWords = 8;    // words per counter record
 constexpr int kBlock = 256;     // threads per block in every kernel
 constexpr int kTile = 16;       // regrowth tile edge (16 x 16 cells per block)
@@ -39,10 +41,12 @@ struct WorldScal {
     int32_t free_head;  // ring of free slots: [head, head + n_free) mod cap
     int32_t free_tail;
     int32_t live_sel;   // which live[] buffer is current
-    int32_t n_child;    // children created by the last scan
+    int32_t n_child;    // children created by the last step
     int64_t spawn_t;    // step of the pending children
-    int32_t err;        // device-side failure code (barrier time-out)
-    int32_t pad[5];
+    int32_t err;        // device-side failure code (1 barrier, 2 look-back time-out)
+    int32_t n_prev;     // live agents at the start of the last closed step
+    int32_t ctr_open;   // 1: eaten/resource totals of step spawn_t not yet summed
+    int32_t pad[3];
 };
 
 struct WorldDev {
@@ -61,6 +65,7 @@ struct WorldDev {
     int32_t* occA;
     int32_t* occB;
     const uint64_t* thr;
+    uint64_t* mclaim;     // per cell: smallest move-claim key of the step (~0 = none)
     // agents
     uint32_t* uid;
     int32_t* cell;
@@ -72,7 +77,9 @@ struct WorldDev {
     uint8_t* alive;
     uint8_t* win;
     int32_t* claim;
+    uint64_t* bkey;       // birth-claim key of eligible agents (written in P2)
     float* h;
+    float* gh;            // recurrent projection W_hh h + b_hh for the next act (slot x 3 hidden)
     float* theta;
     // lists
     int32_t* live[2];
@@ -86,6 +93,14 @@ struct WorldDev {
     float* log_logits;    // log_steps x cap x 5
     int32_t* log_n;       // log_steps
     uint32_t* barrier;    // grid barrier counter of the persistent kernel
+    int32_t* deadlist;    // slots of the agents that died this step, uid order
+    uint64_t* lb_move;    // look-back status words of the move phase (per tile)
+    uint64_t* lb_claim;   // look-back status words of the claim phase (per tile)
+    uint32_t* done;       // completion counter of the claim phase
+    int32_t* eat_part;    // per-wave eaten counts of the move phase (cap / 64)
+    int32_t* res_part;    // per-tile resource counts of the regrowth phase
+    int32_t ntiles;       // regrowth tiles
+    int32_t pad1;
 };
 
 }  // namespace eco

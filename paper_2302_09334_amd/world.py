@@ -14,7 +14,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libworld.so")
+LIB_PATH = os.environ.get("ECO_WORLD_LIB", os.path.join(HERE, "libworld.so"))
 
 WORLD_OK = 0
 ERRORS = {-1: "invalid argument", -2: "invalid config", -3: "buffer too small", -4: "HIP failure",
@@ -65,7 +65,8 @@ EXPORTS = [
     "world_required_bytes", "world_dims", "world_create", "world_step", "world_step_many",
     "world_set_mode", "world_sync", "world_snapshot", "world_load", "world_counters_get",
     "world_destroy", "world_last_error", "world_set_forced_action", "world_action_log",
-    "world_test_philox", "world_test_gauss", "world_threshold_table",
+    "world_test_philox", "world_test_gauss", "world_threshold_table", "world_phase_times",
+    "world_test_copy",
 ]
 
 _lib = None
@@ -97,6 +98,8 @@ def lib():
         L.world_test_philox.argtypes = [P, C.c_size_t, C.c_uint32, C.c_uint32, P, P]
         L.world_test_gauss.argtypes = [P, P, C.c_size_t, P, P, P]
         L.world_threshold_table.argtypes = [C.POINTER(Config), P]
+        L.world_phase_times.argtypes = [P, C.c_int32, P]
+        L.world_test_copy.argtypes = [P, P, C.c_size_t, P]
         for name in EXPORTS:
             getattr(L, name).restype = getattr(L, name).restype or C.c_int
         L.world_last_error.restype = C.c_char_p
@@ -199,6 +202,13 @@ class World:
     def set_forced_action(self, a: int):
         _check(lib().world_set_forced_action(self._h, int(a)), self._h)
 
+    def phase_times(self, K: int) -> np.ndarray:
+        """Run K steps as per-phase kernels timed with HIP events; mean ms per
+        step of act (+ child genomes), move, claim (+ regrowth)."""
+        ms = np.zeros(3, np.float32)
+        _check(lib().world_phase_times(self._h, int(K), _np_ptr(ms)), self._h)
+        return ms
+
     # -- state -----------------------------------------------------------
     def snapshot(self, hidden: bool = False, theta: bool = False) -> dict:
         H, W, cap = self.cfg["H"], self.cfg["W"], self.cfg["cap"]
@@ -272,6 +282,14 @@ def step_many(worlds: list[World], K: int = 1):
     rc = lib().world_step_many(arr, len(worlds), int(K))
     if rc != WORLD_OK:
         _check(rc, worlds[0].handle if rc != -1 else None)
+
+
+def test_copy(src, dst, stream=None):
+    """Plain device copy kernel of src into dst (torch tensors, same size)."""
+    import torch
+    s = stream or torch.cuda.current_stream()
+    _check(lib().world_test_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()),
+                                 src.numel() * src.element_size(), C.c_void_p(s.cuda_stream)))
 
 
 def test_philox(ctr, key, stream=None):
