@@ -577,15 +577,19 @@ int oracle_step(void *vw, const uint32_t *hint_uid, const uint8_t *hint_act, int
         for (int k = 1; k < 5; ++k)
             if (lf[k] > lf[best]) best = k;
         int act = best;
+        int fa = forced_action(w, u);
+        int forced = fa >= 0 && fa < 5;
+        if (forced) act = fa;
         /* Near-tie resync: adopt the hinted action when it lies within
-         * 1e-5 * max(1, |top|) of this oracle's top logit. */
+         * 1e-5 * max(1, |top|) of this oracle's top logit (a forced action
+         * must be matched exactly). */
         while (hint_uid && hi < n_hint && hint_uid[hi] < u) ++hi;
         if (hint_uid && hi < n_hint && hint_uid[hi] == u) {
             int ha = hint_act[hi];
-            if (ha != act && ha >= 0 && ha < 5) {
+            if (ha != act) {
                 double top = lg[best];
                 double band = 1e-5 * fmax(1.0, fabs(top));
-                if (top - lg[ha] < band) {
+                if (!forced && ha >= 0 && ha < 5 && top - lg[ha] < band) {
                     act = ha;
                     inf.resyncs++;
                 } else {
@@ -593,8 +597,6 @@ int oracle_step(void *vw, const uint32_t *hint_uid, const uint8_t *hint_act, int
                 }
             }
         }
-        int fa = forced_action(w, u);
-        if (fa >= 0 && fa < 5) act = fa;
         w->act[a] = act;
         w->last_uid[a] = u;
         w->last_act[a] = (uint8_t)act;
