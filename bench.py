@@ -114,6 +114,55 @@ def cpu_baseline(cfg: dict, seed: int, seconds: float) -> dict:
                       f"{el:.1f} s, plain C oracle, one thread; initialisation excluded)"}
 
 
+def batched_run(args) -> dict:
+    """Uneven worlds (grid 64x128..200x400, caps 512..8192, 10% initial agents,
+    rate scale U[0.5, 2]) in shared launches, autotuned, against the same
+    worlds stepped one at a time on the same GPU."""
+    from paper_2302_09334_amd import batch, tune, workloads
+    entries = workloads.batch_manifest(args.batch_worlds, seed=0)
+    log(f"[bench] batched: {len(entries)} worlds, warm-up {args.batch_warmup}, timed {args.batch_steps}")
+    b = batch.WorldBatch(entries, mode="graph")
+    b.step(args.batch_warmup)
+    b.sync()
+    tuned = tune.autotune(b, trial_steps=100)
+    best = tuned["best"]
+    log(f"[bench] batched autotune: {best}")
+    K = best["K"]
+    wall, chunk_ms = batch.time_chunks(b.step, args.batch_steps, K, b.stream)
+    b.sync()
+    agent_steps = b.acting_agents(args.batch_warmup, args.batch_steps)
+    n_agents = sum(w.snapshot()["n_live"] for w in b.worlds)
+    b.close()
+    seq = batch.run_sequential(entries, args.batch_warmup, args.batch_steps, 100, mode="graph")
+    out = {"worlds": len(entries), "steps": args.batch_steps, "warmup": args.batch_warmup,
+           "agent_steps_per_s": agent_steps / wall, "ms_per_step": wall / args.batch_steps * 1e3,
+           "step_ms_p50": float(np.percentile(chunk_ms / K, 50)), "step_ms_p99": float(np.percentile(chunk_ms / K, 99)),
+           "live_agents_end": int(n_agents), "tuned": best,
+           "sequential_plain": {"agent_steps_per_s": seq["agent_steps_per_s"], "wall_s": seq["wall_s"]},
+           "speedup_vs_sequential": (agent_steps / wall) / seq["agent_steps_per_s"]}
+    log(f"[bench] batched {out['agent_steps_per_s'] / 1e6:.1f} M agent-steps/s vs sequential "
+        f"{seq['agent_steps_per_s'] / 1e6:.1f} M")
+    return out
+
+
+def served_run(args) -> dict:
+    """Poisson(20/s) simulation requests (grid from the uneven set, caps
+    512..8192, steps U[500, 5000], GRU 16 or 32) admitted against the HBM
+    budget and continuously batched."""
+    from paper_2302_09334_amd import serve, workloads
+    trace = workloads.serve_trace(duration_s=args.serve_seconds, rate_hz=20.0, seed=0)
+    reqs = serve.requests_from_trace(trace)
+    log(f"[bench] served: {len(reqs)} requests over {args.serve_seconds:.0f} s of arrivals")
+    be = serve.HipBackend(mode="kernels")
+    srv = serve.Server(be, budget_bytes=int(args.serve_budget_gb * 1e9), K=50)
+    results, m = srv.run(reqs, duration=args.serve_seconds, realtime=True)
+    m["arrival_window_s"] = args.serve_seconds
+    m["rate_hz"] = 20.0
+    log(f"[bench] served {m['requests']} requests: {m['agent_steps_per_s'] / 1e6:.1f} M agent-steps/s, "
+        f"p50 {m['step_ms_p50']:.3f} ms p99 {m['step_ms_p99']:.3f} ms per step")
+    return m
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +177,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run the plain copy kernel on 1 GiB (memory-counter calibration)")
+    ap.add_argument("--batch-worlds", type=int, default=64, help="uneven worlds of the batched run (0 = skip)")
+    ap.add_argument("--batch-steps", type=int, default=400)
+    ap.add_argument("--batch-warmup", type=int, default=100)
+    ap.add_argument("--serve-seconds", type=float, default=20.0, help="arrival window of the served run (0 = skip)")
+    ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     args = ap.parse_args()
 
     world_size = int(os.environ.get("WORLD_SIZE", "1"))
@@ -243,6 +297,13 @@ def main():
         torch.cuda.synchronize()
         log("[bench] copy calibration: 3 x 1 GiB device copies done")
 
+    batched = None
+    if args.batch_worlds > 0:
+        batched = batched_run(args)
+    served = None
+    if args.serve_seconds > 0:
+        served = served_run(args)
+
     cpu = None
     if not args.no_cpu:
         log("[bench] oracle CPU baseline ...")
@@ -300,6 +361,8 @@ def main():
             "kernel_source_sha256_16": src_hash,
         },
         "cpu_baseline": cpu,
+        "batched": batched,
+        "served": served,
     }
     w.close()
     print(json.dumps(out))

@@ -133,6 +133,15 @@ int world_step_many(world_t *const *ws, int32_t n, int32_t K);
 /* Select WORLD_MODE_* for later steps. */
 int world_set_mode(world_t *w, int32_t mode);
 
+/* Move the world to another HIP stream (the old stream is synchronised
+ * first).  Lets a world be created on one stream and then join a batch. */
+int world_set_stream(world_t *w, void *hip_stream);
+
+/* Tuning knob of the act kernel: input rows fetched per wave per round trip
+ * (8, 16 or 32; default 16).  Results are identical for every value.  A
+ * batched step uses the first world's setting. */
+int world_set_tuning(world_t *w, int32_t act_rows);
+
 /* Wait for the world's stream; report device-side failures. */
 int world_sync(world_t *w);
 

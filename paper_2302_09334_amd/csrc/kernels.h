@@ -20,7 +20,14 @@ struct Batch {
     const WorldDev* const* w;   // n descriptors
     const int* pre;             // kPreKinds x (n + 1) block prefixes
     int n;
+    int act_rows;               // act-kernel tuning: input rows per round trip (8, 16, 32)
 };
+
+template <int ROWS>
+__device__ __forceinline__ void act_dispatch(const WorldDev& d, int slot, int li, int64_t t, int lane) {
+    if (d.hd == 32) act_agent<32, ROWS>(d, slot, li, t, lane);
+    else act_agent<16, ROWS>(d, slot, li, t, lane);
+}
 
 __device__ __forceinline__ int find_world(const int* pre, int n, int b) {
     int lo = 0, hi = n;   // largest i with pre[i] <= b
@@ -39,6 +46,7 @@ __device__ __forceinline__ int find_world(const int* pre, int n, int b) {
 // the previous step (rank r, r + kNewbornBlocks, ...) and run their first
 // controller step (they are the last n_child entries of the live list); the
 // remaining blocks run the controller of the other agents, four per block.
+template <int ROWS>
 __device__ __forceinline__ void act_body(const Batch& bt, int vb, int tid, StepShared& sh) {
     const int* pre = bt.pre + kPreAct * (bt.n + 1);
     const int wi = find_world(pre, bt.n, vb);
@@ -61,9 +69,7 @@ __device__ __forceinline__ void act_body(const Batch& bt, int vb, int tid, StepS
             __syncthreads();
             if (tid < 64) {
                 const int li = n - nc + rk;
-                const int slot = d.live[sel][li];
-                if (d.hd == 32) act_agent<32>(d, slot, li, t, tid);
-                else act_agent<16>(d, slot, li, t, tid);
+                act_dispatch<ROWS>(d, d.live[sel][li], li, t, tid);
             }
             __syncthreads();
         }
@@ -71,9 +77,7 @@ __device__ __forceinline__ void act_body(const Batch& bt, int vb, int tid, StepS
     }
     const int li = (lb - kNewbornBlocks) * (kBlock / 64) + (tid >> 6);
     if (li >= n - nc) return;
-    const int slot = d.live[sel][li];
-    if (d.hd == 32) act_agent<32>(d, slot, li, t, tid & 63);
-    else act_agent<16>(d, slot, li, t, tid & 63);
+    act_dispatch<ROWS>(d, d.live[sel][li], li, t, tid & 63);
 }
 
 __device__ __forceinline__ void move_body(const Batch& bt, int vb, int tid, StepShared& sh) {
@@ -118,7 +122,15 @@ __global__ __launch_bounds__(kBlock)
 #endif
 void k_act(Batch bt) {
     __shared__ StepShared sh;
-    act_body(bt, blockIdx.x, threadIdx.x, sh);
+    act_body<16>(bt, blockIdx.x, threadIdx.x, sh);
+}
+
+// Tuning variants of the act kernel (identical results, different numbers of
+// loads in flight per wave).
+template <int ROWS>
+__global__ __launch_bounds__(kBlock) void k_act_rows(Batch bt) {
+    __shared__ StepShared sh;
+    act_body<ROWS>(bt, blockIdx.x, threadIdx.x, sh);
 }
 
 // Creates the pending children of a world's last step now (before its state

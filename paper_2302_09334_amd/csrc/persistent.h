@@ -66,7 +66,7 @@ __global__ __launch_bounds__(kBlock) void k_persistent(PersistArgs a) {
     const int tid = threadIdx.x;
     uint32_t target = 0;
     for (int s = 0; s < a.K; ++s) {
-        for (int vb = blockIdx.x; vb < n_act; vb += gridDim.x) act_body(bt, vb, tid, sh);
+        for (int vb = blockIdx.x; vb < n_act; vb += gridDim.x) act_body<16>(bt, vb, tid, sh);
         if (!grid_sync(a, target, &s_ok)) return;
         for (int vb = blockIdx.x; vb < n_move; vb += gridDim.x) move_body(bt, vb, tid, sh);
         if (!grid_sync(a, target, &s_ok)) return;

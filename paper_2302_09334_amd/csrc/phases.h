@@ -57,10 +57,6 @@ __device__ __forceinline__ float sigmoidf_(float v) { return 1.0f / (1.0f + expf
 // tree.  The summation order therefore depends only on the agent's own
 // observation, never on the launch shape or on other worlds in the launch.
 // ---------------------------------------------------------------------------
-#ifndef ECO_ACT_ROWS
-#define ECO_ACT_ROWS 16   // input rows fetched per wave per batch
-#endif
-
 // ---------------------------------------------------------------------------
 // Recurrent projection gh = W_hh h + b_hh of the agent in `slot` (one wave),
 // written to gh[slot] (3 * HD floats, gate-interleaved per hidden unit).  It
@@ -136,14 +132,17 @@ __device__ __forceinline__ void proj_zero(const WorldDev& d, int slot, int lane)
 // ballots are dealt round-robin to the groups, each group sums its rows in
 // increasing input order, and the group partials are combined by a fixed xor
 // tree.  The summation order therefore depends only on the agent's own
-// observation, never on the launch shape or on other worlds in the launch.
+// observation, never on the launch shape or on other worlds in the launch:
+// ROWS (input rows fetched per wave per round trip) only changes how many
+// loads are in flight, since row q of the enumeration always goes to group
+// q % G and each group adds its rows in increasing q.
 // The recurrent projection comes precomputed from gh[slot].
 // ---------------------------------------------------------------------------
-template <int HD>
+template <int HD, int ROWS>
 __device__ __forceinline__ void act_agent(const WorldDev& d, int slot, int li, int64_t t, int lane) {
     constexpr int G = 64 / HD;
     constexpr int RW = 3 * HD;   // floats per input row
-    constexpr int B = ECO_ACT_ROWS / G;   // input rows per group per batch
+    constexpr int B = ROWS / G;  // input rows per group per round trip
     const int g = lane / HD;
     const int k = lane - g * HD;
     const int H = d.H, W = d.W;

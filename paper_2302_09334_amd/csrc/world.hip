@@ -174,6 +174,7 @@ struct world {
     int max_useful = 1;
     hipStream_t stream;
     int mode = WORLD_MODE_KERNELS;
+    int act_rows = 16;     // act-kernel tuning knob (8, 16, 32)
     bool poisoned = false;
     std::string err;
     std::map<int, hipGraphExec_t> graphs;
@@ -218,10 +219,16 @@ std::vector<int> batch_prefix(const std::vector<const world*>& ws) {
     return pre;
 }
 
+void launch_act(const Batch& b, int grid, hipStream_t s) {
+    if (b.act_rows == 8) hipLaunchKernelGGL(k_act_rows<8>, dim3(grid), dim3(kBlock), 0, s, b);
+    else if (b.act_rows == 32) hipLaunchKernelGGL(k_act_rows<32>, dim3(grid), dim3(kBlock), 0, s, b);
+    else hipLaunchKernelGGL(k_act, dim3(grid), dim3(kBlock), 0, s, b);
+}
+
 // Enqueue one step of the per-phase kernels for a batch.
 hipError_t launch_step(const Batch& b, const int* host_pre, int n, hipStream_t s) {
     const int np = n + 1;
-    hipLaunchKernelGGL(k_act, dim3(host_pre[kPreAct * np + n]), dim3(kBlock), 0, s, b);
+    launch_act(b, host_pre[kPreAct * np + n], s);
     hipLaunchKernelGGL(k_move, dim3(host_pre[kPreMove * np + n]), dim3(kBlock), 0, s, b);
     hipLaunchKernelGGL(k_claim, dim3(host_pre[kPreClaim * np + n]), dim3(kBlock), 0, s, b);
     return hipGetLastError();
@@ -304,13 +311,14 @@ std::vector<char> build_table(const std::vector<const world*>& ws, char* dev_bas
 int run_steps(world* w0, int mode, const TableView& tv, const std::vector<int>& host_bp, int n, int max_useful,
               int K, std::map<int, hipGraphExec_t>& graphs, std::map<int, hipGraph_t>& defs) {
     hipStream_t s = w0->stream;
-    Batch b{tv.w, tv.block_pre, n};
+    Batch b{tv.w, tv.block_pre, n, w0->act_rows};
     if (mode == WORLD_MODE_KERNELS) {
         for (int k = 0; k < K; ++k) HIP_TRY(w0, launch_step(b, host_bp.data(), n, s));
         return WORLD_OK;
     }
     if (mode == WORLD_MODE_GRAPH) {
-        auto it = graphs.find(K);
+        const int gkey = K * 64 + w0->act_rows;
+        auto it = graphs.find(gkey);
         if (it == graphs.end()) {
             hipGraph_t g = nullptr;
             hipGraphExec_t ge = nullptr;
@@ -321,8 +329,8 @@ int run_steps(world* w0, int mode, const TableView& tv, const std::vector<int>& 
             if (le != hipSuccess) return fail(w0, WORLD_E_HIP, std::string("graph capture: ") + hipGetErrorString(le));
             if (ce != hipSuccess) return fail(w0, WORLD_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
             HIP_TRY(w0, hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
-            defs[K] = g;
-            it = graphs.emplace(K, ge).first;
+            defs[gkey] = g;
+            it = graphs.emplace(gkey, ge).first;
         }
         HIP_TRY(w0, hipGraphLaunch(it->second, s));
         return WORLD_OK;
@@ -548,6 +556,21 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
     return WORLD_OK;
 }
 
+int world_set_stream(world_t* w, void* hip_stream) {
+    if (!w) return fail(nullptr, WORLD_E_INVALID_ARG, "world is NULL");
+    if (w->poisoned) return WORLD_E_POISONED;
+    HIP_TRY(w, hipStreamSynchronize(w->stream));
+    w->stream = static_cast<hipStream_t>(hip_stream);
+    return WORLD_OK;
+}
+
+int world_set_tuning(world_t* w, int32_t act_rows) {
+    if (!w) return fail(nullptr, WORLD_E_INVALID_ARG, "world is NULL");
+    if (act_rows != 8 && act_rows != 16 && act_rows != 32) return fail(w, WORLD_E_INVALID_ARG, "act_rows must be 8, 16 or 32");
+    w->act_rows = act_rows;
+    return WORLD_OK;
+}
+
 int world_set_mode(world_t* w, int32_t mode) {
     if (!w) return fail(nullptr, WORLD_E_INVALID_ARG, "world is NULL");
     if (mode != WORLD_MODE_KERNELS && mode != WORLD_MODE_GRAPH && mode != WORLD_MODE_PERSISTENT)
@@ -562,18 +585,24 @@ static int step_single(world* w, int K) {
 }
 
 // Launch tables of batches (device memory owned by the library, one per
-// distinct list of worlds), with their captured graphs.
+// distinct list of worlds), with their captured graphs.  At most kBatchCache
+// tables are kept; the least recently used one is released (after its stream
+// has drained) when a new list needs a table.
 struct BatchEntry {
     void* dev = nullptr;
     TableView tv;
     std::vector<int> host_bp;
     int max_useful = 1;
+    uint64_t last_use = 0;
+    hipStream_t stream = nullptr;
     std::map<int, hipGraphExec_t> graphs;
     std::map<int, hipGraph_t> defs;
 };
 
+constexpr size_t kBatchCache = 64;
 static std::mutex g_batch_mu;
 static std::map<std::vector<uintptr_t>, BatchEntry*> g_batches;
+static uint64_t g_batch_clock = 0;
 
 static std::vector<uintptr_t> batch_key(world_t* const* ws, int n) {
     std::vector<uintptr_t> key;
@@ -587,6 +616,14 @@ static std::vector<uintptr_t> batch_key(world_t* const* ws, int n) {
     return key;
 }
 
+static void release_entry(BatchEntry* be) {
+    if (be->stream) (void)hipStreamSynchronize(be->stream);
+    for (auto& kv : be->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto& kv : be->defs) (void)hipGraphDestroy(kv.second);
+    if (be->dev) (void)hipFree(be->dev);
+    delete be;
+}
+
 static int batch_step(world_t* const* ws, int n, int K) {
     world* w0 = ws[0];
     BatchEntry* be = nullptr;
@@ -595,7 +632,15 @@ static int batch_step(world_t* const* ws, int n, int K) {
         auto key = batch_key(ws, n);
         auto it = g_batches.find(key);
         if (it == g_batches.end()) {
+            if (g_batches.size() >= kBatchCache) {
+                auto lru = g_batches.begin();
+                for (auto jt = g_batches.begin(); jt != g_batches.end(); ++jt)
+                    if (jt->second->last_use < lru->second->last_use) lru = jt;
+                release_entry(lru->second);
+                g_batches.erase(lru);
+            }
             be = new BatchEntry();
+            be->stream = w0->stream;
             hipError_t e = hipMalloc(&be->dev, table_bytes(n));
             if (e != hipSuccess) {
                 delete be;
@@ -610,10 +655,10 @@ static int batch_step(world_t* const* ws, int n, int K) {
                 delete be;
                 return fail(w0, WORLD_E_HIP, std::string("batch table upload: ") + hipGetErrorString(e));
             }
-            g_batches.emplace(std::move(key), be);
-        } else {
-            be = it->second;
+            it = g_batches.emplace(std::move(key), be).first;
         }
+        be = it->second;
+        be->last_use = ++g_batch_clock;
     }
     return run_steps(w0, w0->mode, be->tv, be->host_bp, n, be->max_useful, K, be->graphs, be->defs);
 }
@@ -874,7 +919,7 @@ int world_phase_times(world_t* w, int32_t K, float* ms) {
     if (K < 1) return fail(w, WORLD_E_INVALID_ARG, "K must be >= 1");
     const int np = 2;
     const int* hp = w->host_bp.data();
-    Batch b{w->tv.w, w->tv.block_pre, 1};
+    Batch b{w->tv.w, w->tv.block_pre, 1, w->act_rows};
     hipStream_t s = w->stream;
     std::vector<hipEvent_t> ev(size_t(K) * 4);
     for (auto& e : ev) HIP_TRY(w, hipEventCreate(&e));
@@ -882,7 +927,7 @@ int world_phase_times(world_t* w, int32_t K, float* ms) {
     for (int k = 0; k < K && le == hipSuccess; ++k) {
         hipEvent_t* e = ev.data() + size_t(k) * 4;
         (void)hipEventRecord(e[0], s);
-        hipLaunchKernelGGL(k_act, dim3(hp[kPreAct * np + 1]), dim3(kBlock), 0, s, b);
+        launch_act(b, hp[kPreAct * np + 1], s);
         (void)hipEventRecord(e[1], s);
         hipLaunchKernelGGL(k_move, dim3(hp[kPreMove * np + 1]), dim3(kBlock), 0, s, b);
         (void)hipEventRecord(e[2], s);

@@ -63,7 +63,7 @@ class Image(C.Structure):
 # Every symbol include/world.h declares (checked by the ABI test).
 EXPORTS = [
     "world_required_bytes", "world_dims", "world_create", "world_step", "world_step_many",
-    "world_set_mode", "world_sync", "world_snapshot", "world_load", "world_counters_get",
+    "world_set_mode", "world_set_tuning", "world_set_stream", "world_sync", "world_snapshot", "world_load", "world_counters_get",
     "world_destroy", "world_last_error", "world_set_forced_action", "world_action_log",
     "world_test_philox", "world_test_gauss", "world_threshold_table", "world_phase_times",
     "world_test_copy",
@@ -86,6 +86,8 @@ def lib():
         L.world_step.argtypes = [P, C.c_int32]
         L.world_step_many.argtypes = [C.POINTER(P), C.c_int32, C.c_int32]
         L.world_set_mode.argtypes = [P, C.c_int32]
+        L.world_set_tuning.argtypes = [P, C.c_int32]
+        L.world_set_stream.argtypes = [P, P]
         L.world_sync.argtypes = [P]
         L.world_snapshot.argtypes = [P, C.POINTER(Image)]
         L.world_load.argtypes = [P, C.POINTER(Image)]
@@ -166,6 +168,7 @@ class World:
         self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
         # torch's caching allocator returns 512-byte aligned blocks
         self.arena = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self.nbytes = int(nbytes.value)
         self.n_inputs, self.n_params = dims(cfg)
         h = C.c_void_p()
         _check(lib().world_create(C.byref(self._c), C.c_uint64(self.seed), C.c_void_p(self.arena.data_ptr()),
@@ -192,6 +195,16 @@ class World:
     def set_mode(self, mode: str):
         self.mode = mode
         _check(lib().world_set_mode(self._h, MODES[mode]), self._h)
+
+    def set_stream(self, stream):
+        """Move the world to another torch/HIP stream (synchronises the old one)."""
+        _check(lib().world_set_stream(self._h, C.c_void_p(stream.cuda_stream)), self._h)
+        self.stream = stream
+
+    def set_tuning(self, act_rows: int):
+        """Act-kernel rows per round trip (8, 16, 32); results are identical."""
+        self.act_rows = int(act_rows)
+        _check(lib().world_set_tuning(self._h, int(act_rows)), self._h)
 
     def step(self, K: int = 1):
         _check(lib().world_step(self._h, int(K)), self._h)

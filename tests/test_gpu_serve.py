@@ -1,0 +1,63 @@
+"""Serving and batching on the GPU: each served result equals the same
+request run alone; autotuning leaves the simulation state untouched."""
+import numpy as np
+import pytest
+
+from parity_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2302_09334_amd import batch, serve, tune, workloads, world
+    return world, serve, batch, tune, workloads
+
+
+@pytest.mark.parametrize("mode", ["kernels", "persistent"])
+def test_served_equals_alone(env, mode):
+    world, serve, batch, tune, wl = env
+    reqs = []
+    for i in range(8):
+        cfg = wl.make(H=[64, 100, 128][i % 3], W=[128, 200, 256][i % 3], cap=512 + 64 * i, n_init=51 + 6 * i,
+                      hidden=16 if i % 2 else 32, rate_scale=1.0 + 0.25 * i, res_init_p=0.3)
+        reqs.append(serve.Request(i, arrival=0.02 * i, cfg=cfg, seed=50 + i, steps=60 + 35 * (i % 4)))
+    be = serve.HipBackend(mode=mode)
+    budget = 3 * max(world.required_bytes(r.cfg) for r in reqs)
+    say(f"[serve] mode={mode} budget={budget}")
+    results, m = serve.Server(be, budget_bytes=budget, K=25).run(reqs, realtime=True)
+    say(f"[serve] {m}")
+    assert len(results) == len(reqs) and m["peak_budget_used_bytes"] <= budget
+    for r in reqs:
+        w = world.World(r.cfg, r.seed, mode="graph")
+        w.step(r.steps)
+        alone = serve.state_digest(w.snapshot(hidden=True, theta=True))
+        w.close()
+        assert results[r.rid]["digest"] == alone, r.rid
+
+
+def test_autotune_preserves_state(env):
+    world, serve, batch, tune, wl = env
+    entries = [e for e in wl.batch_manifest(6, seed=4)]
+    for e in entries:
+        e["cfg"] = dict(e["cfg"], cap=min(e["cfg"]["cap"], 1024), n_init=min(e["cfg"]["n_init"], 100))
+    a = batch.WorldBatch(entries, mode="graph")
+    a.step(20)
+    before = a.snapshots()
+    res = tune.autotune(a, trial_steps=20, ks=(10, 20))
+    say(f"[tune] best {res['best']}")
+    after = a.snapshots()
+    for x, y in zip(before, after):
+        for k in ("uid", "row", "col", "energy", "age", "streak", "R", "h", "theta"):
+            assert np.array_equal(np.asarray(x[k]), np.asarray(y[k])), k
+    a.step(30)
+    b = batch.WorldBatch(entries, mode="kernels")
+    b.step(20)
+    b.step(30)
+    for x, y in zip(a.snapshots(), b.snapshots()):
+        assert serve.state_digest(x) == serve.state_digest(y)
+    a.close()
+    b.close()
