@@ -24,9 +24,9 @@ struct Batch {
 };
 
 template <int ROWS>
-__device__ __forceinline__ void act_dispatch(const WorldDev& d, int slot, int li, int64_t t, int lane) {
-    if (d.hd == 32) act_agent<32, ROWS>(d, slot, li, t, lane);
-    else act_agent<16, ROWS>(d, slot, li, t, lane);
+__device__ __forceinline__ void act_dispatch(const WorldDev& d, AgentRec* rec, int li, int64_t t, int lane) {
+    if (d.hd == 32) act_agent<32, ROWS>(d, rec, li, t, lane);
+    else act_agent<16, ROWS>(d, rec, li, t, lane);
 }
 
 __device__ __forceinline__ int find_world(const int* pre, int n, int b) {
@@ -69,7 +69,7 @@ __device__ __forceinline__ void act_body(const Batch& bt, int vb, int tid, StepS
             __syncthreads();
             if (tid < 64) {
                 const int li = n - nc + rk;
-                act_dispatch<ROWS>(d, d.live[sel][li], li, t, tid);
+                act_dispatch<ROWS>(d, d.rec[sel] + li, li, t, tid);
             }
             __syncthreads();
         }
@@ -77,7 +77,7 @@ __device__ __forceinline__ void act_body(const Batch& bt, int vb, int tid, StepS
     }
     const int li = (lb - kNewbornBlocks) * (kBlock / 64) + (tid >> 6);
     if (li >= n - nc) return;
-    act_dispatch<ROWS>(d, d.live[sel][li], li, t, tid & 63);
+    act_dispatch<ROWS>(d, d.rec[sel] + li, li, t, tid & 63);
 }
 
 __device__ __forceinline__ void move_body(const Batch& bt, int vb, int tid, StepShared& sh) {

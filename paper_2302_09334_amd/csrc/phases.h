@@ -139,17 +139,20 @@ __device__ __forceinline__ void proj_zero(const WorldDev& d, int slot, int lane)
 // The recurrent projection comes precomputed from gh[slot].
 // ---------------------------------------------------------------------------
 template <int HD, int ROWS>
-__device__ __forceinline__ void act_agent(const WorldDev& d, int slot, int li, int64_t t, int lane) {
+__device__ __forceinline__ void act_agent(const WorldDev& d, AgentRec* recp, int li, int64_t t, int lane) {
     constexpr int G = 64 / HD;
     constexpr int RW = 3 * HD;   // floats per input row
     constexpr int B = ROWS / G;  // input rows per group per round trip
     const int g = lane / HD;
     const int k = lane - g * HD;
     const int H = d.H, W = d.W;
-    const int cell = d.cell[slot];
+    const int4 rv = *reinterpret_cast<const int4*>(recp);   // slot, cell, energy, uid
+    const int slot = rv.x;
+    const int cell = rv.y;
     const int r = cell / W;
     const int c = cell - r * W;
-    const int e = d.energy[slot];
+    const int e = rv.z;
+    const uint32_t u = uint32_t(rv.w);
     const float* th = d.theta + size_t(slot) * size_t(d.Ppad);
     const int rho = d.rho;
     const int win = 2 * rho + 1;
@@ -260,6 +263,7 @@ __device__ __forceinline__ void act_agent(const WorldDev& d, int slot, int li, i
     if (g == 0) d.h[size_t(slot) * HD + k] = hnew;
     if (lane == 0) {
         d.action[slot] = uint8_t(best);
+        recp->action = best;
         // Move claim (resolved by the next phase): a move targets the window
         // cell one step away, which must be inside the grid and empty at the
         // step start (its occupancy bit, outside cells reading occupied, is 0).
@@ -268,7 +272,6 @@ __device__ __forceinline__ void act_agent(const WorldDev& d, int slot, int li, i
         if (best < 4) {
             const int q = (rho + act_dr(best)) * win + (rho + act_dc(best));
             if (!((occ_bits >> q) & 1ull)) {
-                const uint32_t u = d.uid[slot];
                 const uint64_t key = claim_key(philox(u, uint32_t(t), kMove, 0, d.seed_lo, d.seed_hi).x, u);
                 const int Y = (r + act_dr(best)) * W + (c + act_dc(best));
                 atomicMin(reinterpret_cast<unsigned long long*>(d.mclaim + Y), (unsigned long long)key);
@@ -278,7 +281,7 @@ __device__ __forceinline__ void act_agent(const WorldDev& d, int slot, int li, i
     if (d.log_steps > 0) {
         const size_t row = size_t(t % d.log_steps) * size_t(d.cap) + size_t(li);
         if (lane == 0) {
-            d.log_uid[row] = d.uid[slot];
+            d.log_uid[row] = u;
             d.log_act[row] = uint8_t(best);
         }
         if (lane < 5) {
@@ -315,35 +318,55 @@ __device__ __forceinline__ uint32_t unpack_b(uint64_t v) { return uint32_t(v & k
 
 __device__ __forceinline__ uint64_t lookback(const WorldDev& d, uint64_t* st, int tile, uint32_t epoch,
                                              uint64_t local, int tid, uint64_t* s_bcast) {
-    if (tid == 0) {
-        const uint64_t tag = uint64_t(epoch & 0xFFFFFu) << 44;
+    // Wave 0 publishes this tile's total, then examines the predecessors 64 at
+    // a time (one status word per lane) until the nearest one holding an
+    // inclusive prefix: the prefix is that word plus the totals in between.
+    if (tid < 64) {
+        const int lane = tid;
+        const uint64_t tag = uint64_t(epoch & 0xFFFFFu);
+        if (lane == 0)
+            __hip_atomic_store(st + tile, (tag << 44) | (uint64_t(tile == 0 ? 2 : 1) << 42) | local,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         uint64_t excl = 0;
-        if (tile == 0) {
-            __hip_atomic_store(st, tag | (uint64_t(2) << 42) | local, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            __hip_atomic_store(st + tile, tag | (uint64_t(1) << 42) | local, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            int k = tile - 1;
-            const uint64_t t0 = wall_clock64();
-            while (k >= 0) {
-                const uint64_t v = __hip_atomic_load(st + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const uint32_t flag = uint32_t(v >> 42) & 3u;
-                if ((v >> 44) != (tag >> 44) || flag == 0) {
+        int end = tile;
+        const uint64_t t0 = wall_clock64();
+        bool timed_out = false;
+        while (end > 0) {
+            const int k = end - 1 - lane;   // lane 0 = nearest predecessor
+            uint64_t v = 0;
+            uint32_t flag = 2;              // lanes past tile 0 act as an empty inclusive
+            if (k >= 0) {
+                while (true) {
+                    v = __hip_atomic_load(st + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    flag = uint32_t(v >> 42) & 3u;
+                    if ((v >> 44) == tag && flag != 0) break;
                     if (wall_clock64() - t0 > 200000000ull) {   // 2 s at the 100 MHz wall clock
-                        __hip_atomic_store(&d.scal->err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        timed_out = true;
+                        v = 0;
+                        flag = 2;
                         break;
                     }
                     __builtin_amdgcn_s_sleep(1);
-                    continue;
                 }
-                excl += v & kValMask;
-                if (flag == 2) break;
-                --k;
             }
-            __hip_atomic_store(st + tile, tag | (uint64_t(2) << 42) | (excl + local), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t val = (k >= 0) ? (v & kValMask) : 0;
+            const uint64_t incl = __ballot(flag == 2);
+            const int first = incl ? __builtin_ctzll(incl) : 64;   // nearest inclusive lane
+            uint64_t part = (lane <= first) ? val : 0;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+            excl += part;
+            if (incl) break;
+            end -= 64;
         }
-        *s_bcast = excl;
+        if (__ballot(timed_out) && lane == 0)
+            __hip_atomic_store(&d.scal->err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (lane == 0) {
+            if (tile != 0)
+                __hip_atomic_store(st + tile, (tag << 44) | (uint64_t(2) << 42) | (excl + local), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            *s_bcast = excl;
+        }
     }
     __syncthreads();
     const uint64_t r = *s_bcast;
@@ -399,28 +422,35 @@ __device__ __forceinline__ BlockRank block_rank2(bool a, bool b, int tid, int* s
 // moves and deaths; occA (read by every agent in this phase) is untouched.
 // Returns bit 0 = ate, bit 1 = died.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int move_agent(const WorldDev& d, int slot, int64_t t) {
+__device__ __forceinline__ int move_agent(const WorldDev& d, const AgentRec& a, int64_t t, PostRec* post,
+                                          AgentRec* next_rec_src) {
     const int W = d.W, H = d.H;
-    const int X = d.cell[slot];
-    const int a = d.action[slot];
-    const uint32_t u = d.uid[slot];
+    const int slot = a.slot;
+    const int X = a.cell;
+    const int act = a.action;
+    const uint32_t u = a.uid;
     const int r = X / W, c = X - (X / W) * W;
-    int newX = X;
-    if (a < 4) {
-        const int tr = r + act_dr(a), tc = c + act_dc(a);
-        if (tr >= 0 && tr < H && tc >= 0 && tc < W) {
-            const int Y = tr * W + tc;
-            const uint64_t key = claim_key(philox(u, uint32_t(t), kMove, 0, d.seed_lo, d.seed_hi).x, u);
-            if (d.mclaim[Y] == key) newX = Y;
-        }
-    }
     uint8_t* Rc = d.R[t & 1];
-    const int ate = Rc[newX] != 0;
+    // the claim word of the target and both possible resource bytes together
+    int Y = -1;
+    if (act < 4) {
+        const int tr = r + act_dr(act), tc = c + act_dc(act);
+        if (tr >= 0 && tr < H && tc >= 0 && tc < W) Y = tr * W + tc;
+    }
+    const uint64_t cw = (Y >= 0) ? d.mclaim[Y] : ~0ull;
+    const int rX = Rc[X];
+    const int rY = (Y >= 0) ? Rc[Y] : 0;
+    int newX = X;
+    if (Y >= 0) {
+        const uint64_t key = claim_key(philox(u, uint32_t(t), kMove, 0, d.seed_lo, d.seed_hi).x, u);
+        if (cw == key) newX = Y;
+    }
+    const int ate = (newX == X ? rX : rY) != 0;
     if (ate) Rc[newX] = 0;
-    const int en = d.energy[slot] - d.decay + d.gain * ate;
-    const int ag = d.age[slot] + 1;
+    const int en = a.energy - d.decay + d.gain * ate;
+    const int ag = a.age + 1;
     const bool dead = en <= 0 || ag >= d.L_max;
-    int st = d.streak[slot];
+    int st = a.streak;
     if (!dead) st = (en >= d.E_repr) ? st + 1 : 0;
     d.energy[slot] = en;
     d.age[slot] = ag;
@@ -450,6 +480,26 @@ __device__ __forceinline__ int move_agent(const WorldDev& d, int slot, int64_t t
         d.occA[X] = -1;
     }
     d.occB[newX] = word;
+    PostRec p;
+    p.slot = slot;
+    p.prev_cell = X;
+    p.cell = newX;
+    p.alive = dead ? 0 : 1;
+    p.streak = st;
+    p.action = act;
+    p.uid = u;
+    p.next_pos = -1;
+    *post = p;
+    AgentRec nr;
+    nr.slot = slot;
+    nr.cell = newX;
+    nr.energy = en;
+    nr.uid = u;
+    nr.age = ag;
+    nr.streak = st;
+    nr.action = 4;
+    nr.pad = 0;
+    *next_rec_src = nr;
     return ate | (dead ? 2 : 0);
 }
 
@@ -468,19 +518,23 @@ __device__ __forceinline__ void move_block(const WorldDev& d, int j, int tid, St
     const int sel = S->live_sel;
     const int64_t t = S->t;
     const int i = j * kBlock + tid;
-    int slot = -1, res = 0;
-    if (i < n) {
-        slot = d.live[sel][i];
-        res = move_agent(d, slot, t);
-    }
+    int res = 0;
+    AgentRec nr;
+    nr.slot = -1;
+    if (i < n) res = move_agent(d, d.rec[sel][i], t, d.post + i, &nr);
     const bool alive = i < n && !(res & 2);
     const bool dead = i < n && (res & 2);
     const int cnt = __popcll(__ballot((res & 1) != 0));
     if ((tid & 63) == 0) d.eat_part[i >> 6] = cnt;
     const BlockRank br = block_rank2(alive, dead, tid, sh.sw);
     const uint64_t ex = lookback(d, d.lb_move, j, uint32_t(t), pack2(br.ta, br.tb), tid, &sh.bcast);
-    if (alive) d.live[sel ^ 1][unpack_a(ex) + br.ra] = slot;
-    if (dead) d.deadlist[unpack_b(ex) + br.rb] = slot;
+    if (alive) {
+        const int pos = int(unpack_a(ex)) + br.ra;
+        d.live[sel ^ 1][pos] = nr.slot;
+        d.rec[sel ^ 1][pos] = nr;
+        d.post[i].next_pos = pos;
+    }
+    if (dead) d.deadlist[unpack_b(ex) + br.rb] = nr.slot;
 }
 
 // First free in-grid 4-neighbour of `cell` (order N, S, E, W cyclically from
@@ -512,15 +566,15 @@ __device__ __forceinline__ int birth_target(const WorldDev& d, int cell, int d0)
 // compute its birth claim and resolve it against the other eligible agents
 // next to the claimed cell: their occB words give eligibility and scan start,
 // their claims are recomputed from occB, their keys come from bkey.
-// Returns true for a claim winner.
+// Returns the claimed cell of a claim winner, -1 otherwise.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool claim_agent(const WorldDev& d, int slot, int64_t t) {
-    const int X = d.prev_cell[slot];
-    const int X2 = d.cell[slot];
-    const bool alive = d.alive[slot] != 0;
+__device__ __forceinline__ int claim_agent(const WorldDev& d, const PostRec& p, int64_t t) {
+    const int X = p.prev_cell;
+    const int X2 = p.cell;
+    const bool alive = p.alive != 0;
     {
         // clear the move-claim word this agent may have written in P1
-        const int a = d.action[slot];
+        const int a = p.action;
         if (a < 4) {
             const int tr = X / d.W + act_dr(a), tc = X - (X / d.W) * d.W + act_dc(a);
             if (tr >= 0 && tr < d.H && tc >= 0 && tc < d.W) d.mclaim[tr * d.W + tc] = ~0ull;
@@ -528,8 +582,8 @@ __device__ __forceinline__ bool claim_agent(const WorldDev& d, int slot, int64_t
     }
     int C = -1;
     bool won = false;
-    if (alive && d.streak[slot] >= d.T_repr) {
-        const uint32_t u = d.uid[slot];
+    if (alive && p.streak >= d.T_repr) {
+        const uint32_t u = p.uid;
         const Draw4 b = philox(u, uint32_t(t), kBirth, 0, d.seed_lo, d.seed_hi);
         C = birth_target(d, X2, int(b.x & 3u));
         if (C >= 0) {
@@ -555,8 +609,8 @@ __device__ __forceinline__ bool claim_agent(const WorldDev& d, int slot, int64_t
             }
         }
     }
-    d.claim[slot] = C;
-    return won;
+    d.claim[p.slot] = C;
+    return won ? C : -1;
 }
 
 // P3a for tile `j` of one world.  The winner of global rank r (uid order) is
@@ -571,11 +625,14 @@ __device__ __forceinline__ void claim_block(const WorldDev& d, int j, int tid, S
     const int cap = d.cap;
     const int ntile = (cap + kBlock - 1) / kBlock;
     const int i = j * kBlock + tid;
-    int slot = -1;
+    int slot = -1, cell = -1, pos = -1;
     bool win = false;
     if (i < n) {
-        slot = d.live[sel][i];
-        win = claim_agent(d, slot, t);
+        const PostRec p = d.post[i];
+        slot = p.slot;
+        pos = p.next_pos;
+        cell = claim_agent(d, p, t);
+        win = cell >= 0;
     }
     const BlockRank br = block_rank2(win, false, tid, sh.sw);
     const uint64_t ex = lookback(d, d.lb_claim, j, uint32_t(t), pack2(br.ta, 0), tid, &sh.bcast);
@@ -592,10 +649,23 @@ __device__ __forceinline__ void claim_block(const WorldDev& d, int j, int tid, S
             } else {
                 cs = d.deadlist[rk - nfree];
             }
-            const int cell = d.claim[slot];
-            d.child[rk] = make_int4(cs, slot, cell, int(S->next_uid + uint32_t(rk)));
+            const uint32_t cu = S->next_uid + uint32_t(rk);
+            d.child[rk] = make_int4(cs, slot, cell, int(cu));
             d.live[sel ^ 1][surv + rk] = cs;
+            AgentRec cr;
+            cr.slot = cs;
+            cr.cell = cell;
+            cr.energy = d.E0;
+            cr.uid = cu;
+            cr.age = 0;
+            cr.streak = 0;
+            cr.action = 4;
+            cr.pad = 0;
+            d.rec[sel ^ 1][surv + rk] = cr;
             d.occA[cell] = cs;   // occA is neither read nor written by others in this phase
+            // the parent's streak restarts (no phase reads these in P3)
+            d.rec[sel ^ 1][pos].streak = 0;
+            d.streak[slot] = 0;
         }
     }
     // completion: the last tile to get here closes the step
@@ -692,7 +762,7 @@ __device__ __forceinline__ void regrow_tile(const WorldDev& d, int tile, int tid
 // theta_child[p] = fmaf(sigma, z_p, theta_parent[p]) with z_p lane p % 4 of
 // the MUTATE draw (child uid, birth step, block p / 4); the record gets
 // energy E0, age 0, streak 0 and a zero hidden state; the child enters occB
-// (occA received it when it was born) and the parent's streak restarts.
+// (occA received it when it was born; the parent's streak restarted then).
 // Every store is complete when this returns, so the same block can run the
 // child's controller right after a block barrier.
 // ---------------------------------------------------------------------------
@@ -727,7 +797,6 @@ __device__ __forceinline__ void spawn_child(const WorldDev& d, int rk, int tid) 
         d.claim[cs] = -1;
         d.action[cs] = 4;
         d.occB[rec.z] = cs;
-        d.streak[rec.y] = 0;
     }
     if (tid < d.hd) d.h[size_t(cs) * d.hd + tid] = 0.f;
     __builtin_amdgcn_s_waitcnt(0);   // this thread's stores have completed

@@ -12,7 +12,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/world.h"
+#include "world.h"
 #include "kernels.h"
 #include "persistent.h"
 
@@ -75,7 +75,7 @@ const char* check_config(const world_config* c) {
 struct Layout {
     size_t desc, scal, ring, batch, thr, R0, R1, occA, occB, mclaim;
     size_t uid, cell, prev_cell, energy, age, streak, action, alive, win, claim, bkey;
-    size_t live0, live1, freeq, child, h, gh, theta;
+    size_t live0, live1, rec0, rec1, post, freeq, child, h, gh, theta;
     size_t log_uid, log_act, log_logits, log_n, barrier, eat_part, res_part, deadlist, lb_move, lb_claim, done;
     size_t total;
 };
@@ -116,6 +116,9 @@ Layout layout_of(const world_config& c) {
     l.bkey = take(8 * cap);
     l.live0 = take(4 * cap);
     l.live1 = take(4 * cap);
+    l.rec0 = take(sizeof(AgentRec) * cap);
+    l.rec1 = take(sizeof(AgentRec) * cap);
+    l.post = take(sizeof(PostRec) * cap);
     l.freeq = take(4 * cap);
     l.child = take(16 * cap);
     l.h = take(4 * cap * size_t(c.hidden));
@@ -438,6 +441,9 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
     d.theta = reinterpret_cast<float*>(b + lay.theta);
     d.live[0] = reinterpret_cast<int32_t*>(b + lay.live0);
     d.live[1] = reinterpret_cast<int32_t*>(b + lay.live1);
+    d.rec[0] = reinterpret_cast<AgentRec*>(b + lay.rec0);
+    d.rec[1] = reinterpret_cast<AgentRec*>(b + lay.rec1);
+    d.post = reinterpret_cast<PostRec*>(b + lay.post);
     d.freeq = reinterpret_cast<int32_t*>(b + lay.freeq);
     d.child = reinterpret_cast<int4*>(b + lay.child);
     d.scal = reinterpret_cast<WorldScal*>(b + lay.scal);
@@ -481,6 +487,8 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
         live[a] = int32_t(a);
     }
     for (int s = int(n0); s < c.cap; ++s) freeq[s - int(n0)] = s;
+    std::vector<AgentRec> recs(c.cap);
+    for (size_t a = 0; a < n0; ++a) recs[a] = AgentRec{int32_t(a), cells[a], c.E0, uint32_t(a), 0, 0, 4, 0};
     std::vector<uint64_t> thr(size_t(c.H) * 25);
     build_thresholds(c, thr.data());
     WorldScal sc;
@@ -521,6 +529,7 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
     UP(lay.alive, alive.data(), size_t(c.cap));
     UP(lay.live0, live.data(), size_t(c.cap) * 4);
     UP(lay.live1, live.data(), size_t(c.cap) * 4);
+    UP(lay.rec0, recs.data(), sizeof(AgentRec) * size_t(c.cap));
     UP(lay.freeq, freeq.data(), size_t(c.cap) * 4);
 #undef UP
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.ring, 0, sizeof(int32_t) * kRing * kCtrWords, s);
@@ -798,6 +807,12 @@ int world_load(world_t* w, const world_image* in) {
     HIP_TRY(w, hipMemcpy(b + l.streak, streaks.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
     HIP_TRY(w, hipMemcpy(b + l.alive, alive.data(), size_t(c.cap), hipMemcpyHostToDevice));
     HIP_TRY(w, hipMemcpy(b + l.live0, live.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
+    {
+        std::vector<AgentRec> recs(c.cap);
+        for (int i = 0; i < n; ++i)
+            recs[i] = AgentRec{i, cells[i], energies[i], uids[i], ages[i], streaks[i], 4, 0};
+        HIP_TRY(w, hipMemcpy(b + l.rec0, recs.data(), sizeof(AgentRec) * size_t(c.cap), hipMemcpyHostToDevice));
+    }
     HIP_TRY(w, hipMemcpy(b + l.freeq, freeq.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
     HIP_TRY(w, hipMemset(b + l.lb_move, 0, 8 * size_t(blocks_agent(c))));
     HIP_TRY(w, hipMemset(b + l.lb_claim, 0, 8 * size_t(blocks_agent(c))));

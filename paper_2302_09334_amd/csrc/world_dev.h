@@ -34,6 +34,23 @@ constexpr int kTile = 16;       // regrowth tile edge (16 x 16 cells per block)
 // Counter record fields (match world_counters in world.h).
 enum : int { kCtrLive = 0, kCtrBirths, kCtrDeaths, kCtrEaten, kCtrRes, kCtrWins };
 
+// Agent record by live-list position (the order of the live list): what the
+// act and move phases need about an agent in one 32-byte read.
+struct alignas(16) AgentRec {
+    int32_t slot, cell, energy;
+    uint32_t uid;
+    int32_t age, streak, action, pad;
+};
+
+// Post-move record by live-list position, for the claim phase (next_pos =
+// the survivor's position in the next live list, -1 for the dead).
+struct alignas(16) PostRec {
+    int32_t slot, prev_cell, cell, alive;
+    int32_t streak, action;
+    uint32_t uid;
+    int32_t next_pos;
+};
+
 struct WorldScal {
     int64_t t;          // steps taken
     int32_t n_live;
@@ -83,6 +100,8 @@ struct WorldDev {
     float* theta;
     // lists
     int32_t* live[2];
+    AgentRec* rec[2];     // records of live[0] / live[1]
+    PostRec* post;        // post-move records of the current live list
     int32_t* freeq;
     int4* child;
     // scalars and logs
