@@ -178,7 +178,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--workload", default="m1_4k")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--mode", default="auto", choices=["auto", "kernels", "graph", "persistent"])
+    ap.add_argument("--mode", default="auto", choices=["auto", "kernels", "graph"])
     ap.add_argument("--chunk", type=int, default=100, help="steps per world_step call")
     ap.add_argument("--phase-steps", type=int, default=200, help="steps of the per-phase event pass")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
@@ -226,7 +226,7 @@ def main():
 
     # pick the launch mode and the act kernel's rows per round trip (both
     # leave every result unchanged) on a short calibration from the same state
-    modes = ["graph", "persistent", "kernels"] if args.mode == "auto" else [args.mode]
+    modes = ["graph", "kernels"] if args.mode == "auto" else [args.mode]
     calib = {}
     for m in modes:
         for rows in (8, 16, 32):

@@ -45,7 +45,6 @@ extern "C" {
 /* Execution modes of world_step / world_step_many. */
 #define WORLD_MODE_KERNELS 0      /* one launch per phase per step            */
 #define WORLD_MODE_GRAPH 1        /* K steps of phase launches in a HIP graph */
-#define WORLD_MODE_PERSISTENT 2   /* one cooperative launch runs all K steps  */
 
 /* Parameters of one world (App. B.4 hyperparameters, benchmark form).
  * Supported: H >= 2, W >= 1, H*W <= 2^26, 1 <= cap <= 2^20,

@@ -21,15 +21,29 @@ struct Batch {
     const int* pre;             // kPreKinds x (n + 1) block prefixes
     int n;
     int act_rows;               // act-kernel tuning: input rows per round trip (8, 16, 32)
+    const WorldDev* w0;         // n == 1: the descriptor itself (else null)
+    int cap0;                   // n == 1: its agent capacity
 };
 
 template <int ROWS>
-__device__ __forceinline__ void act_dispatch(const WorldDev& d, AgentRec* rec, int li, int64_t t, int lane) {
-    if (d.hd == 32) act_agent<32, ROWS>(d, rec, li, t, lane);
-    else act_agent<16, ROWS>(d, rec, li, t, lane);
+__device__ __forceinline__ void act_dispatch(DevRef d, AgentRec* rec, int4 rv, int li, int64_t t, int lane) {
+    if (d.hd == 32) act_agent<32, ROWS>(d, rec, rv, li, t, lane);
+    else act_agent<16, ROWS>(d, rec, rv, li, t, lane);
 }
 
-__device__ __forceinline__ int find_world(const int* pre, int n, int b) {
+// A block's world and its index among that world's blocks of one phase.  The
+// launch tables and descriptors are written by the host only, so they are
+// read through the scalar cache; the scalars and the per-position records
+// sit at fixed offsets from the descriptor.
+struct BlockWorld {
+    kptr<WorldDev> d;
+    WorldScal* S;
+    PosRec* P;
+    int lb;
+    int cap;
+};
+
+__device__ __forceinline__ int find_world(kptr<int> pre, int n, int b) {
     int lo = 0, hi = n;   // largest i with pre[i] <= b
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
@@ -39,8 +53,25 @@ __device__ __forceinline__ int find_world(const int* pre, int n, int b) {
     return lo;
 }
 
-// Block bodies, shared by the per-phase kernels and the persistent kernel.
-// `vb` is the block's index in the batch-wide numbering of its phase.
+__device__ __forceinline__ BlockWorld block_world(const Batch& bt, int kind, int vb) {
+    const WorldDev* p = bt.w0;
+    int lb = vb;
+    int cap = bt.cap0;
+    pin_s(cap);
+    if (p == nullptr) {
+        const kptr<int> pre = kconst(bt.pre) + kind * (bt.n + 1);
+        const int wi = find_world(pre, bt.n, vb);
+        p = kconst(bt.w)[wi];
+        lb = vb - pre[wi];
+        cap = kconst(p)->cap;
+    }
+    char* base = (char*)p;
+    return {kconst(p), reinterpret_cast<WorldScal*>(base + kScalOff), reinterpret_cast<PosRec*>(base + kPosOff), lb,
+            cap};
+}
+
+// Block bodies.  `vb` is the block's index in the batch-wide numbering of its
+// phase.
 
 // Act blocks of a world: kNewbornBlocks leading blocks create the children of
 // the previous step (rank r, r + kNewbornBlocks, ...) and run their first
@@ -48,15 +79,23 @@ __device__ __forceinline__ int find_world(const int* pre, int n, int b) {
 // remaining blocks run the controller of the other agents, four per block.
 template <int ROWS>
 __device__ __forceinline__ void act_body(const Batch& bt, int vb, int tid, StepShared& sh) {
-    const int* pre = bt.pre + kPreAct * (bt.n + 1);
-    const int wi = find_world(pre, bt.n, vb);
-    const WorldDev& d = *bt.w[wi];
-    const int lb = vb - pre[wi];
-    const WorldScal* S = d.scal;
-    const int64_t t = S->t;
-    const int n = S->n_live;
-    const int nc = S->n_child;
-    const int sel = S->live_sel;
+    const BlockWorld bw = block_world(bt, kPreAct, vb);
+    DevRef d = *bw.d;
+    PosRec* P = bw.P;
+    const int lb = bw.lb;
+    // the agent's record words in both lists, read together with the
+    // scalars (index clamped; the newborn blocks read theirs later)
+    const int li = (lb - kNewbornBlocks) * (kBlock / 64) + (tid >> 6);
+    const int lc = min(max(li, 0), bw.cap - 1);
+    const int4 q0 = *reinterpret_cast<const int4*>(&P[lc].r[0]);
+    const int4 q1 = *reinterpret_cast<const int4*>(&P[lc].r[1]);
+    const StepScal ss = read_step(bw.S);
+    pin(q0.x);
+    pin(q1.x);
+    const int64_t t = ss.t;
+    const int n = ss.n;
+    const int nc = ss.nc;
+    const int sel = ss.sel;
     if (lb < kNewbornBlocks) {
         if (lb == 0) {
             if (tid == 0) step_open(d, t);
@@ -68,48 +107,70 @@ __device__ __forceinline__ void act_body(const Batch& bt, int vb, int tid, StepS
             spawn_proj(d, rk, tid);
             __syncthreads();
             if (tid < 64) {
-                const int li = n - nc + rk;
-                act_dispatch<ROWS>(d, d.rec[sel] + li, li, t, tid);
+                const int lj = n - nc + rk;
+                const int4 rv = *reinterpret_cast<const int4*>(&P[lj].r[sel]);
+                act_dispatch<ROWS>(d, &P[lj].r[sel], rv, lj, t, tid);
             }
             __syncthreads();
         }
         return;
     }
-    const int li = (lb - kNewbornBlocks) * (kBlock / 64) + (tid >> 6);
     if (li >= n - nc) return;
-    act_dispatch<ROWS>(d, d.rec[sel] + li, li, t, tid & 63);
+    act_dispatch<ROWS>(d, &P[li].r[sel], sel ? q1 : q0, li, t, tid & 63);
 }
 
-__device__ __forceinline__ void move_body(const Batch& bt, int vb, int tid, StepShared& sh) {
-    const int* pre = bt.pre + kPreMove * (bt.n + 1);
-    const int wi = find_world(pre, bt.n, vb);
-    move_block(*bt.w[wi], vb - pre[wi], tid, sh);
-}
-
-// Claim blocks of a world: the claim tiles (look-back order), the regrowth
-// tiles, then one wave per survivor computing the recurrent projection for
-// the next act phase (the survivors are the first entries of the next live
-// list, whose count the move look-back has fixed).
-__device__ __forceinline__ void claim_body(const Batch& bt, int vb, int tid, StepShared& sh) {
-    const int* pre = bt.pre + kPreClaim * (bt.n + 1);
-    const int wi = find_world(pre, bt.n, vb);
-    const WorldDev& d = *bt.w[wi];
-    const int lb = vb - pre[wi];
-    const int ntile = (d.cap + kBlock - 1) / kBlock;
+// Move blocks of a world (one wave each): the move tiles (look-back order),
+// then one block per agent of the current live list computing the recurrent
+// projection W_hh h + b_hh of the hidden state the act phase has just
+// written.  Agents that die in this phase are projected too (unused); a
+// child that takes over their slot is projected when it is created.  The
+// first tile also records the step for the regrowth tiles of the claim
+// phase, which must not read the scalars the last claim tile rewrites.
+__device__ __forceinline__ void move_body(const Batch& bt, int vb, int lane) {
+    const BlockWorld bw = block_world(bt, kPreMove, vb);
+    DevRef d = *bw.d;
+    PosRec* P = bw.P;
+    const int lb = bw.lb;
+    const int ntile = (bw.cap + kTileN - 1) / kTileN;
     if (lb < ntile) {
-        claim_block(d, lb, tid, sh);
+        const int ci = min(lb * kTileN + lane, bw.cap - 1);
+        const AgentRec r0 = P[ci].r[0];
+        const AgentRec r1 = P[ci].r[1];
+        const StepScal ss = read_step(bw.S);
+        pin(r0.slot);
+        pin(r1.slot);
+        if (lb == 0 && lane == 0) bw.S->t_grow = ss.t;
+        move_block(d, P, lb, lane, ss, r0, r1);
         return;
     }
-    if (lb < ntile + d.ntiles) {
-        regrow_tile(d, lb - ntile, tid, sh);
+    const int li = lb - ntile;
+    const int lc = min(li, bw.cap - 1);
+    const int s0 = P[lc].r[0].slot;
+    const int s1 = P[lc].r[1].slot;
+    const StepScal ss = read_step(bw.S);
+    pin(s0);
+    pin(s1);
+    if (li >= ss.n) return;
+    const int slot = ss.sel ? s1 : s0;
+    if (d.hd == 32) proj_agent<32>(d, slot, lane);
+    else proj_agent<16>(d, slot, lane);
+}
+
+// Claim blocks of a world (one wave each): the claim tiles (look-back
+// order), then the regrowth tiles.
+__device__ __forceinline__ void claim_body(const Batch& bt, int vb, int lane, uint8_t* tile) {
+    const BlockWorld bw = block_world(bt, kPreClaim, vb);
+    DevRef d = *bw.d;
+    const int lb = bw.lb;
+    const int ntile = (bw.cap + kTileN - 1) / kTileN;
+    if (lb < ntile) {
+        const PostRec p = bw.P[min(lb * kTileN + lane, bw.cap - 1)].post;
+        const StepScal ss = read_step(bw.S);
+        pin(p.slot);
+        claim_block(d, bw.S, bw.P, lb, lane, ss, p);
         return;
     }
-    const int li = (lb - ntile - d.ntiles) * (kBlock / 64) + (tid >> 6);
-    const int surv = int(unpack_a(lookback_total(d.lb_move, ntile)));
-    if (li >= surv) return;
-    const int slot = d.live[d.scal->live_sel ^ 1][li];
-    if (d.hd == 32) proj_agent<32>(d, slot, tid & 63);
-    else proj_agent<16>(d, slot, tid & 63);
+    regrow_tile(d, lb - ntile, lane, tile, kconst(bw.S)->t_grow);
 }
 
 #ifndef ECO_ACT_WAVES
@@ -137,7 +198,7 @@ __global__ __launch_bounds__(kBlock) void k_act_rows(Batch bt) {
 // is read by the host); k_clear_pending then marks them as created, so the
 // next act phase treats them as ordinary agents.
 __global__ __launch_bounds__(kBlock) void k_materialize(const WorldDev* dp) {
-    const WorldDev& d = *dp;
+    DevRef d = *kconst(dp);
     const int nc = d.scal->n_child;
     for (int rk = blockIdx.x; rk < nc; rk += gridDim.x) {
         spawn_child(d, rk, threadIdx.x);
@@ -150,7 +211,7 @@ __global__ __launch_bounds__(kBlock) void k_materialize(const WorldDev* dp) {
 // Recurrent projections of every live agent of a world (after creation or a
 // load, when no move phase has produced them).
 __global__ __launch_bounds__(kBlock) void k_proj_all(const WorldDev* dp) {
-    const WorldDev& d = *dp;
+    DevRef d = *kconst(dp);
     const WorldScal* S = d.scal;
     const int li = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     if (li >= S->n_live) return;
@@ -166,24 +227,21 @@ __global__ void k_clear_pending(const WorldDev* dp) {
 // Sums the eaten / resource partials of a world's last step if still open.
 __global__ __launch_bounds__(kBlock) void k_close_counters(const WorldDev* dp) {
     __shared__ StepShared sh;
-    close_counters_in_step(*dp, threadIdx.x, sh);
+    close_counters_in_step(*kconst(dp), threadIdx.x, sh);
 }
 
-__global__ __launch_bounds__(kBlock) void k_move(Batch bt) {
-    __shared__ StepShared sh;
-    move_body(bt, blockIdx.x, threadIdx.x, sh);
-}
+__global__ __launch_bounds__(64) void k_move(Batch bt) { move_body(bt, blockIdx.x, threadIdx.x); }
 
-__global__ __launch_bounds__(kBlock) void k_claim(Batch bt) {
-    __shared__ StepShared sh;
-    claim_body(bt, blockIdx.x, threadIdx.x, sh);
+__global__ __launch_bounds__(64) void k_claim(Batch bt) {
+    __shared__ uint8_t tile[kHalo * kHalo];
+    claim_body(bt, blockIdx.x, threadIdx.x, tile);
 }
 
 // Initial genomes: agent slots [0, n_init) hold uids 0..n_init-1; parameter p
 // of uid u is std(p) * z_p with z_p lane p % 4 of INIT_W draw (u, 0, p / 4).
 __global__ __launch_bounds__(kBlock) void k_init_theta(const WorldDev* dp, int n_init, float std_ih,
                                                        float std_hd) {
-    const WorldDev& d = *dp;
+    DevRef d = *kconst(dp);
     const int64_t total = int64_t(n_init) * d.nblk;
     for (int64_t it = int64_t(blockIdx.x) * kBlock + threadIdx.x; it < total;
          it += int64_t(gridDim.x) * kBlock) {

@@ -66,7 +66,7 @@ __device__ __forceinline__ float sigmoidf_(float v) { return 1.0f / (1.0f + expf
 // by a fixed xor tree: the order depends on nothing but the agent.
 // ---------------------------------------------------------------------------
 template <int HD>
-__device__ __forceinline__ void proj_agent(const WorldDev& d, int slot, int lane) {
+__device__ __forceinline__ void proj_agent(DevRef d, int slot, int lane) {
     constexpr int G = 64 / HD;
     constexpr int RW = 3 * HD;
     constexpr int JJ = HD / G;
@@ -108,7 +108,7 @@ __device__ __forceinline__ void proj_agent(const WorldDev& d, int slot, int lane
 
 // A zero hidden state (new agents) projects to b_hh.
 template <int HD>
-__device__ __forceinline__ void proj_zero(const WorldDev& d, int slot, int lane) {
+__device__ __forceinline__ void proj_zero(DevRef d, int slot, int lane) {
     constexpr int RW = 3 * HD;
     if (lane < HD) {
         const float* pbh = d.theta + size_t(slot) * size_t(d.Ppad) + d.off_bhh + 3 * lane;
@@ -139,15 +139,14 @@ __device__ __forceinline__ void proj_zero(const WorldDev& d, int slot, int lane)
 // The recurrent projection comes precomputed from gh[slot].
 // ---------------------------------------------------------------------------
 template <int HD, int ROWS>
-__device__ __forceinline__ void act_agent(const WorldDev& d, AgentRec* recp, int li, int64_t t, int lane) {
+__device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int li, int64_t t, int lane) {
     constexpr int G = 64 / HD;
     constexpr int RW = 3 * HD;   // floats per input row
     constexpr int B = ROWS / G;  // input rows per group per round trip
     const int g = lane / HD;
     const int k = lane - g * HD;
     const int H = d.H, W = d.W;
-    const int4 rv = *reinterpret_cast<const int4*>(recp);   // slot, cell, energy, uid
-    const int slot = rv.x;
+    const int slot = rv.x;   // record words: slot, cell, energy, uid
     const int cell = rv.y;
     const int r = cell / W;
     const int c = cell - r * W;
@@ -295,19 +294,20 @@ __device__ __forceinline__ void act_agent(const WorldDev& d, AgentRec* recp, int
 }
 
 // Step-start bookkeeping done once per world per step by one thread.
-__device__ __forceinline__ void step_open(const WorldDev& d, int64_t t) {
+__device__ __forceinline__ void step_open(DevRef d, int64_t t) {
     if (d.log_steps > 0) d.log_n[t % d.log_steps] = d.scal->n_live;
 }
 
 // ---------------------------------------------------------------------------
-// Decoupled look-back prefix sum over the tiles of one phase (tile = one
-// block of kBlock live-list entries).  A status word packs
+// Decoupled look-back prefix sum over the tiles of one phase (tile = one wave
+// of kTileN live-list entries, one block).  A status word packs
 //   [epoch 20 | flag 2 | a 21 | b 21]   flag 1 = tile total, 2 = inclusive
 // where epoch = step mod 2^20, so words from earlier steps are ignored and the
-// arrays never need clearing between steps.  Returns the exclusive prefix of
-// the packed (a, b) pair; waits are bounded (2 s) and a time-out sets the
-// world's error word.
+// arrays never need clearing between steps.  Every lane returns the
+// exclusive prefix of the packed (a, b) pair; waits are bounded (2 s) and a
+// time-out sets the world's error word.
 // ---------------------------------------------------------------------------
+constexpr int kTileN = 64;   // live-list entries per move / claim tile
 constexpr int kCntBits = 21;
 constexpr uint64_t kCntMask = (uint64_t(1) << kCntBits) - 1;
 constexpr uint64_t kValMask = (uint64_t(1) << (2 * kCntBits)) - 1;
@@ -316,62 +316,53 @@ __device__ __forceinline__ uint64_t pack2(uint32_t a, uint32_t b) { return (uint
 __device__ __forceinline__ uint32_t unpack_a(uint64_t v) { return uint32_t((v >> kCntBits) & kCntMask); }
 __device__ __forceinline__ uint32_t unpack_b(uint64_t v) { return uint32_t(v & kCntMask); }
 
-__device__ __forceinline__ uint64_t lookback(const WorldDev& d, uint64_t* st, int tile, uint32_t epoch,
-                                             uint64_t local, int tid, uint64_t* s_bcast) {
-    // Wave 0 publishes this tile's total, then examines the predecessors 64 at
-    // a time (one status word per lane) until the nearest one holding an
-    // inclusive prefix: the prefix is that word plus the totals in between.
-    if (tid < 64) {
-        const int lane = tid;
-        const uint64_t tag = uint64_t(epoch & 0xFFFFFu);
-        if (lane == 0)
-            __hip_atomic_store(st + tile, (tag << 44) | (uint64_t(tile == 0 ? 2 : 1) << 42) | local,
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        uint64_t excl = 0;
-        int end = tile;
-        const uint64_t t0 = wall_clock64();
-        bool timed_out = false;
-        while (end > 0) {
-            const int k = end - 1 - lane;   // lane 0 = nearest predecessor
-            uint64_t v = 0;
-            uint32_t flag = 2;              // lanes past tile 0 act as an empty inclusive
-            if (k >= 0) {
-                while (true) {
-                    v = __hip_atomic_load(st + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    flag = uint32_t(v >> 42) & 3u;
-                    if ((v >> 44) == tag && flag != 0) break;
-                    if (wall_clock64() - t0 > 200000000ull) {   // 2 s at the 100 MHz wall clock
-                        timed_out = true;
-                        v = 0;
-                        flag = 2;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
+__device__ __forceinline__ uint64_t lookback(DevRef d, uint64_t* st, int tile, uint32_t epoch, uint64_t local,
+                                             int lane) {
+    // Publish this tile's total, then examine the predecessors 64 at a time
+    // (one status word per lane) until the nearest one holding an inclusive
+    // prefix: the prefix is that word plus the totals in between.
+    const uint64_t tag = uint64_t(epoch & 0xFFFFFu);
+    if (lane == 0)
+        __hip_atomic_store(st + tile, (tag << 44) | (uint64_t(tile == 0 ? 2 : 1) << 42) | local, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t excl = 0;
+    int end = tile;
+    const uint64_t t0 = wall_clock64();
+    bool timed_out = false;
+    while (end > 0) {
+        const int k = end - 1 - lane;   // lane 0 = nearest predecessor
+        uint64_t v = 0;
+        uint32_t flag = 2;              // lanes past tile 0 act as an empty inclusive
+        if (k >= 0) {
+            while (true) {
+                v = __hip_atomic_load(st + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                flag = uint32_t(v >> 42) & 3u;
+                if ((v >> 44) == tag && flag != 0) break;
+                if (wall_clock64() - t0 > 200000000ull) {   // 2 s at the 100 MHz wall clock
+                    timed_out = true;
+                    v = 0;
+                    flag = 2;
+                    break;
                 }
+                __builtin_amdgcn_s_sleep(1);
             }
-            const uint64_t val = (k >= 0) ? (v & kValMask) : 0;
-            const uint64_t incl = __ballot(flag == 2);
-            const int first = incl ? __builtin_ctzll(incl) : 64;   // nearest inclusive lane
-            uint64_t part = (lane <= first) ? val : 0;
+        }
+        const uint64_t val = (k >= 0) ? (v & kValMask) : 0;
+        const uint64_t incl = __ballot(flag == 2);
+        const int first = incl ? __builtin_ctzll(incl) : 64;   // nearest inclusive lane
+        uint64_t part = (lane <= first) ? val : 0;
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
-            excl += part;
-            if (incl) break;
-            end -= 64;
-        }
-        if (__ballot(timed_out) && lane == 0)
-            __hip_atomic_store(&d.scal->err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (lane == 0) {
-            if (tile != 0)
-                __hip_atomic_store(st + tile, (tag << 44) | (uint64_t(2) << 42) | (excl + local), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            *s_bcast = excl;
-        }
+        for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+        excl += part;
+        if (incl) break;
+        end -= 64;
     }
-    __syncthreads();
-    const uint64_t r = *s_bcast;
-    __syncthreads();
-    return r;
+    if (__ballot(timed_out) && lane == 0)
+        __hip_atomic_store(&d.scal->err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (lane == 0 && tile != 0)
+        __hip_atomic_store(st + tile, (tag << 44) | (uint64_t(2) << 42) | (excl + local), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    return excl;
 }
 
 // Inclusive total of the last tile of a completed look-back.
@@ -379,37 +370,16 @@ __device__ __forceinline__ uint64_t lookback_total(const uint64_t* st, int ntile
     return __hip_atomic_load(st + ntile - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kValMask;
 }
 
-// Block-local exclusive ranks of two predicates and the block totals.
-struct BlockRank {
-    int ra, rb;   // this thread's exclusive rank among the block's a / b
-    int ta, tb;   // block totals
+// Exclusive ranks of two predicates within the wave and the wave totals.
+struct WaveRank {
+    int ra, rb;   // this lane's exclusive rank among the wave's a / b
+    int ta, tb;   // wave totals
 };
 
-__device__ __forceinline__ BlockRank block_rank2(bool a, bool b, int tid, int* sw) {
-    const int lane = tid & 63, wv = tid >> 6;
-    constexpr int NW = kBlock / 64;
+__device__ __forceinline__ WaveRank wave_rank2(bool a, bool b, int lane) {
     const uint64_t ma = __ballot(a), mb = __ballot(b);
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    if (lane == 0) {
-        sw[wv] = __popcll(ma);
-        sw[NW + wv] = __popcll(mb);
-    }
-    __syncthreads();
-    BlockRank r;
-    r.ra = __popcll(ma & lt);
-    r.rb = __popcll(mb & lt);
-    r.ta = r.tb = 0;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) {
-        if (w < wv) {
-            r.ra += sw[w];
-            r.rb += sw[NW + w];
-        }
-        r.ta += sw[w];
-        r.tb += sw[NW + w];
-    }
-    __syncthreads();
-    return r;
+    return {int(__popcll(ma & lt)), int(__popcll(mb & lt)), int(__popcll(ma)), int(__popcll(mb))};
 }
 
 // ---------------------------------------------------------------------------
@@ -422,7 +392,7 @@ __device__ __forceinline__ BlockRank block_rank2(bool a, bool b, int tid, int* s
 // moves and deaths; occA (read by every agent in this phase) is untouched.
 // Returns bit 0 = ate, bit 1 = died.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int move_agent(const WorldDev& d, const AgentRec& a, int64_t t, PostRec* post,
+__device__ __forceinline__ int move_agent(DevRef d, const AgentRec& a, int64_t t, PostRec* post,
                                           AgentRec* next_rec_src) {
     const int W = d.W, H = d.H;
     const int slot = a.slot;
@@ -461,15 +431,15 @@ __device__ __forceinline__ int move_agent(const WorldDev& d, const AgentRec& a, 
     // Both occupancy grids take the moves and deaths (neither is read in this
     // phase): occA is the next step's start state, occB is read by P3.  A
     // survivor's occB word also says whether it is eligible to reproduce and
-    // from which direction its birth scan starts; its birth key is stored per
-    // slot, so P3 learns a neighbour's claim from occupancy reads alone.
+    // from which direction its birth scan starts; its birth key is stored at
+    // its cell, so P3 learns a neighbour's claim from reads by cell alone.
     int word = -1;
     if (!dead) {
         word = slot;
         if (st >= d.T_repr) {
             const Draw4 b = philox(u, uint32_t(t), kBirth, 0, d.seed_lo, d.seed_hi);
             word |= kOccElig | int((b.x & 3u) << kOccDirShift);
-            d.bkey[slot] = claim_key(b.y, u);
+            d.bkey[newX] = claim_key(b.y, u);
         }
     }
     if (newX != X) {
@@ -503,72 +473,119 @@ __device__ __forceinline__ int move_agent(const WorldDev& d, const AgentRec& a, 
     return ate | (dead ? 2 : 0);
 }
 
-struct StepShared {
-    uint8_t tile[(kTile + 4) * (kTile + 4)];
-    int sw[2 * (kBlock / 64)];
-    uint64_t bcast;
-    int flag;
+// The world scalars a block works with, read once at its start.
+struct StepScal {
+    int64_t t;
+    int n, sel, nc;
+    uint32_t next_uid;
+    int free_head, free_tail;
 };
 
-// P2 for tile `j` (kBlock live-list entries) of one world.  Survivors keep
-// their uid order in the next live list; dead slots are listed in uid order.
-__device__ __forceinline__ void move_block(const WorldDev& d, int j, int tid, StepShared& sh) {
-    const WorldScal* S = d.scal;
-    const int n = S->n_live;
-    const int sel = S->live_sel;
-    const int64_t t = S->t;
-    const int i = j * kBlock + tid;
+template <class P>
+__device__ __forceinline__ StepScal read_step_from(P S) {
+    StepScal s;
+    s.t = S->t;
+    s.n = S->n_live;
+    s.sel = S->live_sel;
+    s.nc = S->n_child;
+    s.next_uid = S->next_uid;
+    s.free_head = S->free_head;
+    s.free_tail = S->free_tail;
+    return s;
+}
+
+// Completes a load at this point, so that it stays among the loads issued
+// together at a block's start instead of being moved into the branch that
+// uses it (which would add a dependent round trip).  pin: per-lane values,
+// pin_s: uniform values.
+__device__ __forceinline__ void pin(int v) { asm volatile("" ::"v"(v)); }
+__device__ __forceinline__ void pin_s(int v) { asm volatile("" ::"s"(v)); }
+__device__ __forceinline__ void pin64(uint64_t v) { asm volatile("" ::"v"(v)); }
+
+// The scalars through the scalar cache: no block writes them before every
+// block of the same kernel has read them (the closing claim tile runs last,
+// and the regrowth tiles read t_grow, which it does not write).
+__device__ __forceinline__ StepScal read_step(const WorldScal* S) {
+    const StepScal s = read_step_from(kconst(S));
+    pin_s(int(s.t));
+    pin_s(s.n);
+    pin_s(s.sel);
+    pin_s(s.nc);
+    return s;
+}
+
+struct StepShared {
+    int sw[2 * (kBlock / 64)];
+};
+
+// P2 for tile `j` (kTileN live-list entries, one wave) of one world.
+// Survivors keep their uid order in the next live list; dead slots are
+// listed in uid order.  `r0` / `r1`: this lane's entry of both record lists,
+// read before the scalars arrived.
+__device__ __forceinline__ void move_block(DevRef d, PosRec* P, int j, int lane, const StepScal& ss,
+                                           const AgentRec& r0, const AgentRec& r1) {
+    const int i = j * kTileN + lane;
+    const int n = ss.n;
+    const int sel = ss.sel;
+    const int64_t t = ss.t;
     int res = 0;
     AgentRec nr;
     nr.slot = -1;
-    if (i < n) res = move_agent(d, d.rec[sel][i], t, d.post + i, &nr);
+    if (i < n) res = move_agent(d, sel ? r1 : r0, t, &P[i].post, &nr);
     const bool alive = i < n && !(res & 2);
     const bool dead = i < n && (res & 2);
     const int cnt = __popcll(__ballot((res & 1) != 0));
-    if ((tid & 63) == 0) d.eat_part[i >> 6] = cnt;
-    const BlockRank br = block_rank2(alive, dead, tid, sh.sw);
-    const uint64_t ex = lookback(d, d.lb_move, j, uint32_t(t), pack2(br.ta, br.tb), tid, &sh.bcast);
+    if (lane == 0) d.eat_part[j] = cnt;
+    const WaveRank wr = wave_rank2(alive, dead, lane);
+    const uint64_t ex = lookback(d, d.lb_move, j, uint32_t(t), pack2(wr.ta, wr.tb), lane);
     if (alive) {
-        const int pos = int(unpack_a(ex)) + br.ra;
+        const int pos = int(unpack_a(ex)) + wr.ra;
         d.live[sel ^ 1][pos] = nr.slot;
-        d.rec[sel ^ 1][pos] = nr;
-        d.post[i].next_pos = pos;
+        P[pos].r[sel ^ 1] = nr;
+        P[i].post.next_pos = pos;
     }
-    if (dead) d.deadlist[unpack_b(ex) + br.rb] = nr.slot;
+    if (dead) d.deadlist[unpack_b(ex) + wr.rb] = nr.slot;
 }
 
-// First free in-grid 4-neighbour of `cell` (order N, S, E, W cyclically from
-// `d0`) in the post-move, post-death occupancy; -1 if none.  The four
-// occupancy words are loaded together.
-__device__ __forceinline__ int birth_target(const WorldDev& d, int cell, int d0) {
-    const int W = d.W, H = d.H;
-    const int r = cell / W, c = cell - (cell / W) * W;
-    int nb[4];
-    bool freec[4];
-#pragma unroll
-    for (int dd = 0; dd < 4; ++dd) {
-        const int nr = r + act_dr(dd), nc = c + act_dc(dd);
-        const bool in = nr >= 0 && nr < H && nc >= 0 && nc < W;
-        nb[dd] = nr * W + nc;
-        freec[dd] = in && d.occB[in ? nb[dd] : cell] == -1;
-    }
-    int C = -1;
+// Direction of the first free cell among the four neighbours of the cell at
+// offset (OY, OX), scanned N, S, E, W cyclically from `d0`; -1 if none.  `fr`
+// is the free map of the radius-3 neighbourhood of the claiming agent.
+template <int OY, int OX>
+__device__ __forceinline__ int first_free_dir(const bool (&fr)[7][7], int d0) {
+    int dir = -1;
 #pragma unroll
     for (int k = 3; k >= 0; --k) {
-        const int dd = (d0 + k) & 3;
-        if (freec[dd]) C = nb[dd];
+#pragma unroll
+        for (int dd = 0; dd < 4; ++dd) {
+            const bool f = fr[OY + 3 + (dd == 0 ? -1 : (dd == 1 ? 1 : 0))][OX + 3 + (dd == 2 ? 1 : (dd == 3 ? -1 : 0))];
+            if (((d0 + k) & 3) == dd && f) dir = dd;
+        }
     }
-    return C;
+    return dir;
+}
+
+// Does the agent whose post-move occB word is `v`, at offset (MY, MX) of the
+// claimant, claim its neighbour in direction BACK?  Only an eligible agent
+// claims; its claim is the first free neighbour from its own scan start,
+// recomputed from the same free map.
+template <int MY, int MX, int BACK>
+__device__ __forceinline__ bool rival_claims(const bool (&fr)[7][7], int v) {
+    if (v < 0 || !(v & kOccElig)) return false;
+    return first_free_dir<MY, MX>(fr, (v >> kOccDirShift) & 3) == BACK;
 }
 
 // ---------------------------------------------------------------------------
 // P3a: clear this agent's move-claim word, then, for an eligible survivor,
 // compute its birth claim and resolve it against the other eligible agents
-// next to the claimed cell: their occB words give eligibility and scan start,
-// their claims are recomputed from occB, their keys come from bkey.
+// next to the claimed cell.  A birth claim is the first free in-grid
+// 4-neighbour (post-move, post-death occupancy) from the agent's scan start;
+// a rival claiming the same cell sits two steps away and its own claim
+// depends on cells up to three steps away, so the occB words of the whole
+// radius-3 diamond (24 cells) and the birth keys of the 8 cells at distance
+// 2 are loaded together, and the resolution is computed from them.
 // Returns the claimed cell of a claim winner, -1 otherwise.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int claim_agent(const WorldDev& d, const PostRec& p, int64_t t) {
+__device__ __forceinline__ int claim_agent(DevRef d, const PostRec& p, int64_t t) {
     const int X = p.prev_cell;
     const int X2 = p.cell;
     const bool alive = p.alive != 0;
@@ -583,73 +600,117 @@ __device__ __forceinline__ int claim_agent(const WorldDev& d, const PostRec& p, 
     int C = -1;
     bool won = false;
     if (alive && p.streak >= d.T_repr) {
+        const int W = d.W, H = d.H;
+        const int r = X2 / W, c = X2 - (X2 / W) * W;
+        // occB words of the diamond (-2 outside the grid; the agent's own
+        // cell is occupied by itself) and the keys at distance 2
+        int occ[7][7];
+        uint64_t kc[7][7];
+#pragma unroll
+        for (int dy = -3; dy <= 3; ++dy) {
+#pragma unroll
+            for (int dx = -3; dx <= 3; ++dx) {
+                const int m = (dy < 0 ? -dy : dy) + (dx < 0 ? -dx : dx);
+                occ[dy + 3][dx + 3] = 0;
+                kc[dy + 3][dx + 3] = 0;
+                if (m == 0 || m > 3) continue;
+                const int rr = r + dy, cc = c + dx;
+                const bool in = rr >= 0 && rr < H && cc >= 0 && cc < W;
+                const int q = in ? rr * W + cc : X2;
+                const int v = d.occB[q];
+                occ[dy + 3][dx + 3] = in ? v : -2;
+                if (m == 2) kc[dy + 3][dx + 3] = d.bkey[q];
+            }
+        }
+        // one round trip for the whole neighbourhood
+#pragma unroll
+        for (int y = 0; y < 7; ++y)
+#pragma unroll
+            for (int x = 0; x < 7; ++x) {
+                const int m = (y < 3 ? 3 - y : y - 3) + (x < 3 ? 3 - x : x - 3);
+                if (m == 0 || m > 3) continue;
+                pin(occ[y][x]);
+                if (m == 2) pin64(kc[y][x]);
+            }
+        bool fr[7][7];
+#pragma unroll
+        for (int y = 0; y < 7; ++y)
+#pragma unroll
+            for (int x = 0; x < 7; ++x) fr[y][x] = occ[y][x] == -1;
         const uint32_t u = p.uid;
         const Draw4 b = philox(u, uint32_t(t), kBirth, 0, d.seed_lo, d.seed_hi);
-        C = birth_target(d, X2, int(b.x & 3u));
-        if (C >= 0) {
+        const int cdir = first_free_dir<0, 0>(fr, int(b.x & 3u));
+        if (cdir >= 0) {
             const uint64_t key = claim_key(b.y, u);
             won = true;
-            const int W = d.W, H = d.H;
-            const int cr = C / W, cc = C - (C / W) * W;
-            int M[4], v[4];
-#pragma unroll
-            for (int dd = 0; dd < 4; ++dd) {
-                const int mr = cr + act_dr(dd), mc = cc + act_dc(dd);
-                const bool in = mr >= 0 && mr < H && mc >= 0 && mc < W;
-                M[dd] = mr * W + mc;
-                v[dd] = (in && M[dd] != X2) ? d.occB[M[dd]] : -1;
-            }
-#pragma unroll
-            for (int dd = 0; dd < 4; ++dd) {
-                if (v[dd] < 0 || !(v[dd] & kOccElig)) continue;
-                const int o = v[dd] & kOccSlotMask;
-                const uint64_t ko = d.bkey[o];
-                if (birth_target(d, M[dd], (v[dd] >> kOccDirShift) & 3) != C) continue;
-                if (ko < key) won = false;
-            }
+            // rivals around C = own cell + e1: at e1 + e2 for the three e2
+            // that do not lead back to the own cell; each claims C iff its
+            // first free neighbour lies in direction -e2
+#define ECO_RIVAL(E1, DY1, DX1, E2, DY2, DX2, BACK)                                                  \
+    if (cdir == E1) {                                                                                \
+        const int v_ = occ[DY1 + DY2 + 3][DX1 + DX2 + 3];                                           \
+        if (rival_claims<DY1 + DY2, DX1 + DX2, BACK>(fr, v_) && kc[DY1 + DY2 + 3][DX1 + DX2 + 3] < key) \
+            won = false;                                                                             \
+    }
+            // directions: 0 = N (-1, 0), 1 = S (+1, 0), 2 = E (0, +1), 3 = W (0, -1)
+            ECO_RIVAL(0, -1, 0, 0, -1, 0, 1)
+            ECO_RIVAL(0, -1, 0, 2, 0, 1, 3)
+            ECO_RIVAL(0, -1, 0, 3, 0, -1, 2)
+            ECO_RIVAL(1, 1, 0, 1, 1, 0, 0)
+            ECO_RIVAL(1, 1, 0, 2, 0, 1, 3)
+            ECO_RIVAL(1, 1, 0, 3, 0, -1, 2)
+            ECO_RIVAL(2, 0, 1, 2, 0, 1, 3)
+            ECO_RIVAL(2, 0, 1, 0, -1, 0, 1)
+            ECO_RIVAL(2, 0, 1, 1, 1, 0, 0)
+            ECO_RIVAL(3, 0, -1, 3, 0, -1, 2)
+            ECO_RIVAL(3, 0, -1, 0, -1, 0, 1)
+            ECO_RIVAL(3, 0, -1, 1, 1, 0, 0)
+#undef ECO_RIVAL
+            C = (r + act_dr(cdir)) * W + (c + act_dc(cdir));
         }
     }
     d.claim[p.slot] = C;
     return won ? C : -1;
 }
 
-// P3a for tile `j` of one world.  The winner of global rank r (uid order) is
-// born iff r < cap - survivors; its child takes free slot r of the ring if the
-// ring holds more than r slots, else the (r - free)-th slot freed this step.
-// The last claim tile to finish closes the step (counts, free ring, scalars).
-__device__ __forceinline__ void claim_block(const WorldDev& d, int j, int tid, StepShared& sh) {
-    WorldScal* S = d.scal;
-    const int n = S->n_live;
-    const int sel = S->live_sel;
-    const int64_t t = S->t;
+// P3a for tile `j` (kTileN live-list entries, one wave) of one world.  The
+// winner of global rank r (uid order) is born iff r < cap - survivors; its
+// child takes free slot r of the ring if the ring holds more than r slots,
+// else the (r - free)-th slot freed this step.  The last claim tile to finish
+// closes the step (counts, free ring, scalars).  `p`: this lane's post-move
+// record, read before the scalars arrived.
+__device__ __forceinline__ void claim_block(DevRef d, WorldScal* S, PosRec* P, int j, int lane, const StepScal& ss,
+                                            const PostRec& p) {
     const int cap = d.cap;
-    const int ntile = (cap + kBlock - 1) / kBlock;
-    const int i = j * kBlock + tid;
+    const int i = j * kTileN + lane;
+    const int n = ss.n;
+    const int sel = ss.sel;
+    const int64_t t = ss.t;
+    const int ntile = (cap + kTileN - 1) / kTileN;
     int slot = -1, cell = -1, pos = -1;
     bool win = false;
     if (i < n) {
-        const PostRec p = d.post[i];
         slot = p.slot;
         pos = p.next_pos;
         cell = claim_agent(d, p, t);
         win = cell >= 0;
     }
-    const BlockRank br = block_rank2(win, false, tid, sh.sw);
-    const uint64_t ex = lookback(d, d.lb_claim, j, uint32_t(t), pack2(br.ta, 0), tid, &sh.bcast);
+    const WaveRank wr = wave_rank2(win, false, lane);
+    const uint64_t ex = lookback(d, d.lb_claim, j, uint32_t(t), pack2(wr.ta, 0), lane);
     const int surv = int(unpack_a(lookback_total(d.lb_move, ntile)));
     const int nfree = cap - n;
     if (win) {
-        const int rk = int(unpack_a(ex)) + br.ra;
+        const int rk = int(unpack_a(ex)) + wr.ra;
         if (rk < cap - surv) {
             int cs;
             if (rk < nfree) {
-                int q = S->free_head + rk;
+                int q = ss.free_head + rk;
                 if (q >= cap) q -= cap;
                 cs = d.freeq[q];
             } else {
                 cs = d.deadlist[rk - nfree];
             }
-            const uint32_t cu = S->next_uid + uint32_t(rk);
+            const uint32_t cu = ss.next_uid + uint32_t(rk);
             d.child[rk] = make_int4(cs, slot, cell, int(cu));
             d.live[sel ^ 1][surv + rk] = cs;
             AgentRec cr;
@@ -661,38 +722,34 @@ __device__ __forceinline__ void claim_block(const WorldDev& d, int j, int tid, S
             cr.streak = 0;
             cr.action = 4;
             cr.pad = 0;
-            d.rec[sel ^ 1][surv + rk] = cr;
+            P[surv + rk].r[sel ^ 1] = cr;
             d.occA[cell] = cs;   // occA is neither read nor written by others in this phase
             // the parent's streak restarts (no phase reads these in P3)
-            d.rec[sel ^ 1][pos].streak = 0;
+            P[pos].r[sel ^ 1].streak = 0;
             d.streak[slot] = 0;
         }
     }
-    // completion: the last tile to get here closes the step
-    __syncthreads();
-    if (tid == 0) {
-        // Relaxed: the closing block reads only look-back words (atomics) and
-        // data of earlier phases; the counter orders its writes of the
-        // scalars after every tile's reads of them.
-        const uint32_t prev = __hip_atomic_fetch_add(d.done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        sh.flag = (prev == uint32_t(ntile - 1)) ? 1 : 0;
-    }
-    __syncthreads();
-    if (!sh.flag) return;
+    // completion: the last tile to get here closes the step.  Relaxed: the
+    // closing tile reads only look-back words (atomics) and data of earlier
+    // phases; the counter orders its writes of the scalars after every
+    // tile's reads of them.
+    uint32_t prev = 0;
+    if (lane == 0) prev = __hip_atomic_fetch_add(d.done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    prev = __shfl(prev, 0);
+    if (prev != uint32_t(ntile - 1)) return;
     const int wins = int(unpack_a(lookback_total(d.lb_claim, ntile)));
     const int dead = n - surv;
     const int nb = min(wins, cap - surv);
     const int consumed = max(0, nb - nfree);
-    const int ft = S->free_tail;
-    for (int q = consumed + tid; q < dead; q += kBlock) {
-        int pos = ft + q - consumed;
-        if (pos >= cap) pos -= cap;
-        d.freeq[pos] = d.deadlist[q];
+    const int ft = ss.free_tail;
+    for (int q = consumed + lane; q < dead; q += kTileN) {
+        int fpos = ft + q - consumed;
+        if (fpos >= cap) fpos -= cap;
+        d.freeq[fpos] = d.deadlist[q];
     }
-    __syncthreads();
-    if (tid == 0) {
+    if (lane == 0) {
         __hip_atomic_store(d.done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        int nfh = S->free_head + min(nb, nfree);
+        int nfh = ss.free_head + min(nb, nfree);
         if (nfh >= cap) nfh -= cap;
         int nft = ft + (dead - consumed);
         if (nft >= cap) nft -= cap;
@@ -705,7 +762,7 @@ __device__ __forceinline__ void claim_block(const WorldDev& d, int j, int tid, S
         S->free_head = nfh;
         S->free_tail = nft;
         S->n_live = surv + nb;
-        S->next_uid = S->next_uid + uint32_t(nb);
+        S->next_uid = ss.next_uid + uint32_t(nb);
         S->live_sel = sel ^ 1;
         S->n_child = nb;
         S->spawn_t = t;
@@ -715,46 +772,51 @@ __device__ __forceinline__ void claim_block(const WorldDev& d, int j, int tid, S
 }
 
 // ---------------------------------------------------------------------------
-// P3b: regrowth of one kTile x kTile tile (one block).  The tile plus a
-// 2-cell halo of the post-eating grid is staged in LDS; an empty cell counts
-// the resources among its 24 neighbours and grows iff its REGROW draw is
-// below thr[row][count].  Writes the other grid buffer (synchronous update)
-// and the tile's resource count.
+// P3b: regrowth of one kTile x kTile tile (one wave, four cells per lane).
+// The tile plus a 2-cell halo of the post-eating grid is staged in LDS; an
+// empty cell counts the resources among its 24 neighbours and grows iff its
+// REGROW draw is below thr[row][count].  Writes the other grid buffer
+// (synchronous update) and the tile's resource count.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void regrow_tile(const WorldDev& d, int tile, int tid, StepShared& sh) {
-    constexpr int E = kTile + 4;
-    const int64_t t = d.scal->t;
-    uint8_t* s = sh.tile;
+constexpr int kHalo = kTile + 4;
+
+__device__ __forceinline__ void regrow_tile(DevRef d, int tile, int lane, uint8_t* s, int64_t t) {
+    constexpr int E = kHalo;
     const int ntx = (d.W + kTile - 1) / kTile;
     const int ty0 = (tile / ntx) * kTile;
     const int tx0 = (tile - (tile / ntx) * ntx) * kTile;
     const uint8_t* Rc = d.R[t & 1];
     uint8_t* Rn = d.R[(t + 1) & 1];
-    for (int idx = tid; idx < E * E; idx += kBlock) {
+    for (int idx = lane; idx < E * E; idx += 64) {
         const int ly = idx / E, lx = idx - (idx / E) * E;
         const int gy = ty0 + ly - 2, gx = tx0 + lx - 2;
         s[idx] = (gy >= 0 && gy < d.H && gx >= 0 && gx < d.W) ? Rc[gy * d.W + gx] : uint8_t(0);
     }
     __syncthreads();
-    const int ly = tid / kTile, lx = tid - (tid / kTile) * kTile;
-    const int gy = ty0 + ly, gx = tx0 + lx;
-    int v = 0;
-    if (gy < d.H && gx < d.W) {
-        const int q = gy * d.W + gx;
-        v = s[(ly + 2) * E + lx + 2];
-        if (!v) {
-            int cnt = 0;
+    int total = 0;
 #pragma unroll
-            for (int dy = 0; dy < 5; ++dy)
+    for (int part = 0; part < kTile * kTile / 64; ++part) {
+        const int c = part * 64 + lane;
+        const int ly = c / kTile, lx = c - (c / kTile) * kTile;
+        const int gy = ty0 + ly, gx = tx0 + lx;
+        int v = 0;
+        if (gy < d.H && gx < d.W) {
+            const int q = gy * d.W + gx;
+            v = s[(ly + 2) * E + lx + 2];
+            if (!v) {
+                int cnt = 0;
 #pragma unroll
-                for (int dx = 0; dx < 5; ++dx) cnt += s[(ly + dy) * E + lx + dx];
-            const Draw4 dr = philox(uint32_t(q), uint32_t(t), kRegrow, 0, d.seed_lo, d.seed_hi);
-            v = uint64_t(dr.x) < d.thr[gy * 25 + cnt] ? 1 : 0;
+                for (int dy = 0; dy < 5; ++dy)
+#pragma unroll
+                    for (int dx = 0; dx < 5; ++dx) cnt += s[(ly + dy) * E + lx + dx];
+                const Draw4 dr = philox(uint32_t(q), uint32_t(t), kRegrow, 0, d.seed_lo, d.seed_hi);
+                v = uint64_t(dr.x) < d.thr[gy * 25 + cnt] ? 1 : 0;
+            }
+            Rn[q] = uint8_t(v);
         }
-        Rn[q] = uint8_t(v);
+        total += __popcll(__ballot(v != 0));
     }
-    const BlockRank br = block_rank2(v != 0, false, tid, sh.sw);
-    if (tid == 0) d.res_part[tile] = br.ta;
+    if (lane == 0) d.res_part[tile] = total;
 }
 
 // ---------------------------------------------------------------------------
@@ -766,7 +828,7 @@ __device__ __forceinline__ void regrow_tile(const WorldDev& d, int tile, int tid
 // Every store is complete when this returns, so the same block can run the
 // child's controller right after a block barrier.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void spawn_child(const WorldDev& d, int rk, int tid) {
+__device__ __forceinline__ void spawn_child(DevRef d, int rk, int tid) {
     const int4 rec = d.child[rk];   // child slot, parent slot, cell, uid
     const uint32_t ts = uint32_t(d.scal->spawn_t);
     const float* par = d.theta + size_t(rec.y) * size_t(d.Ppad);
@@ -803,7 +865,7 @@ __device__ __forceinline__ void spawn_child(const WorldDev& d, int rk, int tid) 
 }
 
 // Recurrent projection of a new agent (after spawn_child and a barrier).
-__device__ __forceinline__ void spawn_proj(const WorldDev& d, int rk, int tid) {
+__device__ __forceinline__ void spawn_proj(DevRef d, int rk, int tid) {
     if (tid < 64) {
         const int cs = d.child[rk].x;
         if (d.hd == 32) proj_zero<32>(d, cs, tid);
@@ -813,7 +875,7 @@ __device__ __forceinline__ void spawn_proj(const WorldDev& d, int rk, int tid) {
 }
 
 // Eaten and resource totals of the step just closed (one block per world).
-__device__ __forceinline__ void close_counters(const WorldDev& d, int tid, StepShared& sh) {
+__device__ __forceinline__ void close_counters(DevRef d, int tid, StepShared& sh) {
     WorldScal* S = d.scal;
     if (!S->ctr_open) return;
     const int nwv = (S->n_prev + 63) / 64;
@@ -845,7 +907,7 @@ __device__ __forceinline__ void close_counters(const WorldDev& d, int tid, StepS
 
 // P1 bookkeeping by the first block of a world: sum the eaten / resource
 // partials of the previous step (written by its P2 and P3).
-__device__ __forceinline__ void close_counters_in_step(const WorldDev& d, int tid, StepShared& sh) {
+__device__ __forceinline__ void close_counters_in_step(DevRef d, int tid, StepShared& sh) {
     close_counters(d, tid, sh);
     if (tid == 0) d.scal->ctr_open = 0;
 }

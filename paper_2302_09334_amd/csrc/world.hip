@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cassert>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -14,7 +15,6 @@
 
 #include "world.h"
 #include "kernels.h"
-#include "persistent.h"
 
 using namespace eco;
 
@@ -75,8 +75,8 @@ const char* check_config(const world_config* c) {
 struct Layout {
     size_t desc, scal, ring, batch, thr, R0, R1, occA, occB, mclaim;
     size_t uid, cell, prev_cell, energy, age, streak, action, alive, win, claim, bkey;
-    size_t live0, live1, rec0, rec1, post, freeq, child, h, gh, theta;
-    size_t log_uid, log_act, log_logits, log_n, barrier, eat_part, res_part, deadlist, lb_move, lb_claim, done;
+    size_t live0, live1, pos, freeq, child, h, gh, theta;
+    size_t log_uid, log_act, log_logits, log_n, eat_part, res_part, deadlist, lb_move, lb_claim, done;
     size_t total;
 };
 
@@ -94,15 +94,16 @@ Layout layout_of(const world_config& c) {
     };
     l.desc = take(sizeof(WorldDev));
     l.scal = take(sizeof(WorldScal));
+    l.pos = take(sizeof(PosRec) * cap);
     l.ring = take(sizeof(int32_t) * kRing * kCtrWords);
     l.batch = take(256);   // single-world launch table
-    l.barrier = take(64);
     l.thr = take(sizeof(uint64_t) * size_t(c.H) * 25);
     l.R0 = take(HW);
     l.R1 = take(HW);
     l.occA = take(4 * HW);
     l.occB = take(4 * HW);
     l.mclaim = take(8 * HW);
+    l.bkey = take(8 * HW);
     l.uid = take(4 * cap);
     l.cell = take(4 * cap);
     l.prev_cell = take(4 * cap);
@@ -113,12 +114,8 @@ Layout layout_of(const world_config& c) {
     l.alive = take(cap);
     l.win = take(cap);
     l.claim = take(4 * cap);
-    l.bkey = take(8 * cap);
     l.live0 = take(4 * cap);
     l.live1 = take(4 * cap);
-    l.rec0 = take(sizeof(AgentRec) * cap);
-    l.rec1 = take(sizeof(AgentRec) * cap);
-    l.post = take(sizeof(PostRec) * cap);
     l.freeq = take(4 * cap);
     l.child = take(16 * cap);
     l.h = take(4 * cap * size_t(c.hidden));
@@ -130,11 +127,13 @@ Layout layout_of(const world_config& c) {
     l.log_n = take(4 * L);
     l.eat_part = take(4 * (cap / 64 + 1));
     l.deadlist = take(4 * cap);
-    l.lb_move = take(8 * ((cap + kBlock - 1) / kBlock));
-    l.lb_claim = take(8 * ((cap + kBlock - 1) / kBlock));
+    l.lb_move = take(8 * ((cap + kTileN - 1) / kTileN));
+    l.lb_claim = take(8 * ((cap + kTileN - 1) / kTileN));
     l.done = take(64);
     l.res_part = take(4 * size_t(((c.H + kTile - 1) / kTile) * ((c.W + kTile - 1) / kTile)));
     l.total = o;
+    static_assert(kArenaAlign == kAlign, "arena alignment");
+    assert(l.scal == kScalOff && l.pos == kPosOff);
     return l;
 }
 
@@ -204,7 +203,7 @@ int fail(world* w, int code, const std::string& msg) {
     } while (0)
 
 int blocks_act(const world_config& c) { return (c.cap + kBlock / 64 - 1) / (kBlock / 64); }
-int blocks_agent(const world_config& c) { return (c.cap + kBlock - 1) / kBlock; }
+int tiles_agent(const world_config& c) { return (c.cap + kTileN - 1) / kTileN; }   // move / claim tiles
 int tiles_of(const world_config& c) {
     return ((c.H + kTile - 1) / kTile) * ((c.W + kTile - 1) / kTile);
 }
@@ -216,8 +215,8 @@ std::vector<int> batch_prefix(const std::vector<const world*>& ws) {
     for (int i = 0; i < n; ++i) {
         const world_config& c = ws[i]->cfg;
         pre[kPreAct * (n + 1) + i + 1] = pre[kPreAct * (n + 1) + i] + kNewbornBlocks + blocks_act(c);
-        pre[kPreMove * (n + 1) + i + 1] = pre[kPreMove * (n + 1) + i] + blocks_agent(c);
-        pre[kPreClaim * (n + 1) + i + 1] = pre[kPreClaim * (n + 1) + i] + blocks_agent(c) + tiles_of(c) + blocks_act(c);
+        pre[kPreMove * (n + 1) + i + 1] = pre[kPreMove * (n + 1) + i] + tiles_agent(c) + c.cap;
+        pre[kPreClaim * (n + 1) + i + 1] = pre[kPreClaim * (n + 1) + i] + tiles_agent(c) + tiles_of(c);
     }
     return pre;
 }
@@ -232,8 +231,8 @@ void launch_act(const Batch& b, int grid, hipStream_t s) {
 hipError_t launch_step(const Batch& b, const int* host_pre, int n, hipStream_t s) {
     const int np = n + 1;
     launch_act(b, host_pre[kPreAct * np + n], s);
-    hipLaunchKernelGGL(k_move, dim3(host_pre[kPreMove * np + n]), dim3(kBlock), 0, s, b);
-    hipLaunchKernelGGL(k_claim, dim3(host_pre[kPreClaim * np + n]), dim3(kBlock), 0, s, b);
+    hipLaunchKernelGGL(k_move, dim3(host_pre[kPreMove * np + n]), dim3(64), 0, s, b);
+    hipLaunchKernelGGL(k_claim, dim3(host_pre[kPreClaim * np + n]), dim3(64), 0, s, b);
     return hipGetLastError();
 }
 
@@ -254,7 +253,7 @@ int check_device_error(world* w) {
     HIP_TRY(w, hipMemcpyAsync(&sc, w->base + w->lay.scal, sizeof(sc), hipMemcpyDeviceToHost, w->stream));
     HIP_TRY(w, hipStreamSynchronize(w->stream));
     if (sc.err != 0)
-        return fail(w, WORLD_E_HIP, std::string(sc.err == 1 ? "grid barrier" : "look-back scan") +
+        return fail(w, WORLD_E_HIP, std::string("look-back scan") +
                                         " wait timed out on the device");
     return WORLD_OK;
 }
@@ -269,17 +268,6 @@ int wall_rate_khz() {
         if (rate <= 0) rate = 100000;
     });
     return rate;
-}
-
-int persistent_blocks_per_cu() {
-    static int nb = 0;
-    static std::once_flag once;
-    std::call_once(once, [] {
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_persistent), kBlock,
-                                                          0) != hipSuccess || nb < 1)
-            nb = 1;
-    });
-    return nb;
 }
 
 // Device table of a batch: world pointers and per-phase block prefixes.
@@ -314,7 +302,8 @@ std::vector<char> build_table(const std::vector<const world*>& ws, char* dev_bas
 int run_steps(world* w0, int mode, const TableView& tv, const std::vector<int>& host_bp, int n, int max_useful,
               int K, std::map<int, hipGraphExec_t>& graphs, std::map<int, hipGraph_t>& defs) {
     hipStream_t s = w0->stream;
-    Batch b{tv.w, tv.block_pre, n, w0->act_rows};
+    Batch b{tv.w, tv.block_pre, n, w0->act_rows, n == 1 ? static_cast<const WorldDev*>(w0->d_dev) : nullptr,
+            w0->cfg.cap};
     if (mode == WORLD_MODE_KERNELS) {
         for (int k = 0; k < K; ++k) HIP_TRY(w0, launch_step(b, host_bp.data(), n, s));
         return WORLD_OK;
@@ -338,23 +327,7 @@ int run_steps(world* w0, int mode, const TableView& tv, const std::vector<int>& 
         HIP_TRY(w0, hipGraphLaunch(it->second, s));
         return WORLD_OK;
     }
-    const int grid = std::max(1, std::min(persistent_blocks_per_cu() * device_cus(), max_useful));
-    PersistArgs pa;
-    pa.bt = b;
-    pa.barrier = reinterpret_cast<uint32_t*>(w0->base + w0->lay.barrier);
-    pa.err = reinterpret_cast<int32_t*>(w0->base + w0->lay.scal + offsetof(WorldScal, err));
-    pa.spin_ticks = uint64_t(wall_rate_khz()) * 1000ull * 2ull;   // 2 s
-    for (int done = 0; done < K;) {
-        const int chunk = std::min(K - done, 1024);
-        pa.K = chunk;
-        hipLaunchKernelGGL(k_zero_barrier, dim3(1), dim3(64), 0, s, pa.barrier);
-        HIP_TRY(w0, hipGetLastError());
-        void* args[] = {&pa};
-        HIP_TRY(w0, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_persistent), dim3(grid), dim3(kBlock),
-                                               args, 0, s));
-        done += chunk;
-    }
-    return WORLD_OK;
+    return fail(w0, WORLD_E_INVALID_ARG, "unknown mode");
 }
 
 }  // namespace
@@ -441,9 +414,7 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
     d.theta = reinterpret_cast<float*>(b + lay.theta);
     d.live[0] = reinterpret_cast<int32_t*>(b + lay.live0);
     d.live[1] = reinterpret_cast<int32_t*>(b + lay.live1);
-    d.rec[0] = reinterpret_cast<AgentRec*>(b + lay.rec0);
-    d.rec[1] = reinterpret_cast<AgentRec*>(b + lay.rec1);
-    d.post = reinterpret_cast<PostRec*>(b + lay.post);
+    d.pos = reinterpret_cast<PosRec*>(b + lay.pos);
     d.freeq = reinterpret_cast<int32_t*>(b + lay.freeq);
     d.child = reinterpret_cast<int4*>(b + lay.child);
     d.scal = reinterpret_cast<WorldScal*>(b + lay.scal);
@@ -452,7 +423,6 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
     d.log_act = reinterpret_cast<uint8_t*>(b + lay.log_act);
     d.log_logits = reinterpret_cast<float*>(b + lay.log_logits);
     d.log_n = reinterpret_cast<int32_t*>(b + lay.log_n);
-    d.barrier = reinterpret_cast<uint32_t*>(b + lay.barrier);
     d.eat_part = reinterpret_cast<int32_t*>(b + lay.eat_part);
     d.deadlist = reinterpret_cast<int32_t*>(b + lay.deadlist);
     d.lb_move = reinterpret_cast<uint64_t*>(b + lay.lb_move);
@@ -487,8 +457,9 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
         live[a] = int32_t(a);
     }
     for (int s = int(n0); s < c.cap; ++s) freeq[s - int(n0)] = s;
-    std::vector<AgentRec> recs(c.cap);
-    for (size_t a = 0; a < n0; ++a) recs[a] = AgentRec{int32_t(a), cells[a], c.E0, uint32_t(a), 0, 0, 4, 0};
+    std::vector<PosRec> recs(c.cap);
+    std::memset(recs.data(), 0, sizeof(PosRec) * recs.size());
+    for (size_t a = 0; a < n0; ++a) recs[a].r[0] = AgentRec{int32_t(a), cells[a], c.E0, uint32_t(a), 0, 0, 4, 0};
     std::vector<uint64_t> thr(size_t(c.H) * 25);
     build_thresholds(c, thr.data());
     WorldScal sc;
@@ -529,15 +500,14 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
     UP(lay.alive, alive.data(), size_t(c.cap));
     UP(lay.live0, live.data(), size_t(c.cap) * 4);
     UP(lay.live1, live.data(), size_t(c.cap) * 4);
-    UP(lay.rec0, recs.data(), sizeof(AgentRec) * size_t(c.cap));
+    UP(lay.pos, recs.data(), sizeof(PosRec) * size_t(c.cap));
     UP(lay.freeq, freeq.data(), size_t(c.cap) * 4);
 #undef UP
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.ring, 0, sizeof(int32_t) * kRing * kCtrWords, s);
-    if (e == hipSuccess) e = hipMemsetAsync(b + lay.barrier, 0, 64, s);
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.done, 0, 64, s);
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.mclaim, 0xFF, 8 * HW, s);
-    if (e == hipSuccess) e = hipMemsetAsync(b + lay.lb_move, 0, 8 * size_t(blocks_agent(c)), s);
-    if (e == hipSuccess) e = hipMemsetAsync(b + lay.lb_claim, 0, 8 * size_t(blocks_agent(c)), s);
+    if (e == hipSuccess) e = hipMemsetAsync(b + lay.lb_move, 0, 8 * size_t(tiles_agent(c)), s);
+    if (e == hipSuccess) e = hipMemsetAsync(b + lay.lb_claim, 0, 8 * size_t(tiles_agent(c)), s);
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.h, 0, 4 * size_t(c.cap) * c.hidden, s);
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.action, 4, size_t(c.cap), s);
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.win, 0, size_t(c.cap), s);
@@ -582,7 +552,7 @@ int world_set_tuning(world_t* w, int32_t act_rows) {
 
 int world_set_mode(world_t* w, int32_t mode) {
     if (!w) return fail(nullptr, WORLD_E_INVALID_ARG, "world is NULL");
-    if (mode != WORLD_MODE_KERNELS && mode != WORLD_MODE_GRAPH && mode != WORLD_MODE_PERSISTENT)
+    if (mode != WORLD_MODE_KERNELS && mode != WORLD_MODE_GRAPH)
         return fail(w, WORLD_E_INVALID_ARG, "unknown mode");
     w->mode = mode;
     return WORLD_OK;
@@ -808,14 +778,15 @@ int world_load(world_t* w, const world_image* in) {
     HIP_TRY(w, hipMemcpy(b + l.alive, alive.data(), size_t(c.cap), hipMemcpyHostToDevice));
     HIP_TRY(w, hipMemcpy(b + l.live0, live.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
     {
-        std::vector<AgentRec> recs(c.cap);
+        std::vector<PosRec> recs(c.cap);
+        std::memset(recs.data(), 0, sizeof(PosRec) * recs.size());
         for (int i = 0; i < n; ++i)
-            recs[i] = AgentRec{i, cells[i], energies[i], uids[i], ages[i], streaks[i], 4, 0};
-        HIP_TRY(w, hipMemcpy(b + l.rec0, recs.data(), sizeof(AgentRec) * size_t(c.cap), hipMemcpyHostToDevice));
+            recs[i].r[0] = AgentRec{i, cells[i], energies[i], uids[i], ages[i], streaks[i], 4, 0};
+        HIP_TRY(w, hipMemcpy(b + l.pos, recs.data(), sizeof(PosRec) * size_t(c.cap), hipMemcpyHostToDevice));
     }
     HIP_TRY(w, hipMemcpy(b + l.freeq, freeq.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
-    HIP_TRY(w, hipMemset(b + l.lb_move, 0, 8 * size_t(blocks_agent(c))));
-    HIP_TRY(w, hipMemset(b + l.lb_claim, 0, 8 * size_t(blocks_agent(c))));
+    HIP_TRY(w, hipMemset(b + l.lb_move, 0, 8 * size_t(tiles_agent(c))));
+    HIP_TRY(w, hipMemset(b + l.lb_claim, 0, 8 * size_t(tiles_agent(c))));
     HIP_TRY(w, hipMemset(b + l.done, 0, 64));
     HIP_TRY(w, hipMemset(b + l.mclaim, 0xFF, 8 * HW));
     if (n > 0) {
@@ -934,7 +905,7 @@ int world_phase_times(world_t* w, int32_t K, float* ms) {
     if (K < 1) return fail(w, WORLD_E_INVALID_ARG, "K must be >= 1");
     const int np = 2;
     const int* hp = w->host_bp.data();
-    Batch b{w->tv.w, w->tv.block_pre, 1, w->act_rows};
+    Batch b{w->tv.w, w->tv.block_pre, 1, w->act_rows, static_cast<const WorldDev*>(w->d_dev), w->cfg.cap};
     hipStream_t s = w->stream;
     std::vector<hipEvent_t> ev(size_t(K) * 4);
     for (auto& e : ev) HIP_TRY(w, hipEventCreate(&e));
@@ -944,9 +915,9 @@ int world_phase_times(world_t* w, int32_t K, float* ms) {
         (void)hipEventRecord(e[0], s);
         launch_act(b, hp[kPreAct * np + 1], s);
         (void)hipEventRecord(e[1], s);
-        hipLaunchKernelGGL(k_move, dim3(hp[kPreMove * np + 1]), dim3(kBlock), 0, s, b);
+        hipLaunchKernelGGL(k_move, dim3(hp[kPreMove * np + 1]), dim3(64), 0, s, b);
         (void)hipEventRecord(e[2], s);
-        hipLaunchKernelGGL(k_claim, dim3(hp[kPreClaim * np + 1]), dim3(kBlock), 0, s, b);
+        hipLaunchKernelGGL(k_claim, dim3(hp[kPreClaim * np + 1]), dim3(64), 0, s, b);
         (void)hipEventRecord(e[3], s);
         le = hipGetLastError();
     }

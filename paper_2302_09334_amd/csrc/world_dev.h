@@ -21,6 +21,7 @@
 //   scalars   WorldScal, counters ring (8192 steps), optional controller log
 #pragma once
 
+#include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -51,6 +52,24 @@ struct alignas(16) PostRec {
     int32_t next_pos;
 };
 
+// Everything about live-list position i, together: the agent's record in
+// each of the two live lists and its post-move record.
+struct alignas(32) PosRec {
+    AgentRec r[2];
+    PostRec post;
+};
+
+// Read-only views of memory that no kernel writes while the reader runs
+// (descriptors, launch tables, scalars of an earlier kernel): loads through a
+// constant-address-space pointer are scalar loads when the address is uniform.
+#define ECO_KAS __attribute__((address_space(4)))
+template <class T>
+using kptr = const ECO_KAS T*;
+template <class T>
+__device__ __forceinline__ kptr<T> kconst(const T* p) {
+    return (kptr<T>)p;
+}
+
 struct WorldScal {
     int64_t t;          // steps taken
     int32_t n_live;
@@ -60,10 +79,11 @@ struct WorldScal {
     int32_t live_sel;   // which live[] buffer is current
     int32_t n_child;    // children created by the last step
     int64_t spawn_t;    // step of the pending children
-    int32_t err;        // device-side failure code (1 barrier, 2 look-back time-out)
+    int32_t err;        // device-side failure code (2 look-back time-out)
     int32_t n_prev;     // live agents at the start of the last closed step
     int32_t ctr_open;   // 1: eaten/resource totals of step spawn_t not yet summed
-    int32_t pad[3];
+    int32_t pad;
+    int64_t t_grow;     // step of the running claim phase (written by its move phase)
 };
 
 struct WorldDev {
@@ -94,14 +114,13 @@ struct WorldDev {
     uint8_t* alive;
     uint8_t* win;
     int32_t* claim;
-    uint64_t* bkey;       // birth-claim key of eligible agents (written in P2)
+    uint64_t* bkey;       // birth-claim key by cell of eligible agents (written in P2)
     float* h;
     float* gh;            // recurrent projection W_hh h + b_hh for the next act (slot x 3 hidden)
     float* theta;
     // lists
     int32_t* live[2];
-    AgentRec* rec[2];     // records of live[0] / live[1]
-    PostRec* post;        // post-move records of the current live list
+    PosRec* pos;          // per-position records (at kPosOff from the descriptor)
     int32_t* freeq;
     int4* child;
     // scalars and logs
@@ -111,7 +130,6 @@ struct WorldDev {
     uint8_t* log_act;     // log_steps x cap
     float* log_logits;    // log_steps x cap x 5
     int32_t* log_n;       // log_steps
-    uint32_t* barrier;    // grid barrier counter of the persistent kernel
     int32_t* deadlist;    // slots of the agents that died this step, uid order
     uint64_t* lb_move;    // look-back status words of the move phase (per tile)
     uint64_t* lb_claim;   // look-back status words of the claim phase (per tile)
@@ -121,5 +139,17 @@ struct WorldDev {
     int32_t ntiles;       // regrowth tiles
     int32_t pad1;
 };
+
+// A world's arena starts with its descriptor; the scalars and the
+// per-position records follow at fixed offsets, so a kernel that knows the
+// descriptor's address reaches them without reading the descriptor first.
+constexpr size_t kArenaAlign = 256;
+constexpr size_t arena_round(size_t v) { return (v + kArenaAlign - 1) / kArenaAlign * kArenaAlign; }
+constexpr size_t kScalOff = arena_round(sizeof(WorldDev));
+constexpr size_t kPosOff = kScalOff + arena_round(sizeof(WorldScal));
+
+// A world descriptor as the kernels see it: written by the host only, read
+// through the constant address space.
+using DevRef = const ECO_KAS WorldDev&;
 
 }  // namespace eco

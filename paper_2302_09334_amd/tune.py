@@ -1,7 +1,7 @@
 """Autotuner for batched launches.
 
 Only knobs that cannot change any result are searched: the launch mode
-(per-phase kernels, a captured graph, the persistent kernel), the number of
+(per-phase kernels or a captured graph), the number of
 steps per launch, and the act kernel's rows per round trip.  Every trial runs
 from the same saved state and the state is restored exactly afterwards, so
 tuning leaves the simulation where it was.
@@ -12,7 +12,7 @@ import time
 
 from .batch import WorldBatch
 
-MODES = ("graph", "kernels", "persistent")
+MODES = ("graph", "kernels")
 ROWS = (8, 16, 32)
 KS = (25, 50, 100)
 

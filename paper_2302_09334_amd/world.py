@@ -19,8 +19,8 @@ LIB_PATH = os.environ.get("ECO_WORLD_LIB", os.path.join(HERE, "libworld.so"))
 WORLD_OK = 0
 ERRORS = {-1: "invalid argument", -2: "invalid config", -3: "buffer too small", -4: "HIP failure",
           -5: "poisoned", -6: "state"}
-MODE_KERNELS, MODE_GRAPH, MODE_PERSISTENT = 0, 1, 2
-MODES = {"kernels": MODE_KERNELS, "graph": MODE_GRAPH, "persistent": MODE_PERSISTENT}
+MODE_KERNELS, MODE_GRAPH = 0, 1
+MODES = {"kernels": MODE_KERNELS, "graph": MODE_GRAPH}
 SNAP_HIDDEN, SNAP_THETA = 1, 2
 
 

@@ -60,7 +60,7 @@ def test_parity_kernels(env, case):
     assert st["agent_steps"] > 0
 
 
-@pytest.mark.parametrize("mode", ["graph", "persistent"])
+@pytest.mark.parametrize("mode", ["graph", "kernels"])
 def test_parity_modes(env, mode):
     world, oracle, wl = env
     cfg, seed, steps, K = CASES["dense_h16_r2"](wl)

@@ -17,7 +17,7 @@ def env():
     return world, serve, batch, tune, workloads
 
 
-@pytest.mark.parametrize("mode", ["kernels", "persistent"])
+@pytest.mark.parametrize("mode", ["kernels", "graph"])
 def test_served_equals_alone(env, mode):
     world, serve, batch, tune, wl = env
     reqs = []
