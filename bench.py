@@ -14,7 +14,9 @@ Also reported:
   algorithmic bytes per launch (live agents x bytes each agent must read and
   write + the grid) against the 8 TB/s HBM peak; ``traffic`` from the
   committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary when the kernel source
-  still matches it.
+  still matches it.  The kernel durations come from a per-phase pass over
+  the same steps (from the same state) whose launches carry start / end
+  events stamped by their own dispatch; ``kernels`` lists all three.
 * ``cpu_baseline``: the oracle (plain C, one thread) on a bounded sample of
   the same workload on the host cores.
 
@@ -80,13 +82,30 @@ def act_bytes_per_agent(cfg: dict, nnz_mean: float) -> float:
 
 
 def proj_bytes_per_agent(cfg: dict) -> float:
-    """Bytes of the recurrent projection (claim kernel) per surviving agent:
-    W_hh, b_hh and h in, the projection out."""
+    """Bytes of the recurrent projection per agent: W_hh, b_hh and h in, the
+    projection out."""
     hd = cfg["hidden"]
     return 3 * hd * hd * 4 + 3 * hd * 4 + hd * 4 + 3 * hd * 4
 
 
-def read_traffic(src_hash: str):
+# Move phase, per agent: its 32-byte record in, the move-claim word and the
+# two resource bytes of the source and target cell, the per-slot state out
+# (energy, age, streak, cell, previous cell: 20 bytes, alive: 1), both
+# occupancy words, the post-move record and the next record (32 + 32), the
+# live-list entry (4) and the eaten resource byte.
+MOVE_BYTES_PER_AGENT = 32 + 8 + 2 + 21 + 8 + 64 + 4 + 1
+# Claim phase, per agent: the post-move record (32), the move-claim clear (8),
+# the claim word (4); per eligible agent the 24 occupancy words (96) and the
+# 8 birth keys (64) of its neighbourhood.  Regrowth, per cell: the resource
+# byte in and out.
+CLAIM_BYTES_PER_AGENT = 32 + 8 + 4
+CLAIM_BYTES_PER_ELIGIBLE = 96 + 64
+
+
+def read_traffic(src_hash: str, rows: int):
+    """HBM bytes per launch of the act kernel compiled for `rows` input rows
+    per round trip, from the committed counter summary (None when the kernel
+    sources changed since it was taken)."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -97,7 +116,7 @@ def read_traffic(src_hash: str):
     if kv.get("kernel_source_sha256_16") != src_hash:
         return None
     try:
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv[f"hbm_bytes_per_launch_rows{rows}"])
     except (KeyError, ValueError):
         return None
 
@@ -293,15 +312,23 @@ def main():
     n_act = float(np.concatenate([[start["n_live"]], pc["n_live"][:-1]]).mean())
     per_agent = act_bytes_per_agent(cfg, nnz_mean)
     grid_bytes = cfg["H"] * cfg["W"] * 5
-    act_bytes = n_act * per_agent + grid_bytes
-    step_bytes = act_bytes + n_act * proj_bytes_per_agent(cfg)
-    act_ms = float(ph_ms[0])
-    achieved = act_bytes / (act_ms * 1e-3) / 1e9
+    elig = float(np.mean([(s["streak"] >= cfg["T_repr"]).sum() for s in (start, mid)]))
+    kbytes = {
+        "act": n_act * per_agent + grid_bytes,
+        "move": n_act * (proj_bytes_per_agent(cfg) + MOVE_BYTES_PER_AGENT),
+        "claim": n_act * CLAIM_BYTES_PER_AGENT + elig * CLAIM_BYTES_PER_ELIGIBLE + 2 * cfg["H"] * cfg["W"],
+    }
+    kms = {"act": float(ph_ms[0]), "move": float(ph_ms[1]), "claim": float(ph_ms[2])}
+    dominant = max(kms, key=kms.get)
+    act_bytes = kbytes["act"]
+    step_bytes = sum(kbytes.values())
+    achieved = kbytes[dominant] / (kms[dominant] * 1e-3) / 1e9
     src_hash = kernel_source_hash()
-    traffic = read_traffic(src_hash)
+    traffic = read_traffic(src_hash, best_rows) if dominant == "act" else None
     dense_per_agent = 4 * w.n_params + 2 * cfg["hidden"] * 4 + 21
-    log(f"[bench] phases ms/step act {ph_ms[0]:.4f} move {ph_ms[1]:.4f} claim+regrow {ph_ms[2]:.4f}; "
-        f"nnz mean {nnz_mean:.2f}; act bytes {act_bytes / 1e6:.2f} MB")
+    log(f"[bench] kernel us act {kms['act'] * 1e3:.2f} move {kms['move'] * 1e3:.2f} claim {kms['claim'] * 1e3:.2f}; "
+        f"nnz mean {nnz_mean:.2f}; MB act {kbytes['act'] / 1e6:.2f} move {kbytes['move'] / 1e6:.2f} "
+        f"claim {kbytes['claim'] / 1e6:.2f}; dominant {dominant}")
 
     if args.calib_copy:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
@@ -357,24 +384,26 @@ def main():
                                 "p99": float(np.percentile(per_step_ms, 99)),
                                 "window": f"per {args.chunk}-step launch"},
         "calibration_us_per_step": {m: v * 1e3 for m, v in calib.items()},
-        "phases_ms_per_step": {"act": float(ph_ms[0]), "move": float(ph_ms[1]),
-                               "claim_regrow": float(ph_ms[2])},
+        "kernels": {k: {"ms_per_launch": kms[k], "algorithmic_bytes": kbytes[k],
+                        "GBps": kbytes[k] / (kms[k] * 1e-3) / 1e9} for k in kms},
         "roofline": {
-            "kernel": "k_act (observation + sparse input rows + GRU + head, one wave per agent)",
+            "kernel": {"act": "k_act (observation + sparse input rows + GRU + head, one wave per agent)",
+                       "move": "k_move (moves, energy, death, survivor scan; recurrent projection)",
+                       "claim": "k_claim (birth claims, birth scan, regrowth)"}[dominant],
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "algorithmic_bytes_per_launch": act_bytes,
-            "per_agent_bytes": per_agent,
+            "algorithmic_bytes_per_launch": kbytes[dominant],
+            "launch_ms": kms[dominant],
+            "act_per_agent_bytes": per_agent,
             "agents_per_launch": n_act,
             "nnz_binary_inputs_mean": nnz_mean,
-            "dense_equivalent_bytes_per_launch": n_act * dense_per_agent + grid_bytes,
+            "act_dense_equivalent_bytes_per_launch": n_act * dense_per_agent + grid_bytes,
             "step_algorithmic_bytes": step_bytes,
             "step_achieved_GBps": step_bytes / (wall / args.steps) / 1e9,
-            "act_ms": act_ms,
             "kernel_source_sha256_16": src_hash,
         },
         "cpu_baseline": cpu,

@@ -182,12 +182,13 @@ int world_test_philox(const uint32_t *d_ctr, size_t n, uint32_t k0, uint32_t k1,
 int world_test_gauss(const uint32_t *d_a, const uint32_t *d_b, size_t n, float *d_z0, float *d_z1,
                      void *hip_stream);
 
-/* Run K steps as per-phase kernels with HIP events between the phases (on
- * the world's stream) and return the mean milliseconds per step of each phase
- * in ms[0..2] = act (child genomes of the previous step, observation and
- * controller), move (moves, energy, death, survivor scan), claim (birth
- * claims, birth scan, regrowth).  The steps are real: the world advances by
- * K.  Synchronises. */
+/* Run K steps as per-phase kernels on the world's stream and return the mean
+ * execution time in milliseconds of each phase kernel (start / end events
+ * stamped by the kernel's own dispatch, so launch gaps are excluded) in
+ * ms[0..2] = act (child genomes of the previous step, observation and
+ * controller), move (moves, energy, death, survivor scan, recurrent
+ * projection), claim (birth claims, birth scan, regrowth).  The steps are
+ * real: the world advances by K.  Synchronises. */
 int world_phase_times(world_t *w, int32_t K, float *ms);
 
 /* Plain device-to-device copy kernel (16-byte vector loads/stores) of `bytes`

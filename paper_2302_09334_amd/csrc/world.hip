@@ -1,6 +1,7 @@
 // world.hip -- host side of libworld.so: configuration checks, arena layout,
 // initialisation, step launches (per-phase kernels, HIP graphs, persistent
 // cooperative kernel), snapshots and the C-ABI of include/world.h.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -221,10 +222,12 @@ std::vector<int> batch_prefix(const std::vector<const world*>& ws) {
     return pre;
 }
 
-void launch_act(const Batch& b, int grid, hipStream_t s) {
-    if (b.act_rows == 8) hipLaunchKernelGGL(k_act_rows<8>, dim3(grid), dim3(kBlock), 0, s, b);
-    else if (b.act_rows == 32) hipLaunchKernelGGL(k_act_rows<32>, dim3(grid), dim3(kBlock), 0, s, b);
-    else hipLaunchKernelGGL(k_act, dim3(grid), dim3(kBlock), 0, s, b);
+// `t0` / `t1` (optional): events the dispatch itself stamps when the kernel
+// starts and ends (its execution time, without launch overhead).
+void launch_act(const Batch& b, int grid, hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr) {
+    if (b.act_rows == 8) hipExtLaunchKernelGGL(k_act_rows<8>, dim3(grid), dim3(kBlock), 0, s, t0, t1, 0, b);
+    else if (b.act_rows == 32) hipExtLaunchKernelGGL(k_act_rows<32>, dim3(grid), dim3(kBlock), 0, s, t0, t1, 0, b);
+    else hipExtLaunchKernelGGL(k_act, dim3(grid), dim3(kBlock), 0, s, t0, t1, 0, b);
 }
 
 // Enqueue one step of the per-phase kernels for a batch.
@@ -907,27 +910,24 @@ int world_phase_times(world_t* w, int32_t K, float* ms) {
     const int* hp = w->host_bp.data();
     Batch b{w->tv.w, w->tv.block_pre, 1, w->act_rows, static_cast<const WorldDev*>(w->d_dev), w->cfg.cap};
     hipStream_t s = w->stream;
-    std::vector<hipEvent_t> ev(size_t(K) * 4);
+    // each kernel between start / end events stamped by its own dispatch
+    std::vector<hipEvent_t> ev(size_t(K) * 6);
     for (auto& e : ev) HIP_TRY(w, hipEventCreate(&e));
     hipError_t le = hipSuccess;
     for (int k = 0; k < K && le == hipSuccess; ++k) {
-        hipEvent_t* e = ev.data() + size_t(k) * 4;
-        (void)hipEventRecord(e[0], s);
-        launch_act(b, hp[kPreAct * np + 1], s);
-        (void)hipEventRecord(e[1], s);
-        hipLaunchKernelGGL(k_move, dim3(hp[kPreMove * np + 1]), dim3(64), 0, s, b);
-        (void)hipEventRecord(e[2], s);
-        hipLaunchKernelGGL(k_claim, dim3(hp[kPreClaim * np + 1]), dim3(64), 0, s, b);
-        (void)hipEventRecord(e[3], s);
+        hipEvent_t* e = ev.data() + size_t(k) * 6;
+        launch_act(b, hp[kPreAct * np + 1], s, e[0], e[1]);
+        hipExtLaunchKernelGGL(k_move, dim3(hp[kPreMove * np + 1]), dim3(64), 0, s, e[2], e[3], 0, b);
+        hipExtLaunchKernelGGL(k_claim, dim3(hp[kPreClaim * np + 1]), dim3(64), 0, s, e[4], e[5], 0, b);
         le = hipGetLastError();
     }
     hipError_t se = hipStreamSynchronize(s);
     double acc[3] = {0, 0, 0};
     for (int k = 0; k < K && le == hipSuccess && se == hipSuccess; ++k) {
-        hipEvent_t* e = ev.data() + size_t(k) * 4;
+        hipEvent_t* e = ev.data() + size_t(k) * 6;
         for (int p = 0; p < 3; ++p) {
             float v = 0.f;
-            if (hipEventElapsedTime(&v, e[p], e[p + 1]) == hipSuccess) acc[p] += v;
+            if (hipEventElapsedTime(&v, e[2 * p], e[2 * p + 1]) == hipSuccess) acc[p] += v;
         }
     }
     for (auto& e : ev) (void)hipEventDestroy(e);
