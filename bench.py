@@ -53,32 +53,39 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def observed_inputs(snap: dict, cfg: dict) -> np.ndarray:
-    """Non-zero binary inputs per agent (resource and occupancy windows; outside
-    cells read as no resource and occupied)."""
+def observed_inputs(snap: dict, cfg: dict) -> tuple[np.ndarray, np.ndarray]:
+    """Per agent: the non-zero binary inputs (resource and occupancy windows;
+    outside cells read as no resource and occupied) and the input rows the act
+    kernel reads for them (per window the rows of its ones, or the rows of its
+    zeros plus the window's column total when ones are the majority)."""
     H, W, rho = cfg["H"], cfg["W"], cfg["obs_radius"]
+    w2 = (2 * rho + 1) ** 2
     R = np.zeros((H + 2 * rho, W + 2 * rho), np.int32)
     R[rho:rho + H, rho:rho + W] = snap["R"]
     O = np.ones((H + 2 * rho, W + 2 * rho), np.int32)
     O[rho:rho + H, rho:rho + W] = 0
     O[snap["row"] + rho, snap["col"] + rho] = 1
-    nnz = np.zeros(snap["n_live"], np.int64)
+    nr = np.zeros(snap["n_live"], np.int64)
+    no = np.zeros(snap["n_live"], np.int64)
     for dy in range(-rho, rho + 1):
         for dx in range(-rho, rho + 1):
             r = snap["row"] + rho + dy
             c = snap["col"] + rho + dx
-            nnz += R[r, c] + O[r, c]
-    return nnz
+            nr += R[r, c]
+            no += O[r, c]
+    rows = sum(np.where(2 * m > w2, w2 - m + 1, m) for m in (nr, no))
+    return nr + no, rows
 
 
-def act_bytes_per_agent(cfg: dict, nnz_mean: float) -> float:
+def act_bytes_per_agent(cfg: dict, rows_mean: float) -> float:
     """Bytes the act phase must move per agent: the precomputed recurrent
     projection (3*hidden floats), the input biases, the head, the energy row,
-    one 3*hidden row per non-zero binary input, the hidden state in and out,
-    and the agent's scalars (slot, cell, energy, uid in; action out)."""
+    one 3*hidden row per input row read (see observed_inputs), the hidden
+    state in and out, and the agent's scalars (slot, cell, energy, uid in;
+    action out)."""
     hd = cfg["hidden"]
     rw = 3 * hd * 4
-    return (rw + rw + (5 * hd + 5) * 4 + rw + nnz_mean * rw + 2 * hd * 4 + 21)
+    return (rw + rw + (5 * hd + 5) * 4 + rw + rows_mean * rw + 2 * hd * 4 + 21)
 
 
 def proj_bytes_per_agent(cfg: dict) -> float:
@@ -303,14 +310,15 @@ def main():
 
     # roofline of the dominant kernel: act phase in per-phase mode with events
     w.load(start)
-    nnz0 = observed_inputs(start, cfg)
+    nnz0, rows0 = observed_inputs(start, cfg)
     ph_ms = w.phase_times(args.phase_steps)
     mid = w.snapshot()
-    nnz1 = observed_inputs(mid, cfg)
+    nnz1, rows1 = observed_inputs(mid, cfg)
     nnz_mean = float(np.concatenate([nnz0, nnz1]).mean())
+    rows_mean = float(np.concatenate([rows0, rows1]).mean())
     pc = w.counters(t_first, args.phase_steps)
     n_act = float(np.concatenate([[start["n_live"]], pc["n_live"][:-1]]).mean())
-    per_agent = act_bytes_per_agent(cfg, nnz_mean)
+    per_agent = act_bytes_per_agent(cfg, rows_mean)
     grid_bytes = cfg["H"] * cfg["W"] * 5
     elig = float(np.mean([(s["streak"] >= cfg["T_repr"]).sum() for s in (start, mid)]))
     kbytes = {
@@ -327,7 +335,7 @@ def main():
     traffic = read_traffic(src_hash, best_rows) if dominant == "act" else None
     dense_per_agent = 4 * w.n_params + 2 * cfg["hidden"] * 4 + 21
     log(f"[bench] kernel us act {kms['act'] * 1e3:.2f} move {kms['move'] * 1e3:.2f} claim {kms['claim'] * 1e3:.2f}; "
-        f"nnz mean {nnz_mean:.2f}; MB act {kbytes['act'] / 1e6:.2f} move {kbytes['move'] / 1e6:.2f} "
+        f"nnz mean {nnz_mean:.2f} rows read {rows_mean:.2f}; MB act {kbytes['act'] / 1e6:.2f} move {kbytes['move'] / 1e6:.2f} "
         f"claim {kbytes['claim'] / 1e6:.2f}; dominant {dominant}")
 
     if args.calib_copy:
@@ -401,6 +409,7 @@ def main():
             "act_per_agent_bytes": per_agent,
             "agents_per_launch": n_act,
             "nnz_binary_inputs_mean": nnz_mean,
+            "act_input_rows_read_mean": rows_mean,
             "act_dense_equivalent_bytes_per_launch": n_act * dense_per_agent + grid_bytes,
             "step_algorithmic_bytes": step_bytes,
             "step_achieved_GBps": step_bytes / (wall / args.steps) / 1e9,

@@ -220,6 +220,15 @@ __global__ __launch_bounds__(kBlock) void k_proj_all(const WorldDev* dp) {
     else proj_agent<16>(d, slot, threadIdx.x & 63);
 }
 
+// Window sums of the input weights of every live agent of a world (after
+// creation or a load), one block per agent.
+__global__ __launch_bounds__(kBlock) void k_rsum_all(const WorldDev* dp) {
+    DevRef d = *kconst(dp);
+    const WorldScal* S = d.scal;
+    if (int(blockIdx.x) >= S->n_live) return;
+    rsum_agent(d, d.live[S->live_sel][blockIdx.x], threadIdx.x, kBlock);
+}
+
 __global__ void k_clear_pending(const WorldDev* dp) {
     if (threadIdx.x == 0) dp->scal->n_child = 0;
 }

@@ -106,6 +106,31 @@ __device__ __forceinline__ void proj_agent(DevRef d, int slot, int lane) {
     }
 }
 
+// Column totals of the agent's input weights over each binary window, kept
+// after its genome (theta rows tot_row and tot_row + 1, same column layout as
+// the input rows): row tot_row holds the sum of the resource-window rows of
+// W_ih, row tot_row + 1 the sum of the occupancy-window rows, each added in
+// increasing row order.  The act phase sums a window that holds more ones
+// than zeros as this total minus the rows of its zeros.
+__device__ __forceinline__ void rsum_agent(DevRef d, int slot, int tid, int nthreads) {
+    const int RW = 3 * d.hd;
+    const int w2 = (2 * d.rho + 1) * (2 * d.rho + 1);
+    float* th = d.theta + size_t(slot) * size_t(d.Ppad);
+    constexpr int kMaxW2 = 49;   // window of radius 3
+    for (int j = tid; j < 2 * RW; j += nthreads) {
+        const int win = j / RW, c = j - win * RW;
+        const float* col = th + size_t(win) * w2 * RW + c;
+        float v[kMaxW2];
+#pragma unroll
+        for (int i = 0; i < kMaxW2; ++i) v[i] = i < w2 ? col[i * RW] : 0.f;   // all loads in flight together
+        float acc = 0.f;
+#pragma unroll
+        for (int i = 0; i < kMaxW2; ++i)
+            if (i < w2) acc += v[i];
+        th[size_t(d.tot_row) * RW + j] = acc;
+    }
+}
+
 // A zero hidden state (new agents) projects to b_hh.
 template <int HD>
 __device__ __forceinline__ void proj_zero(DevRef d, int slot, int lane) {
@@ -128,14 +153,15 @@ __device__ __forceinline__ void proj_zero(DevRef d, int slot, int lane) {
 // of group g.  Each input row of W_ih holds the 3 gate weights of every
 // hidden unit contiguously (3 * HD floats), so a group reads one row with one
 // 12-byte load per lane.  Inputs are binary except the energy, so the input
-// projection is a sum of the rows whose input is 1: the set bits of two wave
-// ballots are dealt round-robin to the groups, each group sums its rows in
-// increasing input order, and the group partials are combined by a fixed xor
-// tree.  The summation order therefore depends only on the agent's own
-// observation, never on the launch shape or on other worlds in the launch:
-// ROWS (input rows fetched per wave per round trip) only changes how many
-// loads are in flight, since row q of the enumeration always goes to group
-// q % G and each group adds its rows in increasing q.
+// projection is a sum of the rows whose input is 1 (or, for a window with
+// more ones than zeros, the window's precomputed column total minus the rows
+// of its zeros): the items are dealt round-robin to the groups, each group
+// sums its items in enumeration order, and the group partials are combined by
+// a fixed xor tree.  The summation order therefore depends only on the
+// agent's own observation, never on the launch shape or on other worlds in
+// the launch: ROWS (input rows fetched per wave per round trip) only changes
+// how many loads are in flight, since item q of the enumeration always goes
+// to group q % G and each group adds its items in increasing q.
 // The recurrent projection comes precomputed from gh[slot].
 // ---------------------------------------------------------------------------
 template <int HD, int ROWS>
@@ -192,35 +218,54 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
     uint64_t mO = __ballot(ob);
     const uint64_t occ_bits = mO;
 
-    // Round trip 2 (usually the last): every input row whose input is 1.
+    // Round trips 2..: the input rows.  A window with more ones than zeros is
+    // summed as its precomputed column total minus the rows of its zeros
+    // (fewer rows to read); the items are dealt to the groups in the order
+    // [total R], R rows, [total O], O rows, each with its sign.
+    const uint64_t wmask = ~0ull >> (64 - w2);
+    const bool cR = 2 * __popcll(mR) > w2;
+    const bool cO = 2 * __popcll(mO) > w2;
+    if (cR) mR = ~mR & wmask;
+    if (cO) mO = ~mO & wmask;
+    int pend = (cR ? 1 : 0) | (cO ? 2 : 0);   // window totals still to add
+    constexpr int kNeg = 1 << 16;
+    const int tot_row = d.tot_row;
     float ar = 0.f, az = 0.f, an = 0.f;
-    while (mR | mO) {
-        int rows[G * B];
+    while (mR | mO | uint64_t(pend)) {
+        int items[G * B];
 #pragma unroll
         for (int q = 0; q < G * B; ++q) {
-            int row = -1;
-            if (mR) {
-                row = __builtin_ctzll(mR);
+            int it = tot_row + 2;   // the zero row: nothing left to add
+            // (every lane loads unconditionally, so the loads of a round trip
+            // stay together)
+            if (pend & 1) {
+                it = tot_row;
+                pend &= ~1;
+            } else if (mR) {
+                it = __builtin_ctzll(mR) | (cR ? kNeg : 0);
                 mR &= mR - 1;
+            } else if (pend & 2) {
+                it = tot_row + 1;
+                pend &= ~2;
             } else if (mO) {
-                row = w2 + __builtin_ctzll(mO);
+                it = (w2 + __builtin_ctzll(mO)) | (cO ? kNeg : 0);
                 mO &= mO - 1;
             }
-            rows[q] = row;
+            items[q] = it;
         }
         float vr[B], vz[B], vn[B];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
-            int row = rows[b * G];
+            int it = items[b * G];
 #pragma unroll
             for (int gg = 1; gg < G; ++gg)
-                if (g == gg) row = rows[b * G + gg];
-            const bool ok = row >= 0;
-            const float* p = th + (ok ? row : erow) * RW + 3 * k;
+                if (g == gg) it = items[b * G + gg];
+            const float* p = th + (it & (kNeg - 1)) * RW + 3 * k;
             const float x0 = p[0], x1 = p[1], x2 = p[2];
-            vr[b] = ok ? x0 : 0.f;
-            vz[b] = ok ? x1 : 0.f;
-            vn[b] = ok ? x2 : 0.f;
+            const bool neg = (it & kNeg) != 0;
+            vr[b] = neg ? -x0 : x0;
+            vz[b] = neg ? -x1 : x1;
+            vn[b] = neg ? -x2 : x2;
         }
 #pragma unroll
         for (int b = 0; b < B; ++b) {
@@ -864,13 +909,15 @@ __device__ __forceinline__ void spawn_child(DevRef d, int rk, int tid) {
     __builtin_amdgcn_s_waitcnt(0);   // this thread's stores have completed
 }
 
-// Recurrent projection of a new agent (after spawn_child and a barrier).
+// Recurrent projection and window sums of a new agent (after spawn_child and
+// a barrier).
 __device__ __forceinline__ void spawn_proj(DevRef d, int rk, int tid) {
+    const int cs = d.child[rk].x;
     if (tid < 64) {
-        const int cs = d.child[rk].x;
         if (d.hd == 32) proj_zero<32>(d, cs, tid);
         else proj_zero<16>(d, cs, tid);
     }
+    rsum_agent(d, cs, tid, kBlock);
     __builtin_amdgcn_s_waitcnt(0);
 }
 

@@ -33,7 +33,7 @@ int n_inputs_of(int rho) {
 }
 
 struct Dims {
-    int n_in, P, Ppad, off_hh, off_bih, off_bhh, off_wo, off_bo, nblk;
+    int n_in, P, Ppad, off_hh, off_bih, off_bhh, off_wo, off_bo, nblk, tot_row;
 };
 
 Dims dims_of(const world_config& c) {
@@ -46,7 +46,12 @@ Dims dims_of(const world_config& c) {
     d.off_wo = d.off_bhh + hd * 3;
     d.off_bo = d.off_wo + 5 * hd;
     d.P = d.off_bo + 5;
-    d.Ppad = int(align_up(size_t(d.P), 64));   // 256-byte rows
+    // after the genome, at a whole number of input rows: the two window totals
+    // of the input weights (rows tot_row, tot_row + 1) and a row of zeros
+    // (tot_row + 2, never written after the arena is cleared), then padding to
+    // 256 bytes
+    d.tot_row = (d.P + 3 * hd - 1) / (3 * hd);
+    d.Ppad = int(align_up(size_t(d.tot_row + 3) * 3 * hd, 64));
     d.nblk = (d.P + 3) / 4;
     return d;
 }
@@ -394,6 +399,7 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
     d.forced = -1;
     d.log_steps = c.log_steps;
     d.off_hh = dm.off_hh; d.off_bih = dm.off_bih; d.off_bhh = dm.off_bhh; d.off_wo = dm.off_wo; d.off_bo = dm.off_bo;
+    d.tot_row = dm.tot_row;
     d.nblk = dm.nblk;
     d.R[0] = reinterpret_cast<uint8_t*>(b + lay.R0);
     d.R[1] = reinterpret_cast<uint8_t*>(b + lay.R1);
@@ -526,6 +532,7 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
     }
     if (e == hipSuccess && n0 > 0) {
         hipLaunchKernelGGL(k_proj_all, dim3(blocks_act(c)), dim3(kBlock), 0, s, static_cast<const WorldDev*>(w->d_dev));
+        hipLaunchKernelGGL(k_rsum_all, dim3(c.cap), dim3(kBlock), 0, s, static_cast<const WorldDev*>(w->d_dev));
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -798,6 +805,8 @@ int world_load(world_t* w, const world_image* in) {
         HIP_TRY(w, hipMemcpy(b + l.h, hs.data(), 4 * hs.size(), hipMemcpyHostToDevice));
         HIP_TRY(w, hipMemcpy(b + l.theta, th.data(), 4 * size_t(n) * Pp, hipMemcpyHostToDevice));
         hipLaunchKernelGGL(k_proj_all, dim3(blocks_act(c)), dim3(kBlock), 0, w->stream,
+                           static_cast<const WorldDev*>(w->d_dev));
+        hipLaunchKernelGGL(k_rsum_all, dim3(c.cap), dim3(kBlock), 0, w->stream,
                            static_cast<const WorldDev*>(w->d_dev));
         HIP_TRY(w, hipGetLastError());
         HIP_TRY(w, hipStreamSynchronize(w->stream));

@@ -96,6 +96,7 @@ struct WorldDev {
     int32_t log_steps;
     int32_t off_hh, off_bih, off_bhh, off_wo, off_bo;  // genome offsets (floats)
     int32_t nblk;       // float4 blocks per genome, ceil(P / 4)
+    int32_t tot_row;    // theta row (of 3*hd floats) of the window totals, after the genome; tot_row + 2 is zeros
     int32_t pad0;
     // grid
     uint8_t* R[2];

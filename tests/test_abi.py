@@ -41,9 +41,12 @@ def test_required_bytes_and_dims(wlib):
         n = wlib.required_bytes(cfg)
         n_in, P = wlib.dims(cfg)
         assert n_in == 2 * (2 * cfg["obs_radius"] + 1) ** 2 + 1
-        # the genome dominates the arena
+        # the genome dominates the arena: per agent slot the genome, three more
+        # rows of 3*hidden floats (the two window totals and a zero row), up to
+        # 64 floats of row padding, and under 1 KiB of records and state
         assert n > cfg["cap"] * P * 4
-        assert n < cfg["cap"] * (P + 200) * 4 + 64 * cfg["H"] * cfg["W"] + (1 << 20)
+        per_slot = (P + 9 * cfg["hidden"] + 64) * 4 + 1024
+        assert n < cfg["cap"] * per_slot + 64 * cfg["H"] * cfg["W"] + (1 << 20)
     assert wlib.dims(workloads.WORKLOADS["m1_4k"]) == (99, 12933)
     assert wlib.dims(workloads.WORKLOADS["cfg0"]) == (51, 3397)
 
