@@ -12,10 +12,10 @@
 //   P3 claim   birth claims and their resolution, ranked by a second
 //              look-back scan (born = rank < cap - survivors, so every
 //              winner knows its child slot at once); regrowth tiles; the
-//              last claim block to finish closes the step's bookkeeping
+//              last claim tile closes the step's bookkeeping
 // Every decision is a gather: an agent reads its neighbours' state and
 // decides on its own; cross-block communication is limited to the look-back
-// status words and one completion counter per world.
+// status words.
 //
 // Paper mapping: observation and controller App. B.2/B.5, moves and energy
 // App. B.2, reproduction/mutation/death App. B.3, regrowth App. B.1 Eq. (1).
@@ -548,8 +548,10 @@ __device__ __forceinline__ void pin_s(int v) { asm volatile("" ::"s"(v)); }
 __device__ __forceinline__ void pin64(uint64_t v) { asm volatile("" ::"v"(v)); }
 
 // The scalars through the scalar cache: no block writes them before every
-// block of the same kernel has read them (the closing claim tile runs last,
-// and the regrowth tiles read t_grow, which it does not write).
+// block of the same kernel that reads them has done so (the last claim tile
+// rewrites them once its look-back has seen every other claim tile publish,
+// which each does after reading them; the regrowth tiles read t_grow, which
+// it does not write).
 __device__ __forceinline__ StepScal read_step(const WorldScal* S) {
     const StepScal s = read_step_from(kconst(S));
     pin_s(int(s.t));
@@ -721,8 +723,8 @@ __device__ __forceinline__ int claim_agent(DevRef d, const PostRec& p, int64_t t
 // P3a for tile `j` (kTileN live-list entries, one wave) of one world.  The
 // winner of global rank r (uid order) is born iff r < cap - survivors; its
 // child takes free slot r of the ring if the ring holds more than r slots,
-// else the (r - free)-th slot freed this step.  The last claim tile to finish
-// closes the step (counts, free ring, scalars).  `p`: this lane's post-move
+// else the (r - free)-th slot freed this step.  The last claim tile closes
+// the step (counts, free ring, scalars) as soon as its look-back returns.  `p`: this lane's post-move
 // record, read before the scalars arrived.
 __device__ __forceinline__ void claim_block(DevRef d, WorldScal* S, PosRec* P, int j, int lane, const StepScal& ss,
                                             const PostRec& p) {
@@ -774,15 +776,11 @@ __device__ __forceinline__ void claim_block(DevRef d, WorldScal* S, PosRec* P, i
             d.streak[slot] = 0;
         }
     }
-    // completion: the last tile to get here closes the step.  Relaxed: the
-    // closing tile reads only look-back words (atomics) and data of earlier
-    // phases; the counter orders its writes of the scalars after every
-    // tile's reads of them.
-    uint32_t prev = 0;
-    if (lane == 0) prev = __hip_atomic_fetch_add(d.done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    prev = __shfl(prev, 0);
-    if (prev != uint32_t(ntile - 1)) return;
-    const int wins = int(unpack_a(lookback_total(d.lb_claim, ntile)));
+    // The last tile closes the step: its look-back prefix covers every other
+    // tile, so all of them have read the scalars (they do so before
+    // publishing their look-back word) and the totals are known.
+    if (j != ntile - 1) return;
+    const int wins = int(unpack_a(ex)) + wr.ta;
     const int dead = n - surv;
     const int nb = min(wins, cap - surv);
     const int consumed = max(0, nb - nfree);
@@ -793,7 +791,6 @@ __device__ __forceinline__ void claim_block(DevRef d, WorldScal* S, PosRec* P, i
         d.freeq[fpos] = d.deadlist[q];
     }
     if (lane == 0) {
-        __hip_atomic_store(d.done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         int nfh = ss.free_head + min(nb, nfree);
         if (nfh >= cap) nfh -= cap;
         int nft = ft + (dead - consumed);

@@ -82,7 +82,7 @@ struct Layout {
     size_t desc, scal, ring, batch, thr, R0, R1, occA, occB, mclaim;
     size_t uid, cell, prev_cell, energy, age, streak, action, alive, win, claim, bkey;
     size_t live0, live1, pos, freeq, child, h, gh, theta;
-    size_t log_uid, log_act, log_logits, log_n, eat_part, res_part, deadlist, lb_move, lb_claim, done;
+    size_t log_uid, log_act, log_logits, log_n, eat_part, res_part, deadlist, lb_move, lb_claim;
     size_t total;
 };
 
@@ -135,7 +135,6 @@ Layout layout_of(const world_config& c) {
     l.deadlist = take(4 * cap);
     l.lb_move = take(8 * ((cap + kTileN - 1) / kTileN));
     l.lb_claim = take(8 * ((cap + kTileN - 1) / kTileN));
-    l.done = take(64);
     l.res_part = take(4 * size_t(((c.H + kTile - 1) / kTile) * ((c.W + kTile - 1) / kTile)));
     l.total = o;
     static_assert(kArenaAlign == kAlign, "arena alignment");
@@ -436,7 +435,6 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
     d.deadlist = reinterpret_cast<int32_t*>(b + lay.deadlist);
     d.lb_move = reinterpret_cast<uint64_t*>(b + lay.lb_move);
     d.lb_claim = reinterpret_cast<uint64_t*>(b + lay.lb_claim);
-    d.done = reinterpret_cast<uint32_t*>(b + lay.done);
     d.res_part = reinterpret_cast<int32_t*>(b + lay.res_part);
     d.ntiles = ((c.H + kTile - 1) / kTile) * ((c.W + kTile - 1) / kTile);
     w->d_dev = reinterpret_cast<WorldDev*>(b + lay.desc);
@@ -513,7 +511,6 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
     UP(lay.freeq, freeq.data(), size_t(c.cap) * 4);
 #undef UP
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.ring, 0, sizeof(int32_t) * kRing * kCtrWords, s);
-    if (e == hipSuccess) e = hipMemsetAsync(b + lay.done, 0, 64, s);
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.mclaim, 0xFF, 8 * HW, s);
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.lb_move, 0, 8 * size_t(tiles_agent(c)), s);
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.lb_claim, 0, 8 * size_t(tiles_agent(c)), s);
@@ -797,7 +794,6 @@ int world_load(world_t* w, const world_image* in) {
     HIP_TRY(w, hipMemcpy(b + l.freeq, freeq.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
     HIP_TRY(w, hipMemset(b + l.lb_move, 0, 8 * size_t(tiles_agent(c))));
     HIP_TRY(w, hipMemset(b + l.lb_claim, 0, 8 * size_t(tiles_agent(c))));
-    HIP_TRY(w, hipMemset(b + l.done, 0, 64));
     HIP_TRY(w, hipMemset(b + l.mclaim, 0xFF, 8 * HW));
     if (n > 0) {
         std::vector<float> hs(size_t(c.cap) * c.hidden, 0.f);

@@ -134,7 +134,6 @@ struct WorldDev {
     int32_t* deadlist;    // slots of the agents that died this step, uid order
     uint64_t* lb_move;    // look-back status words of the move phase (per tile)
     uint64_t* lb_claim;   // look-back status words of the claim phase (per tile)
-    uint32_t* done;       // completion counter of the claim phase
     int32_t* eat_part;    // per-wave eaten counts of the move phase (cap / 64)
     int32_t* res_part;    // per-tile resource counts of the regrowth phase
     int32_t ntiles;       // regrowth tiles
