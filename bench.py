@@ -359,6 +359,12 @@ def main():
         cpu = cpu_baseline(cfg, args.seed, args.cpu_seconds)
         log(f"[bench] oracle: {cpu['value']:.0f} agent-steps/s")
 
+    # every weight read once per acting agent, h in and out, ~20 B of scalars in
+    # and out, parent genome in and child genome out per birth, grid as u8 +
+    # i32 in and out: what a step would move with no input skipped
+    P = w.n_params
+    dense_step = (acting.mean() * (4 * P + 8 * cfg["hidden"] + 40) + ctr["births"].mean() * 8 * P
+                  + cfg["H"] * cfg["W"] * (2 * 1 + 2 * 4))
     ms_per_step = wall / args.steps * 1e3
     out = {
         "metric": "agent-steps/s @200x400, ~4k agents; batched/served p50/p99 step latency",
@@ -413,6 +419,8 @@ def main():
             "act_dense_equivalent_bytes_per_launch": n_act * dense_per_agent + grid_bytes,
             "step_algorithmic_bytes": step_bytes,
             "step_achieved_GBps": step_bytes / (wall / args.steps) / 1e9,
+            "step_dense_equivalent_bytes": dense_step,
+            "step_dense_equivalent_GBps": dense_step / (wall / args.steps) / 1e9,
             "kernel_source_sha256_16": src_hash,
         },
         "cpu_baseline": cpu,
