@@ -323,6 +323,12 @@ typedef struct {
     /* agents, uid order */
     uint32_t *uid;
     int32_t *row, *col, *e, *age, *streak;
+    /* movement metric: position at the start of the current window, and
+     * whether the agent was alive then */
+    int32_t *wrow, *wcol;
+    uint8_t *wvalid;
+    int32_t n_windows, windows_cap;
+    int32_t *move_hist;        /* n_windows x (ORACLE_MOVE_BINS + 1): bins, count */
     float *h;                  /* cap * hd   */
     float *theta;              /* cap * P    */
     /* forced actions */
@@ -371,6 +377,7 @@ void oracle_destroy(void *vw)
     if (!w) return;
     free(w->R); free(w->occ); free(w->thr);
     free(w->uid); free(w->row); free(w->col); free(w->e); free(w->age); free(w->streak);
+    free(w->wrow); free(w->wcol); free(w->wvalid); free(w->move_hist);
     free(w->h); free(w->theta); free(w->forced);
     free(w->last_uid); free(w->last_logits); free(w->last_act);
     free(w->act); free(w->claim); free(w->best); free(w->who);
@@ -439,6 +446,9 @@ void *oracle_create(const oracle_config *cfg, uint64_t seed, char *err, size_t e
     w->e = (int32_t *)calloc(cap, sizeof(int32_t));
     w->age = (int32_t *)calloc(cap, sizeof(int32_t));
     w->streak = (int32_t *)calloc(cap, sizeof(int32_t));
+    w->wrow = (int32_t *)calloc(cap, sizeof(int32_t));
+    w->wcol = (int32_t *)calloc(cap, sizeof(int32_t));
+    w->wvalid = (uint8_t *)calloc(cap, 1);
     w->h = (float *)calloc(cap * hd, sizeof(float));
     w->theta = (float *)calloc(cap * P, sizeof(float));
     w->last_uid = (uint32_t *)calloc(cap, sizeof(uint32_t));
@@ -454,7 +464,8 @@ void *oracle_create(const oracle_config *cfg, uint64_t seed, char *err, size_t e
     w->x = (double *)calloc((size_t)w->n_in, sizeof(double));
     w->hnew = (double *)calloc((size_t)hd, sizeof(double));
     w->forced_default = -1;
-    if (!w->R || !w->occ || !w->thr || !w->uid || !w->h || !w->theta || !w->best || !w->who) {
+    if (!w->R || !w->occ || !w->thr || !w->uid || !w->h || !w->theta || !w->best || !w->who || !w->wrow ||
+        !w->wcol || !w->wvalid) {
         set_err(err, errlen, "out of memory");
         oracle_destroy(w);
         return NULL;
@@ -558,6 +569,16 @@ int oracle_step(void *vw, const uint32_t *hint_uid, const uint8_t *hint_act, int
     oracle_stepinfo inf;
     memset(&inf, 0, sizeof(inf));
 
+    /* Movement metric (App. C): a window starts with this step; remember
+     * where every agent alive now stands. */
+    if (w->t % ORACLE_MOVE_WINDOW == 0) {
+        for (int a = 0; a < w->n; ++a) {
+            w->wrow[a] = w->row[a];
+            w->wcol[a] = w->col[a];
+            w->wvalid[a] = 1;
+        }
+    }
+
     /* ---- S1 + S2: observe and act (App. B.2), all on the step-start state. */
     int hi = 0;
     w->last_n = w->n;
@@ -659,6 +680,7 @@ int oracle_step(void *vw, const uint32_t *hint_uid, const uint8_t *hint_act, int
         int dead = (w->e[a] <= 0) || (w->age[a] >= cfg->L_max);
         if (dead) {
             inf.deaths++;
+            inf.dead_age += w->age[a];   /* life expectancy (App. C): age at death */
             continue;
         }
         if (n_surv != a) {
@@ -668,6 +690,9 @@ int oracle_step(void *vw, const uint32_t *hint_uid, const uint8_t *hint_act, int
             w->e[n_surv] = w->e[a];
             w->age[n_surv] = w->age[a];
             w->streak[n_surv] = w->streak[a];
+            w->wrow[n_surv] = w->wrow[a];
+            w->wcol[n_surv] = w->wcol[a];
+            w->wvalid[n_surv] = w->wvalid[a];
             memmove(w->h + (size_t)n_surv * hd, w->h + (size_t)a * hd, (size_t)hd * sizeof(float));
             memmove(w->theta + (size_t)n_surv * P, w->theta + (size_t)a * P, P * sizeof(float));
         }
@@ -735,6 +760,7 @@ int oracle_step(void *vw, const uint32_t *hint_uid, const uint8_t *hint_act, int
         w->e[c] = cfg->E0;
         w->age[c] = 0;
         w->streak[c] = 0;
+        w->wvalid[c] = 0;   /* not alive at the start of the window */
         memset(w->h + (size_t)c * hd, 0, (size_t)hd * sizeof(float));
         /* Mutation (App. B.3): every parameter gets sigma * z added, z from
          * lane p % 4 of block p / 4 of stream MUTATE keyed by the child uid. */
@@ -784,6 +810,27 @@ int oracle_step(void *vw, const uint32_t *hint_uid, const uint8_t *hint_act, int
 
     inf.n_live = w->n;
     inf.resources = res;
+
+    /* Movement metric: the window ends with this step; the Manhattan distance
+     * travelled by every agent alive at both ends goes into bin distance / 3. */
+    if ((w->t + 1) % ORACLE_MOVE_WINDOW == 0) {
+        if (w->n_windows == w->windows_cap) {
+            int32_t nc = w->windows_cap ? 2 * w->windows_cap : 64;
+            int32_t *nh = (int32_t *)realloc(w->move_hist, (size_t)nc * (ORACLE_MOVE_BINS + 1) * sizeof(int32_t));
+            if (!nh) return -1;
+            w->move_hist = nh;
+            w->windows_cap = nc;
+        }
+        int32_t *hist = w->move_hist + (size_t)w->n_windows * (ORACLE_MOVE_BINS + 1);
+        memset(hist, 0, (ORACLE_MOVE_BINS + 1) * sizeof(int32_t));
+        for (int a = 0; a < w->n; ++a) {
+            if (!w->wvalid[a]) continue;
+            int dist = abs(w->row[a] - w->wrow[a]) + abs(w->col[a] - w->wcol[a]);
+            hist[dist / 3]++;
+            hist[ORACLE_MOVE_BINS]++;
+        }
+        w->n_windows++;
+    }
     w->t++;
     if (info) *info = inf;
     return 0;
@@ -825,6 +872,18 @@ void oracle_get_theta(const void *vw, float *theta)
 }
 
 int32_t oracle_last_n_acted(const void *w) { return ((const world *)w)->last_n; }
+
+int32_t oracle_n_move_windows(const void *w) { return ((const world *)w)->n_windows; }
+
+int oracle_get_move_hist(const void *vw, int32_t k, int32_t *bins, int32_t *count)
+{
+    const world *w = (const world *)vw;
+    if (k < 0 || k >= w->n_windows) return -1;
+    const int32_t *hist = w->move_hist + (size_t)k * (ORACLE_MOVE_BINS + 1);
+    if (bins) memcpy(bins, hist, ORACLE_MOVE_BINS * sizeof(int32_t));
+    if (count) *count = hist[ORACLE_MOVE_BINS];
+    return 0;
+}
 
 void oracle_get_last_logits(const void *vw, uint32_t *uid, double *logits, uint8_t *action)
 {

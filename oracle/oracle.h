@@ -55,7 +55,16 @@ typedef struct oracle_stepinfo {
     int32_t resyncs;     /* near-tie actions adopted from the supplied hints   */
     int32_t mismatches;  /* hints that disagreed outside the near-tie band     */
     int32_t claim_wins;  /* birth-claim winners before the slot cap            */
+    int64_t dead_age;    /* sum of the ages of the agents that died (App. C)   */
 } oracle_stepinfo;
+
+/* Movement metric (App. C): windows of ORACLE_MOVE_WINDOW steps, window k
+ * covering steps [k * W, (k + 1) * W).  For every agent alive at both the
+ * start of the window (before its first step) and its end (after its last
+ * step, deaths applied), the Manhattan distance between the two positions
+ * (0..W) falls into bin distance / 3 of ORACLE_MOVE_BINS bins. */
+#define ORACLE_MOVE_WINDOW 50
+#define ORACLE_MOVE_BINS 17
 
 /* Random stream identifiers of the counter-based generator. */
 enum {
@@ -123,6 +132,10 @@ void oracle_get_theta(const void *w, float *theta);       /* n_live x n_params  
  * order, the population at the start of that step). */
 int32_t oracle_last_n_acted(const void *w);
 void oracle_get_last_logits(const void *w, uint32_t *uid, double *logits, uint8_t *action);
+/* Movement windows that have ended, and the histogram of window k:
+ * bins[ORACLE_MOVE_BINS] and the number of agents counted. */
+int32_t oracle_n_move_windows(const void *w);
+int oracle_get_move_hist(const void *w, int32_t k, int32_t *bins, int32_t *count);
 
 #ifdef __cplusplus
 }

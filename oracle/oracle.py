@@ -42,11 +42,15 @@ class _Cfg(C.Structure):
     ]
 
 
+MOVE_WINDOW = 50   # steps per movement window (App. C)
+MOVE_BINS = 17     # distance bins (distance // 3 for distances 0..50)
+
+
 class StepInfo(C.Structure):
     _fields_ = [
         ("n_live", C.c_int32), ("births", C.c_int32), ("deaths", C.c_int32),
         ("eaten", C.c_int32), ("resources", C.c_int32), ("resyncs", C.c_int32),
-        ("mismatches", C.c_int32), ("claim_wins", C.c_int32),
+        ("mismatches", C.c_int32), ("claim_wins", C.c_int32), ("dead_age", C.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -128,6 +132,10 @@ def lib():
         L.oracle_last_n_acted.argtypes = [P]
         L.oracle_last_n_acted.restype = C.c_int32
         L.oracle_get_last_logits.argtypes = [P, P, P, P]
+        L.oracle_n_move_windows.argtypes = [P]
+        L.oracle_n_move_windows.restype = C.c_int32
+        L.oracle_get_move_hist.argtypes = [P, C.c_int32, P, P]
+        L.oracle_get_move_hist.restype = C.c_int
         _lib = L
     return _lib
 
@@ -272,6 +280,18 @@ class OracleWorld:
         th = np.empty((self.n_live, self.P), np.float32)
         lib().oracle_get_theta(self._h, _ptr(th))
         return th
+
+    def move_hist(self) -> np.ndarray:
+        """Movement histograms of the windows that have ended (App. C): one row
+        per window, MOVE_BINS bin counts then the number of agents counted."""
+        k = int(lib().oracle_n_move_windows(self._h))
+        out = np.zeros((k, MOVE_BINS + 1), np.int32)
+        for i in range(k):
+            cnt = C.c_int32(0)
+            rc = lib().oracle_get_move_hist(self._h, i, _ptr(out[i]), C.byref(cnt))
+            assert rc == 0
+            out[i, MOVE_BINS] = cnt.value
+        return out
 
     def last_controller(self) -> dict:
         n = int(lib().oracle_last_n_acted(self._h))
