@@ -84,8 +84,19 @@ typedef struct world_counters {
     int32_t eaten;       /* resources eaten in the step         */
     int32_t resources;   /* resources on the grid after regrowth*/
     int32_t claim_wins;  /* birth claims won before the slot cap */
-    int32_t reserved[2];
+    int64_t dead_age_sum;/* sum of the ages of the agents that died in the step
+                            (life expectancy over a window, App. C: the sum of
+                            this field over the window / the sum of deaths) */
 } world_counters;
+
+/* Movement metric (App. C).  Window k covers steps [k * WORLD_MOVE_WINDOW,
+ * (k + 1) * WORLD_MOVE_WINDOW).  An agent counts in window k iff it is alive
+ * before the window's first step and after its last step; it falls into bin
+ * d / 3 of WORLD_MOVE_BINS, d = Manhattan distance between its cells at the
+ * two ends (0..WORLD_MOVE_WINDOW).  A window in progress when a world is
+ * created or loaded counts no agent. */
+#define WORLD_MOVE_WINDOW 50
+#define WORLD_MOVE_BINS 17
 
 #define WORLD_SNAP_HIDDEN 1u   /* fill h (agent_capacity x hidden)          */
 #define WORLD_SNAP_THETA 2u    /* fill theta (agent_capacity x n_params)    */
@@ -154,6 +165,12 @@ int world_load(world_t *w, const world_image *in);
 
 /* Synchronise and copy counters of steps [first_step, first_step + n). */
 int world_counters_get(world_t *w, int64_t first_step, int32_t n, world_counters *out);
+
+/* Synchronise and copy the movement histograms of windows [first_window,
+ * first_window + n): out holds n x (WORLD_MOVE_BINS + 1) int32, the bin
+ * counts followed by the number of agents counted.  The windows must have
+ * ended and be among the last 64 (WORLD_E_STATE otherwise).  App. C. */
+int world_move_hist(world_t *w, int64_t first_window, int32_t n, int32_t *out);
 
 /* Synchronise and release the handle.  The arena is not freed. */
 int world_destroy(world_t *w);

@@ -99,6 +99,8 @@ __device__ __forceinline__ void act_body(const Batch& bt, int vb, int tid, StepS
     if (lb < kNewbornBlocks) {
         if (lb == 0) {
             if (tid == 0) step_open(d, t);
+            if (t % kMoveWin == 0 && tid <= kMoveBins)   // a movement window starts: clear its record
+                d.mhist[((t / kMoveWin) % kMoveRing) * (kMoveBins + 1) + tid] = 0;
             close_counters_in_step(d, tid, sh);
         }
         for (int rk = lb; rk < nc; rk += kNewbornBlocks) {

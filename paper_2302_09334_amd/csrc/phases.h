@@ -305,6 +305,10 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
     if (d.forced >= 0) best = d.forced;
 
     if (g == 0) d.h[size_t(slot) * HD + k] = hnew;
+    if (lane == 0 && t % kMoveWin == 0) {   // a movement window starts with this step
+        d.wcell[slot] = cell;
+        d.wuid[slot] = u;
+    }
     if (lane == 0) {
         d.action[slot] = uint8_t(best);
         recp->action = best;
@@ -563,6 +567,7 @@ __device__ __forceinline__ StepScal read_step(const WorldScal* S) {
 
 struct StepShared {
     int sw[2 * (kBlock / 64)];
+    long long sw64[kBlock / 64];
 };
 
 // P2 for tile `j` (kTileN live-list entries, one wave) of one world.
@@ -582,7 +587,37 @@ __device__ __forceinline__ void move_block(DevRef d, PosRec* P, int j, int lane,
     const bool alive = i < n && !(res & 2);
     const bool dead = i < n && (res & 2);
     const int cnt = __popcll(__ballot((res & 1) != 0));
-    if (lane == 0) d.eat_part[j] = cnt;
+    int dage = dead ? nr.age : 0;   // age at death (life expectancy, App. C)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) dage += __shfl_xor(dage, off);
+    if (lane == 0) {
+        d.eat_part[j] = cnt;
+        d.dage_part[j] = dage;
+    }
+    // Movement metric (App. C): the window ends with this step; every
+    // survivor whose slot recorded it at the window start counts, in bin
+    // (Manhattan distance from that cell) / 3.
+    if ((t + 1) % kMoveWin == 0) {
+        bool counted = false;
+        int bin = 0;
+        if (alive && d.wuid[nr.slot] == nr.uid) {
+            const int c0 = d.wcell[nr.slot];
+            const int r0 = c0 / d.W, q0 = c0 - r0 * d.W;
+            const int r1 = nr.cell / d.W, q1 = nr.cell - r1 * d.W;
+            const int dist = abs(r1 - r0) + abs(q1 - q0);
+            bin = dist / 3;
+            counted = true;
+        }
+        int32_t* hist = d.mhist + ((t / kMoveWin) % kMoveRing) * (kMoveBins + 1);
+        const int total = __popcll(__ballot(counted));
+        if (total) {
+            for (int b = 0; b < kMoveBins; ++b) {
+                const int c = __popcll(__ballot(counted && bin == b));
+                if (lane == 0 && c) __hip_atomic_fetch_add(hist + b, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (lane == 0) __hip_atomic_fetch_add(hist + kMoveBins, total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
     const WaveRank wr = wave_rank2(alive, dead, lane);
     const uint64_t ex = lookback(d, d.lb_move, j, uint32_t(t), pack2(wr.ta, wr.tb), lane);
     if (alive) {
@@ -918,33 +953,44 @@ __device__ __forceinline__ void spawn_proj(DevRef d, int rk, int tid) {
     __builtin_amdgcn_s_waitcnt(0);
 }
 
-// Eaten and resource totals of the step just closed (one block per world).
+// Eaten, resource and age-at-death totals of the step just closed (one block
+// per world).
 __device__ __forceinline__ void close_counters(DevRef d, int tid, StepShared& sh) {
     WorldScal* S = d.scal;
     if (!S->ctr_open) return;
     const int nwv = (S->n_prev + 63) / 64;
     int pe = 0, pr = 0;
-    for (int i = tid; i < nwv; i += kBlock) pe += d.eat_part[i];
+    long long pa = 0;
+    for (int i = tid; i < nwv; i += kBlock) {
+        pe += d.eat_part[i];
+        pa += d.dage_part[i];
+    }
     for (int i = tid; i < d.ntiles; i += kBlock) pr += d.res_part[i];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         pe += __shfl_xor(pe, off);
         pr += __shfl_xor(pr, off);
+        pa += __shfl_xor(pa, off);
     }
     if ((tid & 63) == 0) {
         sh.sw[tid >> 6] = pe;
         sh.sw[(kBlock / 64) + (tid >> 6)] = pr;
+        sh.sw64[tid >> 6] = pa;
     }
     __syncthreads();
     if (tid == 0) {
         int te = 0, tr = 0;
+        long long ta = 0;
         for (int w = 0; w < kBlock / 64; ++w) {
             te += sh.sw[w];
             tr += sh.sw[(kBlock / 64) + w];
+            ta += sh.sw64[w];
         }
         int32_t* rec = d.ring + (S->spawn_t % kRing) * kCtrWords;
         rec[kCtrEaten] = te;
         rec[kCtrRes] = tr;
+        rec[kCtrDeadAgeLo] = int32_t(uint64_t(ta) & 0xFFFFFFFFu);
+        rec[kCtrDeadAgeHi] = int32_t(uint64_t(ta) >> 32);
     }
     __syncthreads();
 }

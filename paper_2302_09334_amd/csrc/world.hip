@@ -82,7 +82,8 @@ struct Layout {
     size_t desc, scal, ring, batch, thr, R0, R1, occA, occB, mclaim;
     size_t uid, cell, prev_cell, energy, age, streak, action, alive, win, claim, bkey;
     size_t live0, live1, pos, freeq, child, h, gh, theta;
-    size_t log_uid, log_act, log_logits, log_n, eat_part, res_part, deadlist, lb_move, lb_claim;
+    size_t log_uid, log_act, log_logits, log_n, eat_part, dage_part, wcell, wuid, mhist, res_part, deadlist, lb_move,
+        lb_claim;
     size_t total;
 };
 
@@ -132,6 +133,10 @@ Layout layout_of(const world_config& c) {
     l.log_logits = take(4 * 5 * L * cap);
     l.log_n = take(4 * L);
     l.eat_part = take(4 * (cap / 64 + 1));
+    l.dage_part = take(4 * (cap / 64 + 1));
+    l.wcell = take(4 * cap);
+    l.wuid = take(4 * cap);
+    l.mhist = take(4 * size_t(kMoveRing) * (kMoveBins + 1));
     l.deadlist = take(4 * cap);
     l.lb_move = take(8 * ((cap + kTileN - 1) / kTileN));
     l.lb_claim = take(8 * ((cap + kTileN - 1) / kTileN));
@@ -432,6 +437,10 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
     d.log_logits = reinterpret_cast<float*>(b + lay.log_logits);
     d.log_n = reinterpret_cast<int32_t*>(b + lay.log_n);
     d.eat_part = reinterpret_cast<int32_t*>(b + lay.eat_part);
+    d.dage_part = reinterpret_cast<int32_t*>(b + lay.dage_part);
+    d.wcell = reinterpret_cast<int32_t*>(b + lay.wcell);
+    d.wuid = reinterpret_cast<uint32_t*>(b + lay.wuid);
+    d.mhist = reinterpret_cast<int32_t*>(b + lay.mhist);
     d.deadlist = reinterpret_cast<int32_t*>(b + lay.deadlist);
     d.lb_move = reinterpret_cast<uint64_t*>(b + lay.lb_move);
     d.lb_claim = reinterpret_cast<uint64_t*>(b + lay.lb_claim);
@@ -512,6 +521,8 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
 #undef UP
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.ring, 0, sizeof(int32_t) * kRing * kCtrWords, s);
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.mclaim, 0xFF, 8 * HW, s);
+    if (e == hipSuccess) e = hipMemsetAsync(b + lay.wuid, 0xFF, 4 * size_t(c.cap), s);
+    if (e == hipSuccess) e = hipMemsetAsync(b + lay.mhist, 0, 4 * size_t(kMoveRing) * (kMoveBins + 1), s);
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.lb_move, 0, 8 * size_t(tiles_agent(c)), s);
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.lb_claim, 0, 8 * size_t(tiles_agent(c)), s);
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.h, 0, 4 * size_t(c.cap) * c.hidden, s);
@@ -795,6 +806,8 @@ int world_load(world_t* w, const world_image* in) {
     HIP_TRY(w, hipMemset(b + l.lb_move, 0, 8 * size_t(tiles_agent(c))));
     HIP_TRY(w, hipMemset(b + l.lb_claim, 0, 8 * size_t(tiles_agent(c))));
     HIP_TRY(w, hipMemset(b + l.mclaim, 0xFF, 8 * HW));
+    HIP_TRY(w, hipMemset(b + l.wuid, 0xFF, 4 * size_t(c.cap)));   // no agent counts in the window in progress
+    HIP_TRY(w, hipMemset(b + l.mhist, 0, 4 * size_t(kMoveRing) * (kMoveBins + 1)));
     if (n > 0) {
         std::vector<float> hs(size_t(c.cap) * c.hidden, 0.f);
         std::memcpy(hs.data(), in->h, 4 * size_t(n) * c.hidden);
@@ -832,8 +845,27 @@ int world_counters_get(world_t* w, int64_t first, int32_t n, world_counters* out
         out[i].eaten = r[kCtrEaten];
         out[i].resources = r[kCtrRes];
         out[i].claim_wins = r[kCtrWins];
-        out[i].reserved[0] = out[i].reserved[1] = 0;
+        out[i].dead_age_sum = int64_t((uint64_t(uint32_t(r[kCtrDeadAgeHi])) << 32) | uint32_t(r[kCtrDeadAgeLo]));
     }
+    return WORLD_OK;
+}
+
+int world_move_hist(world_t* w, int64_t first, int32_t n, int32_t* out) {
+    if (!w || (!out && n > 0)) return fail(w, WORLD_E_INVALID_ARG, "NULL argument");
+    if (w->poisoned) return WORLD_E_POISONED;
+    if (int rc = world_sync(w)) return rc;
+    WorldScal sc;
+    HIP_TRY(w, hipMemcpy(&sc, w->base + w->lay.scal, sizeof(sc), hipMemcpyDeviceToHost));
+    // window k has ended once (k + 1) * kMoveWin steps are done; its record is
+    // overwritten when window k + kMoveRing starts
+    const int64_t started = sc.t > 0 ? (sc.t - 1) / kMoveWin : -1;   // last window begun
+    if (n < 0 || first < 0 || (first + n) * kMoveWin > sc.t || (n > 0 && first <= started - kMoveRing))
+        return fail(w, WORLD_E_STATE, "requested windows have not ended or are no longer held");
+    std::vector<int32_t> ring(size_t(kMoveRing) * (kMoveBins + 1));
+    HIP_TRY(w, hipMemcpy(ring.data(), w->base + w->lay.mhist, 4 * ring.size(), hipMemcpyDeviceToHost));
+    for (int i = 0; i < n; ++i)
+        std::memcpy(out + size_t(i) * (kMoveBins + 1), ring.data() + ((first + i) % kMoveRing) * (kMoveBins + 1),
+                    4 * (kMoveBins + 1));
     return WORLD_OK;
 }
 

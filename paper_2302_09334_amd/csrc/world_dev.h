@@ -33,7 +33,15 @@ constexpr int kBlock = 256;     // threads per block in every kernel
 constexpr int kTile = 16;       // regrowth tile edge (16 x 16 cells per block)
 
 // Counter record fields (match world_counters in world.h).
-enum : int { kCtrLive = 0, kCtrBirths, kCtrDeaths, kCtrEaten, kCtrRes, kCtrWins };
+enum : int { kCtrLive = 0, kCtrBirths, kCtrDeaths, kCtrEaten, kCtrRes, kCtrWins, kCtrDeadAgeLo, kCtrDeadAgeHi };
+
+// Movement metric (App. C): windows of kMoveWin steps (window k covers steps
+// [k * kMoveWin, (k + 1) * kMoveWin)), distances binned by 3 into kMoveBins
+// bins; the last kMoveRing windows are kept, kMoveBins counts and the number
+// of agents counted per window.
+constexpr int kMoveWin = 50;
+constexpr int kMoveBins = 17;
+constexpr int kMoveRing = 64;
 
 // Agent record by live-list position (the order of the live list): what the
 // act and move phases need about an agent in one 32-byte read.
@@ -135,6 +143,10 @@ struct WorldDev {
     uint64_t* lb_move;    // look-back status words of the move phase (per tile)
     uint64_t* lb_claim;   // look-back status words of the claim phase (per tile)
     int32_t* eat_part;    // per-wave eaten counts of the move phase (cap / 64)
+    int32_t* dage_part;   // per-wave sums of the ages of the dead (cap / 64)
+    int32_t* wcell;       // per slot: cell at the start of the current movement window
+    uint32_t* wuid;       // per slot: uid of the agent the window start was recorded for
+    int32_t* mhist;       // kMoveRing x (kMoveBins + 1) movement histograms
     int32_t* res_part;    // per-tile resource counts of the regrowth phase
     int32_t ntiles;       // regrowth tiles
     int32_t pad1;

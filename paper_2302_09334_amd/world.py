@@ -46,7 +46,10 @@ class Config(C.Structure):
 class Counters(C.Structure):
     _fields_ = [("n_live", C.c_int32), ("births", C.c_int32), ("deaths", C.c_int32),
                 ("eaten", C.c_int32), ("resources", C.c_int32), ("claim_wins", C.c_int32),
-                ("reserved", C.c_int32 * 2)]
+                ("dead_age_sum", C.c_int64)]
+
+MOVE_WINDOW = 50   # steps per movement window (App. C)
+MOVE_BINS = 17     # distance bins of a movement window
 
 
 class Image(C.Structure):
@@ -66,7 +69,7 @@ EXPORTS = [
     "world_set_mode", "world_set_tuning", "world_set_stream", "world_sync", "world_snapshot", "world_load", "world_counters_get",
     "world_destroy", "world_last_error", "world_set_forced_action", "world_action_log",
     "world_test_philox", "world_test_gauss", "world_threshold_table", "world_phase_times",
-    "world_test_copy",
+    "world_test_copy", "world_move_hist",
 ]
 
 _lib = None
@@ -102,6 +105,7 @@ def lib():
         L.world_threshold_table.argtypes = [C.POINTER(Config), P]
         L.world_phase_times.argtypes = [P, C.c_int32, P]
         L.world_test_copy.argtypes = [P, P, C.c_size_t, P]
+        L.world_move_hist.argtypes = [P, C.c_int64, C.c_int32, P]
         for name in EXPORTS:
             getattr(L, name).restype = getattr(L, name).restype or C.c_int
         L.world_last_error.restype = C.c_char_p
@@ -275,7 +279,23 @@ class World:
         buf = (Counters * max(n, 1))()
         _check(lib().world_counters_get(self._h, int(first), int(n), C.cast(buf, C.c_void_p)), self._h)
         keys = ("n_live", "births", "deaths", "eaten", "resources", "claim_wins")
-        return {k: np.array([getattr(buf[i], k) for i in range(n)], np.int64) for k in keys}
+        out = {k: np.array([getattr(buf[i], k) for i in range(n)], np.int64) for k in keys}
+        out["dead_age"] = np.array([buf[i].dead_age_sum for i in range(n)], np.int64)
+        return out
+
+    def move_hist(self, first: int, n: int) -> np.ndarray:
+        """Movement histograms of windows [first, first + n) (App. C): one row
+        per window, MOVE_BINS bin counts then the number of agents counted."""
+        out = np.zeros((max(n, 0), MOVE_BINS + 1), np.int32)
+        _check(lib().world_move_hist(self._h, int(first), int(n), out.ctypes.data_as(C.c_void_p)), self._h)
+        return out
+
+    def life_expectancy(self, first: int, n: int) -> float:
+        """Mean age at death over steps [first, first + n) (App. C; NaN when no
+        agent died)."""
+        c = self.counters(first, n)
+        d = int(c["deaths"].sum())
+        return float(c["dead_age"].sum()) / d if d else float("nan")
 
     def action_log(self, step: int) -> dict:
         cap = self.cfg["cap"]

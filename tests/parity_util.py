@@ -3,9 +3,11 @@
 The GPU world runs K steps with its controller log on; the oracle then takes
 the same K steps, one at a time, receiving the GPU's actions as near-tie
 hints (adopted only where the oracle's own top logits are within 1e-5 of each
-other).  Compared: every step's counters and acting uids exactly, the
-controller logits within 1e-5 * max(1, max|logit|) per agent, and at every
-chunk end the integer state bit-exactly and the hidden state within 1e-5.
+other).  Compared: every step's counters (including the sum of ages at death) and
+acting uids exactly, the controller logits within 1e-5 * max(1, max|logit|)
+per agent, at every chunk end the integer state bit-exactly and the hidden
+state within 1e-5, and at the end every completed movement window's
+histogram exactly.
 """
 import sys
 
@@ -68,13 +70,21 @@ def run_parity(World, OracleWorld, OracleConfig, cfg, seed, steps, K, mode="kern
             stats["births"] += info["births"]
             stats["deaths"] += info["deaths"]
             stats["agent_steps"] += len(oc["uid"])
-            for key in ("n_live", "births", "deaths", "eaten", "resources", "claim_wins"):
+            for key in ("n_live", "births", "deaths", "eaten", "resources", "claim_wins", "dead_age"):
                 assert ctr[key][s] == info[key], (key, t + s, int(ctr[key][s]), info[key])
         t += k
         chunk += 1
         want_theta = theta_every and chunk % theta_every == 0
         compare_state(gw.snapshot(hidden=True, theta=want_theta),
                       ow.state(with_hidden=True, with_theta=want_theta), f"t={t}", theta=want_theta)
+    # movement windows (App. C) that ended, bit-exact
+    nw = t // 50
+    if nw > 0:
+        k0 = max(0, nw - 64)
+        gh = gw.move_hist(k0, nw - k0)
+        oh = ow.move_hist()[k0:nw]
+        assert np.array_equal(gh, oh), ("movement histograms", k0, gh, oh)
+        stats["move_windows"] = nw - k0
     gw.close()
     ow.close()
     return stats

@@ -85,6 +85,32 @@ def test_batched_equals_alone(env, mode):
         w.close()
 
 
+def test_oversubscribed_batch_equals_alone(env):
+    """A batched launch with more blocks than the GPU holds at once (36 full-size
+    grids: ~14k claim-kernel blocks): blocks of one world start while other
+    blocks of the same world have already finished, including its closing claim
+    tile; every world must still match stepping it alone bit for bit."""
+    world, wl = env
+    import torch
+    cfgs = [(wl.make(H=200, W=400, cap=2048, n_init=1800 - 20 * i, obs_radius=3, hidden=32, res_init_p=0.3,
+                     rate_scale=5.0, T_repr=8), 100 + i) for i in range(36)]
+    say(f"[systems] oversubscribed batch of {len(cfgs)} worlds")
+    stream = torch.cuda.Stream()
+    ws = [world.World(cfg, seed, stream=stream, mode="kernels") for cfg, seed in cfgs]
+    for _ in range(2):
+        world.step_many(ws, 15)
+    batched = [w.snapshot(hidden=True, theta=True) for w in ws]
+    for w in ws:
+        w.close()
+    for i, (cfg, seed) in enumerate(cfgs):
+        if i % 5:
+            continue   # a sample of the worlds stepped alone
+        w = world.World(cfg, seed, mode="kernels")
+        w.step(30)
+        same(w.snapshot(hidden=True, theta=True), batched[i], f"world {i}")
+        w.close()
+
+
 def test_snapshot_load_resume(env):
     world, wl = env
     cfg = dense(wl, obs_radius=3, hidden=32)
@@ -104,6 +130,35 @@ def test_snapshot_load_resume(env):
     ca, cb = a.counters(mid["t"], 60), b.counters(mid["t"], 60)
     for k in ca:
         assert np.array_equal(ca[k], cb[k]), k
+
+
+def test_move_windows_across_load(env):
+    """Movement windows (App. C) after a load: the window in progress at the
+    load counts no agent, the next one equals the uninterrupted run's, and
+    windows not yet ended or no longer held are refused."""
+    world, wl = env
+    cfg = dense(wl, obs_radius=3, hidden=32, L_max=400)
+    a = world.World(cfg, 9, mode="graph")
+    a.step(70)
+    mid = a.snapshot(hidden=True, theta=True)
+    a.step(80)
+    ref = a.move_hist(0, 3)
+    assert ref[:, -1].min() > 0 and np.array_equal(ref[:, :-1].sum(axis=1), ref[:, -1])
+    b = world.World(cfg, 9, mode="kernels")
+    b.load(mid)
+    b.step(80)
+    got = b.move_hist(1, 2)
+    assert got[0, -1] == 0 and got[0, :-1].sum() == 0     # in progress at the load
+    assert np.array_equal(got[1], ref[2])
+    with pytest.raises(world.WorldError):
+        b.move_hist(2, 2)                                 # window 3 has not ended
+    for _ in range(35):
+        a.step(100)
+    with pytest.raises(world.WorldError):
+        a.move_hist(0, 1)                                 # overwritten in the ring
+    assert a.move_hist(a.snapshot()["t"] // 50 - 64, 64).shape == (64, 18)
+    a.close()
+    b.close()
 
 
 def test_load_rejects_bad_images(env):
