@@ -588,8 +588,10 @@ __device__ __forceinline__ void move_block(DevRef d, PosRec* P, int j, int lane,
     const bool dead = i < n && (res & 2);
     const int cnt = __popcll(__ballot((res & 1) != 0));
     int dage = dead ? nr.age : 0;   // age at death (life expectancy, App. C)
+    if (__ballot(dead)) {            // deaths are rare: most tiles skip the sum
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) dage += __shfl_xor(dage, off);
+        for (int off = 32; off > 0; off >>= 1) dage += __shfl_xor(dage, off);
+    }
     if (lane == 0) {
         d.eat_part[j] = cnt;
         d.dage_part[j] = dage;
