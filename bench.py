@@ -304,6 +304,19 @@ def main():
     agent_steps = int(acting.sum())
     value = agent_steps / wall
     end = w.snapshot()
+    # ecology metrics of App. C over the timed steps (computed inside them)
+    deaths = int(ctr["deaths"].sum())
+    win0 = (t_first + 49) // 50
+    win1 = (t_first + args.steps) // 50
+    mh = w.move_hist(win1 - 1, 1)[0] if win1 > win0 else None
+    metrics = {
+        "life_expectancy": float(ctr["dead_age"].sum()) / deaths if deaths else None,
+        "resources_mean": float(ctr["resources"].mean()),
+        "population_mean": float(ctr["n_live"].mean()),
+        "movement_window": None if mh is None else {
+            "window": int(win1 - 1), "counted": int(mh[-1]),
+            "percent_by_bin": [round(100.0 * float(x) / max(int(mh[-1]), 1), 2) for x in mh[:-1]]},
+    }
     log(f"[bench] timed {args.steps} steps in {wall * 1e3:.2f} ms ({best}); agent-steps {agent_steps}; "
         f"N_live mean {acting.mean():.1f} min {acting.min()} max {acting.max()}; births {int(ctr['births'].sum())} "
         f"deaths {int(ctr['deaths'].sum())}")
@@ -423,6 +436,7 @@ def main():
             "step_dense_equivalent_GBps": dense_step / (wall / args.steps) / 1e9,
             "kernel_source_sha256_16": src_hash,
         },
+        "ecology_metrics": metrics,
         "cpu_baseline": cpu,
         "batched": batched,
         "served": served,
