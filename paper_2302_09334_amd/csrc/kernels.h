@@ -14,7 +14,7 @@
 namespace eco {
 
 enum : int { kPreAct = 0, kPreMove = 1, kPreClaim = 2, kPreKinds = 3 };
-constexpr int kNewbornBlocks = 64;   // leading act blocks that create children
+constexpr int kNewbornBlocks = 512;  // leading act blocks that create children (idle ones exit at once)
 
 struct Batch {
     const WorldDev* const* w;   // n descriptors
