@@ -271,6 +271,204 @@ void oracle_gru_eval(int32_t n_in, int32_t hd, const float *th, const double *x,
 }
 
 /* ========================================================================= */
+/* The paper's controller (App. B.5): a two-layer CNN over the 15 x 15 x 3   */
+/* observation, an LSTM cell of 4 units, a dense layer of 8 with tanh and a  */
+/* dense layer of 5 action logits.  Readings where the text is open:         */
+/*  - each convolution pads its input with zeros on both sides as needed for */
+/*    ceil(n / stride) outputs ("SAME"); each pooling keeps only full        */
+/*    windows ("VALID"); no nonlinearity follows a convolution (none is      */
+/*    named); the flattened feature order is (row, column, channel);         */
+/*  - the embedding is [CNN features, one-hot of the previous action (all    */
+/*    zero before the agent's first action), 1 if the agent ate in its       */
+/*    previous step]; the LSTM's input kernel has no bias, its hidden kernel */
+/*    has one; gates in the order i, f, g, o; state (h, c) zero at birth;    */
+/*  - the dense layer of 8 reads [embedding, new h].                         */
+/* These readings give exactly the 2445 parameters the paper states.         */
+/* Genome order (also the key of the initial and mutation draws):            */
+/*   conv1 K[ky][kx][ci][co], conv1 b[co], conv2 K[ky][kx][ci][co], conv2 b, */
+/*   LSTM Wi[i][gate][unit], Wh[j][gate][unit], b[gate][unit],               */
+/*   dense8 W[i][o], b[o], dense5 W[o][a], b[a].                              */
+/* ========================================================================= */
+
+enum { CNN_RHO = 7, CNN_HD = 4, CNN_CH = 3, CNN_F1 = 4, CNN_F2 = 8, CNN_K = 3, CNN_S = 2, CNN_POOL = 2,
+       CNN_D = 8, CNN_NA = 5 };
+
+typedef struct {
+    int32_t win;                 /* observation edge                              */
+    int32_t o1, pad1, p1;        /* conv1 output edge, its low padding, pool1 edge */
+    int32_t o2, pad2, p2;        /* conv2 output edge, its low padding, pool2 edge */
+    int32_t flat, emb, cat;      /* CNN features, LSTM input, dense-8 input        */
+    int32_t c1w, c1b, c2w, c2b, lwi, lwh, lb, d8w, d8b, d5w, d5b, P;
+} cnn_layout;
+
+/* Output edge of a SAME convolution and its low-side padding. */
+static void same_conv(int32_t n, int32_t *out, int32_t *pad_lo)
+{
+    int32_t o = (n + CNN_S - 1) / CNN_S;
+    int32_t total = (o - 1) * CNN_S + CNN_K - n;
+    if (total < 0) total = 0;
+    *out = o;
+    *pad_lo = total / 2;
+}
+
+static cnn_layout cnn_layout_of(void)
+{
+    cnn_layout L;
+    L.win = 2 * CNN_RHO + 1;
+    same_conv(L.win, &L.o1, &L.pad1);
+    L.p1 = L.o1 - CNN_POOL + 1;
+    same_conv(L.p1, &L.o2, &L.pad2);
+    L.p2 = L.o2 - CNN_POOL + 1;
+    L.flat = L.p2 * L.p2 * CNN_F2;
+    L.emb = L.flat + CNN_NA + 1;
+    L.cat = L.emb + CNN_HD;
+    L.c1w = 0;
+    L.c1b = L.c1w + CNN_K * CNN_K * CNN_CH * CNN_F1;
+    L.c2w = L.c1b + CNN_F1;
+    L.c2b = L.c2w + CNN_K * CNN_K * CNN_F1 * CNN_F2;
+    L.lwi = L.c2b + CNN_F2;
+    L.lwh = L.lwi + L.emb * 4 * CNN_HD;
+    L.lb = L.lwh + CNN_HD * 4 * CNN_HD;
+    L.d8w = L.lb + 4 * CNN_HD;
+    L.d8b = L.d8w + L.cat * CNN_D;
+    L.d5w = L.d8b + CNN_D;
+    L.d5b = L.d5w + CNN_D * CNN_NA;
+    L.P = L.d5b + CNN_NA;
+    return L;
+}
+
+int32_t oracle_cnn_n_params(void) { return cnn_layout_of().P; }
+int32_t oracle_cnn_n_features(void) { return cnn_layout_of().flat; }
+
+/* One evaluation in double.  obs: win x win x 3 (row, column, channel);
+ * prev_action in 0..4 or 5 (none); h, c: the 4-unit state (float). */
+void oracle_cnn_eval(const float *th, const double *obs, int32_t prev_action, int32_t ate,
+                     const float *h, const float *c, double *h_out, double *c_out, double *logits)
+{
+    cnn_layout L = cnn_layout_of();
+    double a1[8 * 8 * CNN_F1], q1[7 * 7 * CNN_F1], a2[4 * 4 * CNN_F2], emb[78], cat[82], y8[CNN_D];
+    /* conv1 */
+    for (int oy = 0; oy < L.o1; ++oy)
+        for (int ox = 0; ox < L.o1; ++ox)
+            for (int co = 0; co < CNN_F1; ++co) {
+                double s = (double)th[L.c1b + co];
+                for (int ky = 0; ky < CNN_K; ++ky)
+                    for (int kx = 0; kx < CNN_K; ++kx) {
+                        int iy = oy * CNN_S + ky - L.pad1, ix = ox * CNN_S + kx - L.pad1;
+                        if (iy < 0 || iy >= L.win || ix < 0 || ix >= L.win) continue;   /* zero padding */
+                        for (int ci = 0; ci < CNN_CH; ++ci)
+                            s += (double)th[L.c1w + ((ky * CNN_K + kx) * CNN_CH + ci) * CNN_F1 + co] *
+                                 obs[(iy * L.win + ix) * CNN_CH + ci];
+                    }
+                a1[(oy * L.o1 + ox) * CNN_F1 + co] = s;
+            }
+    /* pool1: mean of each 2 x 2 window, stride 1 */
+    for (int y = 0; y < L.p1; ++y)
+        for (int x = 0; x < L.p1; ++x)
+            for (int ch = 0; ch < CNN_F1; ++ch) {
+                double s = 0.0;
+                for (int dy = 0; dy < CNN_POOL; ++dy)
+                    for (int dx = 0; dx < CNN_POOL; ++dx) s += a1[((y + dy) * L.o1 + x + dx) * CNN_F1 + ch];
+                q1[(y * L.p1 + x) * CNN_F1 + ch] = s / (double)(CNN_POOL * CNN_POOL);
+            }
+    /* conv2 */
+    for (int oy = 0; oy < L.o2; ++oy)
+        for (int ox = 0; ox < L.o2; ++ox)
+            for (int co = 0; co < CNN_F2; ++co) {
+                double s = (double)th[L.c2b + co];
+                for (int ky = 0; ky < CNN_K; ++ky)
+                    for (int kx = 0; kx < CNN_K; ++kx) {
+                        int iy = oy * CNN_S + ky - L.pad2, ix = ox * CNN_S + kx - L.pad2;
+                        if (iy < 0 || iy >= L.p1 || ix < 0 || ix >= L.p1) continue;
+                        for (int ci = 0; ci < CNN_F1; ++ci)
+                            s += (double)th[L.c2w + ((ky * CNN_K + kx) * CNN_F1 + ci) * CNN_F2 + co] *
+                                 q1[(iy * L.p1 + ix) * CNN_F1 + ci];
+                    }
+                a2[(oy * L.o2 + ox) * CNN_F2 + co] = s;
+            }
+    /* pool2, flattened in (row, column, channel) order into the embedding */
+    for (int y = 0; y < L.p2; ++y)
+        for (int x = 0; x < L.p2; ++x)
+            for (int ch = 0; ch < CNN_F2; ++ch) {
+                double s = 0.0;
+                for (int dy = 0; dy < CNN_POOL; ++dy)
+                    for (int dx = 0; dx < CNN_POOL; ++dx) s += a2[((y + dy) * L.o2 + x + dx) * CNN_F2 + ch];
+                emb[(y * L.p2 + x) * CNN_F2 + ch] = s / (double)(CNN_POOL * CNN_POOL);
+            }
+    for (int a = 0; a < CNN_NA; ++a) emb[L.flat + a] = (prev_action == a) ? 1.0 : 0.0;
+    emb[L.flat + CNN_NA] = ate ? 1.0 : 0.0;
+    /* LSTM cell */
+    double z[4][CNN_HD];
+    for (int g = 0; g < 4; ++g)
+        for (int k = 0; k < CNN_HD; ++k) {
+            double s = (double)th[L.lb + g * CNN_HD + k];
+            for (int i = 0; i < L.emb; ++i) s += (double)th[L.lwi + (i * 4 + g) * CNN_HD + k] * emb[i];
+            for (int j = 0; j < CNN_HD; ++j) s += (double)th[L.lwh + (j * 4 + g) * CNN_HD + k] * (double)h[j];
+            z[g][k] = s;
+        }
+    for (int k = 0; k < CNN_HD; ++k) {
+        double ig = sigmoid(z[0][k]), fg = sigmoid(z[1][k]), gg = tanh(z[2][k]), og = sigmoid(z[3][k]);
+        c_out[k] = fg * (double)c[k] + ig * gg;
+        h_out[k] = og * tanh(c_out[k]);
+    }
+    /* dense 8 with tanh over [embedding, h'], then the 5 logits */
+    for (int i = 0; i < L.emb; ++i) cat[i] = emb[i];
+    for (int k = 0; k < CNN_HD; ++k) cat[L.emb + k] = h_out[k];
+    for (int o = 0; o < CNN_D; ++o) {
+        double s = (double)th[L.d8b + o];
+        for (int i = 0; i < L.cat; ++i) s += (double)th[L.d8w + i * CNN_D + o] * cat[i];
+        y8[o] = tanh(s);
+    }
+    for (int a = 0; a < CNN_NA; ++a) {
+        double s = (double)th[L.d5b + a];
+        for (int o = 0; o < CNN_D; ++o) s += (double)th[L.d5w + o * CNN_NA + a] * y8[o];
+        logits[a] = s;
+    }
+}
+
+/* Action sampling of the paper's controller (App. B.5): a draw from the
+ * softmax of the logits at temperature 1/50.  Reading: the Gumbel-max form,
+ * arg max_a (50 l_a + g_a) with g_a = -ln(-ln u_a) standard Gumbel, u_a =
+ * (2 j + 1) 2^-24 from the top 23 bits j of word a % 4 of block a / 4 of the
+ * ACT stream (agent uid, step), in single precision with the logarithm above;
+ * lowest index on an exact tie. */
+static float gumbel_of_word(uint32_t word)
+{
+    float u = (float)(((word >> 9) << 1) | 1u) * 0x1p-24f;   /* exact, in [2^-24, 1 - 2^-24] */
+    float e = -ln_unit(u);                                     /* exponential(1), > 0 */
+    return -ln_unit(e);
+}
+
+void oracle_gumbel(const uint32_t *words, float *g, size_t n)
+{
+    for (size_t i = 0; i < n; ++i) g[i] = gumbel_of_word(words[i]);
+}
+
+/* Sampling scores s_a = 50 * l_a + g_a of agent `u` at step `t`. */
+static void sample_scores(uint64_t seed, uint32_t u, uint32_t t, const float *lf, float *s)
+{
+    uint32_t r0[4], r1[4];
+    draw(seed, u, t, ORACLE_S_ACT, 0, r0);
+    draw(seed, u, t, ORACLE_S_ACT, 1, r1);
+    for (int a = 0; a < CNN_NA; ++a) {
+        float g = gumbel_of_word(a < 4 ? r0[a] : r1[a - 4]);
+        float sc = 50.0f * lf[a];
+        s[a] = sc + g;
+    }
+}
+
+int32_t oracle_sample_action(uint64_t seed, uint32_t uid, uint32_t step, const float *logits, float *scores)
+{
+    float s[CNN_NA];
+    sample_scores(seed, uid, step, logits, s);
+    int best = 0;
+    for (int a = 1; a < CNN_NA; ++a)
+        if (s[a] > s[best]) best = a;
+    if (scores) memcpy(scores, s, sizeof(s));
+    return best;
+}
+
+/* ========================================================================= */
 /* Regrowth threshold table (App. B.1, Eq. (1), benchmark parameterisation): */
 /*   rate(row) = rate_top + (rate_bottom - rate_top) * row / (H - 1)         */
 /*   rate     *= rate_scale                                                  */
@@ -314,6 +512,8 @@ typedef struct {
     uint64_t seed;
     genome_layout gl;
     int32_t rho, win, n_in;
+    int32_t P;                 /* parameters per agent                      */
+    int32_t ss;                /* recurrent state floats per agent          */
     int64_t t;
     uint32_t next_uid;
     int32_t n;                 /* live agents                               */
@@ -329,8 +529,10 @@ typedef struct {
     uint8_t *wvalid;
     int32_t n_windows, windows_cap;
     int32_t *move_hist;        /* n_windows x (ORACLE_MOVE_BINS + 1): bins, count */
-    float *h;                  /* cap * hd   */
+    float *h;                  /* cap * ss: h (GRU); h then c (LSTM)        */
     float *theta;              /* cap * P    */
+    int32_t *pact;             /* previous action, ORACLE_NO_ACTION if none */
+    uint8_t *pate;             /* ate in the previous step                  */
     /* forced actions */
     int32_t *forced;
     int32_t n_forced, forced_default;
@@ -346,6 +548,8 @@ typedef struct {
     uint8_t *alive, *ate, *won;
     double *x, *hnew;
 } world;
+
+static void observe_cnn(const world *w, int a, double *obs);
 
 /* Action deltas: 0 = N (row - 1), 1 = S (row + 1), 2 = E (col + 1),
  * 3 = W (col - 1), 4 = stay. */
@@ -378,7 +582,7 @@ void oracle_destroy(void *vw)
     free(w->R); free(w->occ); free(w->thr);
     free(w->uid); free(w->row); free(w->col); free(w->e); free(w->age); free(w->streak);
     free(w->wrow); free(w->wcol); free(w->wvalid); free(w->move_hist);
-    free(w->h); free(w->theta); free(w->forced);
+    free(w->h); free(w->theta); free(w->forced); free(w->pact); free(w->pate);
     free(w->last_uid); free(w->last_logits); free(w->last_act);
     free(w->act); free(w->claim); free(w->best); free(w->who);
     free(w->alive); free(w->ate); free(w->won); free(w->x); free(w->hnew);
@@ -389,8 +593,14 @@ void oracle_destroy(void *vw)
  * weight is N(0, gain / sqrt(fan_in)) with fan_in = inputs for W_ih and
  * Hd for W_hh and W_o; biases start at 0.  Parameter p uses lane p % 4 of
  * generator block p / 4 of stream INIT_W keyed by the agent's uid. */
+static void init_genome_cnn(const world *w, uint32_t u, float *th);
+
 static void init_genome(const world *w, uint32_t u, float *th)
 {
+    if (w->cfg.controller == ORACLE_CTRL_CNN_LSTM) {
+        init_genome_cnn(w, u, th);
+        return;
+    }
     const genome_layout *L = &w->gl;
     float std_ih = (float)(w->cfg.w_init_gain / sqrt((double)L->n_in));
     float std_hd = (float)(w->cfg.w_init_gain / sqrt((double)L->hd));
@@ -413,6 +623,39 @@ static void init_genome(const world *w, uint32_t u, float *th)
     }
 }
 
+/* The paper's controller starts the same way: weight std gain / sqrt(fan_in)
+ * (fan_in = 27 and 36 for the convolutions, 78 and 4 for the LSTM's input and
+ * hidden kernels, 82 and 8 for the dense layers), biases 0, parameter p from
+ * lane p % 4 of block p / 4 of stream INIT_W. */
+static void init_genome_cnn(const world *w, uint32_t u, float *th)
+{
+    cnn_layout L = cnn_layout_of();
+    double gain = w->cfg.w_init_gain;
+    for (int32_t p = 0; p < L.P; ++p) {
+        int fan = 0;
+        if (p < L.c1b) fan = CNN_K * CNN_K * CNN_CH;
+        else if (p < L.c2w) fan = 0;
+        else if (p < L.c2b) fan = CNN_K * CNN_K * CNN_F1;
+        else if (p < L.lwi) fan = 0;
+        else if (p < L.lwh) fan = L.emb;
+        else if (p < L.lb) fan = CNN_HD;
+        else if (p < L.d8w) fan = 0;
+        else if (p < L.d8b) fan = L.cat;
+        else if (p < L.d5w) fan = 0;
+        else if (p < L.d5b) fan = CNN_D;
+        if (fan == 0) {
+            th[p] = 0.0f;
+            continue;
+        }
+        float std = (float)(gain / sqrt((double)fan));
+        uint32_t r[4];
+        float z[4];
+        draw(w->seed, u, 0, ORACLE_S_INIT_W, (uint32_t)(p / 4), r);
+        gauss_block(r, z);
+        th[p] = std * z[p % 4];
+    }
+}
+
 void *oracle_create(const oracle_config *cfg, uint64_t seed, char *err, size_t errlen)
 {
     if (cfg->H < 2 || cfg->W < 1) { set_err(err, errlen, "grid must be at least 2 x 1"); return NULL; }
@@ -421,8 +664,16 @@ void *oracle_create(const oracle_config *cfg, uint64_t seed, char *err, size_t e
     if (cfg->n_init < 0 || cfg->n_init > cfg->cap || cfg->n_init > cfg->H * cfg->W) {
         set_err(err, errlen, "n_init out of range"); return NULL;
     }
-    if (cfg->obs_radius < 1 || cfg->obs_radius > 3) { set_err(err, errlen, "obs_radius must be 1..3"); return NULL; }
-    if (cfg->hidden != 16 && cfg->hidden != 32) { set_err(err, errlen, "hidden must be 16 or 32"); return NULL; }
+    if (cfg->controller == ORACLE_CTRL_CNN_LSTM) {
+        if (cfg->obs_radius != CNN_RHO) { set_err(err, errlen, "the paper's controller needs obs_radius 7"); return NULL; }
+        if (cfg->hidden != CNN_HD) { set_err(err, errlen, "the paper's controller needs hidden 4"); return NULL; }
+    } else if (cfg->controller == ORACLE_CTRL_GRU) {
+        if (cfg->obs_radius < 1 || cfg->obs_radius > 3) { set_err(err, errlen, "obs_radius must be 1..3"); return NULL; }
+        if (cfg->hidden != 16 && cfg->hidden != 32) { set_err(err, errlen, "hidden must be 16 or 32"); return NULL; }
+    } else {
+        set_err(err, errlen, "unknown controller");
+        return NULL;
+    }
     if (cfg->E0 <= 0) { set_err(err, errlen, "E0 must be positive"); return NULL; }
 
     world *w = (world *)calloc(1, sizeof(world));
@@ -430,12 +681,15 @@ void *oracle_create(const oracle_config *cfg, uint64_t seed, char *err, size_t e
     w->seed = seed;
     w->rho = cfg->obs_radius;
     w->win = 2 * w->rho + 1;
-    w->n_in = oracle_n_inputs(w->rho);
-    w->gl = layout_of(w->n_in, cfg->hidden);
+    int cnn = cfg->controller == ORACLE_CTRL_CNN_LSTM;
+    w->n_in = cnn ? w->win * w->win * CNN_CH : oracle_n_inputs(w->rho);
+    w->gl = layout_of(cnn ? 1 : w->n_in, cfg->hidden);
+    w->P = cnn ? cnn_layout_of().P : w->gl.P;
+    w->ss = cnn ? 2 * cfg->hidden : cfg->hidden;
     size_t HW = (size_t)cfg->H * cfg->W;
     size_t cap = (size_t)cfg->cap;
-    int hd = cfg->hidden;
-    size_t P = (size_t)w->gl.P;
+    int hd = w->ss;
+    size_t P = (size_t)w->P;
 
     w->R = (uint8_t *)calloc(HW, 1);
     w->occ = (int32_t *)malloc(HW * sizeof(int32_t));
@@ -451,6 +705,8 @@ void *oracle_create(const oracle_config *cfg, uint64_t seed, char *err, size_t e
     w->wvalid = (uint8_t *)calloc(cap, 1);
     w->h = (float *)calloc(cap * hd, sizeof(float));
     w->theta = (float *)calloc(cap * P, sizeof(float));
+    w->pact = (int32_t *)calloc(cap, sizeof(int32_t));
+    w->pate = (uint8_t *)calloc(cap, 1);
     w->last_uid = (uint32_t *)calloc(cap, sizeof(uint32_t));
     w->last_logits = (double *)calloc(cap * 5, sizeof(double));
     w->last_act = (uint8_t *)calloc(cap, 1);
@@ -465,7 +721,7 @@ void *oracle_create(const oracle_config *cfg, uint64_t seed, char *err, size_t e
     w->hnew = (double *)calloc((size_t)hd, sizeof(double));
     w->forced_default = -1;
     if (!w->R || !w->occ || !w->thr || !w->uid || !w->h || !w->theta || !w->best || !w->who || !w->wrow ||
-        !w->wcol || !w->wvalid) {
+        !w->wcol || !w->wvalid || !w->pact || !w->pate) {
         set_err(err, errlen, "out of memory");
         oracle_destroy(w);
         return NULL;
@@ -499,6 +755,8 @@ void *oracle_create(const oracle_config *cfg, uint64_t seed, char *err, size_t e
         w->age[a] = 0;
         w->streak[a] = 0;
         w->occ[cell] = a;
+        w->pact[a] = ORACLE_NO_ACTION;
+        w->pate[a] = 0;
         init_genome(w, (uint32_t)a, w->theta + (size_t)a * P);
     }
     free(keys);
@@ -552,6 +810,29 @@ static void observe(const world *w, int a, double *x)
     x[2 * win * win] = (double)w->e[a] / (double)w->cfg.E0;
 }
 
+/* Observation of the paper's controller (App. B.2): the 15 x 15 square around
+ * the agent, three channels per pixel: resource, number of agents (0 or 1
+ * here, the agent itself included), wall.  Reading: the only walls are the
+ * cells outside the grid, which show no resource and no agent. */
+static void observe_cnn(const world *w, int a, double *obs)
+{
+    int rho = w->rho, win = w->win, W = w->cfg.W;
+    for (int dy = -rho; dy <= rho; ++dy)
+        for (int dx = -rho; dx <= rho; ++dx) {
+            double *px = obs + ((dy + rho) * win + (dx + rho)) * CNN_CH;
+            int r = w->row[a] + dy, c = w->col[a] + dx;
+            if (in_grid(w, r, c)) {
+                px[0] = w->R[r * W + c] ? 1.0 : 0.0;
+                px[1] = (w->occ[r * W + c] != -1) ? 1.0 : 0.0;
+                px[2] = 0.0;
+            } else {
+                px[0] = 0.0;
+                px[1] = 0.0;
+                px[2] = 1.0;
+            }
+        }
+}
+
 static uint64_t claim_key(uint32_t draw_word, uint32_t u)
 {
     return ((uint64_t)draw_word << 32) | (uint64_t)u;
@@ -562,9 +843,10 @@ int oracle_step(void *vw, const uint32_t *hint_uid, const uint8_t *hint_act, int
 {
     world *w = (world *)vw;
     const oracle_config *cfg = &w->cfg;
-    const int H = cfg->H, W = cfg->W, hd = cfg->hidden;
+    const int H = cfg->H, W = cfg->W, hd = w->ss;   /* hd: state floats per agent */
     const size_t HW = (size_t)H * W;
-    const size_t P = (size_t)w->gl.P;
+    const size_t P = (size_t)w->P;
+    const int cnn = cfg->controller == ORACLE_CTRL_CNN_LSTM;
     const uint32_t t = (uint32_t)w->t;
     oracle_stepinfo inf;
     memset(&inf, 0, sizeof(inf));
@@ -584,34 +866,53 @@ int oracle_step(void *vw, const uint32_t *hint_uid, const uint8_t *hint_act, int
     w->last_n = w->n;
     for (int a = 0; a < w->n; ++a) {
         uint32_t u = w->uid[a];
-        observe(w, a, w->x);
-        oracle_gru_eval(w->n_in, hd, w->theta + (size_t)a * P, w->x, w->h + (size_t)a * hd,
-                        w->hnew, w->last_logits + (size_t)a * 5);
-        const double *lg = w->last_logits + (size_t)a * 5;
-        /* The hidden state is kept in single precision between steps. */
-        for (int k = 0; k < hd; ++k) w->h[(size_t)a * hd + k] = (float)w->hnew[k];
-        /* Reading: the action is the arg-max of the logits (lowest index on an
-         * exact tie), decided on the single-precision values. */
-        float lf[5];
+        double *lg = w->last_logits + (size_t)a * 5;
+        float *ha = w->h + (size_t)a * hd;
+        float lf[5], sc[5];
+        if (cnn) {
+            observe_cnn(w, a, w->x);
+            oracle_cnn_eval(w->theta + (size_t)a * P, w->x, w->pact[a], w->pate[a], ha, ha + CNN_HD,
+                            w->hnew, w->hnew + CNN_HD, lg);
+        } else {
+            observe(w, a, w->x);
+            oracle_gru_eval(w->n_in, hd, w->theta + (size_t)a * P, w->x, ha, w->hnew, lg);
+        }
+        /* The recurrent state is kept in single precision between steps. */
+        for (int k = 0; k < hd; ++k) ha[k] = (float)w->hnew[k];
         for (int k = 0; k < 5; ++k) lf[k] = (float)lg[k];
+        /* GRU reading: the action is the arg-max of the logits (lowest index
+         * on an exact tie), decided on the single-precision values.  The
+         * paper's controller samples: arg-max of the sampling scores. */
+        if (cnn) sample_scores(w->seed, u, t, lf, sc);
+        else memcpy(sc, lf, sizeof(sc));
         int best = 0;
         for (int k = 1; k < 5; ++k)
-            if (lf[k] > lf[best]) best = k;
+            if (sc[k] > sc[best]) best = k;
         int act = best;
         int fa = forced_action(w, u);
         int forced = fa >= 0 && fa < 5;
         if (forced) act = fa;
-        /* Near-tie resync: adopt the hinted action when it lies within
-         * 1e-5 * max(1, |top|) of this oracle's top logit (a forced action
-         * must be matched exactly). */
+        /* Near-tie resync: adopt the hinted action when its score lies within
+         * the band of this oracle's top score that the logit tolerance allows:
+         * 1e-5 * max(1, |top|) for the GRU's logits; for the sampling scores
+         * 50 times the logit tolerance plus the same relative band (the
+         * Gumbel terms are identical on both sides).  A forced action must be
+         * matched exactly. */
         while (hint_uid && hi < n_hint && hint_uid[hi] < u) ++hi;
         if (hint_uid && hi < n_hint && hint_uid[hi] == u) {
-            int ha = hint_act[hi];
-            if (ha != act) {
-                double top = lg[best];
+            int ha_ = hint_act[hi];
+            if (ha_ != act) {
+                double top = cnn ? (double)sc[best] : lg[best];
+                int hk = (ha_ >= 0 && ha_ < 5) ? ha_ : 0;
+                double hv = cnn ? (double)sc[hk] : lg[hk];
                 double band = 1e-5 * fmax(1.0, fabs(top));
-                if (!forced && ha >= 0 && ha < 5 && top - lg[ha] < band) {
-                    act = ha;
+                if (cnn) {
+                    double lmax = 1.0;
+                    for (int k = 0; k < 5; ++k) lmax = fmax(lmax, fabs(lg[k]));
+                    band += 50.0 * 1e-5 * lmax;
+                }
+                if (!forced && ha_ >= 0 && ha_ < 5 && top - hv < band) {
+                    act = ha_;
                     inf.resyncs++;
                 } else {
                     inf.mismatches++;
@@ -619,6 +920,7 @@ int oracle_step(void *vw, const uint32_t *hint_uid, const uint8_t *hint_act, int
             }
         }
         w->act[a] = act;
+        w->pact[a] = act;
         w->last_uid[a] = u;
         w->last_act[a] = (uint8_t)act;
     }
@@ -669,6 +971,7 @@ int oracle_step(void *vw, const uint32_t *hint_uid, const uint8_t *hint_act, int
             w->ate[a] = 1;
             inf.eaten++;
         }
+        w->pate[a] = w->ate[a];
         w->e[a] = w->e[a] - cfg->decay + cfg->gain * (int32_t)w->ate[a];
         w->age[a] = w->age[a] + 1;
     }
@@ -693,6 +996,8 @@ int oracle_step(void *vw, const uint32_t *hint_uid, const uint8_t *hint_act, int
             w->wrow[n_surv] = w->wrow[a];
             w->wcol[n_surv] = w->wcol[a];
             w->wvalid[n_surv] = w->wvalid[a];
+            w->pact[n_surv] = w->pact[a];
+            w->pate[n_surv] = w->pate[a];
             memmove(w->h + (size_t)n_surv * hd, w->h + (size_t)a * hd, (size_t)hd * sizeof(float));
             memmove(w->theta + (size_t)n_surv * P, w->theta + (size_t)a * P, P * sizeof(float));
         }
@@ -761,6 +1066,8 @@ int oracle_step(void *vw, const uint32_t *hint_uid, const uint8_t *hint_act, int
         w->age[c] = 0;
         w->streak[c] = 0;
         w->wvalid[c] = 0;   /* not alive at the start of the window */
+        w->pact[c] = ORACLE_NO_ACTION;
+        w->pate[c] = 0;
         memset(w->h + (size_t)c * hd, 0, (size_t)hd * sizeof(float));
         /* Mutation (App. B.3): every parameter gets sigma * z added, z from
          * lane p % 4 of block p / 4 of stream MUTATE keyed by the child uid. */
@@ -862,13 +1169,30 @@ void oracle_get_agents(const void *vw, uint32_t *uid, int32_t *row, int32_t *col
 void oracle_get_hidden(const void *vw, float *h)
 {
     const world *w = (const world *)vw;
-    memcpy(h, w->h, (size_t)w->n * w->cfg.hidden * sizeof(float));
+    memcpy(h, w->h, (size_t)w->n * w->ss * sizeof(float));
+}
+
+void oracle_get_recurrent_inputs(const void *vw, uint8_t *last_action, uint8_t *ate)
+{
+    const world *w = (const world *)vw;
+    for (int a = 0; a < w->n; ++a) {
+        if (last_action) last_action[a] = (uint8_t)w->pact[a];
+        if (ate) ate[a] = w->pate[a];
+    }
+}
+
+int oracle_get_obs_cnn(const void *vw, int32_t a, double *obs)
+{
+    const world *w = (const world *)vw;
+    if (w->cfg.controller != ORACLE_CTRL_CNN_LSTM || a < 0 || a >= w->n) return -1;
+    observe_cnn(w, a, obs);
+    return 0;
 }
 
 void oracle_get_theta(const void *vw, float *theta)
 {
     const world *w = (const world *)vw;
-    memcpy(theta, w->theta, (size_t)w->n * w->gl.P * sizeof(float));
+    memcpy(theta, w->theta, (size_t)w->n * w->P * sizeof(float));
 }
 
 int32_t oracle_last_n_acted(const void *w) { return ((const world *)w)->last_n; }

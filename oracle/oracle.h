@@ -43,7 +43,17 @@ typedef struct oracle_config {
     int32_t L_max;         /* age at which an agent dies                           */
     double  sigma_mut;     /* std of the Gaussian weight mutation                  */
     double  w_init_gain;   /* initial weight std = gain / sqrt(fan_in)             */
+    int32_t controller;    /* ORACLE_CTRL_GRU or ORACLE_CTRL_CNN_LSTM              */
 } oracle_config;
+
+/* Controllers.  GRU: the benchmark workloads' GRU cell with a linear head,
+ * actions by arg-max.  CNN_LSTM: the paper's network (App. B.5) over the
+ * 15 x 15 x 3 observation (obs_radius 7, hidden 4), actions sampled from the
+ * softmax at temperature 1/50. */
+#define ORACLE_CTRL_GRU 0
+#define ORACLE_CTRL_CNN_LSTM 1
+/* "No previous action" (an agent that has not acted yet). */
+#define ORACLE_NO_ACTION 5
 
 /* Result of one oracle step. */
 typedef struct oracle_stepinfo {
@@ -74,7 +84,8 @@ enum {
     ORACLE_S_MOVE = 4,
     ORACLE_S_BIRTH = 5,
     ORACLE_S_MUTATE = 6,
-    ORACLE_S_REGROW = 7
+    ORACLE_S_REGROW = 7,
+    ORACLE_S_ACT = 8
 };
 
 /* ---- primitives (exposed so that tests can pin them one by one) ---------- */
@@ -103,6 +114,19 @@ int oracle_threshold_table(const oracle_config *cfg, uint64_t *out);
 void oracle_gru_eval(int32_t n_in, int32_t hidden, const float *theta, const double *x,
                      const float *h, double *h_out, double *logits);
 
+/* The paper's controller (App. B.5).  n_params is 2445, n_features 72.
+ * obs: 15 x 15 x 3 (row, column, channel: resource, agents, wall);
+ * prev_action 0..4 or ORACLE_NO_ACTION; h, c: 4 floats each. */
+int32_t oracle_cnn_n_params(void);
+int32_t oracle_cnn_n_features(void);
+void oracle_cnn_eval(const float *theta, const double *obs, int32_t prev_action, int32_t ate,
+                     const float *h, const float *c, double *h_out, double *c_out, double *logits);
+/* Standard Gumbel deviates from generator words (the sampling reading). */
+void oracle_gumbel(const uint32_t *words, float *g, size_t n);
+/* Sampled action of agent `uid` at `step` from single-precision logits; the
+ * five sampling scores go to `scores` (may be NULL). */
+int32_t oracle_sample_action(uint64_t seed, uint32_t uid, uint32_t step, const float *logits, float *scores);
+
 /* ---- the world ------------------------------------------------------------ */
 
 void *oracle_create(const oracle_config *cfg, uint64_t seed, char *err, size_t errlen);
@@ -126,7 +150,12 @@ uint32_t oracle_next_uid(const void *w);
 void oracle_get_grid(const void *w, uint8_t *R);
 void oracle_get_agents(const void *w, uint32_t *uid, int32_t *row, int32_t *col,
                        int32_t *energy, int32_t *age, int32_t *streak);
-void oracle_get_hidden(const void *w, float *h);          /* n_live x hidden        */
+void oracle_get_hidden(const void *w, float *h);          /* n_live x state: h (GRU); h then c (LSTM) */
+/* Previous action (0..4, ORACLE_NO_ACTION) and whether the agent ate in its
+ * previous step, per live agent. */
+void oracle_get_recurrent_inputs(const void *w, uint8_t *last_action, uint8_t *ate);
+/* Observation of the paper's controller for live agent `a` (uid order). */
+int oracle_get_obs_cnn(const void *w, int32_t a, double *obs);
 void oracle_get_theta(const void *w, float *theta);       /* n_live x n_params      */
 /* Controller outputs of the last step, for the agents that acted in it (uid
  * order, the population at the start of that step). */

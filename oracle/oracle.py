@@ -38,10 +38,13 @@ class _Cfg(C.Structure):
         ("rate_scale", C.c_double), ("spont", C.c_double),
         ("E0", C.c_int32), ("decay", C.c_int32), ("gain", C.c_int32),
         ("E_repr", C.c_int32), ("T_repr", C.c_int32), ("L_max", C.c_int32),
-        ("sigma_mut", C.c_double), ("w_init_gain", C.c_double),
+        ("sigma_mut", C.c_double), ("w_init_gain", C.c_double), ("controller", C.c_int32),
     ]
 
 
+CTRL_GRU = 0        # the benchmark workloads' GRU with arg-max actions
+CTRL_CNN_LSTM = 1   # the paper's CNN + LSTM with sampled actions (App. B.5)
+NO_ACTION = 5       # previous action of an agent that has not acted yet
 MOVE_WINDOW = 50   # steps per movement window (App. C)
 MOVE_BINS = 17     # distance bins (distance // 3 for distances 0..50)
 
@@ -79,6 +82,12 @@ class OracleConfig:
     L_max: int = 2000
     sigma_mut: float = 0.02
     w_init_gain: float = 0.5
+    controller: int = CTRL_GRU
+
+    @property
+    def state_size(self) -> int:
+        """Recurrent state floats per agent: h (GRU), h then c (LSTM)."""
+        return 2 * self.hidden if self.controller == CTRL_CNN_LSTM else self.hidden
 
     def to_c(self) -> _Cfg:
         c = _Cfg()
@@ -136,6 +145,15 @@ def lib():
         L.oracle_n_move_windows.restype = C.c_int32
         L.oracle_get_move_hist.argtypes = [P, C.c_int32, P, P]
         L.oracle_get_move_hist.restype = C.c_int
+        L.oracle_cnn_n_params.restype = C.c_int32
+        L.oracle_cnn_n_features.restype = C.c_int32
+        L.oracle_cnn_eval.argtypes = [P, P, C.c_int32, C.c_int32, P, P, P, P, P]
+        L.oracle_gumbel.argtypes = [P, P, C.c_size_t]
+        L.oracle_sample_action.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, P, P]
+        L.oracle_sample_action.restype = C.c_int32
+        L.oracle_get_recurrent_inputs.argtypes = [P, P, P]
+        L.oracle_get_obs_cnn.argtypes = [P, C.c_int32, P]
+        L.oracle_get_obs_cnn.restype = C.c_int
         _lib = L
     return _lib
 
@@ -206,6 +224,43 @@ def gru_eval(n_in: int, hidden: int, theta: np.ndarray, x: np.ndarray, h: np.nda
     return h_out, logits
 
 
+def cnn_n_params() -> int:
+    return int(lib().oracle_cnn_n_params())
+
+
+def cnn_n_features() -> int:
+    return int(lib().oracle_cnn_n_features())
+
+
+def cnn_eval(theta, obs, prev_action: int, ate: int, h, c):
+    """The paper's controller in double: (h', c', logits)."""
+    theta = np.ascontiguousarray(theta, dtype=np.float32)
+    obs = np.ascontiguousarray(obs, dtype=np.float64)
+    assert theta.size == cnn_n_params() and obs.size == 15 * 15 * 3
+    h = np.ascontiguousarray(h, dtype=np.float32)
+    c = np.ascontiguousarray(c, dtype=np.float32)
+    ho = np.empty(4, np.float64)
+    co = np.empty(4, np.float64)
+    lg = np.empty(5, np.float64)
+    lib().oracle_cnn_eval(_ptr(theta), _ptr(obs), int(prev_action), int(ate), _ptr(h), _ptr(c),
+                          _ptr(ho), _ptr(co), _ptr(lg))
+    return ho, co, lg
+
+
+def gumbel(words) -> np.ndarray:
+    w = np.ascontiguousarray(words, dtype=np.uint32)
+    g = np.empty(w.shape, np.float32)
+    lib().oracle_gumbel(_ptr(w), _ptr(g), w.size)
+    return g
+
+
+def sample_action(seed: int, uid: int, step: int, logits):
+    lf = np.ascontiguousarray(logits, dtype=np.float32)
+    sc = np.empty(5, np.float32)
+    a = lib().oracle_sample_action(C.c_uint64(seed), uid, step, _ptr(lf), _ptr(sc))
+    return int(a), sc
+
+
 # --------------------------------------------------------------------- world
 
 class OracleWorld:
@@ -219,7 +274,7 @@ class OracleWorld:
         self._h = lib().oracle_create(C.byref(c), C.c_uint64(self.seed), err, 256)
         if not self._h:
             raise ValueError(err.value.decode())
-        self.P = n_params(cfg.obs_radius, cfg.hidden)
+        self.P = cnn_n_params() if cfg.controller == CTRL_CNN_LSTM else n_params(cfg.obs_radius, cfg.hidden)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -272,9 +327,26 @@ class OracleWorld:
         return out
 
     def hidden(self) -> np.ndarray:
-        h = np.empty((self.n_live, self.cfg.hidden), np.float32)
+        """Recurrent state per agent: h (GRU), h then c (LSTM)."""
+        h = np.empty((self.n_live, self.cfg.state_size), np.float32)
         lib().oracle_get_hidden(self._h, _ptr(h))
         return h
+
+    def recurrent_inputs(self) -> dict:
+        """Previous action (NO_ACTION before the first) and ate-in-previous-step bit."""
+        n = self.n_live
+        la = np.empty(n, np.uint8)
+        ate = np.empty(n, np.uint8)
+        lib().oracle_get_recurrent_inputs(self._h, _ptr(la), _ptr(ate))
+        return {"last_action": la, "ate": ate}
+
+    def obs_cnn(self, a: int) -> np.ndarray:
+        """Observation (15, 15, 3) of the paper's controller for live agent a."""
+        o = np.empty((15, 15, 3), np.float64)
+        rc = lib().oracle_get_obs_cnn(self._h, int(a), _ptr(o))
+        if rc != 0:
+            raise ValueError("not a paper-controller world or agent out of range")
+        return o
 
     def theta(self) -> np.ndarray:
         th = np.empty((self.n_live, self.P), np.float32)
