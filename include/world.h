@@ -7,8 +7,11 @@
  * observation and recurrent controller with individual weights (App. B.2,
  * B.5), moves, eating and the energy update (App. B.2), minimal-criterion
  * reproduction with Gaussian mutation and death (App. B.3), here in the
- * parameterisation of the benchmark workloads (integer energies, a GRU cell
- * with a linear head, one agent per cell).
+ * parameterisation of the benchmark workloads (integer energies, one agent
+ * per cell).  Two controllers: a GRU cell with a linear head and arg-max
+ * actions, or the paper's network (App. B.5: two convolutions with average
+ * pooling, an LSTM cell of 4 units, dense layers of 8 and 5) with actions
+ * sampled from the softmax at temperature 1/50.
  *
  * Conventions
  *  - Plain C; every function returns an int status: WORLD_OK (0) or a
@@ -46,17 +49,25 @@ extern "C" {
 #define WORLD_MODE_KERNELS 0      /* one launch per phase per step            */
 #define WORLD_MODE_GRAPH 1        /* K steps of phase launches in a HIP graph */
 
+/* Controllers (world_config.controller). */
+#define WORLD_CTRL_GRU 0        /* GRU + linear head, arg-max of the logits          */
+#define WORLD_CTRL_CNN_LSTM 1   /* the paper's network (App. B.5), sampled actions   */
+/* Previous action of an agent that has not acted yet (world_image.last_action). */
+#define WORLD_NO_ACTION 5
+
 /* Parameters of one world (App. B.4 hyperparameters, benchmark form).
  * Supported: H >= 2, W >= 1, H*W <= 2^26, 1 <= cap <= 2^20,
- * 0 <= n_init <= min(cap, H*W), obs_radius in 1..3, hidden in {16, 32},
- * E0 > 0, decay >= 0, gain >= 0, T_repr >= 1, L_max >= 1, log_steps >= 0. */
+ * 0 <= n_init <= min(cap, H*W), E0 > 0, decay >= 0, gain >= 0, T_repr >= 1,
+ * L_max >= 1, log_steps >= 0; with WORLD_CTRL_GRU obs_radius in 1..3 and
+ * hidden in {16, 32}; with WORLD_CTRL_CNN_LSTM obs_radius 7 (the 15 x 15
+ * field of view) and hidden 4 (the LSTM's units). */
 typedef struct world_config {
     uint32_t struct_size;   /* sizeof(world_config)                               */
     int32_t H, W;           /* grid rows x cols; row 0 = top = slowest regrowth    */
     int32_t cap;            /* agent slots (maximum population)                    */
     int32_t n_init;         /* agents placed at step 0                              */
-    int32_t obs_radius;     /* rho: observation window (2 rho + 1)^2 x 2 + energy    */
-    int32_t hidden;         /* GRU hidden size                                      */
+    int32_t obs_radius;     /* rho: observation window (2 rho + 1)^2                 */
+    int32_t hidden;         /* GRU hidden size, or the LSTM's (4)                   */
     double res_init_p;      /* initial resource probability per cell               */
     double rate_bottom;     /* latitude regrowth rate at row H-1                    */
     double rate_top;        /* latitude regrowth rate at row 0                      */
@@ -72,6 +83,7 @@ typedef struct world_config {
     double w_init_gain;     /* initial weight std = w_init_gain / sqrt(fan_in)       */
     int32_t log_steps;      /* steps of controller log kept on device (0 = none)     */
     uint32_t flags;         /* reserved, must be 0                                    */
+    int32_t controller;     /* WORLD_CTRL_*                                           */
 } world_config;
 
 typedef struct world world_t;
@@ -98,12 +110,22 @@ typedef struct world_counters {
 #define WORLD_MOVE_WINDOW 50
 #define WORLD_MOVE_BINS 17
 
-#define WORLD_SNAP_HIDDEN 1u   /* fill h (agent_capacity x hidden)          */
+#define WORLD_SNAP_HIDDEN 1u   /* fill h, last_action, ate                  */
 #define WORLD_SNAP_THETA 2u    /* fill theta (agent_capacity x n_params)    */
 
 /* Canonical host image of a world.  Agents are listed in increasing uid.
- * theta uses the genome order: W_ih[i][k][g] (inputs x hidden x gates r,z,n),
- * W_hh[j][k][g], b_ih[k][g], b_hh[k][g], W_o[a][k] (5 x hidden), b_o[a]. */
+ * Recurrent state h: agent_capacity x hidden floats for the GRU; for the
+ * paper's network agent_capacity x 8 floats, the LSTM's h (4) then c (4).
+ * last_action: the action the agent took in its previous step (0..4) or
+ * WORLD_NO_ACTION; ate: 1 if it ate in its previous step (both are inputs of
+ * the paper's network and are kept for both controllers).
+ * theta uses the genome order.  GRU: W_ih[i][k][g] (inputs x hidden x gates
+ * r,z,n), W_hh[j][k][g], b_ih[k][g], b_hh[k][g], W_o[a][k] (5 x hidden),
+ * b_o[a].  Paper's network (2445 parameters): conv1 K[ky][kx][ci][co]
+ * (3x3x3x4), b[4]; conv2 K[ky][kx][ci][co] (3x3x4x8), b[8]; LSTM input kernel
+ * [i][gate][unit] (78x4x4, gates i,f,g,o), hidden kernel [j][gate][unit]
+ * (4x4x4), bias [gate][unit]; dense W[i][o] (82x8), b[8]; dense W[o][a]
+ * (8x5), b[5]. */
 typedef struct world_image {
     uint32_t struct_size;    /* sizeof(world_image)                             */
     uint32_t flags;          /* WORLD_SNAP_* bits                               */
@@ -117,12 +139,15 @@ typedef struct world_image {
     int32_t *row, *col, *energy, *age, *streak;
     float *h;
     float *theta;
+    uint8_t *last_action;
+    uint8_t *ate;
 } world_image;
 
 /* Device bytes a world with this configuration needs.  Pure host function. */
 int world_required_bytes(const world_config *cfg, size_t *device_bytes);
 
-/* Inputs and parameters per agent for this configuration.  Pure host. */
+/* Inputs and parameters per agent for this configuration (GRU: window cells
+ * x 2 + energy; paper's network: 15 x 15 x 3 observation values).  Pure host. */
 int world_dims(const world_config *cfg, int32_t *n_inputs, int32_t *n_params);
 
 /* Lay out a world in `device_arena` (>= world_required_bytes, 256-byte aligned,
@@ -137,7 +162,8 @@ int world_create(const world_config *cfg, uint64_t seed, void *device_arena, siz
 int world_step(world_t *w, int32_t K);
 
 /* Enqueue K steps of n worlds in shared launches.  All worlds must use the
- * same stream; the result of every world is bit-identical to stepping it alone. */
+ * same stream and the same controller; the result of every world is
+ * bit-identical to stepping it alone. */
 int world_step_many(world_t *const *ws, int32_t n, int32_t K);
 
 /* Select WORLD_MODE_* for later steps. */
@@ -160,7 +186,8 @@ int world_sync(world_t *w);
 int world_snapshot(world_t *w, world_image *out);
 
 /* Overwrite the world's state from a canonical image (both WORLD_SNAP_HIDDEN
- * and WORLD_SNAP_THETA must be set).  Validates positions, uids and sizes. */
+ * and WORLD_SNAP_THETA must be set, every array present).  Validates
+ * positions, uids, actions and sizes. */
 int world_load(world_t *w, const world_image *in);
 
 /* Synchronise and copy counters of steps [first_step, first_step + n). */
@@ -199,13 +226,17 @@ int world_test_philox(const uint32_t *d_ctr, size_t n, uint32_t k0, uint32_t k1,
 int world_test_gauss(const uint32_t *d_a, const uint32_t *d_b, size_t n, float *d_z0, float *d_z1,
                      void *hip_stream);
 
+/* Gumbel deviates of the paper's action sampling on the device: one per
+ * 32-bit word, n words (device) into d_g (device floats), on hip_stream. */
+int world_test_gumbel(const uint32_t *d_words, size_t n, float *d_g, void *hip_stream);
+
 /* Run K steps as per-phase kernels on the world's stream and return the mean
  * execution time in milliseconds of each phase kernel (start / end events
  * stamped by the kernel's own dispatch, so launch gaps are excluded) in
  * ms[0..2] = act (child genomes of the previous step, observation and
- * controller), move (moves, energy, death, survivor scan, recurrent
- * projection), claim (birth claims, birth scan, regrowth).  The steps are
- * real: the world advances by K.  Synchronises. */
+ * controller), move (moves, energy, death, survivor scan, the GRU's
+ * recurrent projection), claim (birth claims, birth scan, regrowth).  The
+ * steps are real: the world advances by K.  Synchronises. */
 int world_phase_times(world_t *w, int32_t K, float *ms);
 
 /* Plain device-to-device copy kernel (16-byte vector loads/stores) of `bytes`

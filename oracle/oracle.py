@@ -378,6 +378,7 @@ class OracleWorld:
         s.update(self.agents())
         if with_hidden:
             s["h"] = self.hidden()
+            s.update(self.recurrent_inputs())
         if with_theta:
             s["theta"] = self.theta()
         return s

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libworld.so")
 SOURCES = [os.path.join(HERE, "csrc", "world.hip")]
-DEPS = [os.path.join(HERE, "csrc", f) for f in ("rng.h", "world_dev.h", "phases.h", "kernels.h")]
+DEPS = [os.path.join(HERE, "csrc", f) for f in ("rng.h", "world_dev.h", "phases.h", "net.h", "kernels.h")]
 ARCH = os.environ.get("ECO_OFFLOAD_ARCH", "gfx950")
 
 

@@ -9,6 +9,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "net.h"
 #include "phases.h"
 
 namespace eco {
@@ -23,6 +24,7 @@ struct Batch {
     int act_rows;               // act-kernel tuning: input rows per round trip (8, 16, 32)
     const WorldDev* w0;         // n == 1: the descriptor itself (else null)
     int cap0;                   // n == 1: its agent capacity
+    int ctrl;                   // controller of every world in the batch
 };
 
 template <int ROWS>
@@ -77,8 +79,9 @@ __device__ __forceinline__ BlockWorld block_world(const Batch& bt, int kind, int
 // the previous step (rank r, r + kNewbornBlocks, ...) and run their first
 // controller step (they are the last n_child entries of the live list); the
 // remaining blocks run the controller of the other agents, four per block.
-template <int ROWS>
-__device__ __forceinline__ void act_body(const Batch& bt, int vb, int tid, StepShared& sh) {
+// NET: the paper's network (with `lds`, one scratch per wave), else the GRU.
+template <int ROWS, bool NET>
+__device__ __forceinline__ void act_body(const Batch& bt, int vb, int tid, StepShared& sh, net::WaveLds* lds) {
     const BlockWorld bw = block_world(bt, kPreAct, vb);
     DevRef d = *bw.d;
     PosRec* P = bw.P;
@@ -89,9 +92,18 @@ __device__ __forceinline__ void act_body(const Batch& bt, int vb, int tid, StepS
     const int lc = min(max(li, 0), bw.cap - 1);
     const int4 q0 = *reinterpret_cast<const int4*>(&P[lc].r[0]);
     const int4 q1 = *reinterpret_cast<const int4*>(&P[lc].r[1]);
+    int4 q0b = make_int4(0, 0, 0, 0), q1b = make_int4(0, 0, 0, 0);
+    if (NET) {   // the second half: previous action and ate bit
+        q0b = *(reinterpret_cast<const int4*>(&P[lc].r[0]) + 1);
+        q1b = *(reinterpret_cast<const int4*>(&P[lc].r[1]) + 1);
+    }
     const StepScal ss = read_step(bw.S);
     pin(q0.x);
     pin(q1.x);
+    if (NET) {
+        pin(q0b.z);
+        pin(q1b.z);
+    }
     const int64_t t = ss.t;
     const int n = ss.n;
     const int nc = ss.nc;
@@ -106,19 +118,27 @@ __device__ __forceinline__ void act_body(const Batch& bt, int vb, int tid, StepS
         for (int rk = lb; rk < nc; rk += kNewbornBlocks) {
             spawn_child(d, rk, tid);
             __syncthreads();
-            spawn_proj(d, rk, tid);
-            __syncthreads();
+            if (!NET) {
+                spawn_proj(d, rk, tid);
+                __syncthreads();
+            }
             if (tid < 64) {
                 const int lj = n - nc + rk;
                 const int4 rv = *reinterpret_cast<const int4*>(&P[lj].r[sel]);
-                act_dispatch<ROWS>(d, &P[lj].r[sel], rv, lj, t, tid);
+                if (NET) {
+                    const int4 rv2 = *(reinterpret_cast<const int4*>(&P[lj].r[sel]) + 1);
+                    net::act_agent(d, &P[lj].r[sel], rv, rv2, lj, t, tid, lds[0]);
+                } else {
+                    act_dispatch<ROWS>(d, &P[lj].r[sel], rv, lj, t, tid);
+                }
             }
             __syncthreads();
         }
         return;
     }
     if (li >= n - nc) return;
-    act_dispatch<ROWS>(d, &P[li].r[sel], sel ? q1 : q0, li, t, tid & 63);
+    if (NET) net::act_agent(d, &P[li].r[sel], sel ? q1 : q0, sel ? q1b : q0b, li, t, tid & 63, lds[tid >> 6]);
+    else act_dispatch<ROWS>(d, &P[li].r[sel], sel ? q1 : q0, li, t, tid & 63);
 }
 
 // Move blocks of a world (one wave each): the move tiles (look-back order),
@@ -185,7 +205,7 @@ __global__ __launch_bounds__(kBlock)
 #endif
 void k_act(Batch bt) {
     __shared__ StepShared sh;
-    act_body<16>(bt, blockIdx.x, threadIdx.x, sh);
+    act_body<16, false>(bt, blockIdx.x, threadIdx.x, sh, nullptr);
 }
 
 // Tuning variants of the act kernel (identical results, different numbers of
@@ -193,7 +213,14 @@ void k_act(Batch bt) {
 template <int ROWS>
 __global__ __launch_bounds__(kBlock) void k_act_rows(Batch bt) {
     __shared__ StepShared sh;
-    act_body<ROWS>(bt, blockIdx.x, threadIdx.x, sh);
+    act_body<ROWS, false>(bt, blockIdx.x, threadIdx.x, sh, nullptr);
+}
+
+// Act kernel of worlds with the paper's network.
+__global__ __launch_bounds__(kBlock) void k_act_net(Batch bt) {
+    __shared__ StepShared sh;
+    __shared__ net::WaveLds lds[kBlock / 64];
+    act_body<16, true>(bt, blockIdx.x, threadIdx.x, sh, lds);
 }
 
 // Creates the pending children of a world's last step now (before its state
@@ -205,8 +232,10 @@ __global__ __launch_bounds__(kBlock) void k_materialize(const WorldDev* dp) {
     for (int rk = blockIdx.x; rk < nc; rk += gridDim.x) {
         spawn_child(d, rk, threadIdx.x);
         __syncthreads();
-        spawn_proj(d, rk, threadIdx.x);
-        __syncthreads();
+        if (d.ctrl == kCtrlGru) {
+            spawn_proj(d, rk, threadIdx.x);
+            __syncthreads();
+        }
     }
 }
 
@@ -248,10 +277,17 @@ __global__ __launch_bounds__(64) void k_claim(Batch bt) {
     claim_body(bt, blockIdx.x, threadIdx.x, tile);
 }
 
+// Spread of the initial weights: parameter p takes sd[k] for the first k with
+// p < end[k] (0 for biases).
+struct InitSegs {
+    int n;
+    int end[12];
+    float sd[12];
+};
+
 // Initial genomes: agent slots [0, n_init) hold uids 0..n_init-1; parameter p
 // of uid u is std(p) * z_p with z_p lane p % 4 of INIT_W draw (u, 0, p / 4).
-__global__ __launch_bounds__(kBlock) void k_init_theta(const WorldDev* dp, int n_init, float std_ih,
-                                                       float std_hd) {
+__global__ __launch_bounds__(kBlock) void k_init_theta(const WorldDev* dp, int n_init, InitSegs segs) {
     DevRef d = *kconst(dp);
     const int64_t total = int64_t(n_init) * d.nblk;
     for (int64_t it = int64_t(blockIdx.x) * kBlock + threadIdx.x; it < total;
@@ -267,10 +303,12 @@ __global__ __launch_bounds__(kBlock) void k_init_theta(const WorldDev* dp, int n
         for (int j = 0; j < 4; ++j) {
             const int p = 4 * blk + j;
             float sd = 0.f;
-            if (p < d.off_hh) sd = std_ih;
-            else if (p < d.off_bih) sd = std_hd;
-            else if (p < d.off_wo) sd = 0.f;
-            else if (p < d.off_bo) sd = std_hd;
+            bool found = false;
+            for (int k = 0; k < segs.n; ++k)
+                if (!found && p < segs.end[k]) {
+                    sd = segs.sd[k];
+                    found = true;
+                }
             o[j] = (p < d.P && sd != 0.f) ? sd * z[j] : 0.f;
         }
         *reinterpret_cast<float4*>(d.theta + size_t(a) * size_t(d.Ppad) + 4 * blk) =
@@ -290,6 +328,12 @@ __global__ void k_test_philox(const uint32_t* ctr, size_t n, uint32_t k0, uint32
     out[4 * i + 1] = r.y;
     out[4 * i + 2] = r.z;
     out[4 * i + 3] = r.w;
+}
+
+__global__ void k_test_gumbel(const uint32_t* w, size_t n, float* g) {
+    const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    g[i] = gumbel_of_word(w[i]);
 }
 
 __global__ void k_test_gauss(const uint32_t* a, const uint32_t* b, size_t n, float* z0, float* z1) {

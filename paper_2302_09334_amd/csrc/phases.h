@@ -477,6 +477,7 @@ __device__ __forceinline__ int move_agent(DevRef d, const AgentRec& a, int64_t t
     d.cell[slot] = newX;
     d.prev_cell[slot] = X;
     d.alive[slot] = dead ? 0 : 1;
+    d.ate[slot] = uint8_t(ate);
     // Both occupancy grids take the moves and deaths (neither is read in this
     // phase): occA is the next step's start state, occB is read by P3.  A
     // survivor's occB word also says whether it is eligible to reproduce and
@@ -516,8 +517,8 @@ __device__ __forceinline__ int move_agent(DevRef d, const AgentRec& a, int64_t t
     nr.uid = u;
     nr.age = ag;
     nr.streak = st;
-    nr.action = 4;
-    nr.pad = 0;
+    nr.action = act;   // the previous action and ate bit of the next step
+    nr.ate = ate;
     *next_rec_src = nr;
     return ate | (dead ? 2 : 0);
 }
@@ -804,8 +805,8 @@ __device__ __forceinline__ void claim_block(DevRef d, WorldScal* S, PosRec* P, i
             cr.uid = cu;
             cr.age = 0;
             cr.streak = 0;
-            cr.action = 4;
-            cr.pad = 0;
+            cr.action = kNoAction;
+            cr.ate = 0;
             P[surv + rk].r[sel ^ 1] = cr;
             d.occA[cell] = cs;   // occA is neither read nor written by others in this phase
             // the parent's streak restarts (no phase reads these in P3)
@@ -902,7 +903,8 @@ __device__ __forceinline__ void regrow_tile(DevRef d, int tile, int lane, uint8_
 // Child creation (start of P1, one block per child): the genome is
 // theta_child[p] = fmaf(sigma, z_p, theta_parent[p]) with z_p lane p % 4 of
 // the MUTATE draw (child uid, birth step, block p / 4); the record gets
-// energy E0, age 0, streak 0 and a zero hidden state; the child enters occB
+// energy E0, age 0, streak 0, no previous action, a zero recurrent state;
+// the child enters occB
 // (occA received it when it was born; the parent's streak restarted then).
 // Every store is complete when this returns, so the same block can run the
 // child's controller right after a block barrier.
@@ -936,15 +938,16 @@ __device__ __forceinline__ void spawn_child(DevRef d, int rk, int tid) {
         d.streak[cs] = 0;
         d.alive[cs] = 1;
         d.claim[cs] = -1;
-        d.action[cs] = 4;
+        d.action[cs] = kNoAction;
+        d.ate[cs] = 0;
         d.occB[rec.z] = cs;
     }
-    if (tid < d.hd) d.h[size_t(cs) * d.hd + tid] = 0.f;
+    if (tid < d.ss) d.h[size_t(cs) * d.ss + tid] = 0.f;
     __builtin_amdgcn_s_waitcnt(0);   // this thread's stores have completed
 }
 
-// Recurrent projection and window sums of a new agent (after spawn_child and
-// a barrier).
+// Recurrent projection and window sums of a new agent of a GRU world (after
+// spawn_child and a barrier).
 __device__ __forceinline__ void spawn_proj(DevRef d, int rk, int tid) {
     const int cs = d.child[rk].x;
     if (tid < 64) {

@@ -25,6 +25,7 @@ enum : uint32_t {
     kBirth = 5,
     kMutate = 6,
     kRegrow = 7,
+    kAct = 8,   // action sampling of the paper's network
 };
 
 struct Draw4 {
@@ -76,6 +77,36 @@ __host__ __device__ inline float ln_of_24bit(uint32_t v) {
     const float lnm = 2.0f * (s * p);
     const float ef = float(e);
     return fmaf(ef, 0x1.62e4p-1f, fmaf(ef, 0x1.7f7d1cp-20f, lnm));
+}
+
+// ln(x) for a positive normal float x: the same mantissa fold and series as
+// ln_of_24bit, with the exponent read from the float's bits.
+__host__ __device__ inline float ln_positive(float x) {
+    const uint32_t b = __builtin_bit_cast(uint32_t, x);
+    int e = int((b >> 23) & 0xFFu) - 126;
+    float m = __builtin_bit_cast(float, (b & 0x807FFFFFu) | 0x3F000000u);  // exact, in [0.5, 1)
+    if (m < 0x1.6a09e6p-1f) {
+        m = m * 2.0f;
+        e -= 1;
+    }
+    const float s = (m - 1.0f) / (m + 1.0f);
+    const float s2 = s * s;
+    float p = 1.0f / 11.0f;
+    p = fmaf(p, s2, 1.0f / 9.0f);
+    p = fmaf(p, s2, 1.0f / 7.0f);
+    p = fmaf(p, s2, 1.0f / 5.0f);
+    p = fmaf(p, s2, 1.0f / 3.0f);
+    p = fmaf(p, s2, 1.0f);
+    const float lnm = 2.0f * (s * p);
+    const float ef = float(e);
+    return fmaf(ef, 0x1.62e4p-1f, fmaf(ef, 0x1.7f7d1cp-20f, lnm));
+}
+
+// Standard Gumbel deviate -ln(-ln u) from a 32-bit word, u = (2 j + 1) 2^-24
+// with j the word's top 23 bits (u in [2^-24, 1 - 2^-24], exact).
+__host__ __device__ inline float gumbel_of_word(uint32_t w) {
+    const float ex = -ln_of_24bit(((w >> 9) << 1) | 1u);   // -ln u > 0
+    return -ln_positive(ex);
 }
 
 // sin((pi/2) g) and cos((pi/2) g) for g in [0, 1/2] from their Taylor series.

@@ -36,8 +36,21 @@ struct Dims {
     int n_in, P, Ppad, off_hh, off_bih, off_bhh, off_wo, off_bo, nblk, tot_row;
 };
 
+bool is_net(const world_config& c) { return c.controller == WORLD_CTRL_CNN_LSTM; }
+
+// Recurrent state floats per agent: the GRU's h, or the LSTM's h and c.
+int state_of(const world_config& c) { return is_net(c) ? 2 * c.hidden : c.hidden; }
+
 Dims dims_of(const world_config& c) {
     Dims d;
+    if (is_net(c)) {
+        std::memset(&d, 0, sizeof(d));
+        d.n_in = net::kPix * 3;
+        d.P = net::kP;
+        d.Ppad = int(align_up(size_t(d.P), 64));
+        d.nblk = (d.P + 3) / 4;
+        return d;
+    }
     d.n_in = n_inputs_of(c.obs_radius);
     const int hd = c.hidden;
     d.off_hh = d.n_in * hd * 3;
@@ -64,8 +77,15 @@ const char* check_config(const world_config* c) {
     if (c->cap < 1 || c->cap > (1 << 20)) return "cap must be in 1..2^20";
     if (c->n_init < 0 || c->n_init > c->cap || int64_t(c->n_init) > int64_t(c->H) * c->W)
         return "n_init must be in 0..min(cap, H*W)";
-    if (c->obs_radius < 1 || c->obs_radius > 3) return "obs_radius must be 1..3";
-    if (c->hidden != 16 && c->hidden != 32) return "hidden must be 16 or 32";
+    if (c->controller == WORLD_CTRL_CNN_LSTM) {
+        if (c->obs_radius != net::kRho) return "the paper's network needs obs_radius 7";
+        if (c->hidden != net::kHd) return "the paper's network needs hidden 4";
+    } else if (c->controller == WORLD_CTRL_GRU) {
+        if (c->obs_radius < 1 || c->obs_radius > 3) return "obs_radius must be 1..3";
+        if (c->hidden != 16 && c->hidden != 32) return "hidden must be 16 or 32";
+    } else {
+        return "unknown controller";
+    }
     if (c->E0 <= 0 || c->decay < 0 || c->gain < 0) return "E0 > 0, decay >= 0, gain >= 0 required";
     if (c->T_repr < 1 || c->L_max < 1) return "T_repr and L_max must be positive";
     if (c->log_steps < 0) return "log_steps must be >= 0";
@@ -80,7 +100,7 @@ const char* check_config(const world_config* c) {
 // Byte offsets of every array inside the arena.
 struct Layout {
     size_t desc, scal, ring, batch, thr, R0, R1, occA, occB, mclaim;
-    size_t uid, cell, prev_cell, energy, age, streak, action, alive, win, claim, bkey;
+    size_t uid, cell, prev_cell, energy, age, streak, action, alive, ate, claim, bkey;
     size_t live0, live1, pos, freeq, child, h, gh, theta;
     size_t log_uid, log_act, log_logits, log_n, eat_part, dage_part, wcell, wuid, mhist, res_part, deadlist, lb_move,
         lb_claim;
@@ -119,14 +139,14 @@ Layout layout_of(const world_config& c) {
     l.streak = take(4 * cap);
     l.action = take(cap);
     l.alive = take(cap);
-    l.win = take(cap);
+    l.ate = take(cap);
     l.claim = take(4 * cap);
     l.live0 = take(4 * cap);
     l.live1 = take(4 * cap);
     l.freeq = take(4 * cap);
     l.child = take(16 * cap);
-    l.h = take(4 * cap * size_t(c.hidden));
-    l.gh = take(4 * cap * 3 * size_t(c.hidden));
+    l.h = take(4 * cap * size_t(state_of(c)));
+    l.gh = take(is_net(c) ? 0 : 4 * cap * 3 * size_t(c.hidden));
     l.theta = take(4 * cap * size_t(dm.Ppad));
     l.log_uid = take(4 * L * cap);
     l.log_act = take(L * cap);
@@ -166,6 +186,39 @@ void build_thresholds(const world_config& c, uint64_t* out) {
             out[row * 25 + n] = threshold_of(q + c.spont);
         }
     }
+}
+
+// Initial weight spread by parameter range (App. B.2: random at the start):
+// std = w_init_gain / sqrt(fan_in) for the weights, 0 for the biases.
+InitSegs init_segments(const world_config& c, const Dims& dm) {
+    InitSegs g;
+    std::memset(&g, 0, sizeof(g));
+    auto add = [&](int end, int fan_in) {
+        g.end[g.n] = end;
+        g.sd[g.n] = fan_in > 0 ? float(c.w_init_gain / std::sqrt(double(fan_in))) : 0.f;
+        g.n++;
+    };
+    if (is_net(c)) {
+        using namespace net;
+        add(kC1b, 9 * 3);           // conv1 kernel
+        add(kC2w, 0);
+        add(kC2b, 9 * kF1);         // conv2 kernel
+        add(kLwi, 0);
+        add(kLwh, kEmb);            // LSTM input kernel
+        add(kLb, kHd);              // LSTM hidden kernel
+        add(kD8w, 0);
+        add(kD8b, kCat);            // dense 8
+        add(kD5w, 0);
+        add(kD5b, kD);              // dense 5
+        add(kP, 0);
+    } else {
+        add(dm.off_hh, dm.n_in);    // W_ih
+        add(dm.off_bih, c.hidden);  // W_hh
+        add(dm.off_wo, 0);          // b_ih, b_hh
+        add(dm.off_bo, c.hidden);   // W_o
+        add(dm.P, 0);               // b_o
+    }
+    return g;
 }
 
 }  // namespace
@@ -225,7 +278,8 @@ std::vector<int> batch_prefix(const std::vector<const world*>& ws) {
     for (int i = 0; i < n; ++i) {
         const world_config& c = ws[i]->cfg;
         pre[kPreAct * (n + 1) + i + 1] = pre[kPreAct * (n + 1) + i] + kNewbornBlocks + blocks_act(c);
-        pre[kPreMove * (n + 1) + i + 1] = pre[kPreMove * (n + 1) + i] + tiles_agent(c) + c.cap;
+        // GRU worlds add one recurrent-projection block per slot
+        pre[kPreMove * (n + 1) + i + 1] = pre[kPreMove * (n + 1) + i] + tiles_agent(c) + (is_net(c) ? 0 : c.cap);
         pre[kPreClaim * (n + 1) + i + 1] = pre[kPreClaim * (n + 1) + i] + tiles_agent(c) + tiles_of(c);
     }
     return pre;
@@ -234,7 +288,8 @@ std::vector<int> batch_prefix(const std::vector<const world*>& ws) {
 // `t0` / `t1` (optional): events the dispatch itself stamps when the kernel
 // starts and ends (its execution time, without launch overhead).
 void launch_act(const Batch& b, int grid, hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr) {
-    if (b.act_rows == 8) hipExtLaunchKernelGGL(k_act_rows<8>, dim3(grid), dim3(kBlock), 0, s, t0, t1, 0, b);
+    if (b.ctrl == kCtrlNet) hipExtLaunchKernelGGL(k_act_net, dim3(grid), dim3(kBlock), 0, s, t0, t1, 0, b);
+    else if (b.act_rows == 8) hipExtLaunchKernelGGL(k_act_rows<8>, dim3(grid), dim3(kBlock), 0, s, t0, t1, 0, b);
     else if (b.act_rows == 32) hipExtLaunchKernelGGL(k_act_rows<32>, dim3(grid), dim3(kBlock), 0, s, t0, t1, 0, b);
     else hipExtLaunchKernelGGL(k_act, dim3(grid), dim3(kBlock), 0, s, t0, t1, 0, b);
 }
@@ -315,7 +370,7 @@ int run_steps(world* w0, int mode, const TableView& tv, const std::vector<int>& 
               int K, std::map<int, hipGraphExec_t>& graphs, std::map<int, hipGraph_t>& defs) {
     hipStream_t s = w0->stream;
     Batch b{tv.w, tv.block_pre, n, w0->act_rows, n == 1 ? static_cast<const WorldDev*>(w0->d_dev) : nullptr,
-            w0->cfg.cap};
+            w0->cfg.cap, w0->dev.ctrl};
     if (mode == WORLD_MODE_KERNELS) {
         for (int k = 0; k < K; ++k) HIP_TRY(w0, launch_step(b, host_bp.data(), n, s));
         return WORLD_OK;
@@ -405,6 +460,8 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
     d.off_hh = dm.off_hh; d.off_bih = dm.off_bih; d.off_bhh = dm.off_bhh; d.off_wo = dm.off_wo; d.off_bo = dm.off_bo;
     d.tot_row = dm.tot_row;
     d.nblk = dm.nblk;
+    d.ctrl = is_net(c) ? kCtrlNet : kCtrlGru;
+    d.ss = state_of(c);
     d.R[0] = reinterpret_cast<uint8_t*>(b + lay.R0);
     d.R[1] = reinterpret_cast<uint8_t*>(b + lay.R1);
     d.occA = reinterpret_cast<int32_t*>(b + lay.occA);
@@ -419,7 +476,7 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
     d.streak = reinterpret_cast<int32_t*>(b + lay.streak);
     d.action = reinterpret_cast<uint8_t*>(b + lay.action);
     d.alive = reinterpret_cast<uint8_t*>(b + lay.alive);
-    d.win = reinterpret_cast<uint8_t*>(b + lay.win);
+    d.ate = reinterpret_cast<uint8_t*>(b + lay.ate);
     d.claim = reinterpret_cast<int32_t*>(b + lay.claim);
     d.bkey = reinterpret_cast<uint64_t*>(b + lay.bkey);
     d.h = reinterpret_cast<float*>(b + lay.h);
@@ -475,7 +532,8 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
     for (int s = int(n0); s < c.cap; ++s) freeq[s - int(n0)] = s;
     std::vector<PosRec> recs(c.cap);
     std::memset(recs.data(), 0, sizeof(PosRec) * recs.size());
-    for (size_t a = 0; a < n0; ++a) recs[a].r[0] = AgentRec{int32_t(a), cells[a], c.E0, uint32_t(a), 0, 0, 4, 0};
+    for (size_t a = 0; a < n0; ++a)
+        recs[a].r[0] = AgentRec{int32_t(a), cells[a], c.E0, uint32_t(a), 0, 0, kNoAction, 0};
     std::vector<uint64_t> thr(size_t(c.H) * 25);
     build_thresholds(c, thr.data());
     WorldScal sc;
@@ -525,20 +583,19 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.mhist, 0, 4 * size_t(kMoveRing) * (kMoveBins + 1), s);
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.lb_move, 0, 8 * size_t(tiles_agent(c)), s);
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.lb_claim, 0, 8 * size_t(tiles_agent(c)), s);
-    if (e == hipSuccess) e = hipMemsetAsync(b + lay.h, 0, 4 * size_t(c.cap) * c.hidden, s);
-    if (e == hipSuccess) e = hipMemsetAsync(b + lay.action, 4, size_t(c.cap), s);
-    if (e == hipSuccess) e = hipMemsetAsync(b + lay.win, 0, size_t(c.cap), s);
+    if (e == hipSuccess) e = hipMemsetAsync(b + lay.h, 0, 4 * size_t(c.cap) * state_of(c), s);
+    if (e == hipSuccess) e = hipMemsetAsync(b + lay.action, kNoAction, size_t(c.cap), s);
+    if (e == hipSuccess) e = hipMemsetAsync(b + lay.ate, 0, size_t(c.cap), s);
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.theta, 0, 4 * size_t(c.cap) * dm.Ppad, s);
     if (e == hipSuccess && c.log_steps > 0) e = hipMemsetAsync(b + lay.log_n, 0, 4 * size_t(c.log_steps), s);
     if (e == hipSuccess && n0 > 0) {
-        const float std_ih = float(c.w_init_gain / std::sqrt(double(dm.n_in)));
-        const float std_hd = float(c.w_init_gain / std::sqrt(double(c.hidden)));
+        const InitSegs segs = init_segments(c, dm);
         const int64_t items = int64_t(n0) * dm.nblk;
         const int grid = int(std::min<int64_t>((items + kBlock - 1) / kBlock, 65536));
-        hipLaunchKernelGGL(k_init_theta, dim3(grid), dim3(kBlock), 0, s, w->d_dev, int(n0), std_ih, std_hd);
+        hipLaunchKernelGGL(k_init_theta, dim3(grid), dim3(kBlock), 0, s, w->d_dev, int(n0), segs);
         e = hipGetLastError();
     }
-    if (e == hipSuccess && n0 > 0) {
+    if (e == hipSuccess && n0 > 0 && !is_net(c)) {
         hipLaunchKernelGGL(k_proj_all, dim3(blocks_act(c)), dim3(kBlock), 0, s, static_cast<const WorldDev*>(w->d_dev));
         hipLaunchKernelGGL(k_rsum_all, dim3(c.cap), dim3(kBlock), 0, s, static_cast<const WorldDev*>(w->d_dev));
         e = hipGetLastError();
@@ -609,6 +666,7 @@ static std::vector<uintptr_t> batch_key(world_t* const* ws, int n) {
         key.push_back(uintptr_t(ws[i]->cfg.cap));
         key.push_back(uintptr_t(ws[i]->cfg.H) << 32 | uintptr_t(ws[i]->cfg.W));
         key.push_back(uintptr_t(ws[i]->cfg.hidden));
+        key.push_back(uintptr_t(ws[i]->cfg.controller));
     }
     return key;
 }
@@ -721,11 +779,22 @@ int world_snapshot(world_t* w, world_image* out) {
     if (int rc = gather_i32(l.energy, out->energy)) return rc;
     if (int rc = gather_i32(l.age, out->age)) return rc;
     if (int rc = gather_i32(l.streak, out->streak)) return rc;
+    const size_t ss = size_t(state_of(c));
     if ((out->flags & WORLD_SNAP_HIDDEN) && out->h) {
-        std::vector<float> hs(size_t(c.cap) * c.hidden);
+        std::vector<float> hs(size_t(c.cap) * ss);
         HIP_TRY(w, hipMemcpy(hs.data(), w->base + l.h, 4 * hs.size(), hipMemcpyDeviceToHost));
-        for (int i = 0; i < n; ++i)
-            std::memcpy(out->h + size_t(i) * c.hidden, hs.data() + size_t(live[i]) * c.hidden, 4 * size_t(c.hidden));
+        for (int i = 0; i < n; ++i) std::memcpy(out->h + size_t(i) * ss, hs.data() + size_t(live[i]) * ss, 4 * ss);
+    }
+    auto gather_u8 = [&](size_t off, uint8_t* dst) -> int {
+        if (!dst) return WORLD_OK;
+        std::vector<uint8_t> all(c.cap);
+        HIP_TRY(w, hipMemcpy(all.data(), w->base + off, size_t(c.cap), hipMemcpyDeviceToHost));
+        for (int i = 0; i < n; ++i) dst[i] = all[live[i]];
+        return WORLD_OK;
+    };
+    if (out->flags & WORLD_SNAP_HIDDEN) {
+        if (int rc = gather_u8(l.action, out->last_action)) return rc;
+        if (int rc = gather_u8(l.ate, out->ate)) return rc;
     }
     if ((out->flags & WORLD_SNAP_THETA) && out->theta) {
         const size_t P = size_t(w->dm.P), Pp = size_t(w->dm.Ppad);
@@ -744,7 +813,8 @@ int world_load(world_t* w, const world_image* in) {
     const int n = in->n_live;
     if (n < 0 || n > c.cap) return fail(w, WORLD_E_INVALID_ARG, "n_live out of range");
     if (!(in->flags & WORLD_SNAP_HIDDEN) || !(in->flags & WORLD_SNAP_THETA) || !in->R || !in->uid || !in->row ||
-        !in->col || !in->energy || !in->age || !in->streak || (n > 0 && (!in->h || !in->theta)))
+        !in->col || !in->energy || !in->age || !in->streak ||
+        (n > 0 && (!in->h || !in->theta || !in->last_action || !in->ate)))
         return fail(w, WORLD_E_INVALID_ARG, "world_load needs the full state");
     if (in->step < 0) return fail(w, WORLD_E_INVALID_ARG, "negative step");
     const size_t HW = size_t(c.H) * c.W;
@@ -756,6 +826,8 @@ int world_load(world_t* w, const world_image* in) {
         if (in->uid[i] >= in->next_uid) return fail(w, WORLD_E_INVALID_ARG, "uid >= next_uid");
         const int cell = in->row[i] * c.W + in->col[i];
         if (occ[cell] != -1) return fail(w, WORLD_E_INVALID_ARG, "two agents in one cell");
+        if (in->last_action[i] > kNoAction || in->ate[i] > 1)
+            return fail(w, WORLD_E_INVALID_ARG, "last_action must be 0..5 and ate 0 or 1");
         occ[cell] = i;
         cells[i] = cell;
         live[i] = i;
@@ -776,11 +848,14 @@ int world_load(world_t* w, const world_image* in) {
     for (int i = 0; i < n; ++i) std::memcpy(th.data() + size_t(i) * Pp, in->theta + size_t(i) * P, 4 * P);
     std::vector<int32_t> ages(c.cap, 0), streaks(c.cap, 0), energies(c.cap, 0);
     std::vector<uint32_t> uids(c.cap, 0);
+    std::vector<uint8_t> acts(c.cap, uint8_t(kNoAction)), ates(c.cap, 0);
     for (int i = 0; i < n; ++i) {
         ages[i] = in->age[i];
         streaks[i] = in->streak[i];
         energies[i] = in->energy[i];
         uids[i] = in->uid[i];
+        acts[i] = in->last_action[i];
+        ates[i] = in->ate[i];
     }
     HIP_TRY(w, hipStreamSynchronize(w->stream));
     HIP_TRY(w, hipMemcpy(b + l.scal, &sc, sizeof(sc), hipMemcpyHostToDevice));
@@ -794,12 +869,15 @@ int world_load(world_t* w, const world_image* in) {
     HIP_TRY(w, hipMemcpy(b + l.age, ages.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
     HIP_TRY(w, hipMemcpy(b + l.streak, streaks.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
     HIP_TRY(w, hipMemcpy(b + l.alive, alive.data(), size_t(c.cap), hipMemcpyHostToDevice));
+    HIP_TRY(w, hipMemcpy(b + l.action, acts.data(), size_t(c.cap), hipMemcpyHostToDevice));
+    HIP_TRY(w, hipMemcpy(b + l.ate, ates.data(), size_t(c.cap), hipMemcpyHostToDevice));
     HIP_TRY(w, hipMemcpy(b + l.live0, live.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
     {
         std::vector<PosRec> recs(c.cap);
         std::memset(recs.data(), 0, sizeof(PosRec) * recs.size());
         for (int i = 0; i < n; ++i)
-            recs[i].r[0] = AgentRec{i, cells[i], energies[i], uids[i], ages[i], streaks[i], 4, 0};
+            recs[i].r[0] = AgentRec{i, cells[i], energies[i], uids[i], ages[i], streaks[i], int32_t(acts[i]),
+                                    int32_t(ates[i])};
         HIP_TRY(w, hipMemcpy(b + l.pos, recs.data(), sizeof(PosRec) * size_t(c.cap), hipMemcpyHostToDevice));
     }
     HIP_TRY(w, hipMemcpy(b + l.freeq, freeq.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
@@ -809,10 +887,13 @@ int world_load(world_t* w, const world_image* in) {
     HIP_TRY(w, hipMemset(b + l.wuid, 0xFF, 4 * size_t(c.cap)));   // no agent counts in the window in progress
     HIP_TRY(w, hipMemset(b + l.mhist, 0, 4 * size_t(kMoveRing) * (kMoveBins + 1)));
     if (n > 0) {
-        std::vector<float> hs(size_t(c.cap) * c.hidden, 0.f);
-        std::memcpy(hs.data(), in->h, 4 * size_t(n) * c.hidden);
+        const size_t ss = size_t(state_of(c));
+        std::vector<float> hs(size_t(c.cap) * ss, 0.f);
+        std::memcpy(hs.data(), in->h, 4 * size_t(n) * ss);
         HIP_TRY(w, hipMemcpy(b + l.h, hs.data(), 4 * hs.size(), hipMemcpyHostToDevice));
         HIP_TRY(w, hipMemcpy(b + l.theta, th.data(), 4 * size_t(n) * Pp, hipMemcpyHostToDevice));
+    }
+    if (n > 0 && !is_net(c)) {
         hipLaunchKernelGGL(k_proj_all, dim3(blocks_act(c)), dim3(kBlock), 0, w->stream,
                            static_cast<const WorldDev*>(w->d_dev));
         hipLaunchKernelGGL(k_rsum_all, dim3(c.cap), dim3(kBlock), 0, w->stream,
@@ -939,13 +1020,24 @@ int world_test_gauss(const uint32_t* d_a, const uint32_t* d_b, size_t n, float* 
     return WORLD_OK;
 }
 
+int world_test_gumbel(const uint32_t* d_words, size_t n, float* d_g, void* stream) {
+    if (!d_words || !d_g) return fail(nullptr, WORLD_E_INVALID_ARG, "NULL argument");
+    if (n == 0) return WORLD_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_test_gumbel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, d_words, n, d_g);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(nullptr, WORLD_E_HIP, hipGetErrorString(e));
+    return WORLD_OK;
+}
+
 int world_phase_times(world_t* w, int32_t K, float* ms) {
     if (!w || !ms) return fail(w, WORLD_E_INVALID_ARG, "NULL argument");
     if (w->poisoned) return WORLD_E_POISONED;
     if (K < 1) return fail(w, WORLD_E_INVALID_ARG, "K must be >= 1");
     const int np = 2;
     const int* hp = w->host_bp.data();
-    Batch b{w->tv.w, w->tv.block_pre, 1, w->act_rows, static_cast<const WorldDev*>(w->d_dev), w->cfg.cap};
+    Batch b{w->tv.w, w->tv.block_pre, 1, w->act_rows, static_cast<const WorldDev*>(w->d_dev), w->cfg.cap, w->dev.ctrl};
     hipStream_t s = w->stream;
     // each kernel between start / end events stamped by its own dispatch
     std::vector<hipEvent_t> ev(size_t(K) * 6);
@@ -994,6 +1086,8 @@ int world_step_many(world_t* const* ws, int32_t n, int32_t K) {
         if (!ws[i]) return fail(nullptr, WORLD_E_INVALID_ARG, "NULL world in list");
         if (ws[i]->poisoned) return WORLD_E_POISONED;
         if (ws[i]->stream != ws[0]->stream) return fail(nullptr, WORLD_E_INVALID_ARG, "worlds must share one stream");
+        if (ws[i]->cfg.controller != ws[0]->cfg.controller)
+            return fail(nullptr, WORLD_E_INVALID_ARG, "worlds of one batch must use the same controller");
     }
     return batch_step(ws, n, K);
 }

@@ -12,10 +12,11 @@
 //             born and occB when they are created),
 //             thr (u64 H x 25 regrowth thresholds)
 //   agents    uid, cell, prev_cell, energy, age, streak (i32 per slot),
-//             action, alive, win (u8), claim (i32), h (f32 slot x hidden),
-//             theta (f32 slot x Ppad, the genome order with each input's
-//             3*hidden gate weights contiguous so that skipping a zero input
-//             skips one contiguous row)
+//             action (the last one taken), alive, ate (u8), claim (i32),
+//             h (f32 slot x state: the GRU's h, or the LSTM's h then c),
+//             theta (f32 slot x Ppad, the genome order; for the GRU each
+//             input's 3*hidden gate weights are contiguous so that skipping
+//             a zero input skips one contiguous row)
 //   lists     live[2] (slots in uid order), freeq (ring of free slots),
 //             child (per step: child slot, parent slot, cell, uid)
 //   scalars   WorldScal, counters ring (8192 steps), optional controller log
@@ -43,12 +44,18 @@ constexpr int kMoveWin = 50;
 constexpr int kMoveBins = 17;
 constexpr int kMoveRing = 64;
 
+// Controllers.
+enum : int { kCtrlGru = 0, kCtrlNet = 1 };
+constexpr int kNoAction = 5;   // previous action of an agent that has not acted yet
+
 // Agent record by live-list position (the order of the live list): what the
-// act and move phases need about an agent in one 32-byte read.
+// act and move phases need about an agent in one 32-byte read.  `action` is
+// the previous step's action until the act phase overwrites it with this
+// step's; `ate` says whether the agent ate in its previous step.
 struct alignas(16) AgentRec {
     int32_t slot, cell, energy;
     uint32_t uid;
-    int32_t age, streak, action, pad;
+    int32_t age, streak, action, ate;
 };
 
 // Post-move record by live-list position, for the claim phase (next_pos =
@@ -105,6 +112,8 @@ struct WorldDev {
     int32_t off_hh, off_bih, off_bhh, off_wo, off_bo;  // genome offsets (floats)
     int32_t nblk;       // float4 blocks per genome, ceil(P / 4)
     int32_t tot_row;    // theta row (of 3*hd floats) of the window totals, after the genome; tot_row + 2 is zeros
+    int32_t ctrl;       // kCtrlGru or kCtrlNet
+    int32_t ss;         // recurrent state floats per slot (hd for the GRU, 2 hd for the LSTM)
     int32_t pad0;
     // grid
     uint8_t* R[2];
@@ -121,7 +130,7 @@ struct WorldDev {
     int32_t* streak;
     uint8_t* action;
     uint8_t* alive;
-    uint8_t* win;
+    uint8_t* ate;         // per slot: ate in its last step
     int32_t* claim;
     uint64_t* bkey;       // birth-claim key by cell of eligible agents (written in P2)
     float* h;

@@ -11,6 +11,11 @@ the sizes of the benchmark configurations:
                 (Bernoulli 0.3) and regrowth x5 so the population stays near 4k.
 * ``cfg2``      200 x 400 grid, 16384 slots, 12000 agents, Bernoulli 0.3, x5.
 * ``batch64``   64 uneven worlds (grid sizes from a fixed set, caps 512..8192).
+* ``net1k``     the paper's own scale with its network (App. B.4, B.5): a
+                200 x 400 grid, at most 1000 agents (1024 slots), 330 placed
+                at the start, 16,000 resources on average (Bernoulli 0.2),
+                15 x 15 x 3 observation, CNN + LSTM(4).
+* ``net_m1_4k`` the m1_4k world (about 4k agents) with the paper's network.
 
 Every random choice of a workload (the uneven-world manifest, the serving
 arrival trace) comes from ``numpy.random.default_rng`` with a fixed seed; the
@@ -38,10 +43,13 @@ WORKLOADS = {
     "cfg1": make(H=200, W=400, cap=8192, n_init=1000, res_init_p=0.05),
     "m1_4k": make(H=200, W=400, cap=4608, n_init=4096, res_init_p=0.3, rate_scale=5.0),
     "cfg2": make(H=200, W=400, cap=16384, n_init=12000, res_init_p=0.3, rate_scale=5.0),
+    "net1k": make(H=200, W=400, cap=1024, n_init=330, res_init_p=0.2, obs_radius=7, hidden=4, controller=1),
+    "net_m1_4k": make(H=200, W=400, cap=4608, n_init=4096, res_init_p=0.3, rate_scale=5.0, obs_radius=7, hidden=4,
+                      controller=1),
 }
 
 # Steps each workload is run for in the benchmark configurations.
-STEPS = {"cfg0": 1000, "cfg1": 10000, "m1_4k": 2000, "cfg2": 5000}
+STEPS = {"cfg0": 1000, "cfg1": 10000, "m1_4k": 2000, "cfg2": 5000, "net1k": 2000, "net_m1_4k": 2000}
 
 GRID_SET = [(64, 128), (100, 200), (128, 256), (200, 400)]
 

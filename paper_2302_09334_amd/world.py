@@ -22,6 +22,8 @@ ERRORS = {-1: "invalid argument", -2: "invalid config", -3: "buffer too small", 
 MODE_KERNELS, MODE_GRAPH = 0, 1
 MODES = {"kernels": MODE_KERNELS, "graph": MODE_GRAPH}
 SNAP_HIDDEN, SNAP_THETA = 1, 2
+CTRL_GRU, CTRL_CNN_LSTM = 0, 1   # GRU + arg-max; the paper's network (App. B.5) + sampling
+NO_ACTION = 5                    # previous action of an agent that has not acted yet
 
 
 class WorldError(RuntimeError):
@@ -39,7 +41,7 @@ class Config(C.Structure):
         ("E0", C.c_int32), ("decay", C.c_int32), ("gain", C.c_int32), ("E_repr", C.c_int32),
         ("T_repr", C.c_int32), ("L_max", C.c_int32),
         ("sigma_mut", C.c_double), ("w_init_gain", C.c_double),
-        ("log_steps", C.c_int32), ("flags", C.c_uint32),
+        ("log_steps", C.c_int32), ("flags", C.c_uint32), ("controller", C.c_int32),
     ]
 
 
@@ -59,7 +61,7 @@ class Image(C.Structure):
         ("reserved", C.c_int32),
         ("R", C.c_void_p), ("uid", C.c_void_p), ("row", C.c_void_p), ("col", C.c_void_p),
         ("energy", C.c_void_p), ("age", C.c_void_p), ("streak", C.c_void_p),
-        ("h", C.c_void_p), ("theta", C.c_void_p),
+        ("h", C.c_void_p), ("theta", C.c_void_p), ("last_action", C.c_void_p), ("ate", C.c_void_p),
     ]
 
 
@@ -69,7 +71,7 @@ EXPORTS = [
     "world_set_mode", "world_set_tuning", "world_set_stream", "world_sync", "world_snapshot", "world_load", "world_counters_get",
     "world_destroy", "world_last_error", "world_set_forced_action", "world_action_log",
     "world_test_philox", "world_test_gauss", "world_threshold_table", "world_phase_times",
-    "world_test_copy", "world_move_hist",
+    "world_test_copy", "world_move_hist", "world_test_gumbel",
 ]
 
 _lib = None
@@ -106,6 +108,7 @@ def lib():
         L.world_phase_times.argtypes = [P, C.c_int32, P]
         L.world_test_copy.argtypes = [P, P, C.c_size_t, P]
         L.world_move_hist.argtypes = [P, C.c_int64, C.c_int32, P]
+        L.world_test_gumbel.argtypes = [P, C.c_size_t, P, P]
         for name in EXPORTS:
             getattr(L, name).restype = getattr(L, name).restype or C.c_int
         L.world_last_error.restype = C.c_char_p
@@ -123,12 +126,18 @@ def make_config(d: dict, log_steps: int = 0) -> Config:
     c = Config()
     c.struct_size = C.sizeof(Config)
     for name, _ in Config._fields_:
-        if name in ("struct_size", "log_steps", "flags"):
+        if name in ("struct_size", "log_steps", "flags", "controller"):
             continue
         setattr(c, name, d[name])
     c.log_steps = int(d.get("log_steps", log_steps))
     c.flags = 0
+    c.controller = int(d.get("controller", CTRL_GRU))
     return c
+
+
+def state_size(cfg: dict) -> int:
+    """Recurrent state floats per agent: h (GRU), h then c (LSTM)."""
+    return 2 * cfg["hidden"] if cfg.get("controller", CTRL_GRU) == CTRL_CNN_LSTM else cfg["hidden"]
 
 
 def required_bytes(cfg: dict) -> int:
@@ -240,8 +249,12 @@ class World:
         for k in ("uid", "row", "col", "energy", "age", "streak"):
             setattr(img, k, _np_ptr(out[k]))
         if hidden:
-            out["h"] = np.empty((cap, self.cfg["hidden"]), np.float32)
+            out["h"] = np.empty((cap, state_size(self.cfg)), np.float32)
+            out["last_action"] = np.empty(cap, np.uint8)
+            out["ate"] = np.empty(cap, np.uint8)
             img.h = _np_ptr(out["h"])
+            img.last_action = _np_ptr(out["last_action"])
+            img.ate = _np_ptr(out["ate"])
         if theta:
             out["theta"] = np.empty((cap, self.n_params), np.float32)
             img.theta = _np_ptr(out["theta"])
@@ -251,7 +264,8 @@ class World:
         for k in ("uid", "row", "col", "energy", "age", "streak"):
             res[k] = out[k][:n].copy()
         if hidden:
-            res["h"] = out["h"][:n].copy()
+            for k in ("h", "last_action", "ate"):
+                res[k] = out[k][:n].copy()
         if theta:
             res["theta"] = out["theta"][:n].copy()
         return res
@@ -262,7 +276,9 @@ class World:
                 "uid": np.ascontiguousarray(s["uid"], np.uint32)}
         for k in ("row", "col", "energy", "age", "streak"):
             arrs[k] = np.ascontiguousarray(s[k], np.int32)
-        arrs["h"] = np.ascontiguousarray(s["h"], np.float32).reshape(n, self.cfg["hidden"])
+        arrs["h"] = np.ascontiguousarray(s["h"], np.float32).reshape(n, state_size(self.cfg))
+        arrs["last_action"] = np.ascontiguousarray(s["last_action"], np.uint8)
+        arrs["ate"] = np.ascontiguousarray(s["ate"], np.uint8)
         arrs["theta"] = np.ascontiguousarray(s["theta"], np.float32).reshape(n, self.n_params)
         img = Image()
         img.struct_size = C.sizeof(Image)
@@ -347,3 +363,14 @@ def test_gauss(a, b, stream=None):
     _check(lib().world_test_gauss(C.c_void_p(ta.data_ptr()), C.c_void_p(tb.data_ptr()), ta.numel(),
                                   C.c_void_p(z0.data_ptr()), C.c_void_p(z1.data_ptr()), C.c_void_p(s.cuda_stream)))
     return z0.cpu().numpy(), z1.cpu().numpy()
+
+
+def test_gumbel(words, stream=None):
+    """Gumbel deviates of the action sampling computed by the device code (test hook)."""
+    import torch
+    w = torch.as_tensor(np.ascontiguousarray(words, np.uint32).view(np.int32)).cuda()
+    g = torch.empty(w.numel(), dtype=torch.float32, device=w.device)
+    s = stream or torch.cuda.current_stream()
+    _check(lib().world_test_gumbel(C.c_void_p(w.data_ptr()), w.numel(), C.c_void_p(g.data_ptr()),
+                                   C.c_void_p(s.cuda_stream)))
+    return g.cpu().numpy()

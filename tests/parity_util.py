@@ -5,9 +5,9 @@ the same K steps, one at a time, receiving the GPU's actions as near-tie
 hints (adopted only where the oracle's own top logits are within 1e-5 of each
 other).  Compared: every step's counters (including the sum of ages at death) and
 acting uids exactly, the controller logits within 1e-5 * max(1, max|logit|)
-per agent, at every chunk end the integer state bit-exactly and the hidden
-state within 1e-5, and at the end every completed movement window's
-histogram exactly.
+per agent, at every chunk end the integer state bit-exactly (with the
+previous action and ate bit) and the recurrent state within 1e-5 * max(1, |v|),
+and at the end every completed movement window's histogram exactly.
 """
 import sys
 
@@ -30,8 +30,11 @@ def compare_state(g, o, where, hidden=True, theta=False):
     for k in STATE_KEYS:
         assert np.array_equal(g[k], o[k]), (where, k)
     if hidden and g["n_live"]:
-        d = np.abs(g["h"].astype(np.float64) - o["h"].astype(np.float64)).max()
+        oh = o["h"].astype(np.float64)
+        d = (np.abs(g["h"].astype(np.float64) - oh) / np.maximum(1.0, np.abs(oh))).max()
         assert d <= LOGIT_TOL, (where, "h", d)
+        for k in ("last_action", "ate"):
+            assert np.array_equal(g[k], o[k]), (where, k)
     if theta and g["n_live"]:
         assert np.array_equal(g["theta"], o["theta"]), (where, "theta")
 

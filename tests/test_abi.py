@@ -40,6 +40,10 @@ def test_required_bytes_and_dims(wlib):
     for name, cfg in workloads.WORKLOADS.items():
         n = wlib.required_bytes(cfg)
         n_in, P = wlib.dims(cfg)
+        if cfg.get("controller", 0) == wlib.CTRL_CNN_LSTM:
+            assert (n_in, P) == (15 * 15 * 3, 2445)
+            assert cfg["cap"] * P * 4 < n < cfg["cap"] * ((P + 64) * 4 + 1024) + 64 * cfg["H"] * cfg["W"] + (1 << 20)
+            continue
         assert n_in == 2 * (2 * cfg["obs_radius"] + 1) ** 2 + 1
         # the genome dominates the arena: per agent slot the genome, three more
         # rows of 3*hidden floats (the two window totals and a zero row), up to
@@ -53,7 +57,9 @@ def test_required_bytes_and_dims(wlib):
 
 @pytest.mark.parametrize("bad,code", [(dict(H=1), -2), (dict(hidden=24), -2), (dict(obs_radius=4), -2),
                                       (dict(n_init=300, cap=256), -2), (dict(E0=0), -2),
-                                      (dict(cap=0), -2), (dict(T_repr=0), -2)])
+                                      (dict(cap=0), -2), (dict(T_repr=0), -2), (dict(controller=2), -2),
+                                      (dict(controller=1), -2), (dict(controller=1, obs_radius=7), -2),
+                                      (dict(controller=1, hidden=4), -2)])
 def test_invalid_configs(wlib, bad, code):
     from paper_2302_09334_amd import workloads
     cfg = dict(workloads.WORKLOADS["cfg0"])
@@ -76,3 +82,10 @@ def test_threshold_table_matches_oracle(wlib, oracle_lib):
         cfg = m["cfg"]
         assert np.array_equal(wlib.threshold_table(cfg),
                               oracle_lib.threshold_table(oracle_lib.OracleConfig.from_dict(cfg)))
+
+
+def test_network_config_accepted(wlib):
+    from paper_2302_09334_amd import workloads
+    cfg = dict(workloads.WORKLOADS["cfg0"], controller=1, obs_radius=7, hidden=4)
+    assert wlib.dims(cfg) == (675, 2445)
+    assert wlib.required_bytes(cfg) > 0

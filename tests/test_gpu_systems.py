@@ -32,6 +32,8 @@ def same(a, b, where):
     for k in KEYS:
         assert np.array_equal(a[k], b[k]), (where, k)
     assert np.array_equal(a["h"].view(np.uint32), b["h"].view(np.uint32)), (where, "h")
+    for k in ("last_action", "ate"):
+        assert np.array_equal(a[k], b[k]), (where, k)
     assert np.array_equal(a["theta"].view(np.uint32), b["theta"].view(np.uint32)), (where, "theta")
 
 
