@@ -19,6 +19,12 @@ Also reported:
   events stamped by their own dispatch; ``kernels`` lists all three.
 * ``cpu_baseline``: the oracle (plain C, one thread) on a bounded sample of
   the same workload on the host cores.
+* ``paper_network``: the same 200 x 400 world with ~4k agents driven by the
+  paper's controller (App. B.5: CNN + LSTM(4), 2445 parameters, sampled
+  actions; workload ``net_m1_4k``): wall-clock agent-steps/s, per-kernel
+  event times, and the act kernel (k_act_net) against the HBM roofline with
+  its algorithmic bytes and flops per agent.  ``--only-net`` runs this leg
+  alone (for profiling).
 
 ``--gpus N`` with N > 1 is refused: this build runs on one GPU.
 """
@@ -38,16 +44,19 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "act_m1_4k_traffic.txt")
+NET_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "act_net_m1_4k_traffic.txt")
 KERNEL_SOURCES = ["rng.h", "world_dev.h", "phases.h", "kernels.h"]
+NET_KERNEL_SOURCES = KERNEL_SOURCES + ["net.h"]
+FP32_VECTOR_PEAK_TFLOPS = 157.3
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(sources=None) -> str:
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources or KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2302_09334_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -97,10 +106,10 @@ def proj_bytes_per_agent(cfg: dict) -> float:
 
 # Move phase, per agent: its 32-byte record in, the move-claim word and the
 # two resource bytes of the source and target cell, the per-slot state out
-# (energy, age, streak, cell, previous cell: 20 bytes, alive: 1), both
-# occupancy words, the post-move record and the next record (32 + 32), the
-# live-list entry (4) and the eaten resource byte.
-MOVE_BYTES_PER_AGENT = 32 + 8 + 2 + 21 + 8 + 64 + 4 + 1
+# (energy, age, streak, cell, previous cell: 20 bytes, alive and ate: 2),
+# both occupancy words, the post-move record and the next record (32 + 32),
+# the live-list entry (4) and the eaten resource byte.
+MOVE_BYTES_PER_AGENT = 32 + 8 + 2 + 22 + 8 + 64 + 4 + 1
 # Claim phase, per agent: the post-move record (32), the move-claim clear (8),
 # the claim word (4); per eligible agent the 24 occupancy words (96) and the
 # 8 birth keys (64) of its neighbourhood.  Regrowth, per cell: the resource
@@ -109,23 +118,111 @@ CLAIM_BYTES_PER_AGENT = 32 + 8 + 4
 CLAIM_BYTES_PER_ELIGIBLE = 96 + 64
 
 
-def read_traffic(src_hash: str, rows: int):
+def read_traffic(src_hash: str, rows, path: str = TRAFFIC_FILE):
     """HBM bytes per launch of the act kernel compiled for `rows` input rows
-    per round trip, from the committed counter summary (None when the kernel
-    sources changed since it was taken)."""
-    if not os.path.exists(TRAFFIC_FILE):
+    per round trip (None: the network's act kernel), from the committed
+    counter summary (None when the kernel sources changed since it was
+    taken)."""
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
     if kv.get("kernel_source_sha256_16") != src_hash:
         return None
     try:
-        return float(kv[f"hbm_bytes_per_launch_rows{rows}"])
+        return float(kv["hbm_bytes_per_launch" if rows is None else f"hbm_bytes_per_launch_rows{rows}"])
     except (KeyError, ValueError):
         return None
+
+
+# The paper's network (App. B.5), per agent and act launch: every parameter
+# read once (2445 floats), the LSTM state in and out (8 floats each way), the
+# agent record in (32 B), the action out (record word and action byte) and the
+# move-claim word (8 B); the grid (resource byte and occupancy word per cell)
+# once per launch.  Multiply-adds: conv1 8x8 outputs x 4 x 27, conv2 4x4 x 8 x
+# 36, LSTM 16 x (78 + 4), dense 8 x 82, head 5 x 8.
+NET_PARAMS = 2445
+NET_ACT_BYTES_PER_AGENT = 4 * NET_PARAMS + 2 * 32 + 32 + 5 + 8
+NET_MACS_PER_AGENT = 64 * 4 * 27 + 16 * 8 * 36 + 16 * 82 + 8 * 82 + 5 * 8
+
+
+def net_run(args) -> dict:
+    """The ~4k-agent world with the paper's network: warm-up, then exactly
+    --net-steps steps timed by the wall clock between two synchronisations
+    (graph launches of --chunk steps), then a per-phase pass from the same
+    state for the kernel durations."""
+    import torch
+    from paper_2302_09334_amd import workloads, world
+    cfg = workloads.WORKLOADS["net_m1_4k"]
+    stream = torch.cuda.Stream()
+    w = world.World(cfg, args.seed, stream=stream, mode="graph")
+    assert w.n_params == NET_PARAMS
+    done = 0
+    while done < args.net_warmup:
+        k = min(args.chunk, args.net_warmup - done)
+        w.step(k)
+        done += k
+    w.sync()
+    start = w.snapshot(hidden=True, theta=True)
+    t_first = start["t"]
+    w.step(min(args.chunk, args.net_steps))   # graph capture outside the timed region
+    w.sync()
+    w.load(start)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < args.net_steps:
+        k = min(args.chunk, args.net_steps - done)
+        w.step(k)
+        done += k
+    w.sync()
+    wall = time.perf_counter() - t0
+    ctr = w.counters(t_first, args.net_steps)
+    acting = np.concatenate([[start["n_live"]], ctr["n_live"][:-1]])
+    w.load(start)
+    ph = w.phase_times(args.net_phase_steps)
+    pc = w.counters(t_first, args.net_phase_steps)
+    n_act = float(np.concatenate([[start["n_live"]], pc["n_live"][:-1]]).mean())
+    grid_bytes = cfg["H"] * cfg["W"] * 5
+    act_bytes = n_act * NET_ACT_BYTES_PER_AGENT + grid_bytes
+    elig = float((start["streak"] >= cfg["T_repr"]).sum())
+    kbytes = {"act": act_bytes, "move": n_act * MOVE_BYTES_PER_AGENT,
+              "claim": n_act * CLAIM_BYTES_PER_AGENT + elig * CLAIM_BYTES_PER_ELIGIBLE + 2 * cfg["H"] * cfg["W"]}
+    kms = {"act": float(ph[0]), "move": float(ph[1]), "claim": float(ph[2])}
+    act_s = kms["act"] * 1e-3
+    achieved = act_bytes / act_s / 1e9
+    tflops = n_act * 2 * NET_MACS_PER_AGENT / act_s / 1e12
+    src_hash = kernel_source_hash(NET_KERNEL_SOURCES)
+    w.close()
+    out = {
+        "workload": "net_m1_4k: 200x400 grid, cap 4608, 4096 initial agents, resources Bernoulli(0.3), "
+                    "regrowth x5.0, obs 15x15x3, CNN + LSTM(4) + dense 8 + 5 (2445 parameters), actions "
+                    "sampled at temperature 1/50, seed %d, steps %d..%d" % (args.seed, t_first,
+                                                                           t_first + args.net_steps - 1),
+        "metric": "agent-steps/s", "value": float(acting.sum()) / wall, "ms_per_step": wall / args.net_steps * 1e3,
+        "steps": args.net_steps, "warmup": args.net_warmup, "launch_mode": "graph",
+        "n_live_mean": float(acting.mean()), "births": int(ctr["births"].sum()), "deaths": int(ctr["deaths"].sum()),
+        "kernels": {k: {"ms_per_launch": kms[k], "algorithmic_bytes": kbytes[k],
+                        "GBps": kbytes[k] / (kms[k] * 1e-3) / 1e9} for k in kms},
+        "roofline": {
+            "kernel": "k_act_net (observation, CNN, LSTM, dense layers, sampling; one wave per agent)",
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": read_traffic(src_hash, None, NET_TRAFFIC_FILE),
+            "algorithmic_bytes_per_launch": act_bytes, "launch_ms": kms["act"],
+            "act_per_agent_bytes": NET_ACT_BYTES_PER_AGENT, "agents_per_launch": n_act,
+            "flops_per_agent": 2 * NET_MACS_PER_AGENT, "achieved_TFLOPs": tflops,
+            "fp32_vector_peak_TFLOPs": FP32_VECTOR_PEAK_TFLOPS,
+            "kernel_source_sha256_16": src_hash,
+        },
+    }
+    log(f"[bench] paper network: {out['value'] / 1e6:.1f} M agent-steps/s, {out['ms_per_step'] * 1e3:.1f} us/step, "
+        f"{out['n_live_mean']:.0f} agents; k_act_net {kms['act'] * 1e3:.2f} us ({achieved:.0f} GB/s, "
+        f"{tflops:.1f} TFLOP/s), move {kms['move'] * 1e3:.2f} us, claim {kms['claim'] * 1e3:.2f} us")
+    return out
 
 
 def cpu_baseline(cfg: dict, seed: int, seconds: float) -> dict:
@@ -241,6 +338,18 @@ def served_run(args) -> dict:
     return m
 
 
+def copy_calibration(torch, world):
+    """Three launches of the plain copy kernel over 1 GiB (the known-size
+    reference for the memory counters)."""
+    src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    s = torch.cuda.Stream()
+    for _ in range(3):
+        world.test_copy(src, dst, s)
+    torch.cuda.synchronize()
+    log("[bench] copy calibration: 3 x 1 GiB device copies done")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -261,6 +370,10 @@ def main():
     ap.add_argument("--batch-warmup", type=int, default=100)
     ap.add_argument("--serve-seconds", type=float, default=20.0, help="arrival window of the served run (0 = skip)")
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
+    ap.add_argument("--net-steps", type=int, default=500, help="timed steps of the paper-network world (0 = skip)")
+    ap.add_argument("--net-warmup", type=int, default=300)
+    ap.add_argument("--net-phase-steps", type=int, default=100)
+    ap.add_argument("--only-net", action="store_true", help="run only the paper-network leg and print it")
     args = ap.parse_args()
 
     world_size = int(os.environ.get("WORLD_SIZE", "1"))
@@ -273,6 +386,13 @@ def main():
 
     import torch
     from paper_2302_09334_amd import workloads, world
+
+    if args.only_net:
+        net = net_run(args)
+        if args.calib_copy:
+            copy_calibration(torch, world)
+        print(json.dumps({"paper_network": net}))
+        return
 
     cfg = workloads.WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
@@ -397,12 +517,11 @@ def main():
         f"claim {kbytes['claim'] / 1e6:.2f}; dominant {dominant}")
 
     if args.calib_copy:
-        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            world.test_copy(src, dst, stream)
-        torch.cuda.synchronize()
-        log("[bench] copy calibration: 3 x 1 GiB device copies done")
+        copy_calibration(torch, world)
+
+    net = None
+    if args.net_steps > 0:
+        net = net_run(args)
 
     m2 = None
     if args.m2_steps > 0:
@@ -486,6 +605,7 @@ def main():
             "kernel_source_sha256_16": src_hash,
         },
         "ecology_metrics": metrics,
+        "paper_network": net,
         "cache_exceeding": m2,
         "cpu_baseline": cpu,
         "batched": batched,

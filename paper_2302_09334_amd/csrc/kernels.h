@@ -93,14 +93,14 @@ __device__ __forceinline__ void act_body(const Batch& bt, int vb, int tid, StepS
     const int4 q0 = *reinterpret_cast<const int4*>(&P[lc].r[0]);
     const int4 q1 = *reinterpret_cast<const int4*>(&P[lc].r[1]);
     int4 q0b = make_int4(0, 0, 0, 0), q1b = make_int4(0, 0, 0, 0);
-    if (NET) {   // the second half: previous action and ate bit
+    if constexpr (NET) {   // the second half: previous action and ate bit
         q0b = *(reinterpret_cast<const int4*>(&P[lc].r[0]) + 1);
         q1b = *(reinterpret_cast<const int4*>(&P[lc].r[1]) + 1);
     }
     const StepScal ss = read_step(bw.S);
     pin(q0.x);
     pin(q1.x);
-    if (NET) {
+    if constexpr (NET) {
         pin(q0b.z);
         pin(q1b.z);
     }
@@ -116,16 +116,16 @@ __device__ __forceinline__ void act_body(const Batch& bt, int vb, int tid, StepS
             close_counters_in_step(d, tid, sh);
         }
         for (int rk = lb; rk < nc; rk += kNewbornBlocks) {
-            spawn_child(d, rk, tid);
+            spawn_child(d, rk, tid, NET ? net::kState : d.hd);
             __syncthreads();
-            if (!NET) {
+            if constexpr (!NET) {
                 spawn_proj(d, rk, tid);
                 __syncthreads();
             }
             if (tid < 64) {
                 const int lj = n - nc + rk;
                 const int4 rv = *reinterpret_cast<const int4*>(&P[lj].r[sel]);
-                if (NET) {
+                if constexpr (NET) {
                     const int4 rv2 = *(reinterpret_cast<const int4*>(&P[lj].r[sel]) + 1);
                     net::act_agent(d, &P[lj].r[sel], rv, rv2, lj, t, tid, lds[0]);
                 } else {
@@ -137,7 +137,7 @@ __device__ __forceinline__ void act_body(const Batch& bt, int vb, int tid, StepS
         return;
     }
     if (li >= n - nc) return;
-    if (NET) net::act_agent(d, &P[li].r[sel], sel ? q1 : q0, sel ? q1b : q0b, li, t, tid & 63, lds[tid >> 6]);
+    if constexpr (NET) net::act_agent(d, &P[li].r[sel], sel ? q1 : q0, sel ? q1b : q0b, li, t, tid & 63, lds[tid >> 6]);
     else act_dispatch<ROWS>(d, &P[li].r[sel], sel ? q1 : q0, li, t, tid & 63);
 }
 
@@ -216,8 +216,19 @@ __global__ __launch_bounds__(kBlock) void k_act_rows(Batch bt) {
     act_body<ROWS, false>(bt, blockIdx.x, threadIdx.x, sh, nullptr);
 }
 
-// Act kernel of worlds with the paper's network.
-__global__ __launch_bounds__(kBlock) void k_act_net(Batch bt) {
+// Act kernel of worlds with the paper's network.  Compiled for four waves per
+// SIMD: the compiler's own choice (about 185 registers, two waves) leaves the
+// load round trip of each wave exposed; four waves with a few spilled
+// registers measured about 20% faster, five or more spill too much.
+#ifndef ECO_NET_WAVES
+#define ECO_NET_WAVES 4   // waves per SIMD the network act kernel is compiled for (0 = compiler's choice)
+#endif
+#if ECO_NET_WAVES > 0
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(ECO_NET_WAVES, ECO_NET_WAVES)))
+#else
+__global__ __launch_bounds__(kBlock)
+#endif
+void k_act_net(Batch bt) {
     __shared__ StepShared sh;
     __shared__ net::WaveLds lds[kBlock / 64];
     act_body<16, true>(bt, blockIdx.x, threadIdx.x, sh, lds);
@@ -230,7 +241,7 @@ __global__ __launch_bounds__(kBlock) void k_materialize(const WorldDev* dp) {
     DevRef d = *kconst(dp);
     const int nc = d.scal->n_child;
     for (int rk = blockIdx.x; rk < nc; rk += gridDim.x) {
-        spawn_child(d, rk, threadIdx.x);
+        spawn_child(d, rk, threadIdx.x, d.ss);
         __syncthreads();
         if (d.ctrl == kCtrlGru) {
             spawn_proj(d, rk, threadIdx.x);

@@ -71,16 +71,25 @@ static_assert(kP == 2445, "parameter count of the paper's network");
 static_assert(kC1b % 4 == 0 && kLwi % 4 == 0 && kLwh % 4 == 0 && kLb % 4 == 0 && kD8w % 4 == 0 && kD8b % 4 == 0,
               "float4 rows");
 
-// One wave's scratch.
+// One wave's scratch.  The observation and the first pooled map carry a
+// border of zeros (the convolutions' padding), so every tap reads at a fixed
+// offset from the lane's base with no bounds test.
+constexpr int kOb = kWin + 2;    // 17: bordered observation edge
+constexpr int kPb = kP1 + 2;     // 9: bordered pool1 edge
+constexpr int kW2N = kLwi - kC2w;   // conv2 kernel and bias: 296 floats
 struct alignas(16) WaveLds {
-    float tab[9][5][4];   // conv1: weight sum of each channel combination per tap
-    float a1[kO1 * kO1][kF1];
-    float p1[kP1 * kP1][kF1];
-    float a2[kO2 * kO2][kF2];
-    float emb[84];        // embedding (78), then the new h (4)
-    float z[16];          // LSTM pre-activations [gate][unit]
-    float y8[kD];
-    uint8_t obs[kPix + 7];   // pixel bits: 1 resource, 2 agent, 4 wall
+    float w2s[kW2N + 24];        // conv2 kernel and bias, staged for the channel-per-lane reads
+    float tab[9][5][4];          // conv1: weight sum of each channel combination per tap
+    float p1[kPb * kPb][kF1];
+    union {
+        float a1[kO1 * kO1][kF1];   // conv1 output, dead after pool1
+        struct {
+            float a2[kO2 * kO2][kF2];
+            float emb[84];          // embedding (78), then the new h (4)
+            float y8[kD];
+        } late;
+    } u;
+    uint8_t obs[kOb * kOb + 3];  // pixel bits: 1 resource, 2 agent, 4 wall (0 on the border)
 };
 
 // LDS written by some lanes of the wave is read by others below: complete
@@ -90,6 +99,7 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
+
 __device__ __forceinline__ float4 add4(float4 a, float4 b) {
     return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
 }
@@ -98,28 +108,47 @@ __device__ __forceinline__ float4 fma4(float s, float4 w, float4 acc) {
     return make_float4(fmaf(s, w.x, acc.x), fmaf(s, w.y, acc.y), fmaf(s, w.z, acc.z), fmaf(s, w.w, acc.w));
 }
 
-__device__ __forceinline__ float4 xor_sum4(float4 v, int off) {
-    return make_float4(v.x + __shfl_xor(v.x, off), v.y + __shfl_xor(v.y, off), v.z + __shfl_xor(v.z, off),
-                       v.w + __shfl_xor(v.w, off));
+// Logistic function and tanh from the hardware exp2 and reciprocal (about one
+// ulp each; absolute error near 1e-7).
+__device__ __forceinline__ float sigm(float v) {
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(v * -1.44269504f));
 }
+__device__ __forceinline__ float tanh_(float v) { return fmaf(2.0f, sigm(2.0f * v), -1.0f); }
 
-__device__ __forceinline__ float sigm(float v) { return 1.0f / (1.0f + expf(-v)); }
-
+__device__ __forceinline__ void pinf(float v) { asm volatile("" ::"v"(v)); }
 __device__ __forceinline__ void pin4(float4 v) {
     asm volatile("" ::"v"(v.x), "v"(v.y), "v"(v.z), "v"(v.w));
 }
-__device__ __forceinline__ void pinf(float v) { asm volatile("" ::"v"(v)); }
+
+// Sum over the lanes that differ in lane bits lo..5 of a 4-vector, spread
+// over those lanes: after the call each lane holds one component, component
+// (2 bit_lo + bit_lo+1) of the total.  Two exchanges split the vector, the
+// remaining bits are summed with one exchange each.
+template <int LO>
+__device__ __forceinline__ float reduce_scatter4(float4 v, int lane) {
+    const bool b0 = (lane >> LO) & 1;
+    float k0 = b0 ? v.z : v.x, k1 = b0 ? v.w : v.y;       // kept: components 2 b0, 2 b0 + 1
+    const float s0 = b0 ? v.x : v.z, s1 = b0 ? v.y : v.w;  // sent to the partner
+    k0 += __shfl_xor(s0, 1 << LO);
+    k1 += __shfl_xor(s1, 1 << LO);
+    const bool b1 = (lane >> (LO + 1)) & 1;
+    float k = b1 ? k1 : k0;
+    k += __shfl_xor(b1 ? k0 : k1, 1 << (LO + 1));
+#pragma unroll
+    for (int off = 1 << (LO + 2); off < 64; off <<= 1) k += __shfl_xor(k, off);
+    return k;
+}
 
 // `rv`, `rv2`: the agent's record (slot, cell, energy, uid / age, streak,
-// previous action, ate).
+// previous action, ate); every field is the same in all lanes.
 __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int4 rv2, int li, int64_t t, int lane,
                                           WaveLds& L) {
     const int H = d.H, W = d.W;
-    const int slot = rv.x;
-    const int cell = rv.y;
-    const uint32_t u = uint32_t(rv.w);
-    const int prev = rv2.z;
-    const int ate = rv2.w;
+    const int slot = __builtin_amdgcn_readfirstlane(rv.x);
+    const int cell = __builtin_amdgcn_readfirstlane(rv.y);
+    const uint32_t u = uint32_t(__builtin_amdgcn_readfirstlane(rv.w));
+    const int prev = __builtin_amdgcn_readfirstlane(rv2.z);
+    const int ate = __builtin_amdgcn_readfirstlane(rv2.w);
     const int r = cell / W;
     const int c = cell - r * W;
     const float* th = d.theta + size_t(slot) * size_t(d.Ppad);
@@ -134,52 +163,57 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
         const int iy = q / kWin, ix = q - (q / kWin) * kWin;
         const int rr = r + iy - kRho, cc = c + ix - kRho;
         const bool in = q < kPix && rr >= 0 && rr < H && cc >= 0 && cc < W;
-        const int qc = in ? rr * W + cc : cell;   // every lane loads (clamped)
+        const uint32_t qc = uint32_t(in ? rr * W + cc : cell);   // every lane loads (clamped)
         const int rb = R[qc];
         const int ob = d.occA[qc];
         pb[m] = in ? ((rb != 0 ? 1 : 0) | (ob != -1 ? 2 : 0)) : 4;
     }
     const float4 hv = *reinterpret_cast<const float4*>(hs);   // h (uniform)
-    const float ck = hs[kHd + (lane & 3)];                       // c of unit lane % 4
     // conv1 weights of tap lane / 4, output channel lane % 4 (lanes < 36)
     const int l36 = min(lane, 35);
-    const float w1r = th[kC1w + ((l36 >> 2) * 3 + 0) * kF1 + (l36 & 3)];
-    const float w1a = th[kC1w + ((l36 >> 2) * 3 + 1) * kF1 + (l36 & 3)];
-    const float w1w = th[kC1w + ((l36 >> 2) * 3 + 2) * kF1 + (l36 & 3)];
+    const uint32_t o1 = uint32_t(kC1w + (l36 >> 2) * 3 * kF1 + (l36 & 3));
+    const float w1r = th[o1];
+    const float w1a = th[o1 + kF1];
+    const float w1w = th[o1 + 2 * kF1];
     const float4 b1 = *reinterpret_cast<const float4*>(th + kC1b);
-    // conv2: the 36 weights of output channel lane % 8
+    // conv2 kernel and bias: five coalesced words per lane, staged in LDS
+    // (each lane later needs the 36 weights of one channel, strided)
     const int co2 = lane & 7;
-    float w2[36];
+    float w2raw[5];
 #pragma unroll
-    for (int k = 0; k < 36; ++k) w2[k] = th[kC2w + k * kF2 + co2];
-    const float b2 = th[kC2b + co2];
-    // LSTM: rows ig + 16 m of the input kernel, gate q = lane % 4
+    for (int j = 0; j < 5; ++j) w2raw[j] = th[uint32_t(kC2w + min(j * 64 + lane, kW2N - 1))];
+    // LSTM: rows ig + 16 m of the input kernel, gate gq = lane % 4; after the
+    // reduction this lane owns unit uk of gate gq
     const int ig = lane >> 2, gq = lane & 3;
+    const int uk = 2 * ((lane >> 2) & 1) + ((lane >> 3) & 1);
     float4 wi[5];
 #pragma unroll
     for (int m = 0; m < 5; ++m) {
         const int i = min(ig + 16 * m, kEmb - 1);
-        wi[m] = *reinterpret_cast<const float4*>(th + kLwi + i * 16 + gq * 4);
+        wi[m] = *reinterpret_cast<const float4*>(th + uint32_t(kLwi + i * 16 + gq * 4));
     }
-    float4 wh[4];
+    float whk[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) wh[j] = *reinterpret_cast<const float4*>(th + kLwh + j * 16 + gq * 4);
-    const float4 lb = *reinterpret_cast<const float4*>(th + kLb + gq * 4);
-    // dense 8: rows ig8 + 32 m, outputs 4 hf .. 4 hf + 3
+    for (int j = 0; j < 4; ++j) whk[j] = th[uint32_t(kLwh + j * 16 + gq * 4 + uk)];
+    const float lbk = th[uint32_t(kLb + gq * 4 + uk)];
+    const float ck = hs[uint32_t(kHd + uk)];                      // c of unit uk
+    // dense 8: rows ig8 + 32 m, outputs 4 hf .. 4 hf + 3; after the reduction
+    // this lane owns output o8
     const int ig8 = lane >> 1, hf = lane & 1;
+    const int o8 = 4 * hf + 2 * ((lane >> 1) & 1) + ((lane >> 2) & 1);
     float4 w8[3];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
         const int i = min(ig8 + 32 * m, kCat - 1);
-        w8[m] = *reinterpret_cast<const float4*>(th + kD8w + i * kD + hf * 4);
+        w8[m] = *reinterpret_cast<const float4*>(th + uint32_t(kD8w + i * kD + hf * 4));
     }
-    const float4 b8 = *reinterpret_cast<const float4*>(th + kD8b + hf * 4);
+    const float b8 = th[uint32_t(kD8b + o8)];
     // head: column a = lane (lanes < 5)
     const int a5 = min(lane, kNA - 1);
     float w5[kD];
 #pragma unroll
-    for (int o = 0; o < kD; ++o) w5[o] = th[kD5w + o * kNA + a5];
-    const float b5 = th[kD5b + a5];
+    for (int o = 0; o < kD; ++o) w5[o] = th[uint32_t(kD5w + o * kNA + a5)];
+    const float b5 = th[uint32_t(kD5b + a5)];
     // complete the loads here, so that none is moved into a branch that uses
     // it (which would add a dependent round trip)
 #pragma unroll
@@ -187,14 +221,27 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
     pinf(w1r);
     pinf(w1a);
     pinf(w1w);
-    pin4(b8);
+    pinf(ck);
 
-    // ---- observation bits and the conv1 table into LDS ---------------------
+    // ---- observation bits (bordered) and the conv1 table into LDS ----------
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         const int q = lane + 64 * m;
-        if (q < kPix) L.obs[q] = uint8_t(pb[m]);
+        if (q < kPix) L.obs[(q / kWin + 1) * kOb + (q - (q / kWin) * kWin) + 1] = uint8_t(pb[m]);
     }
+    {
+        // the 64 border pixels, one per lane: top row, bottom row, left and
+        // right columns
+        int by, bx;
+        if (lane < kOb) { by = 0; bx = lane; }
+        else if (lane < 2 * kOb) { by = kOb - 1; bx = lane - kOb; }
+        else if (lane < 2 * kOb + kWin) { by = lane - 2 * kOb + 1; bx = 0; }
+        else { by = lane - 2 * kOb - kWin + 1; bx = kOb - 1; }
+        L.obs[by * kOb + bx] = 0;
+    }
+#pragma unroll
+    for (int j = 0; j < 5; ++j)
+        if (j * 64 + lane < kW2N) L.w2s[j * 64 + lane] = w2raw[j];
     if (lane < 36) {
         float* tp = &L.tab[lane >> 2][0][lane & 3];
         tp[0 * 4] = 0.f;
@@ -203,61 +250,68 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
         tp[3 * 4] = w1r + w1a;
         tp[4 * 4] = w1w;
     }
+    if (lane < 4 * kPb - 4) {   // zero border of the pooled map
+        int by, bx;
+        if (lane < kPb) { by = 0; bx = lane; }
+        else if (lane < 2 * kPb) { by = kPb - 1; bx = lane - kPb; }
+        else if (lane < 2 * kPb + kP1) { by = lane - 2 * kPb + 1; bx = 0; }
+        else { by = lane - 2 * kPb - kP1 + 1; bx = kPb - 1; }
+        *reinterpret_cast<float4*>(&L.p1[by * kPb + bx][0]) = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
     wave_lds_sync();
 
     // ---- conv1: lane = output pixel ------------------------------------------
     {
         const int oy = lane >> 3, ox = lane & 7;
+        const uint8_t* ob = &L.obs[(2 * oy) * kOb + 2 * ox];
         float4 acc = b1;
 #pragma unroll
         for (int ky = 0; ky < 3; ++ky)
 #pragma unroll
             for (int kx = 0; kx < 3; ++kx) {
-                const int iy = 2 * oy - 1 + ky, ix = 2 * ox - 1 + kx;
-                const bool ok = iy >= 0 && iy < kWin && ix >= 0 && ix < kWin;
-                const int bits = ok ? L.obs[iy * kWin + ix] : 0;   // zero padding
-                const float4 v = *reinterpret_cast<const float4*>(&L.tab[ky * 3 + kx][bits][0]);
-                acc = add4(acc, v);
+                const int bits = ob[ky * kOb + kx];
+                acc = add4(acc, *reinterpret_cast<const float4*>(&L.tab[ky * 3 + kx][bits][0]));
             }
-        *reinterpret_cast<float4*>(&L.a1[lane][0]) = acc;
+        *reinterpret_cast<float4*>(&L.u.a1[lane][0]) = acc;
     }
     wave_lds_sync();
 
     // ---- pool1: lane = pooled pixel ------------------------------------------
     if (lane < kP1 * kP1) {
         const int y = lane / kP1, x = lane - (lane / kP1) * kP1;
-        const float4 v00 = *reinterpret_cast<const float4*>(&L.a1[y * kO1 + x][0]);
-        const float4 v01 = *reinterpret_cast<const float4*>(&L.a1[y * kO1 + x + 1][0]);
-        const float4 v10 = *reinterpret_cast<const float4*>(&L.a1[(y + 1) * kO1 + x][0]);
-        const float4 v11 = *reinterpret_cast<const float4*>(&L.a1[(y + 1) * kO1 + x + 1][0]);
+        const float4 v00 = *reinterpret_cast<const float4*>(&L.u.a1[y * kO1 + x][0]);
+        const float4 v01 = *reinterpret_cast<const float4*>(&L.u.a1[y * kO1 + x + 1][0]);
+        const float4 v10 = *reinterpret_cast<const float4*>(&L.u.a1[(y + 1) * kO1 + x][0]);
+        const float4 v11 = *reinterpret_cast<const float4*>(&L.u.a1[(y + 1) * kO1 + x + 1][0]);
         const float4 s = add4(add4(add4(v00, v01), v10), v11);
-        *reinterpret_cast<float4*>(&L.p1[lane][0]) =
+        *reinterpret_cast<float4*>(&L.p1[(y + 1) * kPb + x + 1][0]) =
             make_float4(s.x * 0.25f, s.y * 0.25f, s.z * 0.25f, s.w * 0.25f);
     }
     wave_lds_sync();
 
     // ---- conv2: lane = (channel lane % 8, pixels lane / 8 and lane / 8 + 8) --
+    float w2[36];
+#pragma unroll
+    for (int k = 0; k < 36; ++k) w2[k] = L.w2s[k * kF2 + co2];
+    const float b2 = L.w2s[kC2b - kC2w + co2];
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
         const int p = (lane >> 3) + 8 * half;
         const int oy = p >> 2, ox = p & 3;
+        const float4* pp = reinterpret_cast<const float4*>(&L.p1[(2 * oy) * kPb + 2 * ox][0]);
         float acc = 0.f;
 #pragma unroll
         for (int ky = 0; ky < 3; ++ky)
 #pragma unroll
             for (int kx = 0; kx < 3; ++kx) {
-                const int iy = 2 * oy - 1 + ky, ix = 2 * ox - 1 + kx;
-                const bool ok = iy >= 0 && iy < kP1 && ix >= 0 && ix < kP1;
-                const int q = ok ? iy * kP1 + ix : 0;
-                float4 v = *reinterpret_cast<const float4*>(&L.p1[q][0]);
-                if (!ok) v = make_float4(0.f, 0.f, 0.f, 0.f);   // zero padding
+                const float4 v = pp[ky * kPb + kx];
                 const int k = (ky * 3 + kx) * kF1;
                 acc = fmaf(v.x, w2[k + 0], acc);
                 acc = fmaf(v.y, w2[k + 1], acc);
                 acc = fmaf(v.z, w2[k + 2], acc);
                 acc = fmaf(v.w, w2[k + 3], acc);
             }
-        L.a2[p][co2] = acc + b2;
+        L.u.late.a2[p][co2] = acc + b2;
     }
     wave_lds_sync();
 
@@ -267,42 +321,38 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
         const int f = lane + 64 * m;   // (y, x, channel) = (f / 24, f / 8 % 3, f % 8)
         if (f < kFlat) {
             const int y = f / 24, x = (f >> 3) % 3, ch = f & 7;
-            const float s = ((L.a2[y * kO2 + x][ch] + L.a2[y * kO2 + x + 1][ch]) + L.a2[(y + 1) * kO2 + x][ch]) +
-                            L.a2[(y + 1) * kO2 + x + 1][ch];
-            L.emb[f] = s * 0.25f;
+            const float(*a2)[kF2] = L.u.late.a2;
+            const float s = ((a2[y * kO2 + x][ch] + a2[y * kO2 + x + 1][ch]) + a2[(y + 1) * kO2 + x][ch]) +
+                            a2[(y + 1) * kO2 + x + 1][ch];
+            L.u.late.emb[f] = s * 0.25f;
         }
     }
-    if (lane < kNA) L.emb[kFlat + lane] = (prev == lane) ? 1.f : 0.f;
-    if (lane == kNA) L.emb[kFlat + kNA] = ate ? 1.f : 0.f;
+    if (lane < kNA) L.u.late.emb[kFlat + lane] = (prev == lane) ? 1.f : 0.f;
+    if (lane == kNA) L.u.late.emb[kFlat + kNA] = ate ? 1.f : 0.f;
     wave_lds_sync();
 
-    // ---- LSTM: lane = (input group, gate) ------------------------------------
+    // ---- LSTM: lane = (input group, gate), then (unit uk, gate gq) ----------
+    float hnew, cnew;
     {
         float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
         for (int m = 0; m < 5; ++m) {
             const int i = ig + 16 * m;
-            const float e = i < kEmb ? L.emb[min(i, kEmb - 1)] : 0.f;
+            const float e = i < kEmb ? L.u.late.emb[min(i, kEmb - 1)] : 0.f;
             acc = fma4(e, wi[m], acc);
         }
-#pragma unroll
-        for (int off = 4; off < 64; off <<= 1) acc = xor_sum4(acc, off);
-        float4 rec = make_float4(0.f, 0.f, 0.f, 0.f);
-        rec = fma4(hv.x, wh[0], rec);
-        rec = fma4(hv.y, wh[1], rec);
-        rec = fma4(hv.z, wh[2], rec);
-        rec = fma4(hv.w, wh[3], rec);
-        const float4 z = add4(add4(acc, rec), lb);
-        if (lane < 4) *reinterpret_cast<float4*>(&L.z[gq * 4]) = z;
-    }
-    wave_lds_sync();
-    float hnew, cnew;
-    {
-        const int k = lane & 3;   // unit
-        const float zi = L.z[0 * 4 + k], zf = L.z[1 * 4 + k], zg = L.z[2 * 4 + k], zo = L.z[3 * 4 + k];
-        cnew = fmaf(sigm(zf), ck, sigm(zi) * tanhf(zg));
-        hnew = sigm(zo) * tanhf(cnew);
-        if (lane < 4) L.emb[kEmb + k] = hnew;
+        float z = reduce_scatter4<2>(acc, lane);
+        float rec = hv.x * whk[0];
+        rec = fmaf(hv.y, whk[1], rec);
+        rec = fmaf(hv.z, whk[2], rec);
+        rec = fmaf(hv.w, whk[3], rec);
+        z = (z + rec) + lbk;
+        // the four gates of unit uk sit in the lane's quad (gq = 0..3)
+        const int q0 = lane & ~3;
+        const float zi = __shfl(z, q0 + 0), zf = __shfl(z, q0 + 1), zg = __shfl(z, q0 + 2), zo = __shfl(z, q0 + 3);
+        cnew = fmaf(sigm(zf), ck, sigm(zi) * tanh_(zg));
+        hnew = sigm(zo) * tanh_(cnew);
+        if (lane < 16 && gq == 0) L.u.late.emb[kEmb + uk] = hnew;
     }
     wave_lds_sync();
 
@@ -312,29 +362,24 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
             const int i = ig8 + 32 * m;
-            const float e = i < kCat ? L.emb[min(i, kCat - 1)] : 0.f;
+            const float e = i < kCat ? L.u.late.emb[min(i, kCat - 1)] : 0.f;
             acc = fma4(e, w8[m], acc);
         }
-#pragma unroll
-        for (int off = 2; off < 64; off <<= 1) acc = xor_sum4(acc, off);
-        if (lane < 2) {
-            L.y8[hf * 4 + 0] = tanhf(acc.x + b8.x);
-            L.y8[hf * 4 + 1] = tanhf(acc.y + b8.y);
-            L.y8[hf * 4 + 2] = tanhf(acc.z + b8.z);
-            L.y8[hf * 4 + 3] = tanhf(acc.w + b8.w);
-        }
+        const float y = tanh_(reduce_scatter4<1>(acc, lane) + b8);
+        if (lane < 8) L.u.late.y8[o8] = y;
     }
     wave_lds_sync();
 
     // ---- logits (lane a < 5) and the sampled action -----------------------------
     float lg = 0.f;
 #pragma unroll
-    for (int o = 0; o < kD; ++o) lg = fmaf(L.y8[o], w5[o], lg);
+    for (int o = 0; o < kD; ++o) lg = fmaf(L.u.late.y8[o], w5[o], lg);
     lg = lg + b5;
-    // sampling score 50 l + g, g from word a % 4 of ACT block a / 4
-    const Draw4 dr = philox(u, uint32_t(t), kAct, lane < 4 ? 0u : 1u, d.seed_lo, d.seed_hi);
-    const int wsel = lane & 3;
-    const uint32_t word = lane >= 4 ? dr.x : (wsel == 0 ? dr.x : (wsel == 1 ? dr.y : (wsel == 2 ? dr.z : dr.w)));
+    // sampling score 50 l + g, g from word a % 4 of ACT block a / 4 (the
+    // draws depend on the agent and the step only: scalar)
+    const Draw4 d0 = philox(u, uint32_t(t), kAct, 0u, d.seed_lo, d.seed_hi);
+    const Draw4 d1 = philox(u, uint32_t(t), kAct, 1u, d.seed_lo, d.seed_hi);
+    const uint32_t word = lane == 0 ? d0.x : (lane == 1 ? d0.y : (lane == 2 ? d0.z : (lane == 3 ? d0.w : d1.x)));
     const float sc = 50.0f * lg + gumbel_of_word(word);
     int best = 0;
     float top = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sc), 0));
@@ -349,9 +394,9 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
     if (d.forced >= 0) best = d.forced;
 
     // ---- outputs ----------------------------------------------------------------
-    if (lane < kHd) {
-        d.h[size_t(slot) * kState + lane] = hnew;
-        d.h[size_t(slot) * kState + kHd + lane] = cnew;
+    if (lane < 16 && gq == 0) {
+        d.h[size_t(slot) * kState + uk] = hnew;
+        d.h[size_t(slot) * kState + kHd + uk] = cnew;
     }
     if (lane == 0 && t % kMoveWin == 0) {   // a movement window starts with this step
         d.wcell[slot] = cell;
@@ -363,7 +408,7 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
         // Move claim: the target must be inside the grid and empty at the
         // step start (no agent, no wall in the observation).
         if (best < 4) {
-            const int q = (kRho + act_dr(best)) * kWin + (kRho + act_dc(best));
+            const int q = (kRho + 1 + act_dr(best)) * kOb + (kRho + 1 + act_dc(best));
             if ((L.obs[q] & 6) == 0) {
                 const uint64_t key = claim_key(philox(u, uint32_t(t), kMove, 0, d.seed_lo, d.seed_hi).x, u);
                 const int Y = (r + act_dr(best)) * W + (c + act_dc(best));

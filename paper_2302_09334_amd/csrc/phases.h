@@ -907,9 +907,11 @@ __device__ __forceinline__ void regrow_tile(DevRef d, int tile, int lane, uint8_
 // the child enters occB
 // (occA received it when it was born; the parent's streak restarted then).
 // Every store is complete when this returns, so the same block can run the
-// child's controller right after a block barrier.
+// child's controller right after a block barrier.  `ss`: recurrent state
+// floats per slot (the caller's, so that the GRU act kernel sizes it by the
+// descriptor field its controller already reads).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void spawn_child(DevRef d, int rk, int tid) {
+__device__ __forceinline__ void spawn_child(DevRef d, int rk, int tid, int ss) {
     const int4 rec = d.child[rk];   // child slot, parent slot, cell, uid
     const uint32_t ts = uint32_t(d.scal->spawn_t);
     const float* par = d.theta + size_t(rec.y) * size_t(d.Ppad);
@@ -942,7 +944,7 @@ __device__ __forceinline__ void spawn_child(DevRef d, int rk, int tid) {
         d.ate[cs] = 0;
         d.occB[rec.z] = cs;
     }
-    if (tid < d.ss) d.h[size_t(cs) * d.ss + tid] = 0.f;
+    if (tid < ss) d.h[size_t(cs) * ss + tid] = 0.f;
     __builtin_amdgcn_s_waitcnt(0);   // this thread's stores have completed
 }
 
