@@ -19,6 +19,11 @@ Also reported:
   events stamped by their own dispatch; ``kernels`` lists all three.
 * ``cpu_baseline``: the oracle (plain C, one thread) on a bounded sample of
   the same workload on the host cores.
+* ``lab``: the lab environments of Sec. 2.2 -- agents evolved in the paper's
+  network world (net1k) tested alone in 40 x 40 worlds without regrowth at
+  three densities (greediness) and with reproduction (peer pressure): all
+  lab worlds in shared launches, their rate against a sample of them stepped
+  one at a time, and the greediness / efficiency statistics.
 * ``paper_network``: the same 200 x 400 world with ~4k agents driven by the
   paper's controller (App. B.5: CNN + LSTM(4), 2445 parameters, sampled
   actions; workload ``net_m1_4k``): wall-clock agent-steps/s, per-kernel
@@ -338,6 +343,69 @@ def served_run(args) -> dict:
     return m
 
 
+def lab_run(args) -> dict:
+    """Lab environments (Sec. 2.2) as a batched workload of many tiny worlds."""
+    import torch
+    from paper_2302_09334_amd import lab, workloads, world
+    base = workloads.WORKLOADS["net1k"]
+    t0 = time.perf_counter()
+    snap = lab.evolve(base, args.seed, args.lab_evolve_steps)
+    genomes = lab.sample_agents(snap, args.lab_agents, seed=0)
+    evolve_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    run = lab.LabRun(genomes, base, lab.conditions(), trials=args.lab_trials)
+    setup_s = time.perf_counter() - t0
+    steps = lab.STEPS
+    run.step(100)   # graph capture outside the timed region
+    run.sync()
+    for w, img in zip(run.worlds, run.images):
+        w.load(img)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run.step(steps)
+    run.sync()
+    wall = time.perf_counter() - t0
+    ctrs = run.counters(steps)
+    acting = sum(int(np.concatenate([[1], c["n_live"][:-1]]).sum()) for c in ctrs)
+    g = lab.greediness_study(run, ctrs, len(genomes))
+    pp = lab.peer_pressure_study(run, ctrs)
+    # a sample of the same worlds stepped one at a time (plain path, graph launches)
+    n_seq = min(args.lab_seq_sample, len(run.worlds))
+    seq_wall = 0.0
+    for i in range(n_seq):
+        w = run.worlds[i]
+        w.load(run.images[i])
+        w.step(100)
+        w.sync()
+        w.load(run.images[i])
+        t1 = time.perf_counter()
+        for _ in range(steps // 100):
+            w.step(100)
+        w.sync()
+        seq_wall += time.perf_counter() - t1
+    seq_rate = n_seq * steps / seq_wall
+    n_worlds = len(run.worlds)
+    run.close()
+    out = {
+        "workload": f"{len(genomes)} agents sampled from net1k after {args.lab_evolve_steps} steps (seed {args.seed}); "
+                    f"40x40 lab worlds without regrowth, densities {lab.DENSITIES} without reproduction and the "
+                    f"high density with reproduction (T_repr {lab.T_REPR_LAB}); {args.lab_trials} trials each; "
+                    f"{steps} steps",
+        "worlds": n_worlds, "steps": steps, "wall_s": wall,
+        "world_steps_per_s": n_worlds * steps / wall, "agent_steps_per_s": acting / wall,
+        "sequential_sample": {"worlds": n_seq, "world_steps_per_s": seq_rate},
+        "speedup_vs_sequential": (n_worlds * steps / wall) / seq_rate,
+        "evolve_s": evolve_s, "setup_s": setup_s,
+        "greediness": {"G_mean_by_density": g["G_mean_by_density"], "sustainable_foragers": g["sustainable_foragers"],
+                       "agents": len(genomes)},
+        "peer_pressure": pp,
+    }
+    log(f"[bench] lab: {n_worlds} worlds x {steps} steps in {wall * 1e3:.1f} ms = {out['world_steps_per_s'] / 1e6:.2f} M "
+        f"world-steps/s ({out['speedup_vs_sequential']:.0f}x one at a time); G {g['G_mean_by_density']}, "
+        f"sustainable {g['sustainable_foragers']}/{len(genomes)}; E off {pp['E_mean_off']:.2f} on {pp['E_mean_on']:.2f}")
+    return out
+
+
 def copy_calibration(torch, world):
     """Three launches of the plain copy kernel over 1 GiB (the known-size
     reference for the memory counters)."""
@@ -374,6 +442,10 @@ def main():
     ap.add_argument("--net-warmup", type=int, default=300)
     ap.add_argument("--net-phase-steps", type=int, default=100)
     ap.add_argument("--only-net", action="store_true", help="run only the paper-network leg and print it")
+    ap.add_argument("--lab-agents", type=int, default=50, help="evolved agents of the lab leg (0 = skip)")
+    ap.add_argument("--lab-trials", type=int, default=10)
+    ap.add_argument("--lab-evolve-steps", type=int, default=20000)
+    ap.add_argument("--lab-seq-sample", type=int, default=20)
     args = ap.parse_args()
 
     world_size = int(os.environ.get("WORLD_SIZE", "1"))
@@ -522,6 +594,9 @@ def main():
     net = None
     if args.net_steps > 0:
         net = net_run(args)
+    labs = None
+    if args.lab_agents > 0:
+        labs = lab_run(args)
 
     m2 = None
     if args.m2_steps > 0:
@@ -606,6 +681,7 @@ def main():
         },
         "ecology_metrics": metrics,
         "paper_network": net,
+        "lab": labs,
         "cache_exceeding": m2,
         "cpu_baseline": cpu,
         "batched": batched,

@@ -99,6 +99,10 @@ typedef struct world_counters {
     int64_t dead_age_sum;/* sum of the ages of the agents that died in the step
                             (life expectancy over a window, App. C: the sum of
                             this field over the window / the sum of deaths) */
+    int32_t seen_resource;/* acting agents with a resource in their field of
+                            view at the step start (greediness of the lab
+                            environments, Sec. 2.2)                         */
+    int32_t reserved;
 } world_counters;
 
 /* Movement metric (App. C).  Window k covers steps [k * WORLD_MOVE_WINDOW,

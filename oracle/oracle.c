@@ -867,6 +867,17 @@ int oracle_step(void *vw, const uint32_t *hint_uid, const uint8_t *hint_act, int
     for (int a = 0; a < w->n; ++a) {
         uint32_t u = w->uid[a];
         double *lg = w->last_logits + (size_t)a * 5;
+        /* lab greediness: does the field of view hold a resource? */
+        int sees = 0;
+        for (int dy = -w->rho; dy <= w->rho && !sees; ++dy)
+            for (int dx = -w->rho; dx <= w->rho; ++dx) {
+                int r = w->row[a] + dy, c = w->col[a] + dx;
+                if (in_grid(w, r, c) && w->R[r * W + c]) {
+                    sees = 1;
+                    break;
+                }
+            }
+        inf.seen += sees;
         float *ha = w->h + (size_t)a * hd;
         float lf[5], sc[5];
         if (cnn) {
@@ -1140,6 +1151,47 @@ int oracle_step(void *vw, const uint32_t *hint_uid, const uint8_t *hint_act, int
     }
     w->t++;
     if (info) *info = inf;
+    return 0;
+}
+
+int oracle_load(void *vw, int64_t step, int32_t n, uint32_t next_uid, const uint8_t *R, const uint32_t *uid,
+                const int32_t *row, const int32_t *col, const int32_t *energy, const int32_t *age,
+                const int32_t *streak, const float *h, const float *theta, const uint8_t *last_action,
+                const uint8_t *ate)
+{
+    world *w = (world *)vw;
+    const int H = w->cfg.H, W = w->cfg.W;
+    const size_t HW = (size_t)H * W, P = (size_t)w->P, ss = (size_t)w->ss;
+    if (n < 0 || n > w->cfg.cap || step < 0) return -1;
+    for (int a = 0; a < n; ++a) {
+        if (!in_grid(w, row[a], col[a])) return -1;
+        if (a > 0 && uid[a] <= uid[a - 1]) return -1;
+        if (uid[a] >= next_uid || last_action[a] > ORACLE_NO_ACTION || ate[a] > 1) return -1;
+    }
+    for (size_t i = 0; i < HW; ++i) w->occ[i] = -1;
+    for (int a = 0; a < n; ++a) {
+        int cell = row[a] * W + col[a];
+        if (w->occ[cell] != -1) return -1;
+        w->occ[cell] = a;
+    }
+    memcpy(w->R, R, HW);
+    for (int a = 0; a < n; ++a) {
+        w->uid[a] = uid[a];
+        w->row[a] = row[a];
+        w->col[a] = col[a];
+        w->e[a] = energy[a];
+        w->age[a] = age[a];
+        w->streak[a] = streak[a];
+        w->pact[a] = last_action[a];
+        w->pate[a] = ate[a];
+        w->wvalid[a] = 0;
+    }
+    memcpy(w->h, h, (size_t)n * ss * sizeof(float));
+    memcpy(w->theta, theta, (size_t)n * P * sizeof(float));
+    w->n = n;
+    w->next_uid = next_uid;
+    w->t = step;
+    w->last_n = 0;
     return 0;
 }
 

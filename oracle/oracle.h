@@ -66,6 +66,9 @@ typedef struct oracle_stepinfo {
     int32_t mismatches;  /* hints that disagreed outside the near-tie band     */
     int32_t claim_wins;  /* birth-claim winners before the slot cap            */
     int64_t dead_age;    /* sum of the ages of the agents that died (App. C)   */
+    int32_t seen;        /* acting agents with a resource in their field of view
+                            at the step start (greediness, Sec. 2.2)          */
+    int32_t pad;
 } oracle_stepinfo;
 
 /* Movement metric (App. C): windows of ORACLE_MOVE_WINDOW steps, window k
@@ -151,6 +154,15 @@ void oracle_get_grid(const void *w, uint8_t *R);
 void oracle_get_agents(const void *w, uint32_t *uid, int32_t *row, int32_t *col,
                        int32_t *energy, int32_t *age, int32_t *streak);
 void oracle_get_hidden(const void *w, float *h);          /* n_live x state: h (GRU); h then c (LSTM) */
+/* Overwrite the state (the canonical image: agents in increasing uid, genomes
+ * in genome order, recurrent state h (and c), previous action, ate bit).  A
+ * movement window in progress counts no agent afterwards.  Returns 0, or -1 on
+ * an invalid image (positions, order, sizes). */
+int oracle_load(void *w, int64_t step, int32_t n, uint32_t next_uid, const uint8_t *R, const uint32_t *uid,
+                const int32_t *row, const int32_t *col, const int32_t *energy, const int32_t *age,
+                const int32_t *streak, const float *h, const float *theta, const uint8_t *last_action,
+                const uint8_t *ate);
+
 /* Previous action (0..4, ORACLE_NO_ACTION) and whether the agent ate in its
  * previous step, per live agent. */
 void oracle_get_recurrent_inputs(const void *w, uint8_t *last_action, uint8_t *ate);

@@ -54,10 +54,11 @@ class StepInfo(C.Structure):
         ("n_live", C.c_int32), ("births", C.c_int32), ("deaths", C.c_int32),
         ("eaten", C.c_int32), ("resources", C.c_int32), ("resyncs", C.c_int32),
         ("mismatches", C.c_int32), ("claim_wins", C.c_int32), ("dead_age", C.c_int64),
+        ("seen", C.c_int32), ("pad", C.c_int32),
     ]
 
     def as_dict(self) -> dict:
-        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+        return {name: int(getattr(self, name)) for name, _ in self._fields_ if name != "pad"}
 
 
 @dataclass
@@ -154,6 +155,8 @@ def lib():
         L.oracle_get_recurrent_inputs.argtypes = [P, P, P]
         L.oracle_get_obs_cnn.argtypes = [P, C.c_int32, P]
         L.oracle_get_obs_cnn.restype = C.c_int
+        L.oracle_load.argtypes = [P, C.c_int64, C.c_int32, C.c_uint32] + [P] * 11
+        L.oracle_load.restype = C.c_int
         _lib = L
     return _lib
 
@@ -331,6 +334,23 @@ class OracleWorld:
         h = np.empty((self.n_live, self.cfg.state_size), np.float32)
         lib().oracle_get_hidden(self._h, _ptr(h))
         return h
+
+    def load(self, s: dict):
+        """Overwrite the state from a canonical image (the keys of state(with_hidden=True,
+        with_theta=True))."""
+        n = int(s["n_live"])
+        arr = {"R": np.ascontiguousarray(s["R"], np.uint8).ravel(), "uid": np.ascontiguousarray(s["uid"], np.uint32)}
+        for k in ("row", "col", "energy", "age", "streak"):
+            arr[k] = np.ascontiguousarray(s[k], np.int32)
+        arr["h"] = np.ascontiguousarray(s["h"], np.float32).reshape(n, self.cfg.state_size)
+        arr["theta"] = np.ascontiguousarray(s["theta"], np.float32).reshape(n, self.P)
+        arr["last_action"] = np.ascontiguousarray(s["last_action"], np.uint8)
+        arr["ate"] = np.ascontiguousarray(s["ate"], np.uint8)
+        rc = lib().oracle_load(self._h, int(s["t"]), n, int(s["next_uid"]),
+                               *[_ptr(arr[k]) for k in ("R", "uid", "row", "col", "energy", "age", "streak", "h",
+                                                        "theta", "last_action", "ate")])
+        if rc != 0:
+            raise ValueError("invalid image")
 
     def recurrent_inputs(self) -> dict:
         """Previous action (NO_ACTION before the first) and ate-in-previous-step bit."""

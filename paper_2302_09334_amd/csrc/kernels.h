@@ -17,6 +17,10 @@ namespace eco {
 enum : int { kPreAct = 0, kPreMove = 1, kPreClaim = 2, kPreKinds = 3 };
 constexpr int kNewbornBlocks = 512;  // leading act blocks that create children (idle ones exit at once)
 
+// Newborn blocks of a world with `cap` slots (a world never has more children
+// per step than slots).
+__host__ __device__ constexpr int newborn_blocks(int cap) { return cap < kNewbornBlocks ? cap : kNewbornBlocks; }
+
 struct Batch {
     const WorldDev* const* w;   // n descriptors
     const int* pre;             // kPreKinds x (n + 1) block prefixes
@@ -75,8 +79,8 @@ __device__ __forceinline__ BlockWorld block_world(const Batch& bt, int kind, int
 // Block bodies.  `vb` is the block's index in the batch-wide numbering of its
 // phase.
 
-// Act blocks of a world: kNewbornBlocks leading blocks create the children of
-// the previous step (rank r, r + kNewbornBlocks, ...) and run their first
+// Act blocks of a world: nb = newborn_blocks(cap) leading blocks create the
+// children of the previous step (rank r, r + nb, ...) and run their first
 // controller step (they are the last n_child entries of the live list); the
 // remaining blocks run the controller of the other agents, four per block.
 // NET: the paper's network (with `lds`, one scratch per wave), else the GRU.
@@ -88,7 +92,8 @@ __device__ __forceinline__ void act_body(const Batch& bt, int vb, int tid, StepS
     const int lb = bw.lb;
     // the agent's record words in both lists, read together with the
     // scalars (index clamped; the newborn blocks read theirs later)
-    const int li = (lb - kNewbornBlocks) * (kBlock / 64) + (tid >> 6);
+    const int nb = newborn_blocks(bw.cap);
+    const int li = (lb - nb) * (kBlock / 64) + (tid >> 6);
     const int lc = min(max(li, 0), bw.cap - 1);
     const int4 q0 = *reinterpret_cast<const int4*>(&P[lc].r[0]);
     const int4 q1 = *reinterpret_cast<const int4*>(&P[lc].r[1]);
@@ -108,14 +113,14 @@ __device__ __forceinline__ void act_body(const Batch& bt, int vb, int tid, StepS
     const int n = ss.n;
     const int nc = ss.nc;
     const int sel = ss.sel;
-    if (lb < kNewbornBlocks) {
+    if (lb < nb) {
         if (lb == 0) {
             if (tid == 0) step_open(d, t);
             if (t % kMoveWin == 0 && tid <= kMoveBins)   // a movement window starts: clear its record
                 d.mhist[((t / kMoveWin) % kMoveRing) * (kMoveBins + 1) + tid] = 0;
             close_counters_in_step(d, tid, sh);
         }
-        for (int rk = lb; rk < nc; rk += kNewbornBlocks) {
+        for (int rk = lb; rk < nc; rk += nb) {
             spawn_child(d, rk, tid, NET ? net::kState : d.hd);
             __syncthreads();
             if constexpr (!NET) {

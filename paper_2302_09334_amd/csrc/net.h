@@ -392,6 +392,8 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
         }
     }
     if (d.forced >= 0) best = d.forced;
+    const bool seen = (__ballot((pb[0] & 1) != 0) | __ballot((pb[1] & 1) != 0) | __ballot((pb[2] & 1) != 0) |
+                       __ballot((pb[3] & 1) != 0 && lane + 192 < kPix)) != 0;   // a resource in view
 
     // ---- outputs ----------------------------------------------------------------
     if (lane < 16 && gq == 0) {
@@ -404,7 +406,7 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
     }
     if (lane == 0) {
         d.action[slot] = uint8_t(best);
-        recp->action = best;
+        recp->action = best | (seen ? kSeenBit : 0);
         // Move claim: the target must be inside the grid and empty at the
         // step start (no agent, no wall in the observation).
         if (best < 4) {

@@ -217,6 +217,7 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
     uint64_t mR = __ballot(rb);
     uint64_t mO = __ballot(ob);
     const uint64_t occ_bits = mO;
+    const bool seen = mR != 0;   // a resource in the field of view
 
     // Round trips 2..: the input rows.  A window with more ones than zeros is
     // summed as its precomputed column total minus the rows of its zeros
@@ -311,7 +312,7 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
     }
     if (lane == 0) {
         d.action[slot] = uint8_t(best);
-        recp->action = best;
+        recp->action = best | (seen ? kSeenBit : 0);
         // Move claim (resolved by the next phase): a move targets the window
         // cell one step away, which must be inside the grid and empty at the
         // step start (its occupancy bit, outside cells reading occupied, is 0).
@@ -439,14 +440,14 @@ __device__ __forceinline__ WaveRank wave_rank2(bool a, bool b, int lane) {
 // resource of the final cell, energy += gain * ate - decay, age += 1, death
 // at energy <= 0 or age >= L_max, streak of survivors.  occB receives the
 // moves and deaths; occA (read by every agent in this phase) is untouched.
-// Returns bit 0 = ate, bit 1 = died.
+// Returns bit 0 = ate, bit 1 = died, bit 2 = had a resource in view.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int move_agent(DevRef d, const AgentRec& a, int64_t t, PostRec* post,
                                           AgentRec* next_rec_src) {
     const int W = d.W, H = d.H;
     const int slot = a.slot;
     const int X = a.cell;
-    const int act = a.action;
+    const int act = a.action & kActMask;
     const uint32_t u = a.uid;
     const int r = X / W, c = X - (X / W) * W;
     uint8_t* Rc = d.R[t & 1];
@@ -520,7 +521,7 @@ __device__ __forceinline__ int move_agent(DevRef d, const AgentRec& a, int64_t t
     nr.action = act;   // the previous action and ate bit of the next step
     nr.ate = ate;
     *next_rec_src = nr;
-    return ate | (dead ? 2 : 0);
+    return ate | (dead ? 2 : 0) | ((a.action & kSeenBit) ? 4 : 0);
 }
 
 // The world scalars a block works with, read once at its start.
@@ -567,7 +568,7 @@ __device__ __forceinline__ StepScal read_step(const WorldScal* S) {
 }
 
 struct StepShared {
-    int sw[2 * (kBlock / 64)];
+    int sw[3 * (kBlock / 64)];
     long long sw64[kBlock / 64];
 };
 
@@ -588,13 +589,14 @@ __device__ __forceinline__ void move_block(DevRef d, PosRec* P, int j, int lane,
     const bool alive = i < n && !(res & 2);
     const bool dead = i < n && (res & 2);
     const int cnt = __popcll(__ballot((res & 1) != 0));
+    const int cnt_seen = __popcll(__ballot((res & 4) != 0));
     int dage = dead ? nr.age : 0;   // age at death (life expectancy, App. C)
     if (__ballot(dead)) {            // deaths are rare: most tiles skip the sum
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) dage += __shfl_xor(dage, off);
     }
     if (lane == 0) {
-        d.eat_part[j] = cnt;
+        d.eat_part[j] = cnt | (cnt_seen << 16);
         d.dage_part[j] = dage;
     }
     // Movement metric (App. C): the window ends with this step; every
@@ -966,10 +968,12 @@ __device__ __forceinline__ void close_counters(DevRef d, int tid, StepShared& sh
     WorldScal* S = d.scal;
     if (!S->ctr_open) return;
     const int nwv = (S->n_prev + 63) / 64;
-    int pe = 0, pr = 0;
+    int pe = 0, pr = 0, ps = 0;
     long long pa = 0;
     for (int i = tid; i < nwv; i += kBlock) {
-        pe += d.eat_part[i];
+        const int ep = d.eat_part[i];
+        pe += ep & 0xFFFF;
+        ps += ep >> 16;
         pa += d.dage_part[i];
     }
     for (int i = tid; i < d.ntiles; i += kBlock) pr += d.res_part[i];
@@ -977,20 +981,23 @@ __device__ __forceinline__ void close_counters(DevRef d, int tid, StepShared& sh
     for (int off = 32; off > 0; off >>= 1) {
         pe += __shfl_xor(pe, off);
         pr += __shfl_xor(pr, off);
+        ps += __shfl_xor(ps, off);
         pa += __shfl_xor(pa, off);
     }
     if ((tid & 63) == 0) {
         sh.sw[tid >> 6] = pe;
         sh.sw[(kBlock / 64) + (tid >> 6)] = pr;
+        sh.sw[2 * (kBlock / 64) + (tid >> 6)] = ps;
         sh.sw64[tid >> 6] = pa;
     }
     __syncthreads();
     if (tid == 0) {
-        int te = 0, tr = 0;
+        int te = 0, tr = 0, ts = 0;
         long long ta = 0;
         for (int w = 0; w < kBlock / 64; ++w) {
             te += sh.sw[w];
             tr += sh.sw[(kBlock / 64) + w];
+            ts += sh.sw[2 * (kBlock / 64) + w];
             ta += sh.sw64[w];
         }
         int32_t* rec = d.ring + (S->spawn_t % kRing) * kCtrWords;
@@ -998,6 +1005,7 @@ __device__ __forceinline__ void close_counters(DevRef d, int tid, StepShared& sh
         rec[kCtrRes] = tr;
         rec[kCtrDeadAgeLo] = int32_t(uint64_t(ta) & 0xFFFFFFFFu);
         rec[kCtrDeadAgeHi] = int32_t(uint64_t(ta) >> 32);
+        rec[kCtrSeen] = ts;
     }
     __syncthreads();
 }

@@ -277,7 +277,7 @@ std::vector<int> batch_prefix(const std::vector<const world*>& ws) {
     std::vector<int> pre(size_t(kPreKinds) * (n + 1), 0);
     for (int i = 0; i < n; ++i) {
         const world_config& c = ws[i]->cfg;
-        pre[kPreAct * (n + 1) + i + 1] = pre[kPreAct * (n + 1) + i] + kNewbornBlocks + blocks_act(c);
+        pre[kPreAct * (n + 1) + i + 1] = pre[kPreAct * (n + 1) + i] + newborn_blocks(c.cap) + blocks_act(c);
         // GRU worlds add one recurrent-projection block per slot
         pre[kPreMove * (n + 1) + i + 1] = pre[kPreMove * (n + 1) + i] + tiles_agent(c) + (is_net(c) ? 0 : c.cap);
         pre[kPreClaim * (n + 1) + i + 1] = pre[kPreClaim * (n + 1) + i] + tiles_agent(c) + tiles_of(c);
@@ -927,6 +927,8 @@ int world_counters_get(world_t* w, int64_t first, int32_t n, world_counters* out
         out[i].resources = r[kCtrRes];
         out[i].claim_wins = r[kCtrWins];
         out[i].dead_age_sum = int64_t((uint64_t(uint32_t(r[kCtrDeadAgeHi])) << 32) | uint32_t(r[kCtrDeadAgeLo]));
+        out[i].seen_resource = r[kCtrSeen];
+        out[i].reserved = 0;
     }
     return WORLD_OK;
 }

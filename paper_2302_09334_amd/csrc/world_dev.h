@@ -29,12 +29,19 @@
 namespace eco {
 
 constexpr int kRing = 8192;     // steps of counters kept on device
-constexpr int kCtrWords = 8;    // words per counter record
+constexpr int kCtrWords = 10;   // words per counter record
 constexpr int kBlock = 256;     // threads per block in every kernel
 constexpr int kTile = 16;       // regrowth tile edge (16 x 16 cells per block)
 
 // Counter record fields (match world_counters in world.h).
-enum : int { kCtrLive = 0, kCtrBirths, kCtrDeaths, kCtrEaten, kCtrRes, kCtrWins, kCtrDeadAgeLo, kCtrDeadAgeHi };
+enum : int { kCtrLive = 0, kCtrBirths, kCtrDeaths, kCtrEaten, kCtrRes, kCtrWins, kCtrDeadAgeLo, kCtrDeadAgeHi,
+             kCtrSeen };
+
+// The act phase marks in the agent record's action word whether the agent had
+// a resource in its field of view (greediness of the lab environments, Sec.
+// 2.2); the move phase counts and strips the mark.
+constexpr int kSeenBit = 1 << 8;
+constexpr int kActMask = 0xFF;
 
 // Movement metric (App. C): windows of kMoveWin steps (window k covers steps
 // [k * kMoveWin, (k + 1) * kMoveWin)), distances binned by 3 into kMoveBins
@@ -151,7 +158,7 @@ struct WorldDev {
     int32_t* deadlist;    // slots of the agents that died this step, uid order
     uint64_t* lb_move;    // look-back status words of the move phase (per tile)
     uint64_t* lb_claim;   // look-back status words of the claim phase (per tile)
-    int32_t* eat_part;    // per-wave eaten counts of the move phase (cap / 64)
+    int32_t* eat_part;    // per-wave eaten counts | seen counts << 16 of the move phase (cap / 64)
     int32_t* dage_part;   // per-wave sums of the ages of the dead (cap / 64)
     int32_t* wcell;       // per slot: cell at the start of the current movement window
     uint32_t* wuid;       // per slot: uid of the agent the window start was recorded for

@@ -48,7 +48,7 @@ class Config(C.Structure):
 class Counters(C.Structure):
     _fields_ = [("n_live", C.c_int32), ("births", C.c_int32), ("deaths", C.c_int32),
                 ("eaten", C.c_int32), ("resources", C.c_int32), ("claim_wins", C.c_int32),
-                ("dead_age_sum", C.c_int64)]
+                ("dead_age_sum", C.c_int64), ("seen_resource", C.c_int32), ("reserved", C.c_int32)]
 
 MOVE_WINDOW = 50   # steps per movement window (App. C)
 MOVE_BINS = 17     # distance bins of a movement window
@@ -297,6 +297,7 @@ class World:
         keys = ("n_live", "births", "deaths", "eaten", "resources", "claim_wins")
         out = {k: np.array([getattr(buf[i], k) for i in range(n)], np.int64) for k in keys}
         out["dead_age"] = np.array([buf[i].dead_age_sum for i in range(n)], np.int64)
+        out["seen"] = np.array([buf[i].seen_resource for i in range(n)], np.int64)
         return out
 
     def move_hist(self, first: int, n: int) -> np.ndarray:

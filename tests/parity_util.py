@@ -73,7 +73,7 @@ def run_parity(World, OracleWorld, OracleConfig, cfg, seed, steps, K, mode="kern
             stats["births"] += info["births"]
             stats["deaths"] += info["deaths"]
             stats["agent_steps"] += len(oc["uid"])
-            for key in ("n_live", "births", "deaths", "eaten", "resources", "claim_wins", "dead_age"):
+            for key in ("n_live", "births", "deaths", "eaten", "resources", "claim_wins", "dead_age", "seen"):
                 assert ctr[key][s] == info[key], (key, t + s, int(ctr[key][s]), info[key])
         t += k
         chunk += 1

@@ -210,6 +210,7 @@ def test_forced_dynamics_independent_of_controller(oracle_lib):
         b.set_forced(forced)
         ia, ib = a.step(), b.step()
         births += ia["births"]
+        ia.pop("seen"), ib.pop("seen")   # depends on the field of view (15 x 15 against 5 x 5)
         assert ia == ib, s
         assert np.array_equal(a.grid(), b.grid())
         sa, sb = a.agents(), b.agents()

@@ -115,3 +115,58 @@ def test_move_hist_lone_agent_north(oracle_lib):
         d = min(r0, WIN)
         assert h[BINS] == 1 and h[d // 3] == 1, (seed, r0, h)
         assert int(ow.agents()["row"][0]) == r0 - d
+
+
+def window_sees(R, row, col, rho):
+    H, W = R.shape
+    r0, r1 = max(row - rho, 0), min(row + rho + 1, H)
+    c0, c1 = max(col - rho, 0), min(col + rho + 1, W)
+    return bool(R[r0:r1, c0:c1].any())
+
+
+def test_seen_from_snapshots(oracle_lib):
+    # agents with a resource in their field of view at the step start (the
+    # greediness of the lab environments, Sec. 2.2), recomputed from the state
+    for cfg in (dense_cfg(oracle_lib, res_init_p=0.05, rate_scale=0.5),
+                dense_cfg(oracle_lib, res_init_p=0.02, rate_scale=0.2, obs_radius=7, hidden=4,
+                          controller=oracle_lib.CTRL_CNN_LSTM)):
+        ow = oracle_lib.OracleWorld(cfg, 5)
+        partial = 0
+        for _ in range(60):
+            R = ow.grid()
+            a = ow.agents()
+            ref = sum(window_sees(R, int(r), int(c), cfg.obs_radius) for r, c in zip(a["row"], a["col"]))
+            info = ow.step()
+            assert info["seen"] == ref
+            partial += 0 < ref < len(a["uid"])
+        assert partial > 10   # the runs exercised both outcomes
+
+
+def test_seen_closed_forms(oracle_lib):
+    full = oracle_lib.OracleWorld(dense_cfg(oracle_lib, res_init_p=1.0, n_init=50), 1)
+    assert full.step()["seen"] == 50
+    bare = oracle_lib.OracleWorld(dense_cfg(oracle_lib, res_init_p=0.0, rate_top=0.0, rate_bottom=0.0, spont=0.0,
+                                            n_init=50), 1)
+    for _ in range(5):
+        assert bare.step()["seen"] == 0
+
+
+def test_load_resumes_exactly(oracle_lib):
+    for cfg in (dense_cfg(oracle_lib),
+                dense_cfg(oracle_lib, obs_radius=7, hidden=4, controller=oracle_lib.CTRL_CNN_LSTM)):
+        a = oracle_lib.OracleWorld(cfg, 8)
+        for _ in range(37):
+            a.step()
+        mid = a.state(with_hidden=True, with_theta=True)
+        b = oracle_lib.OracleWorld(cfg, 8)
+        b.step()   # any other state
+        b.load(mid)
+        for _ in range(40):
+            ia, ib = a.step(), b.step()
+            assert ia == ib
+        sa, sb = a.state(with_hidden=True, with_theta=True), b.state(with_hidden=True, with_theta=True)
+        for k in sa:
+            assert np.array_equal(np.asarray(sa[k]), np.asarray(sb[k])), k
+        # a window in progress at the load counts no agent
+        assert b.move_hist().shape[0] == 1 and b.move_hist()[0, BINS] == 0
+        assert a.move_hist()[-1, BINS] > 0
