@@ -6,6 +6,8 @@ CPU-baseline leg of ``bench.py``.  The product package never imports it.
 from .oracle import (  # noqa: F401
     CTRL_CNN_LSTM,
     CTRL_GRU,
+    DYN_BENCH,
+    DYN_PAPER,
     NO_ACTION,
     OracleConfig,
     OracleWorld,

@@ -487,6 +487,22 @@ static uint64_t prob_threshold(double p)
 int oracle_threshold_table(const oracle_config *cfg, uint64_t *out)
 {
     if (cfg->H < 2) return -1;
+    if (cfg->dynamics == ORACLE_DYN_PAPER) {
+        /* App. B.1, Eq. (1): p = p_I c(x) + c, p_I = regrow_pI when exactly one
+         * of the four direct neighbours holds a resource (entry n = that count),
+         * c(x) = (alpha^x + 1) / (alpha + 1), x = row / (H - 1): row 0 (top)
+         * has the lowest climate value. */
+        for (int row = 0; row < cfg->H; ++row) {
+            double x = (double)row / (double)(cfg->H - 1);
+            double cx = (pow(cfg->regrow_alpha, x) + 1.0) / (cfg->regrow_alpha + 1.0);
+            for (int n = 0; n <= 24; ++n) {
+                double pI = (n == 1) ? cfg->regrow_pI : 0.0;
+                double p = pI * cx + cfg->spont;
+                out[row * 25 + n] = prob_threshold(p);
+            }
+        }
+        return 0;
+    }
     for (int row = 0; row < cfg->H; ++row) {
         double d = cfg->rate_bottom - cfg->rate_top;
         double a = d * (double)row;
@@ -546,10 +562,13 @@ typedef struct {
     uint64_t *best;
     int32_t *who;
     uint8_t *alive, *ate, *won;
+    int32_t *cnt;              /* H*W agents per cell at the step start     */
+    uint8_t *walldead;         /* moved into a wall this step (paper rules) */
     double *x, *hnew;
 } world;
 
 static void observe_cnn(const world *w, int a, double *obs);
+static void count_cells(world *w);
 
 /* Action deltas: 0 = N (row - 1), 1 = S (row + 1), 2 = E (col + 1),
  * 3 = W (col - 1), 4 = stay. */
@@ -582,7 +601,7 @@ void oracle_destroy(void *vw)
     free(w->R); free(w->occ); free(w->thr);
     free(w->uid); free(w->row); free(w->col); free(w->e); free(w->age); free(w->streak);
     free(w->wrow); free(w->wcol); free(w->wvalid); free(w->move_hist);
-    free(w->h); free(w->theta); free(w->forced); free(w->pact); free(w->pate);
+    free(w->h); free(w->theta); free(w->forced); free(w->pact); free(w->pate); free(w->cnt); free(w->walldead);
     free(w->last_uid); free(w->last_logits); free(w->last_act);
     free(w->act); free(w->claim); free(w->best); free(w->who);
     free(w->alive); free(w->ate); free(w->won); free(w->x); free(w->hnew);
@@ -675,6 +694,12 @@ void *oracle_create(const oracle_config *cfg, uint64_t seed, char *err, size_t e
         return NULL;
     }
     if (cfg->E0 <= 0) { set_err(err, errlen, "E0 must be positive"); return NULL; }
+    if (cfg->dynamics != ORACLE_DYN_BENCH && cfg->dynamics != ORACLE_DYN_PAPER) {
+        set_err(err, errlen, "unknown dynamics"); return NULL;
+    }
+    if (cfg->dynamics == ORACLE_DYN_PAPER && (cfg->E_max < cfg->E0 || cfg->T_death < 1 || !(cfg->regrow_alpha > 0.0))) {
+        set_err(err, errlen, "paper dynamics need E_max >= E0, T_death >= 1, alpha > 0"); return NULL;
+    }
 
     world *w = (world *)calloc(1, sizeof(world));
     w->cfg = *cfg;
@@ -707,6 +732,8 @@ void *oracle_create(const oracle_config *cfg, uint64_t seed, char *err, size_t e
     w->theta = (float *)calloc(cap * P, sizeof(float));
     w->pact = (int32_t *)calloc(cap, sizeof(int32_t));
     w->pate = (uint8_t *)calloc(cap, 1);
+    w->cnt = (int32_t *)calloc(HW, sizeof(int32_t));
+    w->walldead = (uint8_t *)calloc(cap, 1);
     w->last_uid = (uint32_t *)calloc(cap, sizeof(uint32_t));
     w->last_logits = (double *)calloc(cap * 5, sizeof(double));
     w->last_act = (uint8_t *)calloc(cap, 1);
@@ -721,7 +748,7 @@ void *oracle_create(const oracle_config *cfg, uint64_t seed, char *err, size_t e
     w->hnew = (double *)calloc((size_t)hd, sizeof(double));
     w->forced_default = -1;
     if (!w->R || !w->occ || !w->thr || !w->uid || !w->h || !w->theta || !w->best || !w->who || !w->wrow ||
-        !w->wcol || !w->wvalid || !w->pact || !w->pate) {
+        !w->wcol || !w->wvalid || !w->pact || !w->pate || !w->cnt || !w->walldead) {
         set_err(err, errlen, "out of memory");
         oracle_destroy(w);
         return NULL;
@@ -763,6 +790,7 @@ void *oracle_create(const oracle_config *cfg, uint64_t seed, char *err, size_t e
     w->n = cfg->n_init;
     w->next_uid = (uint32_t)cfg->n_init;
     w->t = 0;
+    count_cells(w);
     return w;
 }
 
@@ -786,6 +814,14 @@ static int forced_action(const world *w, uint32_t u)
     return w->forced_default;
 }
 
+/* Agents per cell (one at most under the benchmark rules). */
+static void count_cells(world *w)
+{
+    size_t HW = (size_t)w->cfg.H * w->cfg.W;
+    for (size_t i = 0; i < HW; ++i) w->cnt[i] = 0;
+    for (int a = 0; a < w->n; ++a) w->cnt[w->row[a] * w->cfg.W + w->col[a]]++;
+}
+
 /* Observation (App. B.2) of agent a: the (2 rho + 1)^2 window of resource
  * bits, then the same window of occupancy bits, row-major (dy outer, dx
  * inner), then energy / E0.  Reading for the boundary (the grid does not
@@ -800,7 +836,7 @@ static void observe(const world *w, int a, double *x)
             int r = w->row[a] + dy, c = w->col[a] + dx;
             if (in_grid(w, r, c)) {
                 x[k] = w->R[r * W + c] ? 1.0 : 0.0;
-                x[win * win + k] = (w->occ[r * W + c] != -1) ? 1.0 : 0.0;
+                x[win * win + k] = (w->cnt[r * W + c] > 0) ? 1.0 : 0.0;
             } else {
                 x[k] = 0.0;
                 x[win * win + k] = 1.0;
@@ -823,7 +859,7 @@ static void observe_cnn(const world *w, int a, double *obs)
             int r = w->row[a] + dy, c = w->col[a] + dx;
             if (in_grid(w, r, c)) {
                 px[0] = w->R[r * W + c] ? 1.0 : 0.0;
-                px[1] = (w->occ[r * W + c] != -1) ? 1.0 : 0.0;
+                px[1] = (double)w->cnt[r * W + c];   /* the number of agents on the pixel */
                 px[2] = 0.0;
             } else {
                 px[0] = 0.0;
@@ -836,6 +872,133 @@ static void observe_cnn(const world *w, int a, double *obs)
 static uint64_t claim_key(uint32_t draw_word, uint32_t u)
 {
     return ((uint64_t)draw_word << 32) | (uint64_t)u;
+}
+
+/* S3-S8 under the paper's rules (App. B.2, B.3), on the actions in w->act.
+ * Readings: a move into a wall (outside the grid) kills the agent; agents may
+ * share cells; on a cell holding a resource after the moves, the agent with the
+ * smallest (EAT draw, uid) eats it; e <- min(e - decay + gain ate, E_max);
+ * the signed streak counts consecutive steps above E_repr (positive) or below
+ * it (negative), 0 at E_repr; death when it reaches -T_death, when age exceeds
+ * L_max or at a wall; an agent whose streak reaches T_repr has one child on its
+ * own cell (uid order while slots remain) and its streak restarts. */
+static void step_paper(world *w, uint32_t t, oracle_stepinfo *inf)
+{
+    const oracle_config *cfg = &w->cfg;
+    const int W = cfg->W, hd = w->ss;
+    const size_t HW = (size_t)cfg->H * W, P = (size_t)w->P;
+    /* S3 moves */
+    for (int a = 0; a < w->n; ++a) {
+        w->walldead[a] = 0;
+        int act = w->act[a];
+        if (act == 4) continue;
+        int r = w->row[a] + DR[act], c = w->col[a] + DC[act];
+        if (!in_grid(w, r, c)) {
+            w->walldead[a] = 1;
+            continue;
+        }
+        w->row[a] = r;
+        w->col[a] = c;
+    }
+    /* S4 eat: one agent per resource, smallest (EAT draw, uid) */
+    for (size_t i = 0; i < HW; ++i) {
+        w->best[i] = UINT64_MAX;
+        w->who[i] = -1;
+    }
+    for (int a = 0; a < w->n; ++a) {
+        w->ate[a] = 0;
+        if (w->walldead[a]) continue;
+        int cell = w->row[a] * W + w->col[a];
+        if (!w->R[cell]) continue;
+        uint32_t rr[4];
+        draw(w->seed, w->uid[a], t, ORACLE_S_EAT, 0, rr);
+        uint64_t key = claim_key(rr[0], w->uid[a]);
+        if (key < w->best[cell]) {
+            w->best[cell] = key;
+            w->who[cell] = a;
+        }
+    }
+    for (size_t i = 0; i < HW; ++i)
+        if (w->who[i] >= 0) {
+            w->ate[w->who[i]] = 1;
+            w->R[i] = 0;
+            inf->eaten++;
+        }
+    /* S5 energy (clipped) and age; S6 streak and death */
+    int n_surv = 0;
+    for (int a = 0; a < w->n; ++a) {
+        int e = w->e[a] - cfg->decay + cfg->gain * (int32_t)w->ate[a];
+        if (e > cfg->E_max) e = cfg->E_max;
+        w->e[a] = e;
+        w->age[a] = w->age[a] + 1;
+        w->pate[a] = w->ate[a];
+        int s = w->streak[a];
+        if (e > cfg->E_repr) s = (s > 0 ? s : 0) + 1;
+        else if (e < cfg->E_repr) s = (s < 0 ? s : 0) - 1;
+        else s = 0;
+        w->streak[a] = s;
+        int dead = w->walldead[a] || (-s >= cfg->T_death) || (w->age[a] > cfg->L_max);
+        if (dead) {
+            inf->deaths++;
+            inf->dead_age += w->age[a];
+            continue;
+        }
+        if (n_surv != a) {
+            w->uid[n_surv] = w->uid[a];
+            w->row[n_surv] = w->row[a];
+            w->col[n_surv] = w->col[a];
+            w->e[n_surv] = w->e[a];
+            w->age[n_surv] = w->age[a];
+            w->streak[n_surv] = w->streak[a];
+            w->wrow[n_surv] = w->wrow[a];
+            w->wcol[n_surv] = w->wcol[a];
+            w->wvalid[n_surv] = w->wvalid[a];
+            w->pact[n_surv] = w->pact[a];
+            w->pate[n_surv] = w->pate[a];
+            memmove(w->h + (size_t)n_surv * hd, w->h + (size_t)a * hd, (size_t)hd * sizeof(float));
+            memmove(w->theta + (size_t)n_surv * P, w->theta + (size_t)a * P, P * sizeof(float));
+        }
+        n_surv++;
+    }
+    w->n = n_surv;
+    /* S8 births on the parent's cell */
+    int n_elig = 0;
+    for (int a = 0; a < w->n; ++a) n_elig += w->streak[a] >= cfg->T_repr;
+    inf->claim_wins = n_elig;
+    int free_slots = cfg->cap - w->n;
+    int n_born = n_elig < free_slots ? n_elig : free_slots;
+    int rank = 0;
+    int n_before = w->n;
+    for (int a = 0; a < n_before && rank < n_born; ++a) {
+        if (w->streak[a] < cfg->T_repr) continue;
+        int c = w->n;
+        uint32_t cu = w->next_uid + (uint32_t)rank;
+        w->uid[c] = cu;
+        w->row[c] = w->row[a];
+        w->col[c] = w->col[a];
+        w->e[c] = cfg->E0;
+        w->age[c] = 0;
+        w->streak[c] = 0;
+        w->wvalid[c] = 0;
+        w->pact[c] = ORACLE_NO_ACTION;
+        w->pate[c] = 0;
+        memset(w->h + (size_t)c * hd, 0, (size_t)hd * sizeof(float));
+        const float *pth = w->theta + (size_t)a * P;
+        float *cth = w->theta + (size_t)c * P;
+        float sigma = (float)cfg->sigma_mut;
+        for (int32_t p = 0; p < (int32_t)P; ++p) {
+            uint32_t r[4];
+            float z[4];
+            draw(w->seed, cu, t, ORACLE_S_MUTATE, (uint32_t)(p / 4), r);
+            gauss_block(r, z);
+            cth[p] = fmaf(sigma, z[p % 4], pth[p]);
+        }
+        w->streak[a] = 0;
+        w->n++;
+        rank++;
+    }
+    w->next_uid += (uint32_t)n_born;
+    inf->births = n_born;
 }
 
 int oracle_step(void *vw, const uint32_t *hint_uid, const uint8_t *hint_act, int32_t n_hint,
@@ -936,169 +1099,173 @@ int oracle_step(void *vw, const uint32_t *hint_uid, const uint8_t *hint_act, int
         w->last_act[a] = (uint8_t)act;
     }
 
-    /* ---- S3: moves.  Reading (the paper lets agents share cells; the
-     * benchmark forbids it): a move targets an in-grid cell that is empty at
-     * the start of the step; among the claimants of one cell the smallest
-     * (MOVE draw, uid) wins; everyone else stays.  Moves apply together. */
-    for (size_t i = 0; i < HW; ++i) {
-        w->best[i] = UINT64_MAX;
-        w->who[i] = -1;
-    }
-    for (int a = 0; a < w->n; ++a) {
-        w->claim[a] = -1;
-        int act = w->act[a];
-        if (act == 4) continue;
-        int r = w->row[a] + DR[act], c = w->col[a] + DC[act];
-        if (!in_grid(w, r, c)) continue;
-        int cell = r * W + c;
-        if (w->occ[cell] != -1) continue;
-        uint32_t rr[4];
-        draw(w->seed, w->uid[a], t, ORACLE_S_MOVE, 0, rr);
-        uint64_t key = claim_key(rr[0], w->uid[a]);
-        w->claim[a] = cell;
-        if (key < w->best[cell]) {
-            w->best[cell] = key;
-            w->who[cell] = a;
+    if (cfg->dynamics == ORACLE_DYN_PAPER) {
+        step_paper(w, t, &inf);
+    } else {
+        /* ---- S3: moves.  Reading (the paper lets agents share cells; the
+         * benchmark forbids it): a move targets an in-grid cell that is empty at
+         * the start of the step; among the claimants of one cell the smallest
+         * (MOVE draw, uid) wins; everyone else stays.  Moves apply together. */
+        for (size_t i = 0; i < HW; ++i) {
+            w->best[i] = UINT64_MAX;
+            w->who[i] = -1;
         }
-    }
-    for (int a = 0; a < w->n; ++a) {
-        int cell = w->claim[a];
-        if (cell >= 0 && w->who[cell] == a) {
-            w->occ[w->row[a] * W + w->col[a]] = -1;
-            w->row[a] = cell / W;
-            w->col[a] = cell % W;
-        }
-    }
-    for (int a = 0; a < w->n; ++a) w->occ[w->row[a] * W + w->col[a]] = a;
-
-    /* ---- S4 + S5: eat and update energy and age (App. B.2).  Reading: an
-     * agent eats the resource of the cell it occupies after moving; energy
-     * changes by gain * ate - decay, unclipped; age counts steps lived. */
-    for (int a = 0; a < w->n; ++a) {
-        int cell = w->row[a] * W + w->col[a];
-        w->ate[a] = 0;
-        if (w->R[cell]) {
-            w->R[cell] = 0;
-            w->ate[a] = 1;
-            inf.eaten++;
-        }
-        w->pate[a] = w->ate[a];
-        w->e[a] = w->e[a] - cfg->decay + cfg->gain * (int32_t)w->ate[a];
-        w->age[a] = w->age[a] + 1;
-    }
-
-    /* ---- S6: death (App. B.3): energy at or below zero, or age reaching
-     * L_max.  Survivors keep their uid order. */
-    int n_surv = 0;
-    for (int a = 0; a < w->n; ++a) {
-        int dead = (w->e[a] <= 0) || (w->age[a] >= cfg->L_max);
-        if (dead) {
-            inf.deaths++;
-            inf.dead_age += w->age[a];   /* life expectancy (App. C): age at death */
-            continue;
-        }
-        if (n_surv != a) {
-            w->uid[n_surv] = w->uid[a];
-            w->row[n_surv] = w->row[a];
-            w->col[n_surv] = w->col[a];
-            w->e[n_surv] = w->e[a];
-            w->age[n_surv] = w->age[a];
-            w->streak[n_surv] = w->streak[a];
-            w->wrow[n_surv] = w->wrow[a];
-            w->wcol[n_surv] = w->wcol[a];
-            w->wvalid[n_surv] = w->wvalid[a];
-            w->pact[n_surv] = w->pact[a];
-            w->pate[n_surv] = w->pate[a];
-            memmove(w->h + (size_t)n_surv * hd, w->h + (size_t)a * hd, (size_t)hd * sizeof(float));
-            memmove(w->theta + (size_t)n_surv * P, w->theta + (size_t)a * P, P * sizeof(float));
-        }
-        n_surv++;
-    }
-    w->n = n_surv;
-    for (size_t i = 0; i < HW; ++i) w->occ[i] = -1;
-    for (int a = 0; a < w->n; ++a) w->occ[w->row[a] * W + w->col[a]] = a;
-
-    /* ---- S7: the minimal criterion (App. B.3): count consecutive steps
-     * with energy at or above E_repr; eligible once the count reaches T_repr. */
-    for (int a = 0; a < w->n; ++a)
-        w->streak[a] = (w->e[a] >= cfg->E_repr) ? w->streak[a] + 1 : 0;
-
-    /* ---- S8: births.  Reading (the paper places the child on the parent's
-     * cell; the benchmark forbids sharing): an eligible parent scans its four
-     * neighbours in the order N, S, E, W cyclically from a random start and
-     * claims the first free in-grid cell; claims resolve like moves with the
-     * BIRTH draw; winners are born in uid order while slots remain. */
-    for (size_t i = 0; i < HW; ++i) {
-        w->best[i] = UINT64_MAX;
-        w->who[i] = -1;
-    }
-    for (int a = 0; a < w->n; ++a) {
-        w->claim[a] = -1;
-        w->won[a] = 0;
-        if (w->streak[a] < cfg->T_repr) continue;
-        uint32_t rr[4];
-        draw(w->seed, w->uid[a], t, ORACLE_S_BIRTH, 0, rr);
-        int d0 = (int)(rr[0] & 3u);
-        for (int k = 0; k < 4; ++k) {
-            int d = (d0 + k) & 3;
-            int r = w->row[a] + DR[d], c = w->col[a] + DC[d];
-            if (in_grid(w, r, c) && w->occ[r * W + c] == -1) {
-                w->claim[a] = r * W + c;
-                break;
+        for (int a = 0; a < w->n; ++a) {
+            w->claim[a] = -1;
+            int act = w->act[a];
+            if (act == 4) continue;
+            int r = w->row[a] + DR[act], c = w->col[a] + DC[act];
+            if (!in_grid(w, r, c)) continue;
+            int cell = r * W + c;
+            if (w->occ[cell] != -1) continue;
+            uint32_t rr[4];
+            draw(w->seed, w->uid[a], t, ORACLE_S_MOVE, 0, rr);
+            uint64_t key = claim_key(rr[0], w->uid[a]);
+            w->claim[a] = cell;
+            if (key < w->best[cell]) {
+                w->best[cell] = key;
+                w->who[cell] = a;
             }
         }
-        if (w->claim[a] < 0) continue;
-        uint64_t key = claim_key(rr[1], w->uid[a]);
-        int cell = w->claim[a];
-        if (key < w->best[cell]) {
-            w->best[cell] = key;
-            w->who[cell] = a;
+        for (int a = 0; a < w->n; ++a) {
+            int cell = w->claim[a];
+            if (cell >= 0 && w->who[cell] == a) {
+                w->occ[w->row[a] * W + w->col[a]] = -1;
+                w->row[a] = cell / W;
+                w->col[a] = cell % W;
+            }
         }
+        for (int a = 0; a < w->n; ++a) w->occ[w->row[a] * W + w->col[a]] = a;
+
+        /* ---- S4 + S5: eat and update energy and age (App. B.2).  Reading: an
+         * agent eats the resource of the cell it occupies after moving; energy
+         * changes by gain * ate - decay, unclipped; age counts steps lived. */
+        for (int a = 0; a < w->n; ++a) {
+            int cell = w->row[a] * W + w->col[a];
+            w->ate[a] = 0;
+            if (w->R[cell]) {
+                w->R[cell] = 0;
+                w->ate[a] = 1;
+                inf.eaten++;
+            }
+            w->pate[a] = w->ate[a];
+            w->e[a] = w->e[a] - cfg->decay + cfg->gain * (int32_t)w->ate[a];
+            w->age[a] = w->age[a] + 1;
+        }
+
+        /* ---- S6: death (App. B.3): energy at or below zero, or age reaching
+         * L_max.  Survivors keep their uid order. */
+        int n_surv = 0;
+        for (int a = 0; a < w->n; ++a) {
+            int dead = (w->e[a] <= 0) || (w->age[a] >= cfg->L_max);
+            if (dead) {
+                inf.deaths++;
+                inf.dead_age += w->age[a];   /* life expectancy (App. C): age at death */
+                continue;
+            }
+            if (n_surv != a) {
+                w->uid[n_surv] = w->uid[a];
+                w->row[n_surv] = w->row[a];
+                w->col[n_surv] = w->col[a];
+                w->e[n_surv] = w->e[a];
+                w->age[n_surv] = w->age[a];
+                w->streak[n_surv] = w->streak[a];
+                w->wrow[n_surv] = w->wrow[a];
+                w->wcol[n_surv] = w->wcol[a];
+                w->wvalid[n_surv] = w->wvalid[a];
+                w->pact[n_surv] = w->pact[a];
+                w->pate[n_surv] = w->pate[a];
+                memmove(w->h + (size_t)n_surv * hd, w->h + (size_t)a * hd, (size_t)hd * sizeof(float));
+                memmove(w->theta + (size_t)n_surv * P, w->theta + (size_t)a * P, P * sizeof(float));
+            }
+            n_surv++;
+        }
+        w->n = n_surv;
+        for (size_t i = 0; i < HW; ++i) w->occ[i] = -1;
+        for (int a = 0; a < w->n; ++a) w->occ[w->row[a] * W + w->col[a]] = a;
+
+        /* ---- S7: the minimal criterion (App. B.3): count consecutive steps
+         * with energy at or above E_repr; eligible once the count reaches T_repr. */
+        for (int a = 0; a < w->n; ++a)
+            w->streak[a] = (w->e[a] >= cfg->E_repr) ? w->streak[a] + 1 : 0;
+
+        /* ---- S8: births.  Reading (the paper places the child on the parent's
+         * cell; the benchmark forbids sharing): an eligible parent scans its four
+         * neighbours in the order N, S, E, W cyclically from a random start and
+         * claims the first free in-grid cell; claims resolve like moves with the
+         * BIRTH draw; winners are born in uid order while slots remain. */
+        for (size_t i = 0; i < HW; ++i) {
+            w->best[i] = UINT64_MAX;
+            w->who[i] = -1;
+        }
+        for (int a = 0; a < w->n; ++a) {
+            w->claim[a] = -1;
+            w->won[a] = 0;
+            if (w->streak[a] < cfg->T_repr) continue;
+            uint32_t rr[4];
+            draw(w->seed, w->uid[a], t, ORACLE_S_BIRTH, 0, rr);
+            int d0 = (int)(rr[0] & 3u);
+            for (int k = 0; k < 4; ++k) {
+                int d = (d0 + k) & 3;
+                int r = w->row[a] + DR[d], c = w->col[a] + DC[d];
+                if (in_grid(w, r, c) && w->occ[r * W + c] == -1) {
+                    w->claim[a] = r * W + c;
+                    break;
+                }
+            }
+            if (w->claim[a] < 0) continue;
+            uint64_t key = claim_key(rr[1], w->uid[a]);
+            int cell = w->claim[a];
+            if (key < w->best[cell]) {
+                w->best[cell] = key;
+                w->who[cell] = a;
+            }
+        }
+        int n_win = 0;
+        for (int a = 0; a < w->n; ++a)
+            if (w->claim[a] >= 0 && w->who[w->claim[a]] == a) {
+                w->won[a] = 1;
+                n_win++;
+            }
+        inf.claim_wins = n_win;
+        int free_slots = cfg->cap - w->n;
+        int n_born = n_win < free_slots ? n_win : free_slots;
+        int rank = 0;
+        int n_before = w->n;
+        for (int a = 0; a < n_before && rank < n_born; ++a) {
+            if (!w->won[a]) continue;
+            int c = w->n;                         /* child index (appended) */
+            uint32_t cu = w->next_uid + (uint32_t)rank;
+            w->uid[c] = cu;
+            w->row[c] = w->claim[a] / W;
+            w->col[c] = w->claim[a] % W;
+            w->e[c] = cfg->E0;
+            w->age[c] = 0;
+            w->streak[c] = 0;
+            w->wvalid[c] = 0;   /* not alive at the start of the window */
+            w->pact[c] = ORACLE_NO_ACTION;
+            w->pate[c] = 0;
+            memset(w->h + (size_t)c * hd, 0, (size_t)hd * sizeof(float));
+            /* Mutation (App. B.3): every parameter gets sigma * z added, z from
+             * lane p % 4 of block p / 4 of stream MUTATE keyed by the child uid. */
+            const float *pth = w->theta + (size_t)a * P;
+            float *cth = w->theta + (size_t)c * P;
+            float sigma = (float)cfg->sigma_mut;
+            for (int32_t p = 0; p < (int32_t)P; ++p) {
+                uint32_t r[4];
+                float z[4];
+                draw(w->seed, cu, t, ORACLE_S_MUTATE, (uint32_t)(p / 4), r);
+                gauss_block(r, z);
+                cth[p] = fmaf(sigma, z[p % 4], pth[p]);
+            }
+            w->streak[a] = 0;
+            w->occ[w->claim[a]] = c;
+            w->n++;
+            rank++;
+        }
+        w->next_uid += (uint32_t)n_born;
+        inf.births = n_born;
     }
-    int n_win = 0;
-    for (int a = 0; a < w->n; ++a)
-        if (w->claim[a] >= 0 && w->who[w->claim[a]] == a) {
-            w->won[a] = 1;
-            n_win++;
-        }
-    inf.claim_wins = n_win;
-    int free_slots = cfg->cap - w->n;
-    int n_born = n_win < free_slots ? n_win : free_slots;
-    int rank = 0;
-    int n_before = w->n;
-    for (int a = 0; a < n_before && rank < n_born; ++a) {
-        if (!w->won[a]) continue;
-        int c = w->n;                         /* child index (appended) */
-        uint32_t cu = w->next_uid + (uint32_t)rank;
-        w->uid[c] = cu;
-        w->row[c] = w->claim[a] / W;
-        w->col[c] = w->claim[a] % W;
-        w->e[c] = cfg->E0;
-        w->age[c] = 0;
-        w->streak[c] = 0;
-        w->wvalid[c] = 0;   /* not alive at the start of the window */
-        w->pact[c] = ORACLE_NO_ACTION;
-        w->pate[c] = 0;
-        memset(w->h + (size_t)c * hd, 0, (size_t)hd * sizeof(float));
-        /* Mutation (App. B.3): every parameter gets sigma * z added, z from
-         * lane p % 4 of block p / 4 of stream MUTATE keyed by the child uid. */
-        const float *pth = w->theta + (size_t)a * P;
-        float *cth = w->theta + (size_t)c * P;
-        float sigma = (float)cfg->sigma_mut;
-        for (int32_t p = 0; p < (int32_t)P; ++p) {
-            uint32_t r[4];
-            float z[4];
-            draw(w->seed, cu, t, ORACLE_S_MUTATE, (uint32_t)(p / 4), r);
-            gauss_block(r, z);
-            cth[p] = fmaf(sigma, z[p % 4], pth[p]);
-        }
-        w->streak[a] = 0;
-        w->occ[w->claim[a]] = c;
-        w->n++;
-        rank++;
-    }
-    w->next_uid += (uint32_t)n_born;
-    inf.births = n_born;
 
     /* ---- S10: regrowth (App. B.1, Eq. (1)), synchronous on the grid left by
      * eating: an empty cell grows iff its REGROW draw is below the threshold
@@ -1111,11 +1278,17 @@ int oracle_step(void *vw, const uint32_t *hint_uid, const uint8_t *hint_act, int
         for (int c = 0; c < W; ++c) {
             if (w->R[r * W + c]) continue;
             int n = 0;
-            for (int dy = -2; dy <= 2; ++dy)
-                for (int dx = -2; dx <= 2; ++dx) {
-                    if (dy == 0 && dx == 0) continue;
-                    if (in_grid(w, r + dy, c + dx) && w->R[(r + dy) * W + c + dx]) n++;
-                }
+            if (cfg->dynamics == ORACLE_DYN_PAPER) {
+                /* the four direct neighbours (App. B.1) */
+                for (int k = 0; k < 4; ++k)
+                    if (in_grid(w, r + DR[k], c + DC[k]) && w->R[(r + DR[k]) * W + c + DC[k]]) n++;
+            } else {
+                for (int dy = -2; dy <= 2; ++dy)
+                    for (int dx = -2; dx <= 2; ++dx) {
+                        if (dy == 0 && dx == 0) continue;
+                        if (in_grid(w, r + dy, c + dx) && w->R[(r + dy) * W + c + dx]) n++;
+                    }
+            }
             uint32_t rr[4];
             draw(w->seed, (uint32_t)(r * W + c), t, ORACLE_S_REGROW, 0, rr);
             if ((uint64_t)rr[0] < w->thr[r * 25 + n]) Rn[r * W + c] = 1;
@@ -1150,6 +1323,7 @@ int oracle_step(void *vw, const uint32_t *hint_uid, const uint8_t *hint_act, int
         w->n_windows++;
     }
     w->t++;
+    count_cells(w);
     if (info) *info = inf;
     return 0;
 }
@@ -1171,7 +1345,7 @@ int oracle_load(void *vw, int64_t step, int32_t n, uint32_t next_uid, const uint
     for (size_t i = 0; i < HW; ++i) w->occ[i] = -1;
     for (int a = 0; a < n; ++a) {
         int cell = row[a] * W + col[a];
-        if (w->occ[cell] != -1) return -1;
+        if (w->occ[cell] != -1 && w->cfg.dynamics != ORACLE_DYN_PAPER) return -1;
         w->occ[cell] = a;
     }
     memcpy(w->R, R, HW);
@@ -1192,6 +1366,7 @@ int oracle_load(void *vw, int64_t step, int32_t n, uint32_t next_uid, const uint
     w->next_uid = next_uid;
     w->t = step;
     w->last_n = 0;
+    count_cells(w);
     return 0;
 }
 

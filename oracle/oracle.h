@@ -44,7 +44,23 @@ typedef struct oracle_config {
     double  sigma_mut;     /* std of the Gaussian weight mutation                  */
     double  w_init_gain;   /* initial weight std = gain / sqrt(fan_in)             */
     int32_t controller;    /* ORACLE_CTRL_GRU or ORACLE_CTRL_CNN_LSTM              */
+    int32_t dynamics;      /* ORACLE_DYN_BENCH or ORACLE_DYN_PAPER                 */
+    int32_t E_max;         /* paper dynamics: energy clip                          */
+    int32_t T_death;       /* paper dynamics: steps below E_repr before death      */
+    int32_t pad;
+    double  regrow_pI;     /* paper dynamics: p_I of Eq. (1)                       */
+    double  regrow_alpha;  /* paper dynamics: alpha of the climate c(x)            */
 } oracle_config;
+
+/* Dynamics.  BENCH: the benchmark workloads' rules (one agent per cell, move
+ * and birth claims, regrowth from the 24-cell neighbourhood, no energy clip,
+ * death at energy <= 0).  PAPER: the rules of App. B (stacking, walls that
+ * kill, offspring on the parent's cell, regrowth p = p_I 1[one of the four
+ * neighbours holds a resource] c(x) + c with c(x) = (alpha^x + 1)/(alpha + 1),
+ * energy clipped at E_max, reproduction after T_repr steps above E_repr and
+ * death after T_death steps below it or past L_max). */
+#define ORACLE_DYN_BENCH 0
+#define ORACLE_DYN_PAPER 1
 
 /* Controllers.  GRU: the benchmark workloads' GRU cell with a linear head,
  * actions by arg-max.  CNN_LSTM: the paper's network (App. B.5) over the
@@ -88,7 +104,8 @@ enum {
     ORACLE_S_BIRTH = 5,
     ORACLE_S_MUTATE = 6,
     ORACLE_S_REGROW = 7,
-    ORACLE_S_ACT = 8
+    ORACLE_S_ACT = 8,
+    ORACLE_S_EAT = 9
 };
 
 /* ---- primitives (exposed so that tests can pin them one by one) ---------- */

@@ -39,9 +39,13 @@ class _Cfg(C.Structure):
         ("E0", C.c_int32), ("decay", C.c_int32), ("gain", C.c_int32),
         ("E_repr", C.c_int32), ("T_repr", C.c_int32), ("L_max", C.c_int32),
         ("sigma_mut", C.c_double), ("w_init_gain", C.c_double), ("controller", C.c_int32),
+        ("dynamics", C.c_int32), ("E_max", C.c_int32), ("T_death", C.c_int32), ("pad", C.c_int32),
+        ("regrow_pI", C.c_double), ("regrow_alpha", C.c_double),
     ]
 
 
+DYN_BENCH = 0       # the benchmark workloads' rules
+DYN_PAPER = 1       # the paper's rules (App. B): stacking, walls, clip, offspring on the parent's cell
 CTRL_GRU = 0        # the benchmark workloads' GRU with arg-max actions
 CTRL_CNN_LSTM = 1   # the paper's CNN + LSTM with sampled actions (App. B.5)
 NO_ACTION = 5       # previous action of an agent that has not acted yet
@@ -84,6 +88,12 @@ class OracleConfig:
     sigma_mut: float = 0.02
     w_init_gain: float = 0.5
     controller: int = CTRL_GRU
+    dynamics: int = 0          # DYN_BENCH or DYN_PAPER
+    E_max: int = 0             # paper dynamics: energy clip
+    T_death: int = 0           # paper dynamics: steps below E_repr before death
+    pad: int = 0
+    regrow_pI: float = 0.0     # paper dynamics: p_I of Eq. (1)
+    regrow_alpha: float = 1.0  # paper dynamics: alpha of c(x)
 
     @property
     def state_size(self) -> int:
