@@ -55,6 +55,26 @@ extern "C" {
 /* Previous action of an agent that has not acted yet (world_image.last_action). */
 #define WORLD_NO_ACTION 5
 
+/* Dynamics (world_config.dynamics).
+ * WORLD_DYN_BENCH: the benchmark workloads' rules -- one agent per cell (moves
+ *   into cells empty at the step start, claims resolved by a random key),
+ *   children on a free neighbouring cell, regrowth from the count of
+ *   resources among the 24 cells around (rates linear in the row), energy
+ *   e - decay + gain * ate without clip, death at e <= 0 or age >= L_max,
+ *   reproduction after T_repr consecutive steps with e >= E_repr.
+ * WORLD_DYN_PAPER: the rules of App. B -- agents share cells (the paper
+ *   network's agent channel counts them); a move into a wall (outside the
+ *   grid) kills the agent; on a cell holding a resource the agent with the
+ *   smallest random key eats it; e <- min(e - decay + gain * ate, E_max);
+ *   a signed streak counts consecutive steps above E_repr (positive) or below
+ *   it (negative): reproduction at +T_repr (one child on the parent's own
+ *   cell, the streak restarts), death at -T_death or when age > L_max;
+ *   regrowth p = p_I c(x) + spont where p_I = regrow_pI when exactly one of
+ *   the four direct neighbours holds a resource, c(x) = (alpha^x + 1) /
+ *   (alpha + 1), x = row / (H - 1) (App. B.1, Eq. (1)). */
+#define WORLD_DYN_BENCH 0
+#define WORLD_DYN_PAPER 1
+
 /* Parameters of one world (App. B.4 hyperparameters, benchmark form).
  * Supported: H >= 2, W >= 1, H*W <= 2^26, 1 <= cap <= 2^20,
  * 0 <= n_init <= min(cap, H*W), E0 > 0, decay >= 0, gain >= 0, T_repr >= 1,
@@ -84,6 +104,12 @@ typedef struct world_config {
     int32_t log_steps;      /* steps of controller log kept on device (0 = none)     */
     uint32_t flags;         /* reserved, must be 0                                    */
     int32_t controller;     /* WORLD_CTRL_*                                           */
+    int32_t dynamics;       /* WORLD_DYN_*                                            */
+    int32_t E_max;          /* paper dynamics: energy clip (>= E0)                    */
+    int32_t T_death;        /* paper dynamics: steps below E_repr before death (>= 1) */
+    int32_t pad;
+    double regrow_pI;       /* paper dynamics: p_I of Eq. (1)                         */
+    double regrow_alpha;    /* paper dynamics: alpha of the climate c(x) (> 0)        */
 } world_config;
 
 typedef struct world world_t;

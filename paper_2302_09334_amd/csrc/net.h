@@ -90,6 +90,7 @@ struct alignas(16) WaveLds {
         } late;
     } u;
     uint8_t obs[kOb * kOb + 3];  // pixel bits: 1 resource, 2 agent, 4 wall (0 on the border)
+    uint8_t extra[kOb * kOb + 3];   // agents on the pixel beyond the first (paper dynamics; 0 on the border)
 };
 
 // LDS written by some lanes of the wave is read by others below: complete
@@ -156,7 +157,8 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
     const uint8_t* R = d.R[t & 1];
 
     // ---- one round trip: observation, state and every weight --------------
-    int pb[4];
+    int pb[4], px[4];
+    const bool paper = d.dyn == kDynPaper;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         const int q = lane + 64 * m;
@@ -167,6 +169,8 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
         const int rb = R[qc];
         const int ob = d.occA[qc];
         pb[m] = in ? ((rb != 0 ? 1 : 0) | (ob != -1 ? 2 : 0)) : 4;
+        // under the paper's dynamics occA holds the agents on the cell minus one
+        px[m] = (paper && in && ob > 0) ? min(ob, 255) : 0;
     }
     const float4 hv = *reinterpret_cast<const float4*>(hs);   // h (uniform)
     // conv1 weights of tap lane / 4, output channel lane % 4 (lanes < 36)
@@ -227,7 +231,11 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         const int q = lane + 64 * m;
-        if (q < kPix) L.obs[(q / kWin + 1) * kOb + (q - (q / kWin) * kWin) + 1] = uint8_t(pb[m]);
+        if (q < kPix) {
+            const int o = (q / kWin + 1) * kOb + (q - (q / kWin) * kWin) + 1;
+            L.obs[o] = uint8_t(pb[m]);
+            if (paper) L.extra[o] = uint8_t(px[m]);
+        }
     }
     {
         // the 64 border pixels, one per lane: top row, bottom row, left and
@@ -238,6 +246,7 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
         else if (lane < 2 * kOb + kWin) { by = lane - 2 * kOb + 1; bx = 0; }
         else { by = lane - 2 * kOb - kWin + 1; bx = kOb - 1; }
         L.obs[by * kOb + bx] = 0;
+        if (paper) L.extra[by * kOb + bx] = 0;
     }
 #pragma unroll
     for (int j = 0; j < 5; ++j)
@@ -272,6 +281,15 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
                 const int bits = ob[ky * kOb + kx];
                 acc = add4(acc, *reinterpret_cast<const float4*>(&L.tab[ky * 3 + kx][bits][0]));
             }
+        if (paper) {   // stacked agents: the agent channel holds their number
+            const uint8_t* ex = &L.extra[(2 * oy) * kOb + 2 * ox];
+#pragma unroll
+            for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+                for (int kx = 0; kx < 3; ++kx)
+                    acc = fma4(float(ex[ky * kOb + kx]), *reinterpret_cast<const float4*>(&L.tab[ky * 3 + kx][2][0]),
+                               acc);
+        }
         *reinterpret_cast<float4*>(&L.u.a1[lane][0]) = acc;
     }
     wave_lds_sync();
@@ -407,16 +425,10 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
     if (lane == 0) {
         d.action[slot] = uint8_t(best);
         recp->action = best | (seen ? kSeenBit : 0);
-        // Move claim: the target must be inside the grid and empty at the
-        // step start (no agent, no wall in the observation).
-        if (best < 4) {
-            const int q = (kRho + 1 + act_dr(best)) * kOb + (kRho + 1 + act_dc(best));
-            if ((L.obs[q] & 6) == 0) {
-                const uint64_t key = claim_key(philox(u, uint32_t(t), kMove, 0, d.seed_lo, d.seed_hi).x, u);
-                const int Y = (r + act_dr(best)) * W + (c + act_dc(best));
-                atomicMin(reinterpret_cast<unsigned long long*>(d.mclaim + Y), (unsigned long long)key);
-            }
-        }
+        // the claim on the target cell: its observed pixel (no agent and no
+        // wall = free)
+        const int bits = L.obs[(kRho + 1 + act_dr(best)) * kOb + (kRho + 1 + act_dc(best))];
+        act_claim(d, best, r, c, u, t, (bits & 6) == 0, (bits & 1) != 0);
     }
     if (d.log_steps > 0) {
         const size_t row = size_t(t % d.log_steps) * size_t(d.cap) + size_t(li);

@@ -44,6 +44,33 @@ __device__ __forceinline__ uint64_t claim_key(uint32_t draw_word, uint32_t u) {
 
 __device__ __forceinline__ float sigmoidf_(float v) { return 1.0f / (1.0f + expf(-v)); }
 
+// The act phase's claim on the cell the chosen action leads to (one lane per
+// agent).  Benchmark rules: a move claims its target when it lies inside the
+// grid and is empty at the step start; the smallest (MOVE draw, uid) moves.
+// Paper rules: the agent claims the resource of the cell it will stand on
+// (its target, or its own cell when it stays) when that cell lies inside the
+// grid and holds a resource at the step start; the smallest (EAT draw, uid)
+// eats it.  `t_free` / `t_res`: the target's occupancy and resource as
+// observed; an atomic minimum does not depend on the order of the claims.
+__device__ __forceinline__ void act_claim(DevRef d, int best, int r, int c, uint32_t u, int64_t t, bool t_free,
+                                          bool t_res) {
+    const int tr = r + act_dr(best), tc = c + act_dc(best);
+    const bool in = tr >= 0 && tr < d.H && tc >= 0 && tc < d.W;
+    bool claim;
+    uint32_t stream;
+    if (d.dyn == kDynPaper) {
+        claim = in && t_res;
+        stream = kEat;
+    } else {
+        claim = best < 4 && in && t_free;
+        stream = kMove;
+    }
+    if (claim) {
+        const uint64_t key = claim_key(philox(u, uint32_t(t), stream, 0, d.seed_lo, d.seed_hi).x, u);
+        atomicMin(reinterpret_cast<unsigned long long*>(d.mclaim + tr * d.W + tc), (unsigned long long)key);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // P1: observation + GRU + head + arg-max for the agent in `slot` (one wave).
 //
@@ -218,6 +245,7 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
     uint64_t mO = __ballot(ob);
     const uint64_t occ_bits = mO;
     const bool seen = mR != 0;   // a resource in the field of view
+    const uint64_t res_bits = mR;
 
     // Round trips 2..: the input rows.  A window with more ones than zeros is
     // summed as its precomputed column total minus the rows of its zeros
@@ -313,19 +341,10 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
     if (lane == 0) {
         d.action[slot] = uint8_t(best);
         recp->action = best | (seen ? kSeenBit : 0);
-        // Move claim (resolved by the next phase): a move targets the window
-        // cell one step away, which must be inside the grid and empty at the
-        // step start (its occupancy bit, outside cells reading occupied, is 0).
-        // The smallest (MOVE draw, uid) among a cell's claimants wins; an
-        // atomic minimum is independent of the order of the claims.
-        if (best < 4) {
-            const int q = (rho + act_dr(best)) * win + (rho + act_dc(best));
-            if (!((occ_bits >> q) & 1ull)) {
-                const uint64_t key = claim_key(philox(u, uint32_t(t), kMove, 0, d.seed_lo, d.seed_hi).x, u);
-                const int Y = (r + act_dr(best)) * W + (c + act_dc(best));
-                atomicMin(reinterpret_cast<unsigned long long*>(d.mclaim + Y), (unsigned long long)key);
-            }
-        }
+        // the claim on the target cell (resolved by the next phase); the
+        // target's window bits (outside cells read occupied, no resource)
+        const int q = (rho + act_dr(best)) * win + (rho + act_dc(best));
+        act_claim(d, best, r, c, u, t, !((occ_bits >> q) & 1ull), ((res_bits >> q) & 1ull) != 0);
     }
     if (d.log_steps > 0) {
         const size_t row = size_t(t % d.log_steps) * size_t(d.cap) + size_t(li);
@@ -524,6 +543,73 @@ __device__ __forceinline__ int move_agent(DevRef d, const AgentRec& a, int64_t t
     return ate | (dead ? 2 : 0) | ((a.action & kSeenBit) ? 4 : 0);
 }
 
+// P2 under the paper's dynamics (App. B.2, B.3): the move always happens,
+// except into a wall (outside the grid), which kills; the agent eats the
+// resource of its final cell iff its act-phase claim on that cell is the
+// smallest; e <- min(e - decay + gain * ate, E_max); the signed streak counts
+// consecutive steps above (+) or below (-) E_repr; death at -T_death, past
+// L_max or at a wall.  occA (agents minus one per cell) takes the moves and
+// deaths by atomic steps.  Same record outputs and return bits as move_agent.
+__device__ __forceinline__ int move_agent_paper(DevRef d, const AgentRec& a, int64_t t, PostRec* post,
+                                                AgentRec* next_rec_src) {
+    const int W = d.W, H = d.H;
+    const int slot = a.slot;
+    const int X = a.cell;
+    const int act = a.action & kActMask;
+    const uint32_t u = a.uid;
+    const int r = X / W, c = X - (X / W) * W;
+    uint8_t* Rc = d.R[t & 1];
+    const int tr = r + act_dr(act), tc = c + act_dc(act);
+    const bool wall = !(tr >= 0 && tr < H && tc >= 0 && tc < W);
+    const int newX = wall ? X : tr * W + tc;
+    const uint64_t cw = d.mclaim[newX];
+    const int rY = Rc[newX];
+    int ate = 0;
+    if (!wall && rY) {
+        const uint64_t key = claim_key(philox(u, uint32_t(t), kEat, 0, d.seed_lo, d.seed_hi).x, u);
+        ate = cw == key;
+    }
+    if (ate) Rc[newX] = 0;
+    int en = a.energy - d.decay + d.gain * ate;
+    if (en > d.E_max) en = d.E_max;
+    const int ag = a.age + 1;
+    int st = a.streak;
+    if (en > d.E_repr) st = (st > 0 ? st : 0) + 1;
+    else if (en < d.E_repr) st = (st < 0 ? st : 0) - 1;
+    else st = 0;
+    const bool dead = wall || -st >= d.T_death || ag > d.L_max;
+    d.energy[slot] = en;
+    d.age[slot] = ag;
+    d.streak[slot] = st;
+    d.cell[slot] = newX;
+    d.prev_cell[slot] = X;
+    d.alive[slot] = dead ? 0 : 1;
+    d.ate[slot] = uint8_t(ate);
+    if (dead || newX != X) atomicAdd(d.occA + X, -1);
+    if (!dead && newX != X) atomicAdd(d.occA + newX, 1);
+    PostRec p;
+    p.slot = slot;
+    p.prev_cell = X;
+    p.cell = newX;
+    p.alive = dead ? 0 : 1;
+    p.streak = st;
+    p.action = act;
+    p.uid = u;
+    p.next_pos = -1;
+    *post = p;
+    AgentRec nr;
+    nr.slot = slot;
+    nr.cell = newX;
+    nr.energy = en;
+    nr.uid = u;
+    nr.age = ag;
+    nr.streak = st;
+    nr.action = act;
+    nr.ate = ate;
+    *next_rec_src = nr;
+    return ate | (dead ? 2 : 0) | ((a.action & kSeenBit) ? 4 : 0);
+}
+
 // The world scalars a block works with, read once at its start.
 struct StepScal {
     int64_t t;
@@ -585,7 +671,9 @@ __device__ __forceinline__ void move_block(DevRef d, PosRec* P, int j, int lane,
     int res = 0;
     AgentRec nr;
     nr.slot = -1;
-    if (i < n) res = move_agent(d, sel ? r1 : r0, t, &P[i].post, &nr);
+    if (i < n)
+        res = d.dyn == kDynPaper ? move_agent_paper(d, sel ? r1 : r0, t, &P[i].post, &nr)
+                                 : move_agent(d, sel ? r1 : r0, t, &P[i].post, &nr);
     const bool alive = i < n && !(res & 2);
     const bool dead = i < n && (res & 2);
     const int cnt = __popcll(__ballot((res & 1) != 0));
@@ -676,17 +764,25 @@ __device__ __forceinline__ int claim_agent(DevRef d, const PostRec& p, int64_t t
     const int X = p.prev_cell;
     const int X2 = p.cell;
     const bool alive = p.alive != 0;
+    const bool paper = d.dyn == kDynPaper;
     {
-        // clear the move-claim word this agent may have written in P1
+        // clear the claim word this agent may have written in P1 (its move
+        // target; under the paper's rules also its own cell when it stayed)
         const int a = p.action;
-        if (a < 4) {
+        if (a < 4 || paper) {
             const int tr = X / d.W + act_dr(a), tc = X - (X / d.W) * d.W + act_dc(a);
             if (tr >= 0 && tr < d.H && tc >= 0 && tc < d.W) d.mclaim[tr * d.W + tc] = ~0ull;
         }
     }
     int C = -1;
     bool won = false;
-    if (alive && p.streak >= d.T_repr) {
+    if (paper) {
+        // the paper's rules: the offspring appears on the parent's cell
+        if (alive && p.streak >= d.T_repr) {
+            won = true;
+            C = X2;
+        }
+    } else if (alive && p.streak >= d.T_repr) {
         const int W = d.W, H = d.H;
         const int r = X2 / W, c = X2 - (X2 / W) * W;
         // occB words of the diamond (-2 outside the grid; the agent's own
@@ -810,7 +906,10 @@ __device__ __forceinline__ void claim_block(DevRef d, WorldScal* S, PosRec* P, i
             cr.action = kNoAction;
             cr.ate = 0;
             P[surv + rk].r[sel ^ 1] = cr;
-            d.occA[cell] = cs;   // occA is neither read nor written by others in this phase
+            // occA is not read in this phase; under the paper's rules it
+            // counts the agents per cell (several children may share one)
+            if (d.dyn == kDynPaper) atomicAdd(d.occA + cell, 1);
+            else d.occA[cell] = cs;
             // the parent's streak restarts (no phase reads these in P3)
             P[pos].r[sel ^ 1].streak = 0;
             d.streak[slot] = 0;
@@ -887,10 +986,15 @@ __device__ __forceinline__ void regrow_tile(DevRef d, int tile, int lane, uint8_
             v = s[(ly + 2) * E + lx + 2];
             if (!v) {
                 int cnt = 0;
+                if (d.dyn == kDynPaper) {   // the four direct neighbours (App. B.1)
+                    cnt = s[(ly + 1) * E + lx + 2] + s[(ly + 3) * E + lx + 2] + s[(ly + 2) * E + lx + 1] +
+                          s[(ly + 2) * E + lx + 3];
+                } else {
 #pragma unroll
-                for (int dy = 0; dy < 5; ++dy)
+                    for (int dy = 0; dy < 5; ++dy)
 #pragma unroll
-                    for (int dx = 0; dx < 5; ++dx) cnt += s[(ly + dy) * E + lx + dx];
+                        for (int dx = 0; dx < 5; ++dx) cnt += s[(ly + dy) * E + lx + dx];
+                }
                 const Draw4 dr = philox(uint32_t(q), uint32_t(t), kRegrow, 0, d.seed_lo, d.seed_hi);
                 v = uint64_t(dr.x) < d.thr[gy * 25 + cnt] ? 1 : 0;
             }

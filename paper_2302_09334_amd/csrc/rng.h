@@ -26,6 +26,7 @@ enum : uint32_t {
     kMutate = 6,
     kRegrow = 7,
     kAct = 8,   // action sampling of the paper's network
+    kEat = 9,   // eater of a shared resource cell under the paper's dynamics
 };
 
 struct Draw4 {

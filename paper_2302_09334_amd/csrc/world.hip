@@ -89,6 +89,11 @@ const char* check_config(const world_config* c) {
     if (c->E0 <= 0 || c->decay < 0 || c->gain < 0) return "E0 > 0, decay >= 0, gain >= 0 required";
     if (c->T_repr < 1 || c->L_max < 1) return "T_repr and L_max must be positive";
     if (c->log_steps < 0) return "log_steps must be >= 0";
+    if (c->dynamics != WORLD_DYN_BENCH && c->dynamics != WORLD_DYN_PAPER) return "unknown dynamics";
+    if (c->dynamics == WORLD_DYN_PAPER &&
+        (c->E_max < c->E0 || c->T_death < 1 || !(c->regrow_alpha > 0.0) || !std::isfinite(c->regrow_alpha) ||
+         !std::isfinite(c->regrow_pI)))
+        return "paper dynamics need E_max >= E0, T_death >= 1 and a finite alpha > 0";
     if (c->flags != 0) return "flags must be 0";
     if (!std::isfinite(c->res_init_p) || !std::isfinite(c->rate_bottom) || !std::isfinite(c->rate_top) ||
         !std::isfinite(c->rate_scale) || !std::isfinite(c->spont) || !std::isfinite(c->sigma_mut) ||
@@ -177,6 +182,16 @@ uint64_t threshold_of(double p) {
 }
 
 void build_thresholds(const world_config& c, uint64_t* out) {
+    if (c.dynamics == WORLD_DYN_PAPER) {
+        // App. B.1, Eq. (1): entry n = the number of the four direct
+        // neighbours holding a resource; p_I applies when it is exactly one
+        for (int row = 0; row < c.H; ++row) {
+            const double x = double(row) / double(c.H - 1);
+            const double climate = (std::pow(c.regrow_alpha, x) + 1.0) / (c.regrow_alpha + 1.0);
+            for (int n = 0; n <= 24; ++n) out[row * 25 + n] = threshold_of((n == 1 ? c.regrow_pI : 0.0) * climate + c.spont);
+        }
+        return;
+    }
     for (int row = 0; row < c.H; ++row) {
         const double span = c.rate_bottom - c.rate_top;
         const double lat = (span * double(row)) / double(c.H - 1);
@@ -462,6 +477,9 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
     d.nblk = dm.nblk;
     d.ctrl = is_net(c) ? kCtrlNet : kCtrlGru;
     d.ss = state_of(c);
+    d.dyn = c.dynamics == WORLD_DYN_PAPER ? kDynPaper : kDynBench;
+    d.E_max = c.E_max;
+    d.T_death = c.T_death;
     d.R[0] = reinterpret_cast<uint8_t*>(b + lay.R0);
     d.R[1] = reinterpret_cast<uint8_t*>(b + lay.R1);
     d.occA = reinterpret_cast<int32_t*>(b + lay.occA);
@@ -520,9 +538,10 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
     std::vector<int32_t> cells(c.cap, 0), energy(c.cap, 0), zeros(c.cap, 0), live(c.cap, 0), freeq(c.cap, 0);
     std::vector<uint32_t> uid(c.cap, 0);
     std::vector<uint8_t> alive(c.cap, 0);
+    const bool paper = c.dynamics == WORLD_DYN_PAPER;
     for (size_t a = 0; a < n0; ++a) {
         const int32_t cell = int32_t(keys[a] & 0xFFFFFFFFu);
-        occ[cell] = int32_t(a);
+        occ[cell] = paper ? 0 : int32_t(a);   // paper dynamics: agents on the cell minus one
         cells[a] = cell;
         energy[a] = c.E0;
         uid[a] = uint32_t(a);
@@ -825,10 +844,14 @@ int world_load(world_t* w, const world_image* in) {
         if (i > 0 && in->uid[i] <= in->uid[i - 1]) return fail(w, WORLD_E_INVALID_ARG, "uids must increase");
         if (in->uid[i] >= in->next_uid) return fail(w, WORLD_E_INVALID_ARG, "uid >= next_uid");
         const int cell = in->row[i] * c.W + in->col[i];
-        if (occ[cell] != -1) return fail(w, WORLD_E_INVALID_ARG, "two agents in one cell");
         if (in->last_action[i] > kNoAction || in->ate[i] > 1)
             return fail(w, WORLD_E_INVALID_ARG, "last_action must be 0..5 and ate 0 or 1");
-        occ[cell] = i;
+        if (c.dynamics == WORLD_DYN_PAPER) {
+            occ[cell] += 1;   // agents on the cell minus one (-1 = empty)
+        } else {
+            if (occ[cell] != -1) return fail(w, WORLD_E_INVALID_ARG, "two agents in one cell");
+            occ[cell] = i;
+        }
         cells[i] = cell;
         live[i] = i;
     }

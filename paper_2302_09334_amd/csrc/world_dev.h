@@ -9,7 +9,9 @@
 //             occA/occB (i32 slot or -1; occA = state at the step start,
 //             read by the act phase; occB = state after moves and deaths,
 //             read by the claim phase; children enter occA when they are
-//             born and occB when they are created),
+//             born and occB when they are created); under the paper's
+//             dynamics occA holds the number of agents on the cell minus one
+//             (so -1 is still "empty") and occB is unused,
 //             thr (u64 H x 25 regrowth thresholds)
 //   agents    uid, cell, prev_cell, energy, age, streak (i32 per slot),
 //             action (the last one taken), alive, ate (u8), claim (i32),
@@ -51,8 +53,9 @@ constexpr int kMoveWin = 50;
 constexpr int kMoveBins = 17;
 constexpr int kMoveRing = 64;
 
-// Controllers.
+// Controllers and dynamics.
 enum : int { kCtrlGru = 0, kCtrlNet = 1 };
+enum : int { kDynBench = 0, kDynPaper = 1 };
 constexpr int kNoAction = 5;   // previous action of an agent that has not acted yet
 
 // Agent record by live-list position (the order of the live list): what the
@@ -121,6 +124,8 @@ struct WorldDev {
     int32_t tot_row;    // theta row (of 3*hd floats) of the window totals, after the genome; tot_row + 2 is zeros
     int32_t ctrl;       // kCtrlGru or kCtrlNet
     int32_t ss;         // recurrent state floats per slot (hd for the GRU, 2 hd for the LSTM)
+    int32_t dyn;        // kDynBench or kDynPaper
+    int32_t E_max, T_death;   // paper dynamics
     int32_t pad0;
     // grid
     uint8_t* R[2];

@@ -16,6 +16,13 @@ the sizes of the benchmark configurations:
                 at the start, 16,000 resources on average (Bernoulli 0.2),
                 15 x 15 x 3 observation, CNN + LSTM(4).
 * ``net_m1_4k`` the m1_4k world (about 4k agents) with the paper's network.
+* ``paper1k``   the paper's own world (App. B.4): 200 x 400, at most 1000
+                agents, 330 at the start, 16,000 resources on average, the
+                paper's network and dynamics (stacking, walls, energy in units
+                of 1/40 with E0 = E_max = 3, decay 0.025, +1 per resource,
+                reproduction after 140 steps above 0, death after 200 steps
+                below 0 or past age 650, regrowth 0.002 c(x) + 5e-5 with
+                alpha = 200).
 
 Every random choice of a workload (the uneven-world manifest, the serving
 arrival trace) comes from ``numpy.random.default_rng`` with a fixed seed; the
@@ -46,10 +53,13 @@ WORKLOADS = {
     "net1k": make(H=200, W=400, cap=1024, n_init=330, res_init_p=0.2, obs_radius=7, hidden=4, controller=1),
     "net_m1_4k": make(H=200, W=400, cap=4608, n_init=4096, res_init_p=0.3, rate_scale=5.0, obs_radius=7, hidden=4,
                       controller=1),
+    "paper1k": make(H=200, W=400, cap=1000, n_init=330, res_init_p=0.2, obs_radius=7, hidden=4, controller=1,
+                    dynamics=1, E0=120, E_max=120, decay=1, gain=40, E_repr=0, T_repr=140, T_death=200, L_max=650,
+                    sigma_mut=0.02, spont=5e-5, regrow_pI=0.002, regrow_alpha=200.0, rate_top=0.0, rate_bottom=0.0),
 }
 
 # Steps each workload is run for in the benchmark configurations.
-STEPS = {"cfg0": 1000, "cfg1": 10000, "m1_4k": 2000, "cfg2": 5000, "net1k": 2000, "net_m1_4k": 2000}
+STEPS = {"cfg0": 1000, "cfg1": 10000, "m1_4k": 2000, "cfg2": 5000, "net1k": 2000, "net_m1_4k": 2000, "paper1k": 5000}
 
 GRID_SET = [(64, 128), (100, 200), (128, 256), (200, 400)]
 

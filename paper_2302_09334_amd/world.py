@@ -23,6 +23,10 @@ MODE_KERNELS, MODE_GRAPH = 0, 1
 MODES = {"kernels": MODE_KERNELS, "graph": MODE_GRAPH}
 SNAP_HIDDEN, SNAP_THETA = 1, 2
 CTRL_GRU, CTRL_CNN_LSTM = 0, 1   # GRU + arg-max; the paper's network (App. B.5) + sampling
+DYN_BENCH, DYN_PAPER = 0, 1      # the benchmark workloads' rules; the paper's (App. B)
+# configuration fields a workload dict may leave out (the benchmark rules' values)
+OPTIONAL = {"controller": CTRL_GRU, "dynamics": DYN_BENCH, "E_max": 0, "T_death": 0, "regrow_pI": 0.0,
+            "regrow_alpha": 1.0}
 NO_ACTION = 5                    # previous action of an agent that has not acted yet
 
 
@@ -42,6 +46,8 @@ class Config(C.Structure):
         ("T_repr", C.c_int32), ("L_max", C.c_int32),
         ("sigma_mut", C.c_double), ("w_init_gain", C.c_double),
         ("log_steps", C.c_int32), ("flags", C.c_uint32), ("controller", C.c_int32),
+        ("dynamics", C.c_int32), ("E_max", C.c_int32), ("T_death", C.c_int32), ("pad", C.c_int32),
+        ("regrow_pI", C.c_double), ("regrow_alpha", C.c_double),
     ]
 
 
@@ -126,12 +132,14 @@ def make_config(d: dict, log_steps: int = 0) -> Config:
     c = Config()
     c.struct_size = C.sizeof(Config)
     for name, _ in Config._fields_:
-        if name in ("struct_size", "log_steps", "flags", "controller"):
+        if name in ("struct_size", "log_steps", "flags", "pad"):
+            continue
+        if name in OPTIONAL:
+            setattr(c, name, d.get(name, OPTIONAL[name]))
             continue
         setattr(c, name, d[name])
     c.log_steps = int(d.get("log_steps", log_steps))
     c.flags = 0
-    c.controller = int(d.get("controller", CTRL_GRU))
     return c
 
 

@@ -73,7 +73,7 @@ def test_threshold_table_matches_oracle(wlib, oracle_lib):
     """The library builds its own regrowth table; it must equal the oracle's
     (both evaluate the same double-precision expression)."""
     from paper_2302_09334_amd import workloads
-    for name in ("cfg0", "m1_4k", "cfg2"):
+    for name in ("cfg0", "m1_4k", "cfg2", "paper1k"):
         cfg = workloads.WORKLOADS[name]
         a = wlib.threshold_table(cfg)
         b = oracle_lib.threshold_table(oracle_lib.OracleConfig.from_dict(cfg))
