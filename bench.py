@@ -19,6 +19,10 @@ Also reported:
   events stamped by their own dispatch; ``kernels`` lists all three.
 * ``cpu_baseline``: the oracle (plain C, one thread) on a bounded sample of
   the same workload on the host cores.
+* ``paper_dynamics``: the paper's own world (``paper1k``: its constants, its
+  network and its rules -- stacking, walls, energy clip, offspring on the
+  parent's cell) timed by the wall clock; the paper reports 1e6 steps of this
+  world in 20 minutes on one GPU (App. B.4), quoted beside it as context.
 * ``lab``: the lab environments of Sec. 2.2 -- agents evolved in the paper's
   network world (net1k) tested alone in 40 x 40 worlds without regrowth at
   three densities (greediness) and with reproduction (peer pressure): all
@@ -343,6 +347,64 @@ def served_run(args) -> dict:
     return m
 
 
+# App. B.4: 1e6 steps of the paper's world (at most 1000 agents) in about 20
+# minutes on one GPU (JAX; the GPU model is not named).
+PAPER_STEPS_PER_S = 1e6 / (20 * 60)
+
+
+def paper_run(args) -> dict:
+    """The paper's world with its own dynamics and network (paper1k)."""
+    import torch
+    from paper_2302_09334_amd import workloads, world
+    cfg = workloads.WORKLOADS["paper1k"]
+    stream = torch.cuda.Stream()
+    w = world.World(cfg, args.seed, stream=stream, mode="graph")
+    done = 0
+    while done < args.paper_warmup:
+        k = min(args.chunk, args.paper_warmup - done)
+        w.step(k)
+        done += k
+    w.sync()
+    start = w.snapshot(hidden=True, theta=True)
+    t_first = start["t"]
+    w.step(min(args.chunk, args.paper_steps))
+    w.sync()
+    w.load(start)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < args.paper_steps:
+        k = min(args.chunk, args.paper_steps - done)
+        w.step(k)
+        done += k
+    w.sync()
+    wall = time.perf_counter() - t0
+    ctr = w.counters(t_first, args.paper_steps)
+    acting = np.concatenate([[start["n_live"]], ctr["n_live"][:-1]])
+    w.load(start)
+    ph = w.phase_times(args.net_phase_steps)
+    w.close()
+    steps_per_s = args.paper_steps / wall
+    out = {
+        "workload": "paper1k: the paper's world (App. B.4): 200x400 grid, at most 1000 agents, 330 initial, resources "
+                    "Bernoulli(0.2), its network (15x15x3, CNN + LSTM(4), sampled at T = 1/50) and rules (stacking, "
+                    "walls, energy in 1/40 units with E0 = E_max = 120, decay 1, gain 40, reproduction after 140 steps "
+                    "above 0, death after 200 below or past age 650, regrowth 0.002 c(x) + 5e-5, alpha 200), seed %d, "
+                    "steps %d..%d" % (args.seed, t_first, t_first + args.paper_steps - 1),
+        "metric": "agent-steps/s", "value": float(acting.sum()) / wall, "steps_per_s": steps_per_s,
+        "ms_per_step": wall / args.paper_steps * 1e3, "steps": args.paper_steps, "warmup": args.paper_warmup,
+        "n_live_mean": float(acting.mean()), "births": int(ctr["births"].sum()), "deaths": int(ctr["deaths"].sum()),
+        "kernel_ms": {"act": float(ph[0]), "move": float(ph[1]), "claim": float(ph[2])},
+        "million_steps_s": 1e6 / steps_per_s,
+        "paper_reported": {"steps_per_s": PAPER_STEPS_PER_S, "million_steps_s": 1200.0,
+                           "hardware": "one GPU, JAX (App. B.4; model not named)"},
+        "steps_per_s_vs_paper": steps_per_s / PAPER_STEPS_PER_S,
+    }
+    log(f"[bench] paper dynamics: {steps_per_s:.0f} steps/s ({out['value'] / 1e6:.1f} M agent-steps/s, "
+        f"{out['n_live_mean']:.0f} agents): 1e6 steps in {out['million_steps_s']:.0f} s against ~1200 s reported")
+    return out
+
+
 def lab_run(args) -> dict:
     """Lab environments (Sec. 2.2) as a batched workload of many tiny worlds."""
     import torch
@@ -442,6 +504,8 @@ def main():
     ap.add_argument("--net-warmup", type=int, default=300)
     ap.add_argument("--net-phase-steps", type=int, default=100)
     ap.add_argument("--only-net", action="store_true", help="run only the paper-network leg and print it")
+    ap.add_argument("--paper-steps", type=int, default=2000, help="timed steps of the paper-dynamics world (0 = skip)")
+    ap.add_argument("--paper-warmup", type=int, default=1000)
     ap.add_argument("--lab-agents", type=int, default=50, help="evolved agents of the lab leg (0 = skip)")
     ap.add_argument("--lab-trials", type=int, default=10)
     ap.add_argument("--lab-evolve-steps", type=int, default=20000)
@@ -594,6 +658,9 @@ def main():
     net = None
     if args.net_steps > 0:
         net = net_run(args)
+    paper = None
+    if args.paper_steps > 0:
+        paper = paper_run(args)
     labs = None
     if args.lab_agents > 0:
         labs = lab_run(args)
@@ -681,6 +748,7 @@ def main():
         },
         "ecology_metrics": metrics,
         "paper_network": net,
+        "paper_dynamics": paper,
         "lab": labs,
         "cache_exceeding": m2,
         "cpu_baseline": cpu,

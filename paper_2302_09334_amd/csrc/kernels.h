@@ -29,6 +29,7 @@ struct Batch {
     const WorldDev* w0;         // n == 1: the descriptor itself (else null)
     int cap0;                   // n == 1: its agent capacity
     int ctrl;                   // controller of every world in the batch
+    int dyn;                    // dynamics of every world in the batch
 };
 
 template <int ROWS>
@@ -84,7 +85,7 @@ __device__ __forceinline__ BlockWorld block_world(const Batch& bt, int kind, int
 // controller step (they are the last n_child entries of the live list); the
 // remaining blocks run the controller of the other agents, four per block.
 // NET: the paper's network (with `lds`, one scratch per wave), else the GRU.
-template <int ROWS, bool NET>
+template <int ROWS, bool NET, bool PAPER = false>
 __device__ __forceinline__ void act_body(const Batch& bt, int vb, int tid, StepShared& sh, net::WaveLds* lds) {
     const BlockWorld bw = block_world(bt, kPreAct, vb);
     DevRef d = *bw.d;
@@ -132,7 +133,7 @@ __device__ __forceinline__ void act_body(const Batch& bt, int vb, int tid, StepS
                 const int4 rv = *reinterpret_cast<const int4*>(&P[lj].r[sel]);
                 if constexpr (NET) {
                     const int4 rv2 = *(reinterpret_cast<const int4*>(&P[lj].r[sel]) + 1);
-                    net::act_agent(d, &P[lj].r[sel], rv, rv2, lj, t, tid, lds[0]);
+                    net::act_agent<PAPER>(d, &P[lj].r[sel], rv, rv2, lj, t, tid, lds[0]);
                 } else {
                     act_dispatch<ROWS>(d, &P[lj].r[sel], rv, lj, t, tid);
                 }
@@ -142,7 +143,8 @@ __device__ __forceinline__ void act_body(const Batch& bt, int vb, int tid, StepS
         return;
     }
     if (li >= n - nc) return;
-    if constexpr (NET) net::act_agent(d, &P[li].r[sel], sel ? q1 : q0, sel ? q1b : q0b, li, t, tid & 63, lds[tid >> 6]);
+    if constexpr (NET)
+        net::act_agent<PAPER>(d, &P[li].r[sel], sel ? q1 : q0, sel ? q1b : q0b, li, t, tid & 63, lds[tid >> 6]);
     else act_dispatch<ROWS>(d, &P[li].r[sel], sel ? q1 : q0, li, t, tid & 63);
 }
 
@@ -185,6 +187,7 @@ __device__ __forceinline__ void move_body(const Batch& bt, int vb, int lane) {
 
 // Claim blocks of a world (one wave each): the claim tiles (look-back
 // order), then the regrowth tiles.
+template <bool PAPER>
 __device__ __forceinline__ void claim_body(const Batch& bt, int vb, int lane, uint8_t* tile) {
     const BlockWorld bw = block_world(bt, kPreClaim, vb);
     DevRef d = *bw.d;
@@ -194,7 +197,7 @@ __device__ __forceinline__ void claim_body(const Batch& bt, int vb, int lane, ui
         const PostRec p = bw.P[min(lb * kTileN + lane, bw.cap - 1)].post;
         const StepScal ss = read_step(bw.S);
         pin(p.slot);
-        claim_block(d, bw.S, bw.P, lb, lane, ss, p);
+        claim_block<PAPER>(d, bw.S, bw.P, lb, lane, ss, p);
         return;
     }
     regrow_tile(d, lb - ntile, lane, tile, kconst(bw.S)->t_grow);
@@ -236,7 +239,19 @@ __global__ __launch_bounds__(kBlock)
 void k_act_net(Batch bt) {
     __shared__ StepShared sh;
     __shared__ net::WaveLds lds[kBlock / 64];
-    act_body<16, true>(bt, blockIdx.x, threadIdx.x, sh, lds);
+    act_body<16, true, false>(bt, blockIdx.x, threadIdx.x, sh, lds);
+}
+
+// The same for worlds with the paper's dynamics.
+#if ECO_NET_WAVES > 0
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(ECO_NET_WAVES, ECO_NET_WAVES)))
+#else
+__global__ __launch_bounds__(kBlock)
+#endif
+void k_act_net_paper(Batch bt) {
+    __shared__ StepShared sh;
+    __shared__ net::WaveLds lds[kBlock / 64];
+    act_body<16, true, true>(bt, blockIdx.x, threadIdx.x, sh, lds);
 }
 
 // Creates the pending children of a world's last step now (before its state
@@ -290,7 +305,14 @@ __global__ __launch_bounds__(64) void k_move(Batch bt) { move_body(bt, blockIdx.
 
 __global__ __launch_bounds__(64) void k_claim(Batch bt) {
     __shared__ uint8_t tile[kHalo * kHalo];
-    claim_body(bt, blockIdx.x, threadIdx.x, tile);
+    claim_body<false>(bt, blockIdx.x, threadIdx.x, tile);
+}
+
+// The claim phase of worlds with the paper's dynamics (births on the parent's
+// cell, no neighbour scan).
+__global__ __launch_bounds__(64) void k_claim_paper(Batch bt) {
+    __shared__ uint8_t tile[kHalo * kHalo];
+    claim_body<true>(bt, blockIdx.x, threadIdx.x, tile);
 }
 
 // Spread of the initial weights: parameter p takes sd[k] for the first k with

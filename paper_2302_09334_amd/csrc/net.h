@@ -141,7 +141,10 @@ __device__ __forceinline__ float reduce_scatter4(float4 v, int lane) {
 }
 
 // `rv`, `rv2`: the agent's record (slot, cell, energy, uid / age, streak,
-// previous action, ate); every field is the same in all lanes.
+// previous action, ate); every field is the same in all lanes.  PAPER: the
+// world runs the paper's dynamics (agents stack: the agent channel counts
+// them); a compile-time choice, so the other rules pay nothing for it.
+template <bool PAPER>
 __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int4 rv2, int li, int64_t t, int lane,
                                           WaveLds& L) {
     const int H = d.H, W = d.W;
@@ -158,7 +161,7 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
 
     // ---- one round trip: observation, state and every weight --------------
     int pb[4], px[4];
-    const bool paper = d.dyn == kDynPaper;
+    constexpr bool paper = PAPER;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         const int q = lane + 64 * m;
@@ -228,13 +231,15 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
     pinf(ck);
 
     // ---- observation bits (bordered) and the conv1 table into LDS ----------
+    // (pixels past the window carry only the wall bit)
+    const bool seen = __ballot(((pb[0] | pb[1] | pb[2] | pb[3]) & 1) != 0) != 0;   // a resource in view
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         const int q = lane + 64 * m;
         if (q < kPix) {
             const int o = (q / kWin + 1) * kOb + (q - (q / kWin) * kWin) + 1;
             L.obs[o] = uint8_t(pb[m]);
-            if (paper) L.extra[o] = uint8_t(px[m]);
+            if constexpr (PAPER) L.extra[o] = uint8_t(px[m]);
         }
     }
     {
@@ -246,7 +251,7 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
         else if (lane < 2 * kOb + kWin) { by = lane - 2 * kOb + 1; bx = 0; }
         else { by = lane - 2 * kOb - kWin + 1; bx = kOb - 1; }
         L.obs[by * kOb + bx] = 0;
-        if (paper) L.extra[by * kOb + bx] = 0;
+        if constexpr (PAPER) L.extra[by * kOb + bx] = 0;
     }
 #pragma unroll
     for (int j = 0; j < 5; ++j)
@@ -281,7 +286,7 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
                 const int bits = ob[ky * kOb + kx];
                 acc = add4(acc, *reinterpret_cast<const float4*>(&L.tab[ky * 3 + kx][bits][0]));
             }
-        if (paper) {   // stacked agents: the agent channel holds their number
+        if constexpr (PAPER) {   // stacked agents: the agent channel holds their number
             const uint8_t* ex = &L.extra[(2 * oy) * kOb + 2 * ox];
 #pragma unroll
             for (int ky = 0; ky < 3; ++ky)
@@ -410,8 +415,6 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
         }
     }
     if (d.forced >= 0) best = d.forced;
-    const bool seen = (__ballot((pb[0] & 1) != 0) | __ballot((pb[1] & 1) != 0) | __ballot((pb[2] & 1) != 0) |
-                       __ballot((pb[3] & 1) != 0 && lane + 192 < kPix)) != 0;   // a resource in view
 
     // ---- outputs ----------------------------------------------------------------
     if (lane < 16 && gq == 0) {

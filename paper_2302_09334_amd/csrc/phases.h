@@ -760,11 +760,12 @@ __device__ __forceinline__ bool rival_claims(const bool (&fr)[7][7], int v) {
 // 2 are loaded together, and the resolution is computed from them.
 // Returns the claimed cell of a claim winner, -1 otherwise.
 // ---------------------------------------------------------------------------
+template <bool PAPER>
 __device__ __forceinline__ int claim_agent(DevRef d, const PostRec& p, int64_t t) {
     const int X = p.prev_cell;
     const int X2 = p.cell;
     const bool alive = p.alive != 0;
-    const bool paper = d.dyn == kDynPaper;
+    constexpr bool paper = PAPER;
     {
         // clear the claim word this agent may have written in P1 (its move
         // target; under the paper's rules also its own cell when it stayed)
@@ -776,7 +777,7 @@ __device__ __forceinline__ int claim_agent(DevRef d, const PostRec& p, int64_t t
     }
     int C = -1;
     bool won = false;
-    if (paper) {
+    if constexpr (PAPER) {
         // the paper's rules: the offspring appears on the parent's cell
         if (alive && p.streak >= d.T_repr) {
             won = true;
@@ -862,6 +863,7 @@ __device__ __forceinline__ int claim_agent(DevRef d, const PostRec& p, int64_t t
 // else the (r - free)-th slot freed this step.  The last claim tile closes
 // the step (counts, free ring, scalars) as soon as its look-back returns.  `p`: this lane's post-move
 // record, read before the scalars arrived.
+template <bool PAPER>
 __device__ __forceinline__ void claim_block(DevRef d, WorldScal* S, PosRec* P, int j, int lane, const StepScal& ss,
                                             const PostRec& p) {
     const int cap = d.cap;
@@ -875,7 +877,7 @@ __device__ __forceinline__ void claim_block(DevRef d, WorldScal* S, PosRec* P, i
     if (i < n) {
         slot = p.slot;
         pos = p.next_pos;
-        cell = claim_agent(d, p, t);
+        cell = claim_agent<PAPER>(d, p, t);
         win = cell >= 0;
     }
     const WaveRank wr = wave_rank2(win, false, lane);
@@ -908,7 +910,7 @@ __device__ __forceinline__ void claim_block(DevRef d, WorldScal* S, PosRec* P, i
             P[surv + rk].r[sel ^ 1] = cr;
             // occA is not read in this phase; under the paper's rules it
             // counts the agents per cell (several children may share one)
-            if (d.dyn == kDynPaper) atomicAdd(d.occA + cell, 1);
+            if constexpr (PAPER) atomicAdd(d.occA + cell, 1);
             else d.occA[cell] = cs;
             // the parent's streak restarts (no phase reads these in P3)
             P[pos].r[sel ^ 1].streak = 0;

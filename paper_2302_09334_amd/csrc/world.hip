@@ -303,10 +303,17 @@ std::vector<int> batch_prefix(const std::vector<const world*>& ws) {
 // `t0` / `t1` (optional): events the dispatch itself stamps when the kernel
 // starts and ends (its execution time, without launch overhead).
 void launch_act(const Batch& b, int grid, hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr) {
-    if (b.ctrl == kCtrlNet) hipExtLaunchKernelGGL(k_act_net, dim3(grid), dim3(kBlock), 0, s, t0, t1, 0, b);
+    if (b.ctrl == kCtrlNet && b.dyn == kDynPaper)
+        hipExtLaunchKernelGGL(k_act_net_paper, dim3(grid), dim3(kBlock), 0, s, t0, t1, 0, b);
+    else if (b.ctrl == kCtrlNet) hipExtLaunchKernelGGL(k_act_net, dim3(grid), dim3(kBlock), 0, s, t0, t1, 0, b);
     else if (b.act_rows == 8) hipExtLaunchKernelGGL(k_act_rows<8>, dim3(grid), dim3(kBlock), 0, s, t0, t1, 0, b);
     else if (b.act_rows == 32) hipExtLaunchKernelGGL(k_act_rows<32>, dim3(grid), dim3(kBlock), 0, s, t0, t1, 0, b);
     else hipExtLaunchKernelGGL(k_act, dim3(grid), dim3(kBlock), 0, s, t0, t1, 0, b);
+}
+
+void launch_claim(const Batch& b, int grid, hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr) {
+    if (b.dyn == kDynPaper) hipExtLaunchKernelGGL(k_claim_paper, dim3(grid), dim3(64), 0, s, t0, t1, 0, b);
+    else hipExtLaunchKernelGGL(k_claim, dim3(grid), dim3(64), 0, s, t0, t1, 0, b);
 }
 
 // Enqueue one step of the per-phase kernels for a batch.
@@ -314,7 +321,7 @@ hipError_t launch_step(const Batch& b, const int* host_pre, int n, hipStream_t s
     const int np = n + 1;
     launch_act(b, host_pre[kPreAct * np + n], s);
     hipLaunchKernelGGL(k_move, dim3(host_pre[kPreMove * np + n]), dim3(64), 0, s, b);
-    hipLaunchKernelGGL(k_claim, dim3(host_pre[kPreClaim * np + n]), dim3(64), 0, s, b);
+    launch_claim(b, host_pre[kPreClaim * np + n], s);
     return hipGetLastError();
 }
 
@@ -385,7 +392,7 @@ int run_steps(world* w0, int mode, const TableView& tv, const std::vector<int>& 
               int K, std::map<int, hipGraphExec_t>& graphs, std::map<int, hipGraph_t>& defs) {
     hipStream_t s = w0->stream;
     Batch b{tv.w, tv.block_pre, n, w0->act_rows, n == 1 ? static_cast<const WorldDev*>(w0->d_dev) : nullptr,
-            w0->cfg.cap, w0->dev.ctrl};
+            w0->cfg.cap, w0->dev.ctrl, w0->dev.dyn};
     if (mode == WORLD_MODE_KERNELS) {
         for (int k = 0; k < K; ++k) HIP_TRY(w0, launch_step(b, host_bp.data(), n, s));
         return WORLD_OK;
@@ -686,6 +693,7 @@ static std::vector<uintptr_t> batch_key(world_t* const* ws, int n) {
         key.push_back(uintptr_t(ws[i]->cfg.H) << 32 | uintptr_t(ws[i]->cfg.W));
         key.push_back(uintptr_t(ws[i]->cfg.hidden));
         key.push_back(uintptr_t(ws[i]->cfg.controller));
+        key.push_back(uintptr_t(ws[i]->cfg.dynamics));
     }
     return key;
 }
@@ -1062,7 +1070,8 @@ int world_phase_times(world_t* w, int32_t K, float* ms) {
     if (K < 1) return fail(w, WORLD_E_INVALID_ARG, "K must be >= 1");
     const int np = 2;
     const int* hp = w->host_bp.data();
-    Batch b{w->tv.w, w->tv.block_pre, 1, w->act_rows, static_cast<const WorldDev*>(w->d_dev), w->cfg.cap, w->dev.ctrl};
+    Batch b{w->tv.w, w->tv.block_pre, 1, w->act_rows, static_cast<const WorldDev*>(w->d_dev), w->cfg.cap, w->dev.ctrl,
+            w->dev.dyn};
     hipStream_t s = w->stream;
     // each kernel between start / end events stamped by its own dispatch
     std::vector<hipEvent_t> ev(size_t(K) * 6);
@@ -1072,7 +1081,7 @@ int world_phase_times(world_t* w, int32_t K, float* ms) {
         hipEvent_t* e = ev.data() + size_t(k) * 6;
         launch_act(b, hp[kPreAct * np + 1], s, e[0], e[1]);
         hipExtLaunchKernelGGL(k_move, dim3(hp[kPreMove * np + 1]), dim3(64), 0, s, e[2], e[3], 0, b);
-        hipExtLaunchKernelGGL(k_claim, dim3(hp[kPreClaim * np + 1]), dim3(64), 0, s, e[4], e[5], 0, b);
+        launch_claim(b, hp[kPreClaim * np + 1], s, e[4], e[5]);
         le = hipGetLastError();
     }
     hipError_t se = hipStreamSynchronize(s);
@@ -1111,8 +1120,8 @@ int world_step_many(world_t* const* ws, int32_t n, int32_t K) {
         if (!ws[i]) return fail(nullptr, WORLD_E_INVALID_ARG, "NULL world in list");
         if (ws[i]->poisoned) return WORLD_E_POISONED;
         if (ws[i]->stream != ws[0]->stream) return fail(nullptr, WORLD_E_INVALID_ARG, "worlds must share one stream");
-        if (ws[i]->cfg.controller != ws[0]->cfg.controller)
-            return fail(nullptr, WORLD_E_INVALID_ARG, "worlds of one batch must use the same controller");
+        if (ws[i]->cfg.controller != ws[0]->cfg.controller || ws[i]->cfg.dynamics != ws[0]->cfg.dynamics)
+            return fail(nullptr, WORLD_E_INVALID_ARG, "worlds of one batch must use the same controller and dynamics");
     }
     return batch_step(ws, n, K);
 }

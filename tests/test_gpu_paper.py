@@ -92,3 +92,16 @@ def test_paper_modes_batch_resume(env):
             same(a.snapshot(hidden=True, theta=True), wk.snapshot(hidden=True, theta=True), f"batched {k}")
             a.close()
             wk.close()
+
+
+def test_mixed_dynamics_rejected(env):
+    world, oracle, wl = env
+    import torch
+    stream = torch.cuda.Stream()
+    a = world.World(paper(wl), 1, stream=stream)
+    b = world.World(wl.make(H=40, W=72, cap=400, n_init=200, obs_radius=2, hidden=16), 1, stream=stream)
+    with pytest.raises(world.WorldError) as ei:
+        world.step_many([a, b], 1)
+    assert ei.value.code == -1
+    a.close()
+    b.close()
