@@ -32,8 +32,9 @@ Also reported:
   paper's controller (App. B.5: CNN + LSTM(4), 2445 parameters, sampled
   actions; workload ``net_m1_4k``): wall-clock agent-steps/s, per-kernel
   event times, and the act kernel (k_act_net) against the HBM roofline with
-  its algorithmic bytes and flops per agent.  ``--only-net`` runs this leg
-  alone (for profiling).
+  its algorithmic bytes and flops per agent.
+* ``--only net|paper|lab`` runs one of these legs alone and prints it (for
+  profiling).
 
 ``--gpus N`` with N > 1 is refused: this build runs on one GPU.
 """
@@ -503,7 +504,7 @@ def main():
     ap.add_argument("--net-steps", type=int, default=500, help="timed steps of the paper-network world (0 = skip)")
     ap.add_argument("--net-warmup", type=int, default=300)
     ap.add_argument("--net-phase-steps", type=int, default=100)
-    ap.add_argument("--only-net", action="store_true", help="run only the paper-network leg and print it")
+    ap.add_argument("--only", choices=["net", "paper", "lab"], help="run only this leg and print it")
     ap.add_argument("--paper-steps", type=int, default=2000, help="timed steps of the paper-dynamics world (0 = skip)")
     ap.add_argument("--paper-warmup", type=int, default=1000)
     ap.add_argument("--lab-agents", type=int, default=50, help="evolved agents of the lab leg (0 = skip)")
@@ -523,11 +524,13 @@ def main():
     import torch
     from paper_2302_09334_amd import workloads, world
 
-    if args.only_net:
-        net = net_run(args)
+    if args.only:
+        leg = {"net": ("paper_network", net_run), "paper": ("paper_dynamics", paper_run), "lab": ("lab", lab_run)}
+        name, fn = leg[args.only]
+        out = fn(args)
         if args.calib_copy:
             copy_calibration(torch, world)
-        print(json.dumps({"paper_network": net}))
+        print(json.dumps({name: out}))
         return
 
     cfg = workloads.WORKLOADS[args.workload]
