@@ -25,11 +25,12 @@ import numpy as np
 
 
 def state_digest(s: dict) -> str:
-    """Digest of a canonical world image (integer state, hidden state, genomes)."""
+    """Digest of a canonical world image (integer state, recurrent state and
+    inputs, genomes)."""
     h = hashlib.sha256()
     for k in ("t", "n_live", "next_uid"):
         h.update(str(int(s[k])).encode())
-    for k in ("R", "uid", "row", "col", "energy", "age", "streak", "h", "theta"):
+    for k in ("R", "uid", "row", "col", "energy", "age", "streak", "h", "theta", "last_action", "ate"):
         if k in s:
             h.update(np.ascontiguousarray(s[k]).tobytes())
     return h.hexdigest()
@@ -166,7 +167,10 @@ class Server:
                 continue
             k = min(self.K, min(a.req.steps - a.done for a in active))
             batch = list(active)
-            self.backend.step_many([a.world for a in batch], k)
+            # one shared launch per kind of world (a launch covers worlds of one
+            # controller and one rule set); the launches queue on one stream
+            for group in world_kinds(batch).values():
+                self.backend.step_many([a.world for a in group], k)
             end = self.backend.mark()
             launches += 1
             # overlap: admit requests that arrived meanwhile while the launch runs
@@ -211,6 +215,18 @@ class Server:
             "peak_budget_used_bytes": peak_used, "budget_bytes": self.budget,
         }
         return results, metrics
+
+
+def world_kind(cfg: dict) -> tuple:
+    """Worlds of one kind (controller, dynamics) can share a launch."""
+    return (int(cfg.get("controller", 0)), int(cfg.get("dynamics", 0)))
+
+
+def world_kinds(active: list) -> dict:
+    groups: dict = {}
+    for a in active:
+        groups.setdefault(world_kind(a.req.cfg), []).append(a)
+    return groups
 
 
 def requests_from_trace(trace: list[dict]) -> list[Request]:

@@ -61,3 +61,30 @@ def test_autotune_preserves_state(env):
         assert serve.state_digest(x) == serve.state_digest(y)
     a.close()
     b.close()
+
+
+def test_served_mixed_kinds_equal_alone(env):
+    """Requests with both controllers and both rule sets served together (one
+    shared launch per kind): every result equals the same request run alone."""
+    world, serve, batch, tune, wl = env
+    reqs = []
+    for i in range(8):
+        kw = dict(H=[64, 100][i % 2], W=[128, 200][i % 2], cap=256 + 64 * i, n_init=40 + 5 * i, res_init_p=0.3,
+                  rate_scale=2.0, T_repr=10, L_max=300)
+        if i % 2:
+            kw.update(obs_radius=7, hidden=4, controller=1, w_init_gain=1.0)
+        if i % 4 >= 2:
+            kw.update(dynamics=1, E0=120, E_max=120, decay=1, gain=40, E_repr=0, T_repr=20, T_death=25,
+                      regrow_pI=0.2, regrow_alpha=200.0, spont=0.002)
+        reqs.append(serve.Request(i, arrival=0.01 * i, cfg=wl.make(**kw), seed=70 + i, steps=40 + 20 * (i % 3)))
+    be = serve.HipBackend(mode="graph")
+    budget = 4 * max(world.required_bytes(r.cfg) for r in reqs)
+    results, m = serve.Server(be, budget_bytes=budget, K=20).run(reqs, realtime=True)
+    say(f"[serve mixed] {m}")
+    assert len(results) == len(reqs)
+    for r in reqs:
+        w = world.World(r.cfg, r.seed, mode="graph")
+        w.step(r.steps)
+        alone = serve.state_digest(w.snapshot(hidden=True, theta=True))
+        w.close()
+        assert results[r.rid]["digest"] == alone, r.rid

@@ -26,6 +26,8 @@ class OracleBackend:
         return w
 
     def step_many(self, ws, k):
+        kinds = {serve.world_kind(w["cfg"]) for w in ws}
+        assert len(kinds) == 1, kinds   # one controller and rule set per launch
         for w in ws:
             for _ in range(k):
                 w["acted"] += w["ow"].n_live
@@ -101,3 +103,27 @@ def test_trace_generators_are_seeded():
     assert len(m) == 64 and len({e["seed"] for e in m}) == 64
     assert all(512 <= e["cfg"]["cap"] <= 8192 and e["cfg"]["cap"] % 64 == 0 for e in m)
     assert np.all([(e["cfg"]["H"], e["cfg"]["W"]) in workloads.GRID_SET for e in m])
+
+
+def test_mixed_kinds_are_launched_apart(oracle_lib):
+    # requests with both controllers and both rule sets in one trace: every
+    # launch holds worlds of one kind; every result equals the request alone
+    reqs = []
+    for i in range(8):
+        kw = dict(H=14, W=18 + i, cap=40, n_init=12, res_init_p=0.4, rate_scale=4.0, T_repr=6, L_max=60)
+        if i % 2:
+            kw.update(obs_radius=7, hidden=4, controller=1)
+        else:
+            kw.update(obs_radius=2, hidden=16)
+        if i % 4 >= 2:
+            kw.update(dynamics=1, E0=120, E_max=120, decay=1, gain=40, E_repr=0, T_repr=12, T_death=15,
+                      regrow_pI=0.3, regrow_alpha=200.0, spont=0.01)
+        reqs.append(serve.Request(i, arrival=0.0, cfg=workloads.make(**kw), seed=300 + i, steps=10 + 3 * i))
+    be = OracleBackend(oracle_lib)
+    results, m = serve.Server(be, budget_bytes=10 ** 9, K=5).run(reqs, realtime=False)
+    assert len(results) == len(reqs)
+    for r in reqs:
+        ow = oracle_lib.OracleWorld(oracle_lib.OracleConfig.from_dict(r.cfg), r.seed)
+        for _ in range(r.steps):
+            ow.step()
+        assert results[r.rid]["digest"] == serve.state_digest(ow.state(with_hidden=True, with_theta=True))
