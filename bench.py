@@ -286,16 +286,20 @@ def hbm_honest_run(args, rows: int) -> dict:
     rows_read = float(np.concatenate([observed_inputs(s, cfg)[1] for s in (s0, s1)]).mean())
     n = acting / steps
     act_b = n * act_bytes_per_agent(cfg, rows_read) + cfg["H"] * cfg["W"] * 5
-    move_b = n * (proj_bytes_per_agent(cfg) + MOVE_BYTES_PER_AGENT)
+    move_b = n * MOVE_BYTES_PER_AGENT
+    claim_b = ((n - float(c["deaths"].mean())) * proj_bytes_per_agent(cfg) + n * CLAIM_BYTES_PER_AGENT
+               + 2 * cfg["H"] * cfg["W"])
     out = {"workload": "cfg2: 200x400 grid, cap 16384, 12000 initial agents, resources Bernoulli(0.3), "
                        "regrowth x5.0, obs 7x7x2+1, GRU 32, seed %d, steps 0..%d" % (args.seed, steps - 1),
            "steps": steps, "agent_steps_per_s": acting / wall, "ms_per_step": wall / steps * 1e3,
            "n_live_mean": n, "births_mean": float(c["births"].mean()),
            "kernel_ms": {"act": float(ph[0]), "move": float(ph[1]), "claim": float(ph[2])},
            "act_GBps": act_b / (float(ph[0]) * 1e-3) / 1e9, "move_GBps": move_b / (float(ph[1]) * 1e-3) / 1e9,
-           "step_algorithmic_MB": (act_b + move_b) / 1e6}
+           "claim_GBps": claim_b / (float(ph[2]) * 1e-3) / 1e9,
+           "step_algorithmic_MB": (act_b + move_b + claim_b) / 1e6}
     log(f"[bench] cfg2 (cache-exceeding, {n:.0f} agents): {out['agent_steps_per_s'] / 1e6:.1f} M agent-steps/s, "
-        f"{out['ms_per_step'] * 1e3:.1f} us/step, act {out['act_GBps']:.0f} GB/s, move {out['move_GBps']:.0f} GB/s")
+        f"{out['ms_per_step'] * 1e3:.1f} us/step, act {out['act_GBps']:.0f} GB/s, move {out['move_GBps']:.0f} GB/s, "
+        f"claim {out['claim_GBps']:.0f} GB/s")
     return out
 
 
@@ -640,8 +644,9 @@ def main():
     elig = float(np.mean([(s["streak"] >= cfg["T_repr"]).sum() for s in (start, mid)]))
     kbytes = {
         "act": n_act * per_agent + grid_bytes,
-        "move": n_act * (proj_bytes_per_agent(cfg) + MOVE_BYTES_PER_AGENT),
-        "claim": n_act * CLAIM_BYTES_PER_AGENT + elig * CLAIM_BYTES_PER_ELIGIBLE + 2 * cfg["H"] * cfg["W"],
+        "move": n_act * MOVE_BYTES_PER_AGENT,
+        "claim": (n_act - float(pc["deaths"].mean())) * proj_bytes_per_agent(cfg) + n_act * CLAIM_BYTES_PER_AGENT
+                 + elig * CLAIM_BYTES_PER_ELIGIBLE + 2 * cfg["H"] * cfg["W"],
     }
     kms = {"act": float(ph_ms[0]), "move": float(ph_ms[1]), "claim": float(ph_ms[2])}
     dominant = max(kms, key=kms.get)
@@ -728,8 +733,8 @@ def main():
                         "GBps": kbytes[k] / (kms[k] * 1e-3) / 1e9} for k in kms},
         "roofline": {
             "kernel": {"act": "k_act (observation + sparse input rows + GRU + head, one wave per agent)",
-                       "move": "k_move (moves, energy, death, survivor scan; recurrent projection)",
-                       "claim": "k_claim (birth claims, birth scan, regrowth)"}[dominant],
+                       "move": "k_move (moves, energy, death, survivor scan)",
+                       "claim": "k_claim (birth claims, birth scan, regrowth; recurrent projection)"}[dominant],
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

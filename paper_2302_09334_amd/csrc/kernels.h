@@ -17,6 +17,14 @@ namespace eco {
 enum : int { kPreAct = 0, kPreMove = 1, kPreClaim = 2, kPreKinds = 3 };
 constexpr int kNewbornBlocks = 512;  // leading act blocks that create children (idle ones exit at once)
 
+#ifndef ECO_PROJ_PER
+#define ECO_PROJ_PER 2   // live-list positions per recurrent-projection wave
+#endif
+constexpr int kProjPer = ECO_PROJ_PER;
+
+// Recurrent-projection waves of a GRU world with `cap` slots.
+__host__ __device__ constexpr int proj_waves(int cap) { return (cap + kProjPer - 1) / kProjPer; }
+
 // Newborn blocks of a world with `cap` slots (a world never has more children
 // per step than slots).
 __host__ __device__ constexpr int newborn_blocks(int cap) { return cap < kNewbornBlocks ? cap : kNewbornBlocks; }
@@ -148,45 +156,38 @@ __device__ __forceinline__ void act_body(const Batch& bt, int vb, int tid, StepS
     else act_dispatch<ROWS>(d, &P[li].r[sel], sel ? q1 : q0, li, t, tid & 63);
 }
 
-// Move blocks of a world (one wave each): the move tiles (look-back order),
-// then one block per agent of the current live list computing the recurrent
-// projection W_hh h + b_hh of the hidden state the act phase has just
-// written.  Agents that die in this phase are projected too (unused); a
-// child that takes over their slot is projected when it is created.  The
-// first tile also records the step for the regrowth tiles of the claim
-// phase, which must not read the scalars the last claim tile rewrites.
+// Move blocks of a world (one wave each): the move tiles, in look-back
+// order.  The first tile also records the step and its live count for the
+// claim phase, whose regrowth and projection blocks must not read the scalars
+// the last claim tile rewrites.
 __device__ __forceinline__ void move_body(const Batch& bt, int vb, int lane) {
     const BlockWorld bw = block_world(bt, kPreMove, vb);
     DevRef d = *bw.d;
     PosRec* P = bw.P;
     const int lb = bw.lb;
-    const int ntile = (bw.cap + kTileN - 1) / kTileN;
-    if (lb < ntile) {
-        const int ci = min(lb * kTileN + lane, bw.cap - 1);
-        const AgentRec r0 = P[ci].r[0];
-        const AgentRec r1 = P[ci].r[1];
-        const StepScal ss = read_step(bw.S);
-        pin(r0.slot);
-        pin(r1.slot);
-        if (lb == 0 && lane == 0) bw.S->t_grow = ss.t;
-        move_block(d, P, lb, lane, ss, r0, r1);
-        return;
-    }
-    const int li = lb - ntile;
-    const int lc = min(li, bw.cap - 1);
-    const int s0 = P[lc].r[0].slot;
-    const int s1 = P[lc].r[1].slot;
+    const int ci = min(lb * kTileN + lane, bw.cap - 1);
+    const AgentRec r0 = P[ci].r[0];
+    const AgentRec r1 = P[ci].r[1];
     const StepScal ss = read_step(bw.S);
-    pin(s0);
-    pin(s1);
-    if (li >= ss.n) return;
-    const int slot = ss.sel ? s1 : s0;
-    if (d.hd == 32) proj_agent<32>(d, slot, lane);
-    else proj_agent<16>(d, slot, lane);
+    pin(r0.slot);
+    pin(r1.slot);
+    if (lb == 0 && lane == 0) {
+        bw.S->t_grow = ss.t;
+        bw.S->n_grow = ss.n;
+    }
+    move_block(d, P, lb, lane, ss, r0, r1);
 }
 
 // Claim blocks of a world (one wave each): the claim tiles (look-back
-// order), then the regrowth tiles.
+// order), the regrowth tiles, then (GRU worlds) proj_waves(cap) blocks that
+// compute, position by position of the step's live list, the recurrent
+// projection W_hh h + b_hh of the hidden state its act phase wrote, for the
+// next act phase.  Only survivors of the move phase are projected: no kernel
+// of this phase writes a hidden state or genome, and a child taking over a
+// dead agent's slot is projected when the next act phase creates it.  The
+// projection streams the W_hh blocks while the claim tiles wait on their
+// look-back; few waves, each looping over several agents, keep the loads in
+// flight few enough that the look-back's round trips do not queue behind them.
 template <bool PAPER>
 __device__ __forceinline__ void claim_body(const Batch& bt, int vb, int lane, uint8_t* tile) {
     const BlockWorld bw = block_world(bt, kPreClaim, vb);
@@ -200,7 +201,19 @@ __device__ __forceinline__ void claim_body(const Batch& bt, int vb, int lane, ui
         claim_block<PAPER>(d, bw.S, bw.P, lb, lane, ss, p);
         return;
     }
-    regrow_tile(d, lb - ntile, lane, tile, kconst(bw.S)->t_grow);
+    const int ngrow = ((d.H + kTile - 1) / kTile) * ((d.W + kTile - 1) / kTile);
+    if (lb < ntile + ngrow) {
+        regrow_tile(d, lb - ntile, lane, tile, kconst(bw.S)->t_grow);
+        return;
+    }
+    const int nw = proj_waves(bw.cap);
+    const int n = kconst(bw.S)->n_grow;
+    for (int li = lb - ntile - ngrow; li < n; li += nw) {
+        const int4 q = *reinterpret_cast<const int4*>(&bw.P[li].post);   // slot, ..., alive
+        if (!q.w) continue;
+        if (d.hd == 32) proj_agent<32>(d, q.x, lane);
+        else proj_agent<16>(d, q.x, lane);
+    }
 }
 
 #ifndef ECO_ACT_WAVES
@@ -271,7 +284,7 @@ __global__ __launch_bounds__(kBlock) void k_materialize(const WorldDev* dp) {
 }
 
 // Recurrent projections of every live agent of a world (after creation or a
-// load, when no move phase has produced them).
+// load, when no claim phase has produced them).
 __global__ __launch_bounds__(kBlock) void k_proj_all(const WorldDev* dp) {
     DevRef d = *kconst(dp);
     const WorldScal* S = d.scal;

@@ -107,7 +107,7 @@ struct WorldScal {
     int32_t err;        // device-side failure code (2 look-back time-out)
     int32_t n_prev;     // live agents at the start of the last closed step
     int32_t ctr_open;   // 1: eaten/resource totals of step spawn_t not yet summed
-    int32_t pad;
+    int32_t n_grow;     // live agents of the running claim phase's step (written by its move phase)
     int64_t t_grow;     // step of the running claim phase (written by its move phase)
 };
 
