@@ -22,8 +22,8 @@
 //          weight sums (none, R, A, R + A, wall), tabulated per agent in LDS:
 //          nine float4 lookups per lane instead of 108 multiply-adds.
 //   pool1  lane = pooled pixel (7 x 7), four channels as a float4.
-//   conv2  lane = (output channel, pixel pair): the 36 weights of its
-//          channel in registers, the pooled inputs read as float4 (4 ci).
+//   conv2  lane = (output channel, pixel pair): per tap the 4 weights of
+//          its channel and the pooled inputs as float4 reads (4 ci) from LDS.
 //   pool2  lane = feature (72, two per lane for the last eight).
 //   LSTM   lane = (input group of 16, gate): float4 rows of the input kernel
 //          (each load instruction covers 1 KB of the genome contiguously),
@@ -78,7 +78,7 @@ constexpr int kOb = kWin + 2;    // 17: bordered observation edge
 constexpr int kPb = kP1 + 2;     // 9: bordered pool1 edge
 constexpr int kW2N = kLwi - kC2w;   // conv2 kernel and bias: 296 floats
 struct alignas(16) WaveLds {
-    float w2s[kW2N + 24];        // conv2 kernel and bias, staged for the channel-per-lane reads
+    float w2s[kW2N + 24];        // conv2 kernel [tap][co][ci] and bias, staged for the channel-per-lane reads
     float tab[9][5][4];          // conv1: weight sum of each channel combination per tap
     float p1[kPb * kPb][kF1];
     union {
@@ -254,8 +254,14 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
         if constexpr (PAPER) L.extra[by * kOb + bx] = 0;
     }
 #pragma unroll
-    for (int j = 0; j < 5; ++j)
-        if (j * 64 + lane < kW2N) L.w2s[j * 64 + lane] = w2raw[j];
+    for (int j = 0; j < 5; ++j) {
+        // kernel word (tap, ci, co) to [tap][co][ci]: one float4 per tap and
+        // output channel; the bias stays behind the kernel
+        const int gi = j * 64 + lane;
+        const int tap = gi >> 5, ci = (gi >> 3) & 3, co = gi & 7;
+        if (gi < kC2b - kC2w) L.w2s[tap * 32 + co * 4 + ci] = w2raw[j];
+        else if (gi < kW2N) L.w2s[gi] = w2raw[j];
+    }
     if (lane < 36) {
         float* tp = &L.tab[lane >> 2][0][lane & 3];
         tp[0 * 4] = 0.f;
@@ -313,28 +319,33 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
     wave_lds_sync();
 
     // ---- conv2: lane = (channel lane % 8, pixels lane / 8 and lane / 8 + 8) --
-    float w2[36];
-#pragma unroll
-    for (int k = 0; k < 36; ++k) w2[k] = L.w2s[k * kF2 + co2];
-    const float b2 = L.w2s[kC2b - kC2w + co2];
-#pragma unroll
-    for (int half = 0; half < 2; ++half) {
-        const int p = (lane >> 3) + 8 * half;
-        const int oy = p >> 2, ox = p & 3;
-        const float4* pp = reinterpret_cast<const float4*>(&L.p1[(2 * oy) * kPb + 2 * ox][0]);
-        float acc = 0.f;
+    // the 4 weights of a tap and the lane's channel are one float4 read from
+    // LDS, shared by the lane's two pixels
+    {
+        const float b2 = L.w2s[kC2b - kC2w + co2];
+        const int p0 = lane >> 3, p1 = p0 + 8;
+        const float4* pp0 = reinterpret_cast<const float4*>(&L.p1[(2 * (p0 >> 2)) * kPb + 2 * (p0 & 3)][0]);
+        const float4* pp1 = reinterpret_cast<const float4*>(&L.p1[(2 * (p1 >> 2)) * kPb + 2 * (p1 & 3)][0]);
+        const float4* wt = reinterpret_cast<const float4*>(&L.w2s[co2 * 4]);
+        float acc0 = 0.f, acc1 = 0.f;
 #pragma unroll
         for (int ky = 0; ky < 3; ++ky)
 #pragma unroll
             for (int kx = 0; kx < 3; ++kx) {
-                const float4 v = pp[ky * kPb + kx];
-                const int k = (ky * 3 + kx) * kF1;
-                acc = fmaf(v.x, w2[k + 0], acc);
-                acc = fmaf(v.y, w2[k + 1], acc);
-                acc = fmaf(v.z, w2[k + 2], acc);
-                acc = fmaf(v.w, w2[k + 3], acc);
+                const float4 w = wt[(ky * 3 + kx) * kF2];
+                const float4 v0 = pp0[ky * kPb + kx];
+                const float4 v1 = pp1[ky * kPb + kx];
+                acc0 = fmaf(v0.x, w.x, acc0);
+                acc0 = fmaf(v0.y, w.y, acc0);
+                acc0 = fmaf(v0.z, w.z, acc0);
+                acc0 = fmaf(v0.w, w.w, acc0);
+                acc1 = fmaf(v1.x, w.x, acc1);
+                acc1 = fmaf(v1.y, w.y, acc1);
+                acc1 = fmaf(v1.z, w.z, acc1);
+                acc1 = fmaf(v1.w, w.w, acc1);
             }
-        L.u.late.a2[p][co2] = acc + b2;
+        L.u.late.a2[p0][co2] = acc0 + b2;
+        L.u.late.a2[p1][co2] = acc1 + b2;
     }
     wave_lds_sync();
 
