@@ -241,6 +241,15 @@ const char *world_last_error(const world_t *w);
  * returns control to the controller. */
 int world_set_forced_action(world_t *w, int32_t action);
 
+/* Failure injection for the look-back scans: from the next step on, move
+ * tile `tile` (0 <= tile < ceil(cap / 64); -1 = none) publishes no look-back
+ * word, and a wait ends after `spin_ticks` ticks of the 100 MHz wall clock
+ * (0 = the default bound of 2 s).  The next tile's wait then times out: the
+ * device sets the world's error word and stops stepping it, and the next
+ * synchronising call returns WORLD_E_HIP and poisons the handle.  Every wait
+ * stays bounded.  Synchronises. */
+int world_test_stall_lookback(world_t *w, int32_t tile, uint32_t spin_ticks);
+
 /* Synchronise and copy the controller log of `step` (needs log_steps > 0 and
  * the step among the last log_steps): per acting agent in uid order its uid,
  * action and 5 logits.  *n receives the number of agents. */
@@ -264,8 +273,8 @@ int world_test_gumbel(const uint32_t *d_words, size_t n, float *d_g, void *hip_s
  * execution time in milliseconds of each phase kernel (start / end events
  * stamped by the kernel's own dispatch, so launch gaps are excluded) in
  * ms[0..2] = act (child genomes of the previous step, observation and
- * controller), move (moves, energy, death, survivor scan, the GRU's
- * recurrent projection), claim (birth claims, birth scan, regrowth).  The
+ * controller), move (moves, energy, death, survivor scan), claim (birth
+ * claims, birth scan, regrowth, the GRU's recurrent projection).  The
  * steps are real: the world advances by K.  Synchronises. */
 int world_phase_times(world_t *w, int32_t K, float *ms);
 

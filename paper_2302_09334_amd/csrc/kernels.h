@@ -118,6 +118,7 @@ __device__ __forceinline__ void act_body(const Batch& bt, int vb, int tid, StepS
         pin(q0b.z);
         pin(q1b.z);
     }
+    if (ss.err) return;   // the world failed: it no longer steps
     const int64_t t = ss.t;
     const int n = ss.n;
     const int nc = ss.nc;
@@ -171,6 +172,7 @@ __device__ __forceinline__ void move_body(const Batch& bt, int vb, int lane) {
     const StepScal ss = read_step(bw.S);
     pin(r0.slot);
     pin(r1.slot);
+    if (ss.err) return;
     if (lb == 0 && lane == 0) {
         bw.S->t_grow = ss.t;
         bw.S->n_grow = ss.n;
@@ -198,6 +200,7 @@ __device__ __forceinline__ void claim_body(const Batch& bt, int vb, int lane, ui
         const PostRec p = bw.P[min(lb * kTileN + lane, bw.cap - 1)].post;
         const StepScal ss = read_step(bw.S);
         pin(p.slot);
+        if (ss.err) return;
         claim_block<PAPER>(d, bw.S, bw.P, lb, lane, ss, p);
         return;
     }
@@ -272,6 +275,7 @@ void k_act_net_paper(Batch bt) {
 // next act phase treats them as ordinary agents.
 __global__ __launch_bounds__(kBlock) void k_materialize(const WorldDev* dp) {
     DevRef d = *kconst(dp);
+    if (d.scal->err) return;
     const int nc = d.scal->n_child;
     for (int rk = blockIdx.x; rk < nc; rk += gridDim.x) {
         spawn_child(d, rk, threadIdx.x, d.ss);

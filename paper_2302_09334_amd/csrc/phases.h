@@ -373,8 +373,12 @@ __device__ __forceinline__ void step_open(DevRef d, int64_t t) {
 //   [epoch 20 | flag 2 | a 21 | b 21]   flag 1 = tile total, 2 = inclusive
 // where epoch = step mod 2^20, so words from earlier steps are ignored and the
 // arrays never need clearing between steps.  Every lane returns the
-// exclusive prefix of the packed (a, b) pair; waits are bounded (2 s) and a
-// time-out sets the world's error word.
+// exclusive prefix of the packed (a, b) pair; waits are bounded (d.spin_ticks,
+// 2 s unless a test shortens it) and a time-out sets the world's error word,
+// after which every phase kernel of the world exits at once (the prefixes of
+// a timed-out scan are partial sums: every index they yield stays in range,
+// but the step's state is not valid).  `withhold`: publish nothing (a test
+// hook that makes the next tile's wait time out).
 // ---------------------------------------------------------------------------
 constexpr int kTileN = 64;   // live-list entries per move / claim tile
 constexpr int kCntBits = 21;
@@ -386,17 +390,18 @@ __device__ __forceinline__ uint32_t unpack_a(uint64_t v) { return uint32_t((v >>
 __device__ __forceinline__ uint32_t unpack_b(uint64_t v) { return uint32_t(v & kCntMask); }
 
 __device__ __forceinline__ uint64_t lookback(DevRef d, uint64_t* st, int tile, uint32_t epoch, uint64_t local,
-                                             int lane) {
+                                             int lane, bool withhold = false) {
     // Publish this tile's total, then examine the predecessors 64 at a time
     // (one status word per lane) until the nearest one holding an inclusive
     // prefix: the prefix is that word plus the totals in between.
     const uint64_t tag = uint64_t(epoch & 0xFFFFFu);
-    if (lane == 0)
+    if (lane == 0 && !withhold)
         __hip_atomic_store(st + tile, (tag << 44) | (uint64_t(tile == 0 ? 2 : 1) << 42) | local, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
     uint64_t excl = 0;
     int end = tile;
     const uint64_t t0 = wall_clock64();
+    const uint64_t limit = d.spin_ticks;
     bool timed_out = false;
     while (end > 0) {
         const int k = end - 1 - lane;   // lane 0 = nearest predecessor
@@ -407,7 +412,7 @@ __device__ __forceinline__ uint64_t lookback(DevRef d, uint64_t* st, int tile, u
                 v = __hip_atomic_load(st + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 flag = uint32_t(v >> 42) & 3u;
                 if ((v >> 44) == tag && flag != 0) break;
-                if (wall_clock64() - t0 > 200000000ull) {   // 2 s at the 100 MHz wall clock
+                if (wall_clock64() - t0 > limit) {
                     timed_out = true;
                     v = 0;
                     flag = 2;
@@ -428,7 +433,7 @@ __device__ __forceinline__ uint64_t lookback(DevRef d, uint64_t* st, int tile, u
     }
     if (__ballot(timed_out) && lane == 0)
         __hip_atomic_store(&d.scal->err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (lane == 0 && tile != 0)
+    if (lane == 0 && tile != 0 && !withhold)
         __hip_atomic_store(st + tile, (tag << 44) | (uint64_t(2) << 42) | (excl + local), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
     return excl;
@@ -614,6 +619,7 @@ __device__ __forceinline__ int move_agent_paper(DevRef d, const AgentRec& a, int
 struct StepScal {
     int64_t t;
     int n, sel, nc;
+    int err;   // nonzero after a device failure: the world no longer steps
     uint32_t next_uid;
     int free_head, free_tail;
 };
@@ -628,6 +634,7 @@ __device__ __forceinline__ StepScal read_step_from(P S) {
     s.next_uid = S->next_uid;
     s.free_head = S->free_head;
     s.free_tail = S->free_tail;
+    s.err = S->err;
     return s;
 }
 
@@ -712,7 +719,7 @@ __device__ __forceinline__ void move_block(DevRef d, PosRec* P, int j, int lane,
         }
     }
     const WaveRank wr = wave_rank2(alive, dead, lane);
-    const uint64_t ex = lookback(d, d.lb_move, j, uint32_t(t), pack2(wr.ta, wr.tb), lane);
+    const uint64_t ex = lookback(d, d.lb_move, j, uint32_t(t), pack2(wr.ta, wr.tb), lane, j == d.stall_tile);
     if (alive) {
         const int pos = int(unpack_a(ex)) + wr.ra;
         d.live[sel ^ 1][pos] = nr.slot;

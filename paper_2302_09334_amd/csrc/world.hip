@@ -479,6 +479,8 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
     d.sigma = float(c.sigma_mut);
     d.seed_lo = uint32_t(seed); d.seed_hi = uint32_t(seed >> 32);
     d.forced = -1;
+    d.stall_tile = -1;
+    d.spin_ticks = kSpinTicks;
     d.log_steps = c.log_steps;
     d.off_hh = dm.off_hh; d.off_bih = dm.off_bih; d.off_bhh = dm.off_bhh; d.off_wo = dm.off_wo; d.off_bo = dm.off_bo;
     d.tot_row = dm.tot_row;
@@ -607,6 +609,10 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.ring, 0, sizeof(int32_t) * kRing * kCtrWords, s);
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.mclaim, 0xFF, 8 * HW, s);
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.wuid, 0xFF, 4 * size_t(c.cap), s);
+    // tables a step fills before reading: zeroed so that no entry ever holds
+    // a slot index out of range
+    if (e == hipSuccess) e = hipMemsetAsync(b + lay.child, 0, 16 * size_t(c.cap), s);
+    if (e == hipSuccess) e = hipMemsetAsync(b + lay.deadlist, 0, 4 * size_t(c.cap), s);
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.mhist, 0, 4 * size_t(kMoveRing) * (kMoveBins + 1), s);
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.lb_move, 0, 8 * size_t(tiles_agent(c)), s);
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.lb_claim, 0, 8 * size_t(tiles_agent(c)), s);
@@ -1005,6 +1011,21 @@ int world_set_forced_action(world_t* w, int32_t action) {
     w->dev.forced = action;
     HIP_TRY(w, hipStreamSynchronize(w->stream));
     HIP_TRY(w, hipMemcpy(w->base + w->lay.desc + offsetof(WorldDev, forced), &action, sizeof(action),
+                         hipMemcpyHostToDevice));
+    return WORLD_OK;
+}
+
+int world_test_stall_lookback(world_t* w, int32_t tile, uint32_t spin_ticks) {
+    if (!w) return fail(nullptr, WORLD_E_INVALID_ARG, "world is NULL");
+    if (w->poisoned) return WORLD_E_POISONED;
+    if (tile < -1 || tile >= tiles_agent(w->cfg)) return fail(w, WORLD_E_INVALID_ARG, "tile out of range");
+    const uint32_t ticks = spin_ticks ? spin_ticks : kSpinTicks;
+    w->dev.stall_tile = tile;
+    w->dev.spin_ticks = ticks;
+    HIP_TRY(w, hipStreamSynchronize(w->stream));
+    HIP_TRY(w, hipMemcpy(w->base + w->lay.desc + offsetof(WorldDev, stall_tile), &tile, sizeof(tile),
+                         hipMemcpyHostToDevice));
+    HIP_TRY(w, hipMemcpy(w->base + w->lay.desc + offsetof(WorldDev, spin_ticks), &ticks, sizeof(ticks),
                          hipMemcpyHostToDevice));
     return WORLD_OK;
 }

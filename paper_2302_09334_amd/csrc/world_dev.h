@@ -34,6 +34,7 @@ constexpr int kRing = 8192;     // steps of counters kept on device
 constexpr int kCtrWords = 10;   // words per counter record
 constexpr int kBlock = 256;     // threads per block in every kernel
 constexpr int kTile = 16;       // regrowth tile edge (16 x 16 cells per block)
+constexpr uint32_t kSpinTicks = 200000000u;   // look-back wait bound: 2 s at the 100 MHz wall clock
 
 // Counter record fields (match world_counters in world.h).
 enum : int { kCtrLive = 0, kCtrBirths, kCtrDeaths, kCtrEaten, kCtrRes, kCtrWins, kCtrDeadAgeLo, kCtrDeadAgeHi,
@@ -126,7 +127,8 @@ struct WorldDev {
     int32_t ss;         // recurrent state floats per slot (hd for the GRU, 2 hd for the LSTM)
     int32_t dyn;        // kDynBench or kDynPaper
     int32_t E_max, T_death;   // paper dynamics
-    int32_t pad0;
+    int32_t stall_tile;       // test hook: move tile that publishes no look-back word (-1: none)
+    uint32_t spin_ticks;      // bound of a look-back wait, in 100 MHz wall-clock ticks
     // grid
     uint8_t* R[2];
     int32_t* occA;

@@ -77,7 +77,7 @@ EXPORTS = [
     "world_set_mode", "world_set_tuning", "world_set_stream", "world_sync", "world_snapshot", "world_load", "world_counters_get",
     "world_destroy", "world_last_error", "world_set_forced_action", "world_action_log",
     "world_test_philox", "world_test_gauss", "world_threshold_table", "world_phase_times",
-    "world_test_copy", "world_move_hist", "world_test_gumbel",
+    "world_test_copy", "world_move_hist", "world_test_gumbel", "world_test_stall_lookback",
 ]
 
 _lib = None
@@ -115,6 +115,7 @@ def lib():
         L.world_test_copy.argtypes = [P, P, C.c_size_t, P]
         L.world_move_hist.argtypes = [P, C.c_int64, C.c_int32, P]
         L.world_test_gumbel.argtypes = [P, C.c_size_t, P, P]
+        L.world_test_stall_lookback.argtypes = [P, C.c_int32, C.c_uint32]
         for name in EXPORTS:
             getattr(L, name).restype = getattr(L, name).restype or C.c_int
         L.world_last_error.restype = C.c_char_p
@@ -235,6 +236,11 @@ class World:
 
     def set_forced_action(self, a: int):
         _check(lib().world_set_forced_action(self._h, int(a)), self._h)
+
+    def test_stall_lookback(self, tile: int, spin_ticks: int = 0):
+        """Failure injection: move tile `tile` withholds its look-back word and
+        waits end after `spin_ticks` wall-clock ticks (include/world.h)."""
+        _check(lib().world_test_stall_lookback(self._h, int(tile), int(spin_ticks)), self._h)
 
     def phase_times(self, K: int) -> np.ndarray:
         """Run K steps as per-phase kernels timed with HIP events; mean ms per

@@ -181,3 +181,33 @@ def test_load_rejects_bad_images(env):
     # the world is still usable after a rejected load
     w.step(3)
     w.sync()
+
+
+def test_lookback_timeout_poisons(env):
+    # Failure injection through the scan's own bounded wait: move tile 1
+    # publishes no look-back word and waits end after 1 ms, so tile 2's wait
+    # times out.  The device then stops stepping the world, the next
+    # synchronising call reports the failure and poisons the handle, and a
+    # second world on the same device is unaffected.
+    world, wl = env
+    cfg = dense(wl)   # 300 slots: 5 move tiles
+    say("[lookback timeout] cfg", cfg["H"], cfg["W"], cfg["cap"])
+    w = world.World(cfg, 3)
+    other = world.World(cfg, 3)
+    w.step(2)
+    w.sync()
+    w.test_stall_lookback(1, 100_000)
+    w.step(3)
+    with pytest.raises(world.WorldError) as e:
+        w.sync()
+    assert e.value.code == -4 and "look-back" in str(e.value)
+    with pytest.raises(world.WorldError) as e:
+        w.step(1)
+    assert e.value.code == -5
+    w.close()
+    other.step(5)
+    ref = world.World(cfg, 3)
+    ref.step(5)
+    same(other.snapshot(hidden=True, theta=True), ref.snapshot(hidden=True, theta=True), "unaffected world")
+    other.close()
+    ref.close()
