@@ -15,7 +15,10 @@
 namespace eco {
 
 enum : int { kPreAct = 0, kPreMove = 1, kPreClaim = 2, kPreKinds = 3 };
-constexpr int kNewbornBlocks = 512;  // leading act blocks that create children (idle ones exit at once)
+#ifndef ECO_NEWBORN_BLOCKS
+#define ECO_NEWBORN_BLOCKS 512
+#endif
+constexpr int kNewbornBlocks = ECO_NEWBORN_BLOCKS;  // leading act blocks that create children (idle ones exit at once)
 
 #ifndef ECO_PROJ_PER
 #define ECO_PROJ_PER 2   // live-list positions per recurrent-projection wave
@@ -85,6 +88,17 @@ __device__ __forceinline__ BlockWorld block_world(const Batch& bt, int kind, int
             cap};
 }
 
+// The first controller step of a child with the paper's network.  Kept out
+// of line: inlined a second time into the newborn path, the network raised
+// the whole act kernel to 128 registers with 22 spilled (the compiler sizes
+// the kernel for its worst path); out of line the kernel needs 120 and
+// spills none, and the call's own cost falls on the rare newborn blocks.
+template <bool PAPER>
+__device__ __attribute__((noinline)) void net_child_act(DevRef d, AgentRec* recp, int4 rv, int4 rv2, int li,
+                                                        int64_t t, int lane, net::WaveLds& L) {
+    net::act_agent<PAPER>(d, recp, rv, rv2, li, t, lane, L);
+}
+
 // Block bodies.  `vb` is the block's index in the batch-wide numbering of its
 // phase.
 
@@ -142,7 +156,7 @@ __device__ __forceinline__ void act_body(const Batch& bt, int vb, int tid, StepS
                 const int4 rv = *reinterpret_cast<const int4*>(&P[lj].r[sel]);
                 if constexpr (NET) {
                     const int4 rv2 = *(reinterpret_cast<const int4*>(&P[lj].r[sel]) + 1);
-                    net::act_agent<PAPER>(d, &P[lj].r[sel], rv, rv2, lj, t, tid, lds[0]);
+                    net_child_act<PAPER>(d, &P[lj].r[sel], rv, rv2, lj, t, tid, lds[0]);
                 } else {
                     act_dispatch<ROWS>(d, &P[lj].r[sel], rv, lj, t, tid);
                 }
@@ -242,8 +256,9 @@ __global__ __launch_bounds__(kBlock) void k_act_rows(Batch bt) {
 
 // Act kernel of worlds with the paper's network.  Compiled for four waves per
 // SIMD: the compiler's own choice (about 185 registers, two waves) leaves the
-// load round trip of each wave exposed; four waves with a few spilled
-// registers measured about 20% faster, five or more spill too much.
+// load round trip of each wave exposed; four waves measured about 20% faster.
+// Five or more spill registers holding loads of the first round trip, and
+// each such spill waits for its load, which splits the round trip.
 #ifndef ECO_NET_WAVES
 #define ECO_NET_WAVES 4   // waves per SIMD the network act kernel is compiled for (0 = compiler's choice)
 #endif

@@ -84,6 +84,7 @@ __device__ __forceinline__ void act_claim(DevRef d, int best, int r, int c, uint
 // tree.  The summation order therefore depends only on the agent's own
 // observation, never on the launch shape or on other worlds in the launch.
 // ---------------------------------------------------------------------------
+
 // ---------------------------------------------------------------------------
 // Recurrent projection gh = W_hh h + b_hh of the agent in `slot` (one wave),
 // written to gh[slot] (3 * HD floats, gate-interleaved per hidden unit).  It
