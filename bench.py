@@ -107,6 +107,12 @@ def act_bytes_per_agent(cfg: dict, rows_mean: float) -> float:
     return (rw + rw + (5 * hd + 5) * 4 + rw + rows_mean * rw + 2 * hd * 4 + 21)
 
 
+# Share of the live list whose recurrent projection runs in the move kernel
+# (the library's build default, ECO_PROJ_MOVE_EIGHTHS = 3); the rest, minus
+# the agents that died in the move phase, runs in the claim kernel.
+PROJ_MOVE_SHARE = 3 / 8
+
+
 def proj_bytes_per_agent(cfg: dict) -> float:
     """Bytes of the recurrent projection per agent: W_hh, b_hh and h in, the
     projection out."""
@@ -286,8 +292,9 @@ def hbm_honest_run(args, rows: int) -> dict:
     rows_read = float(np.concatenate([observed_inputs(s, cfg)[1] for s in (s0, s1)]).mean())
     n = acting / steps
     act_b = n * act_bytes_per_agent(cfg, rows_read) + cfg["H"] * cfg["W"] * 5
-    move_b = n * MOVE_BYTES_PER_AGENT
-    claim_b = ((n - float(c["deaths"].mean())) * proj_bytes_per_agent(cfg) + n * CLAIM_BYTES_PER_AGENT
+    pb = proj_bytes_per_agent(cfg)
+    move_b = n * (MOVE_BYTES_PER_AGENT + PROJ_MOVE_SHARE * pb)
+    claim_b = ((1 - PROJ_MOVE_SHARE) * (n - float(c["deaths"].mean())) * pb + n * CLAIM_BYTES_PER_AGENT
                + 2 * cfg["H"] * cfg["W"])
     out = {"workload": "cfg2: 200x400 grid, cap 16384, 12000 initial agents, resources Bernoulli(0.3), "
                        "regrowth x5.0, obs 7x7x2+1, GRU 32, seed %d, steps 0..%d" % (args.seed, steps - 1),
@@ -644,9 +651,9 @@ def main():
     elig = float(np.mean([(s["streak"] >= cfg["T_repr"]).sum() for s in (start, mid)]))
     kbytes = {
         "act": n_act * per_agent + grid_bytes,
-        "move": n_act * MOVE_BYTES_PER_AGENT,
-        "claim": (n_act - float(pc["deaths"].mean())) * proj_bytes_per_agent(cfg) + n_act * CLAIM_BYTES_PER_AGENT
-                 + elig * CLAIM_BYTES_PER_ELIGIBLE + 2 * cfg["H"] * cfg["W"],
+        "move": n_act * (MOVE_BYTES_PER_AGENT + PROJ_MOVE_SHARE * proj_bytes_per_agent(cfg)),
+        "claim": (1 - PROJ_MOVE_SHARE) * (n_act - float(pc["deaths"].mean())) * proj_bytes_per_agent(cfg)
+                 + n_act * CLAIM_BYTES_PER_AGENT + elig * CLAIM_BYTES_PER_ELIGIBLE + 2 * cfg["H"] * cfg["W"],
     }
     kms = {"act": float(ph_ms[0]), "move": float(ph_ms[1]), "claim": float(ph_ms[2])}
     dominant = max(kms, key=kms.get)
@@ -733,8 +740,8 @@ def main():
                         "GBps": kbytes[k] / (kms[k] * 1e-3) / 1e9} for k in kms},
         "roofline": {
             "kernel": {"act": "k_act (observation + sparse input rows + GRU + head, one wave per agent)",
-                       "move": "k_move (moves, energy, death, survivor scan)",
-                       "claim": "k_claim (birth claims, birth scan, regrowth; recurrent projection)"}[dominant],
+                       "move": "k_move (moves, energy, death, survivor scan; 3/8 of the recurrent projection)",
+                       "claim": "k_claim (birth claims, birth scan, regrowth; 5/8 of the recurrent projection)"}[dominant],
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

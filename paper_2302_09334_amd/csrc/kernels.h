@@ -24,9 +24,21 @@ constexpr int kNewbornBlocks = ECO_NEWBORN_BLOCKS;  // leading act blocks that c
 #define ECO_PROJ_PER 2   // live-list positions per recurrent-projection wave
 #endif
 constexpr int kProjPer = ECO_PROJ_PER;
+#ifndef ECO_PROJ_MOVE_EIGHTHS
+#define ECO_PROJ_MOVE_EIGHTHS 3   // eighths of the live list whose projection runs in the move phase
+#endif
+constexpr int kProjMove8 = ECO_PROJ_MOVE_EIGHTHS;
+#ifndef ECO_PROJ_DELAY
+#define ECO_PROJ_DELAY 50   // wall-clock ticks (10 ns) a claim-phase projection wave waits before its loads
+#endif
 
-// Recurrent-projection waves of a GRU world with `cap` slots.
-__host__ __device__ constexpr int proj_waves(int cap) { return (cap + kProjPer - 1) / kProjPer; }
+// Live-list positions [0, proj_split(n)) are projected in the move phase, the
+// rest in the claim phase.
+__host__ __device__ constexpr int proj_split(int n) { return n * kProjMove8 / 8; }
+// Recurrent-projection waves of a GRU world with `cap` slots in the move and
+// in the claim phase (n - proj_split(n) grows with n, so cap bounds both).
+__host__ __device__ constexpr int proj_waves_move(int cap) { return (proj_split(cap) + kProjPer - 1) / kProjPer; }
+__host__ __device__ constexpr int proj_waves(int cap) { return (cap - proj_split(cap) + kProjPer - 1) / kProjPer; }
 
 // Newborn blocks of a world with `cap` slots (a world never has more children
 // per step than slots).
@@ -172,14 +184,30 @@ __device__ __forceinline__ void act_body(const Batch& bt, int vb, int tid, StepS
 }
 
 // Move blocks of a world (one wave each): the move tiles, in look-back
-// order.  The first tile also records the step and its live count for the
-// claim phase, whose regrowth and projection blocks must not read the scalars
-// the last claim tile rewrites.
+// order, then (GRU worlds) proj_waves_move(cap) blocks computing the
+// recurrent projection of live-list positions [0, proj_split(n)) (see
+// claim_body; a dying agent is projected too, harmlessly: a child taking
+// over its slot is projected when the next act phase creates it).  The first
+// tile also records the step and its live count for the claim phase, whose
+// regrowth and projection blocks must not read the scalars the last claim
+// tile rewrites.
 __device__ __forceinline__ void move_body(const Batch& bt, int vb, int lane) {
     const BlockWorld bw = block_world(bt, kPreMove, vb);
     DevRef d = *bw.d;
     PosRec* P = bw.P;
     const int lb = bw.lb;
+    const int ntile = (bw.cap + kTileN - 1) / kTileN;
+    if (kProjMove8 > 0 && lb >= ntile) {   // recurrent projections of positions [0, proj_split(n))
+        const StepScal ss = read_step(bw.S);
+        if (ss.err) return;
+        const int nw = proj_waves_move(bw.cap);
+        for (int li = lb - ntile; li < proj_split(ss.n); li += nw) {
+            const int slot = P[li].r[ss.sel].slot;
+            if (d.hd == 32) proj_agent<32>(d, slot, lane);
+            else proj_agent<16>(d, slot, lane);
+        }
+        return;
+    }
     const int ci = min(lb * kTileN + lane, bw.cap - 1);
     const AgentRec r0 = P[ci].r[0];
     const AgentRec r1 = P[ci].r[1];
@@ -196,14 +224,20 @@ __device__ __forceinline__ void move_body(const Batch& bt, int vb, int lane) {
 
 // Claim blocks of a world (one wave each): the claim tiles (look-back
 // order), the regrowth tiles, then (GRU worlds) proj_waves(cap) blocks that
-// compute, position by position of the step's live list, the recurrent
-// projection W_hh h + b_hh of the hidden state its act phase wrote, for the
-// next act phase.  Only survivors of the move phase are projected: no kernel
-// of this phase writes a hidden state or genome, and a child taking over a
-// dead agent's slot is projected when the next act phase creates it.  The
-// projection streams the W_hh blocks while the claim tiles wait on their
-// look-back; few waves, each looping over several agents, keep the loads in
-// flight few enough that the look-back's round trips do not queue behind them.
+// compute, position by position of the step's live list from proj_split(n)
+// on, the recurrent projection W_hh h + b_hh of the hidden state its act phase
+// wrote, for the next act phase.  Only survivors of the move phase are
+// projected here: no kernel of this phase writes a hidden state or genome,
+// and a child taking over a dead agent's slot is projected when the next act
+// phase creates it.
+//
+// The projection (about 40% of a step's bytes) streams while the move and
+// claim tiles, which are latency-bound, wait on their round trips; but every
+// tile load then queues behind the projection's loads.  Measured at 4608
+// agents: three eighths of the list in the move phase, the rest here after a
+// 0.5 us pause (the tiles' first gathers and the regrowth loads go first),
+// two positions per wave, gave 32.7 us per step against 34.4 us with all of
+// it here and no pause.
 template <bool PAPER>
 __device__ __forceinline__ void claim_body(const Batch& bt, int vb, int lane, uint8_t* tile) {
     const BlockWorld bw = block_world(bt, kPreClaim, vb);
@@ -223,9 +257,13 @@ __device__ __forceinline__ void claim_body(const Batch& bt, int vb, int lane, ui
         regrow_tile(d, lb - ntile, lane, tile, kconst(bw.S)->t_grow);
         return;
     }
+    if (ECO_PROJ_DELAY > 0) {   // let the tiles' loads pass first
+        const uint64_t t0 = wall_clock64();
+        while (wall_clock64() - t0 < uint64_t(ECO_PROJ_DELAY)) __builtin_amdgcn_s_sleep(4);
+    }
     const int nw = proj_waves(bw.cap);
     const int n = kconst(bw.S)->n_grow;
-    for (int li = lb - ntile - ngrow; li < n; li += nw) {
+    for (int li = proj_split(n) + lb - ntile - ngrow; li < n; li += nw) {
         const int4 q = *reinterpret_cast<const int4*>(&bw.P[li].post);   // slot, ..., alive
         if (!q.w) continue;
         if (d.hd == 32) proj_agent<32>(d, q.x, lane);

@@ -293,7 +293,8 @@ std::vector<int> batch_prefix(const std::vector<const world*>& ws) {
     for (int i = 0; i < n; ++i) {
         const world_config& c = ws[i]->cfg;
         pre[kPreAct * (n + 1) + i + 1] = pre[kPreAct * (n + 1) + i] + newborn_blocks(c.cap) + blocks_act(c);
-        pre[kPreMove * (n + 1) + i + 1] = pre[kPreMove * (n + 1) + i] + tiles_agent(c);
+        pre[kPreMove * (n + 1) + i + 1] =
+            pre[kPreMove * (n + 1) + i] + tiles_agent(c) + (is_net(c) ? 0 : proj_waves_move(c.cap));
         // GRU worlds add the recurrent-projection blocks to the claim phase
         pre[kPreClaim * (n + 1) + i + 1] =
             pre[kPreClaim * (n + 1) + i] + tiles_agent(c) + tiles_of(c) + (is_net(c) ? 0 : proj_waves(c.cap));
