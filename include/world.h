@@ -273,8 +273,9 @@ int world_test_gumbel(const uint32_t *d_words, size_t n, float *d_g, void *hip_s
  * execution time in milliseconds of each phase kernel (start / end events
  * stamped by the kernel's own dispatch, so launch gaps are excluded) in
  * ms[0..2] = act (child genomes of the previous step, observation and
- * controller), move (moves, energy, death, survivor scan), claim (birth
- * claims, birth scan, regrowth, the GRU's recurrent projection).  The
+ * controller), move (moves, energy, death, survivor scan, part of the GRU's
+ * recurrent projection), claim (birth claims, birth scan, regrowth, the rest
+ * of the projection).  The
  * steps are real: the world advances by K.  Synchronises. */
 int world_phase_times(world_t *w, int32_t K, float *ms);
 
