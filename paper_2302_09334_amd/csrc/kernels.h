@@ -53,6 +53,7 @@ struct Batch {
     int cap0;                   // n == 1: its agent capacity
     int ctrl;                   // controller of every world in the batch
     int dyn;                    // dynamics of every world in the batch
+    int net_wide;               // host only: the network act kernel for five waves per SIMD
 };
 
 template <int ROWS>
@@ -105,7 +106,9 @@ __device__ __forceinline__ BlockWorld block_world(const Batch& bt, int kind, int
 // the whole act kernel to 128 registers with 22 spilled (the compiler sizes
 // the kernel for its worst path); out of line the kernel needs 120 and
 // spills none, and the call's own cost falls on the rare newborn blocks.
-template <bool PAPER>
+// One instance per kernel (WIDE): an instance shared by the kernels for four
+// and five waves per SIMD is allocated for the tighter budget of the two.
+template <bool PAPER, bool WIDE>
 __device__ __attribute__((noinline)) void net_child_act(DevRef d, AgentRec* recp, int4 rv, int4 rv2, int li,
                                                         int64_t t, int lane, net::WaveLds& L) {
     net::act_agent<PAPER>(d, recp, rv, rv2, li, t, lane, L);
@@ -118,8 +121,9 @@ __device__ __attribute__((noinline)) void net_child_act(DevRef d, AgentRec* recp
 // children of the previous step (rank r, r + nb, ...) and run their first
 // controller step (they are the last n_child entries of the live list); the
 // remaining blocks run the controller of the other agents, four per block.
-// NET: the paper's network (with `lds`, one scratch per wave), else the GRU.
-template <int ROWS, bool NET, bool PAPER = false>
+// NET: the paper's network (with `lds`, one scratch per wave), else the GRU;
+// WIDE: the kernel is compiled for five waves per SIMD.
+template <int ROWS, bool NET, bool PAPER = false, bool WIDE = false>
 __device__ __forceinline__ void act_body(const Batch& bt, int vb, int tid, StepShared& sh, net::WaveLds* lds) {
     const BlockWorld bw = block_world(bt, kPreAct, vb);
     DevRef d = *bw.d;
@@ -168,7 +172,7 @@ __device__ __forceinline__ void act_body(const Batch& bt, int vb, int tid, StepS
                 const int4 rv = *reinterpret_cast<const int4*>(&P[lj].r[sel]);
                 if constexpr (NET) {
                     const int4 rv2 = *(reinterpret_cast<const int4*>(&P[lj].r[sel]) + 1);
-                    net_child_act<PAPER>(d, &P[lj].r[sel], rv, rv2, lj, t, tid, lds[0]);
+                    net_child_act<PAPER, WIDE>(d, &P[lj].r[sel], rv, rv2, lj, t, tid, lds[0]);
                 } else {
                     act_dispatch<ROWS>(d, &P[lj].r[sel], rv, lj, t, tid);
                 }
@@ -292,11 +296,19 @@ __global__ __launch_bounds__(kBlock) void k_act_rows(Batch bt) {
     act_body<ROWS, false>(bt, blockIdx.x, threadIdx.x, sh, nullptr);
 }
 
-// Act kernel of worlds with the paper's network.  Compiled for four waves per
-// SIMD: the compiler's own choice (about 185 registers, two waves) leaves the
-// load round trip of each wave exposed; four waves measured about 20% faster.
-// Five or more spill registers holding loads of the first round trip, and
-// each such spill waits for its load, which splits the round trip.
+// Act kernels of worlds with the paper's network.  The compiler's own
+// register choice (about 185, two waves per SIMD) leaves the load round trip
+// of each wave exposed; four waves measured about 20% faster.  Four waves per
+// SIMD hold 16 waves per CU, one agent each: a launch with more agents runs
+// the rest as a second round, so such launches use the kernels compiled for
+// five waves (96 registers, none spilled; 29.7 against 31.5 us per step with
+// 4608 agents), while smaller ones keep four (five cost 0.1 to 0.3 us per step
+// with 1000 agents).  A spill of a register that holds a load of the first
+// round trip waits for that load and splits the round trip: six waves spill
+// and are slower.
+#ifndef ECO_NET_WAVES_WIDE
+#define ECO_NET_WAVES_WIDE 5
+#endif
 #ifndef ECO_NET_WAVES
 #define ECO_NET_WAVES 4   // waves per SIMD the network act kernel is compiled for (0 = compiler's choice)
 #endif
@@ -321,6 +333,22 @@ void k_act_net_paper(Batch bt) {
     __shared__ StepShared sh;
     __shared__ net::WaveLds lds[kBlock / 64];
     act_body<16, true, true>(bt, blockIdx.x, threadIdx.x, sh, lds);
+}
+
+// The same two kernels for launches with more agents than four waves per
+// SIMD hold.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(ECO_NET_WAVES_WIDE, ECO_NET_WAVES_WIDE)))
+void k_act_net_wide(Batch bt) {
+    __shared__ StepShared sh;
+    __shared__ net::WaveLds lds[kBlock / 64];
+    act_body<16, true, false, true>(bt, blockIdx.x, threadIdx.x, sh, lds);
+}
+
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(ECO_NET_WAVES_WIDE, ECO_NET_WAVES_WIDE)))
+void k_act_net_paper_wide(Batch bt) {
+    __shared__ StepShared sh;
+    __shared__ net::WaveLds lds[kBlock / 64];
+    act_body<16, true, true, true>(bt, blockIdx.x, threadIdx.x, sh, lds);
 }
 
 // Creates the pending children of a world's last step now (before its state

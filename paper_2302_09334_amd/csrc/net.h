@@ -27,9 +27,15 @@
 //   pool2  lane = feature (72, two per lane for the last eight).
 //   LSTM   lane = (input group of 16, gate): float4 rows of the input kernel
 //          (each load instruction covers 1 KB of the genome contiguously),
-//          reduced over the input groups by an xor tree.
+//          reduced over the input groups by an xor tree; the recurrent term
+//          h_j Wh[j][gate][unit] on the four lanes of a (gate, unit), one j
+//          each, summed by two exchanges.
 //   dense  lane = (input group of 32, half of the 8 outputs), same scheme.
-//   head   lane = action (5 lanes), then the sampling draw on the same lanes.
+//   head   lane = (action, input) for 40 lanes, one weight each, summed over
+//          the 8 inputs by an xor tree; then lane = action (5 lanes) for the
+//          sampling draw.
+// Each lane holds only the weights it multiplies (no copies across lanes),
+// which keeps the kernel within 96 registers: five waves per SIMD.
 // The summation order of every value depends only on the agent, never on the
 // launch shape.
 #pragma once
@@ -175,7 +181,6 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
         // under the paper's dynamics occA holds the agents on the cell minus one
         px[m] = (paper && in && ob > 0) ? min(ob, 255) : 0;
     }
-    const float4 hv = *reinterpret_cast<const float4*>(hs);   // h (uniform)
     // conv1 weights of tap lane / 4, output channel lane % 4 (lanes < 36)
     const int l36 = min(lane, 35);
     const uint32_t o1 = uint32_t(kC1w + (l36 >> 2) * 3 * kF1 + (l36 & 3));
@@ -199,9 +204,11 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
         const int i = min(ig + 16 * m, kEmb - 1);
         wi[m] = *reinterpret_cast<const float4*>(th + uint32_t(kLwi + i * 16 + gq * 4));
     }
-    float whk[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) whk[j] = th[uint32_t(kLwh + j * 16 + gq * 4 + uk)];
+    // recurrent term: lane takes unit j = lane / 16 of h and its weight to
+    // (gate gq, unit uk); the four lanes of one (gq, uk) differ in j
+    const int jr = lane >> 4;
+    const float hj = hs[uint32_t(jr)];
+    const float whj = th[uint32_t(kLwh + jr * 16 + gq * 4 + uk)];
     const float lbk = th[uint32_t(kLb + gq * 4 + uk)];
     const float ck = hs[uint32_t(kHd + uk)];                      // c of unit uk
     // dense 8: rows ig8 + 32 m, outputs 4 hf .. 4 hf + 3; after the reduction
@@ -215,12 +222,11 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
         w8[m] = *reinterpret_cast<const float4*>(th + uint32_t(kD8w + i * kD + hf * 4));
     }
     const float b8 = th[uint32_t(kD8b + o8)];
-    // head: column a = lane (lanes < 5)
-    const int a5 = min(lane, kNA - 1);
-    float w5[kD];
-#pragma unroll
-    for (int o = 0; o < kD; ++o) w5[o] = th[uint32_t(kD5w + o * kNA + a5)];
-    const float b5 = th[uint32_t(kD5b + a5)];
+    // head: lane = (action lane / 8, input lane % 8) for lanes < 40, one
+    // weight each; bias of action `lane` on lanes < 5
+    const int o5 = lane & 7;
+    const float w5j = th[uint32_t(kD5w + o5 * kNA + min(lane >> 3, kNA - 1))];
+    const float b5 = th[uint32_t(kD5b + min(lane, kNA - 1))];
     // complete the loads here, so that none is moved into a branch that uses
     // it (which would add a dependent round trip)
 #pragma unroll
@@ -376,10 +382,9 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
             acc = fma4(e, wi[m], acc);
         }
         float z = reduce_scatter4<2>(acc, lane);
-        float rec = hv.x * whk[0];
-        rec = fmaf(hv.y, whk[1], rec);
-        rec = fmaf(hv.z, whk[2], rec);
-        rec = fmaf(hv.w, whk[3], rec);
+        float rec = hj * whj;
+        rec += __shfl_xor(rec, 16);
+        rec += __shfl_xor(rec, 32);
         z = (z + rec) + lbk;
         // the four gates of unit uk sit in the lane's quad (gq = 0..3)
         const int q0 = lane & ~3;
@@ -405,10 +410,11 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
     wave_lds_sync();
 
     // ---- logits (lane a < 5) and the sampled action -----------------------------
-    float lg = 0.f;
-#pragma unroll
-    for (int o = 0; o < kD; ++o) lg = fmaf(L.u.late.y8[o], w5[o], lg);
-    lg = lg + b5;
+    float pl = L.u.late.y8[o5] * w5j;
+    pl += __shfl_xor(pl, 1);
+    pl += __shfl_xor(pl, 2);
+    pl += __shfl_xor(pl, 4);
+    const float lg = __shfl(pl, min(lane, kNA - 1) * 8) + b5;   // lanes < 5: logit of action `lane`
     // sampling score 50 l + g, g from word a % 4 of ACT block a / 4 (the
     // draws depend on the agent and the step only: scalar)
     const Draw4 d0 = philox(u, uint32_t(t), kAct, 0u, d.seed_lo, d.seed_hi);

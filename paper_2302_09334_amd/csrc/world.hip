@@ -249,6 +249,7 @@ struct world {
     struct {
         const WorldDev* const* w;
         const int* block_pre;
+        int slots;
     } tv;                  // single-world launch table (inside the arena)
     std::vector<int> host_bp;
     int max_useful = 1;
@@ -306,8 +307,10 @@ std::vector<int> batch_prefix(const std::vector<const world*>& ws) {
 // starts and ends (its execution time, without launch overhead).
 void launch_act(const Batch& b, int grid, hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr) {
     if (b.ctrl == kCtrlNet && b.dyn == kDynPaper)
-        hipExtLaunchKernelGGL(k_act_net_paper, dim3(grid), dim3(kBlock), 0, s, t0, t1, 0, b);
-    else if (b.ctrl == kCtrlNet) hipExtLaunchKernelGGL(k_act_net, dim3(grid), dim3(kBlock), 0, s, t0, t1, 0, b);
+        hipExtLaunchKernelGGL(b.net_wide ? k_act_net_paper_wide : k_act_net_paper, dim3(grid), dim3(kBlock), 0, s,
+                              t0, t1, 0, b);
+    else if (b.ctrl == kCtrlNet)
+        hipExtLaunchKernelGGL(b.net_wide ? k_act_net_wide : k_act_net, dim3(grid), dim3(kBlock), 0, s, t0, t1, 0, b);
     else if (b.act_rows == 8) hipExtLaunchKernelGGL(k_act_rows<8>, dim3(grid), dim3(kBlock), 0, s, t0, t1, 0, b);
     else if (b.act_rows == 32) hipExtLaunchKernelGGL(k_act_rows<32>, dim3(grid), dim3(kBlock), 0, s, t0, t1, 0, b);
     else hipExtLaunchKernelGGL(k_act, dim3(grid), dim3(kBlock), 0, s, t0, t1, 0, b);
@@ -339,6 +342,10 @@ int device_cus() {
     return cus;
 }
 
+// Whether a launch over `slots` agent slots in all uses the network act
+// kernels compiled for five waves per SIMD: at four, a CU holds 16 agent waves.
+int net_wide(int slots) { return slots > 16 * device_cus() ? 1 : 0; }
+
 int check_device_error(world* w) {
     WorldScal sc;
     HIP_TRY(w, hipMemcpyAsync(&sc, w->base + w->lay.scal, sizeof(sc), hipMemcpyDeviceToHost, w->stream));
@@ -365,6 +372,7 @@ int wall_rate_khz() {
 struct TableView {
     const WorldDev* const* w;
     const int* block_pre;
+    int slots = 0;   // agent slots of all worlds of the batch
 };
 
 size_t table_bytes(int n) { return align_up(sizeof(void*) * size_t(n), 16) + sizeof(int) * size_t(kPreKinds) * (n + 1); }
@@ -373,6 +381,8 @@ std::vector<char> build_table(const std::vector<const world*>& ws, char* dev_bas
                               std::vector<int>* host_block_pre, int* max_useful) {
     const int n = int(ws.size());
     const std::vector<int> bp = batch_prefix(ws);
+    view->slots = 0;
+    for (const world* x : ws) view->slots += x->cfg.cap;
     int useful = 1;
     for (int k = 0; k < kPreKinds; ++k) useful = std::max(useful, bp[size_t(k) * (n + 1) + n]);
     const size_t ptr_bytes = align_up(sizeof(void*) * size_t(n), 16);
@@ -394,7 +404,7 @@ int run_steps(world* w0, int mode, const TableView& tv, const std::vector<int>& 
               int K, std::map<int, hipGraphExec_t>& graphs, std::map<int, hipGraph_t>& defs) {
     hipStream_t s = w0->stream;
     Batch b{tv.w, tv.block_pre, n, w0->act_rows, n == 1 ? static_cast<const WorldDev*>(w0->d_dev) : nullptr,
-            w0->cfg.cap, w0->dev.ctrl, w0->dev.dyn};
+            w0->cfg.cap, w0->dev.ctrl, w0->dev.dyn, net_wide(tv.slots)};
     if (mode == WORLD_MODE_KERNELS) {
         for (int k = 0; k < K; ++k) HIP_TRY(w0, launch_step(b, host_bp.data(), n, s));
         return WORLD_OK;
@@ -578,6 +588,7 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
     const std::vector<char> table = build_table(one, b + lay.batch, &tv, &w->host_bp, &w->max_useful);
     w->tv.w = tv.w;
     w->tv.block_pre = tv.block_pre;
+    w->tv.slots = tv.slots;
 
     hipStream_t s = w->stream;
     auto up = [&](size_t off, const void* src, size_t bytes) {
@@ -668,7 +679,10 @@ int world_set_mode(world_t* w, int32_t mode) {
 }
 
 static int step_single(world* w, int K) {
-    TableView tv{w->tv.w, w->tv.block_pre};
+    TableView tv;
+    tv.w = w->tv.w;
+    tv.block_pre = w->tv.block_pre;
+    tv.slots = w->tv.slots;
     return run_steps(w, w->mode, tv, w->host_bp, 1, w->max_useful, K, w->graphs, w->graph_defs);
 }
 
@@ -1094,7 +1108,7 @@ int world_phase_times(world_t* w, int32_t K, float* ms) {
     const int np = 2;
     const int* hp = w->host_bp.data();
     Batch b{w->tv.w, w->tv.block_pre, 1, w->act_rows, static_cast<const WorldDev*>(w->d_dev), w->cfg.cap, w->dev.ctrl,
-            w->dev.dyn};
+            w->dev.dyn, net_wide(w->tv.slots)};
     hipStream_t s = w->stream;
     // each kernel between start / end events stamped by its own dispatch
     std::vector<hipEvent_t> ev(size_t(K) * 6);
