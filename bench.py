@@ -224,7 +224,9 @@ def net_run(args) -> dict:
         "kernels": {k: {"ms_per_launch": kms[k], "algorithmic_bytes": kbytes[k],
                         "GBps": kbytes[k] / (kms[k] * 1e-3) / 1e9} for k in kms},
         "roofline": {
-            "kernel": "k_act_net (observation, CNN, LSTM, dense layers, sampling; one wave per agent)",
+            "kernel": "k_act_net_wide (observation, CNN, LSTM, dense layers, sampling; one wave per agent; "
+                      "the network act kernel compiled for five waves per SIMD, used when a launch has more "
+                      "agent slots than four waves per SIMD hold)",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": read_traffic(src_hash, None, NET_TRAFFIC_FILE),
