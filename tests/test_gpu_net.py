@@ -71,9 +71,15 @@ def test_net_parity_fullsize(env):
 
 
 def test_net_graph_batch_resume(env):
+    # Each world alone has at most 16 agent slots per CU, so it runs the act
+    # kernel compiled for four waves per SIMD; together they exceed that and
+    # the batched launch runs the five-wave kernel: the results must not change.
     world, oracle, wl = env
     import torch
-    cfgs = [(net(wl), 5), (net(wl, H=64, W=128, cap=512, n_init=300), 6), (wl.WORKLOADS["net1k"], 7)]
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    cfgs = [(net(wl), 5), (net(wl, H=64, W=128, cap=512, n_init=300), 6), (wl.WORKLOADS["net1k"], 7),
+            (net(wl, H=100, W=200, cap=16 * cus, n_init=1500), 8)]
+    assert all(c["cap"] <= 16 * cus for c, _ in cfgs) and sum(c["cap"] for c, _ in cfgs) > 16 * cus
     say("[net systems] alone (kernels), alone (graph), batched")
     alone = {}
     for mode in ("kernels", "graph"):
