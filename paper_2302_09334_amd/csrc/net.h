@@ -166,20 +166,22 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
     const uint8_t* R = d.R[t & 1];
 
     // ---- one round trip: observation, state and every weight --------------
-    int pb[4], px[4];
-    constexpr bool paper = PAPER;
+    // (the bounds test with bitwise ands and the raw words kept until the
+    // loads complete below: a short-circuit test let the compiler put each
+    // pixel's loads in a branch of its own, which waited for them there, four
+    // round trips instead of one)
+    int rbv[4], obv[4];
+    bool inm[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         const int q = lane + 64 * m;
         const int iy = q / kWin, ix = q - (q / kWin) * kWin;
         const int rr = r + iy - kRho, cc = c + ix - kRho;
-        const bool in = q < kPix && rr >= 0 && rr < H && cc >= 0 && cc < W;
+        const bool in = (q < kPix) & (rr >= 0) & (rr < H) & (cc >= 0) & (cc < W);
         const uint32_t qc = uint32_t(in ? rr * W + cc : cell);   // every lane loads (clamped)
-        const int rb = R[qc];
-        const int ob = d.occA[qc];
-        pb[m] = in ? ((rb != 0 ? 1 : 0) | (ob != -1 ? 2 : 0)) : 4;
-        // under the paper's dynamics occA holds the agents on the cell minus one
-        px[m] = (paper && in && ob > 0) ? min(ob, 255) : 0;
+        rbv[m] = R[qc];
+        obv[m] = d.occA[qc];
+        inm[m] = in;
     }
     // conv1 weights of tap lane / 4, output channel lane % 4 (lanes < 36)
     const int l36 = min(lane, 35);
@@ -230,7 +232,18 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
     // complete the loads here, so that none is moved into a branch that uses
     // it (which would add a dependent round trip)
 #pragma unroll
-    for (int m = 0; m < 4; ++m) pin(pb[m]);
+    for (int m = 0; m < 4; ++m) {
+        pin(rbv[m]);
+        pin(obv[m]);
+    }
+    int pb[4], px[4];
+    constexpr bool paper = PAPER;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        pb[m] = inm[m] ? ((rbv[m] != 0 ? 1 : 0) | (obv[m] != -1 ? 2 : 0)) : 4;
+        // under the paper's dynamics occA holds the agents on the cell minus one
+        px[m] = (paper && inm[m] && obv[m] > 0) ? min(obv[m], 255) : 0;
+    }
     pinf(w1r);
     pinf(w1a);
     pinf(w1w);
