@@ -31,12 +31,19 @@ Also reported:
 * ``paper_network``: the same 200 x 400 world with ~4k agents driven by the
   paper's controller (App. B.5: CNN + LSTM(4), 2445 parameters, sampled
   actions; workload ``net_m1_4k``): wall-clock agent-steps/s, per-kernel
-  event times, and the act kernel (k_act_net) against the HBM roofline with
-  its algorithmic bytes and flops per agent.
+  event times, and the act kernel (k_act_net_wide, the network act kernel
+  compiled for five waves per SIMD) against the HBM roofline with its
+  algorithmic bytes and flops per agent.
+* ``cache_exceeding``: the dense start of cfg2 (12k-16k agents, beyond the
+  last-level cache); ``batched``: 64 uneven worlds in shared launches,
+  autotuned, against the same worlds stepped one at a time; ``served``: the
+  continuous-batching server over a Poisson arrival trace, with p50/p99
+  per-step latency; ``ecology_metrics``: the App. C metrics over the timed
+  steps.
 * ``--only net|paper|lab`` runs one of these legs alone and prints it (for
   profiling).
 
-``--gpus N`` with N > 1 is refused: this build runs on one GPU.
+``--gpus N`` with N > 1 is refused: the benchmark runs on one GPU.
 """
 from __future__ import annotations
 
@@ -528,7 +535,7 @@ def main():
 
     world_size = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world_size != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.steps < 1 or args.steps > 8000:
