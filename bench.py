@@ -266,6 +266,7 @@ def cpu_baseline(cfg: dict, seed: int, seconds: float) -> dict:
             break
     ow.close()
     return {"value": acted / el, "unit": "agent-steps/s", "cores": 1, "kind": "oracle",
+            "host_cores": len(os.sched_getaffinity(0)),
             "sample": f"steps 0..{steps - 1} of the same workload from its seed ({acted} agent-steps, "
                       f"{el:.1f} s, plain C oracle, one thread; initialisation excluded)"}
 

@@ -70,3 +70,11 @@ def test_traffic_summary_tied_to_sources(bench, tmp_path):
     # the committed summaries carry a hash of the current sources or none at all
     h = bench.kernel_source_hash()
     assert len(h) == 16 and all(ch in "0123456789abcdef" for ch in h)
+
+
+def test_cpu_baseline_fields(bench, oracle_lib):
+    from paper_2302_09334_amd import workloads
+    out = bench.cpu_baseline(workloads.WORKLOADS["cfg0"], 0, 0.2)
+    assert out["kind"] == "oracle" and out["cores"] == 1 and out["unit"] == "agent-steps/s"
+    assert out["value"] > 0 and 1 <= out["host_cores"] <= os.cpu_count()
+    assert "steps 0.." in out["sample"]
