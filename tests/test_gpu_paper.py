@@ -49,6 +49,32 @@ def test_paper_parity(env, case):
     assert st["agent_steps"] > 0 and st["births"] > 0 and st["deaths"] > 0
 
 
+NET = dict(obs_radius=7, hidden=4, controller=1, w_init_gain=1.0)
+EDGES = {
+    # no agents: the paper's regrowth alone
+    "empty": lambda wl: (paper(wl, H=30, W=50, cap=64, n_init=0, **NET), 60, 20),
+    # a grid smaller than the field of view with one agent: walls everywhere
+    "tiny": lambda wl: (paper(wl, H=2, W=1, cap=4, n_init=1, res_init_p=1.0, spont=1.0, T_repr=3, **NET), 40, 7),
+    # 20 cells, up to 64 agents stacked on them: the slot table binds every step
+    "crowded": lambda wl: (paper(wl, H=4, W=5, cap=64, n_init=20, res_init_p=1.0, spont=1.0, regrow_pI=1.0,
+                                 T_repr=3, L_max=40, **NET), 100, 25),
+    "crowded_gru": lambda wl: (paper(wl, H=4, W=5, cap=64, n_init=20, res_init_p=1.0, spont=1.0, regrow_pI=1.0,
+                                     T_repr=3, L_max=40), 100, 25),
+    # no food at all: every agent starves, then the world stays empty
+    "extinct": lambda wl: (paper(wl, H=12, W=20, cap=100, n_init=80, res_init_p=0.0, spont=0.0, regrow_pI=0.0,
+                                 T_death=4, E0=4, E_max=4, **NET), 60, 20),
+}
+
+
+@pytest.mark.parametrize("case", list(EDGES))
+def test_paper_edges(env, case):
+    world, oracle, wl = env
+    cfg, steps, K = EDGES[case](wl)
+    say(f"[paper edge] {case} steps={steps} K={K}")
+    st = run_parity(world.World, oracle.OracleWorld, oracle.OracleConfig, cfg, 5, steps, K, theta_every=1)
+    say(f"[paper edge] {case} ok {st}")
+
+
 def test_paper_stacks(env):
     world, oracle, wl = env
     w = world.World(paper(wl, obs_radius=7, hidden=4, controller=1, w_init_gain=1.0), 2)
