@@ -15,7 +15,10 @@ from dataclasses import dataclass
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# The planted-mistake test builds edited copies of the source on the side and
+# points a child process at them; otherwise these are the committed files.
+SRC_PATH = os.environ.get("ORACLE_SRC", os.path.join(HERE, "oracle.c"))
+LIB_PATH = os.environ.get("ORACLE_LIB", os.path.join(HERE, "liboracle.so"))
 
 
 def build(quiet: bool = True) -> str:
@@ -23,7 +26,7 @@ def build(quiet: bool = True) -> str:
     cmd = [
         "gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
         "-Wall", "-Wextra", "-Wno-unused-parameter",
-        os.path.join(HERE, "oracle.c"), "-o", LIB_PATH + ".tmp", "-lm",
+        SRC_PATH, "-o", LIB_PATH + ".tmp", "-lm",
     ]
     subprocess.run(cmd, check=True, capture_output=quiet)
     os.replace(LIB_PATH + ".tmp", LIB_PATH)

@@ -100,6 +100,53 @@ def test_first_birth_after_t_repr(oracle_lib):
     assert w.next_uid == 2
 
 
+def test_child_direction_uniform(oracle_lib):
+    """A lone interior parent's child lands on each of its four neighbours
+    equally often over seeds (the start of the neighbour scan is random)."""
+    counts = {(-1, 0): 0, (1, 0): 0, (0, 1): 0, (0, -1): 0}
+    for seed in range(800):
+        cfg = tiny_cfg(oracle_lib, H=9, W=9, n_init=1, cap=2, E_repr=0, T_repr=1)
+        w = oracle_lib.OracleWorld(cfg, seed)
+        w.set_forced(None, default=4)
+        p = w.agents()
+        info = w.step()
+        assert info["births"] == 1
+        if 1 <= p["row"][0] <= 7 and 1 <= p["col"][0] <= 7:
+            a = w.agents()
+            counts[(int(a["row"][1] - a["row"][0]), int(a["col"][1] - a["col"][0]))] += 1
+        w.close()
+    obs = np.array(list(counts.values()))
+    assert obs.sum() > 400
+    assert stats.chisquare(obs).pvalue > 1e-4, counts
+
+
+@pytest.mark.parametrize("free", range(4))
+def test_child_takes_the_only_free_neighbour(oracle_lib, free):
+    """Three neighbours held by agents that cannot reproduce (energy below
+    E_repr): over many seeds the child always takes the fourth."""
+    nbr = [(-1, 0), (1, 0), (0, 1), (0, -1)]
+    for seed in range(40):
+        cfg = tiny_cfg(oracle_lib, H=5, W=5, n_init=4, cap=5, E_repr=40, T_repr=1)
+        w = oracle_lib.OracleWorld(cfg, seed)
+        w.set_forced(None, default=4)
+        s = w.state(with_hidden=True, with_theta=True)
+        rows, cols = [2], [2]
+        for k, (dr, dc) in enumerate(nbr):
+            if k != free:
+                rows.append(2 + dr)
+                cols.append(2 + dc)
+        s["row"] = np.array(rows, np.int32)
+        s["col"] = np.array(cols, np.int32)
+        s["energy"] = np.array([50, 10, 10, 10], np.int32)
+        s["streak"] = np.zeros(4, np.int32)
+        w.load(s)
+        info = w.step()
+        assert info["births"] == 1 and info["deaths"] == 0
+        a = w.agents()
+        assert (int(a["row"][4]), int(a["col"][4])) == (2 + nbr[free][0], 2 + nbr[free][1]), seed
+        w.close()
+
+
 def test_full_world_keeps_streak(oracle_lib):
     cfg = tiny_cfg(oracle_lib, H=5, W=5, n_init=1, cap=1, decay=1, gain=10, res_init_p=1.0,
                    spont=1.0, E_repr=40, T_repr=20)
