@@ -313,11 +313,16 @@ def hbm_honest_run(args, rows: int) -> dict:
            "kernel_ms": {"act": float(ph[0]), "move": float(ph[1]), "claim": float(ph[2])},
            "act_GBps": act_b / (float(ph[0]) * 1e-3) / 1e9, "move_GBps": move_b / (float(ph[1]) * 1e-3) / 1e9,
            "claim_GBps": claim_b / (float(ph[2]) * 1e-3) / 1e9,
-           "step_algorithmic_MB": (act_b + move_b + claim_b) / 1e6}
+           "act_algorithmic_MB_per_launch": act_b / 1e6, "step_algorithmic_MB": (act_b + move_b + claim_b) / 1e6}
     log(f"[bench] cfg2 (cache-exceeding, {n:.0f} agents): {out['agent_steps_per_s'] / 1e6:.1f} M agent-steps/s, "
         f"{out['ms_per_step'] * 1e3:.1f} us/step, act {out['act_GBps']:.0f} GB/s, move {out['move_GBps']:.0f} GB/s, "
         f"claim {out['claim_GBps']:.0f} GB/s")
     return out
+
+
+# Act rows per round trip of the cache-exceeding leg when it runs alone (the
+# calibration of the main leg picks this value at 200 x 400).
+ONLY_M2_ROWS = 8
 
 
 def batched_run(args) -> dict:
@@ -525,7 +530,7 @@ def main():
     ap.add_argument("--net-steps", type=int, default=500, help="timed steps of the paper-network world (0 = skip)")
     ap.add_argument("--net-warmup", type=int, default=300)
     ap.add_argument("--net-phase-steps", type=int, default=100)
-    ap.add_argument("--only", choices=["net", "paper", "lab"], help="run only this leg and print it")
+    ap.add_argument("--only", choices=["net", "paper", "lab", "m2"], help="run only this leg and print it")
     ap.add_argument("--paper-steps", type=int, default=2000, help="timed steps of the paper-dynamics world (0 = skip)")
     ap.add_argument("--paper-warmup", type=int, default=1000)
     ap.add_argument("--lab-agents", type=int, default=50, help="evolved agents of the lab leg (0 = skip)")
@@ -546,7 +551,8 @@ def main():
     from paper_2302_09334_amd import workloads, world
 
     if args.only:
-        leg = {"net": ("paper_network", net_run), "paper": ("paper_dynamics", paper_run), "lab": ("lab", lab_run)}
+        leg = {"net": ("paper_network", net_run), "paper": ("paper_dynamics", paper_run), "lab": ("lab", lab_run),
+               "m2": ("cache_exceeding", lambda a: hbm_honest_run(a, ONLY_M2_ROWS))}
         name, fn = leg[args.only]
         out = fn(args)
         if args.calib_copy:
