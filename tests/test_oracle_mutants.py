@@ -38,6 +38,7 @@ MUTANTS = {
     "gru_update_convention": ("(1.0 - z) * n + z * (double)h[k]", "z * n + (1.0 - z) * (double)h[k]", 1, (GRU,)),
     "gru_w_hh_transposed": ("th[L.hh + (j * hd + k) * 3 + g]", "th[L.hh + (k * hd + j) * 3 + g]", 1, (GRU,)),
     "gru_head_bias_dropped": ("double s = (double)th[L.bo + a];", "double s = 0.0;", 1, (GRU,)),
+    "init_biases_random": ("else if (p < L->wo) std = 0.0f;", "else if (p < L->wo) std = std_hd;", 1, (GRU,)),
     "init_std_over_fan_in": ("float std_ih = (float)(w->cfg.w_init_gain / sqrt((double)L->n_in));",
                              "float std_ih = (float)(w->cfg.w_init_gain / (double)L->n_in);", 1, (GRU,)),
     # observation
@@ -45,6 +46,8 @@ MUTANTS = {
                                   (GRU,)),
     "observe_outside_free": ("                x[win * win + k] = 1.0;", "                x[win * win + k] = 0.0;", 1,
                              (GRU,)),
+    "observe_own_cell_free": ("x[win * win + k] = (w->cnt[r * W + c] > 0) ? 1.0 : 0.0;",
+                              "x[win * win + k] = (w->cnt[r * W + c] > 0 && (dy || dx)) ? 1.0 : 0.0;", 1, (GRU,)),
     "observe_energy_scale": ("x[2 * win * win] = (double)w->e[a] / (double)w->cfg.E0;",
                              "x[2 * win * win] = (double)w->e[a];", 1, (GRU,)),
     # the paper's network and its sampling
@@ -56,6 +59,7 @@ MUTANTS = {
                      "q1[(y * L.p1 + x) * CNN_F1 + ch] = s;", 1, (CNN,)),
     "lstm_input_forget_swapped": ("c_out[k] = fg * (double)c[k] + ig * gg;", "c_out[k] = ig * (double)c[k] + fg * gg;",
                                   1, (CNN,)),
+    "lstm_bias_dropped": ("double s = (double)th[L.lb + g * CNN_HD + k];", "double s = 0.0;", 1, (CNN,)),
     "dense8_reads_cell_state": ("cat[L.emb + k] = h_out[k];", "cat[L.emb + k] = c_out[k];", 1, (CNN,)),
     "ate_bit_dropped": ("emb[L.flat + CNN_NA] = ate ? 1.0 : 0.0;", "emb[L.flat + CNN_NA] = 0.0;", 1, (CNN,)),
     "temperature_inverted": ("float sc = 50.0f * lf[a];", "float sc = lf[a] / 50.0f;", 1, (CNN,)),
@@ -69,6 +73,8 @@ MUTANTS = {
     "streak_not_reset": ("            w->streak[a] = 0;\n            w->occ[w->claim[a]] = c;",
                          "            w->occ[w->claim[a]] = c;", 1, (DYN,)),
     "birth_start_direction": ("int d0 = (int)(rr[0] & 3u);", "int d0 = 0;", 1, (DYN,)),
+    "move_draw_stream": ("draw(w->seed, w->uid[a], t, ORACLE_S_MOVE, 0, rr);",
+                         "draw(w->seed, w->uid[a], t, ORACLE_S_BIRTH, 0, rr);", 1, (DYN,)),
     "child_energy": ("w->e[c] = cfg->E0;", "w->e[c] = w->e[a];", 2, (DYN,)),
     "mutation_keyed_by_parent": ("draw(w->seed, cu, t, ORACLE_S_MUTATE", "draw(w->seed, w->uid[a], t, ORACLE_S_MUTATE",
                                  2, (DYN,)),
@@ -77,6 +83,8 @@ MUTANTS = {
     # regrowth
     "regrowth_latitude_flipped": ("double a = d * (double)row;", "double a = d * (double)(cfg->H - 1 - row);", 1,
                                   (REG,)),
+    "threshold_rounded_up": ("return (uint64_t)floor(p * 4294967296.0);", "return (uint64_t)ceil(p * 4294967296.0);",
+                             1, (REG,)),
     "regrowth_spontaneous_dropped": ("double p = q + cfg->spont;", "double p = q;", 1, (REG,)),
     "regrowth_neighbourhood_short": (
         "for (int dy = -2; dy <= 2; ++dy)\n                    for (int dx = -2; dx <= 2; ++dx)",
@@ -87,11 +95,19 @@ MUTANTS = {
     # the paper's dynamics
     "paper_climate_flipped": ("double x = (double)row / (double)(cfg->H - 1);",
                               "double x = 1.0 - (double)row / (double)(cfg->H - 1);", 1, (PAP,)),
+    "paper_climate_denominator": ("double x = (double)row / (double)(cfg->H - 1);",
+                                  "double x = (double)row / (double)cfg->H;", 1, (PAP,)),
     "paper_any_neighbour": ("double pI = (n == 1) ? cfg->regrow_pI : 0.0;",
                             "double pI = (n >= 1) ? cfg->regrow_pI : 0.0;", 1, (PAP,)),
     "paper_no_energy_clip": ("        if (e > cfg->E_max) e = cfg->E_max;\n", "", 1, (PAP,)),
     "paper_walls_block": ("            w->walldead[a] = 1;\n", "", 1, (PAP,)),
     "paper_death_streak_bound": ("(-s >= cfg->T_death)", "(-s > cfg->T_death)", 1, (PAP,)),
+    "paper_agent_channel_binary": ("px[1] = (double)w->cnt[r * W + c];", "px[1] = w->cnt[r * W + c] > 0 ? 1.0 : 0.0;",
+                                   1, (PAP,)),
+    "paper_eat_draw_stream": ("draw(w->seed, w->uid[a], t, ORACLE_S_EAT, 0, rr);",
+                              "draw(w->seed, w->uid[a], t, ORACLE_S_MOVE, 0, rr);", 1, (PAP,)),
+    "paper_wall_dead_eats": ("        if (w->walldead[a]) continue;\n", "", 1, (PAP,)),
+    "paper_dead_age_off_by_one": ("inf->dead_age += w->age[a];", "inf->dead_age += w->age[a] - 1;", 1, (PAP, MET)),
     "paper_parent_streak_kept": ("        w->streak[a] = 0;\n        w->n++;", "        w->n++;", 1, (PAP,)),
     # ecology metrics and the lab's greediness
     "move_metric_chebyshev": ("int dist = abs(w->row[a] - w->wrow[a]) + abs(w->col[a] - w->wcol[a]);",

@@ -148,6 +148,42 @@ def test_wall_kills(oracle_lib):
     assert infos[0]["deaths"] == 0 and ow.agents()["row"][0] == 4
 
 
+def test_wall_death_eats_nothing(oracle_lib):
+    # an agent on a resource cell that walks into the wall dies where it stood
+    # and eats nothing: the resource stays (regrowth off)
+    R = np.zeros((20, 20), np.uint8)
+    R[0, 5] = 1
+    ow, infos = run_alone(oracle_lib, 1, R, pos=(0, 5), forced=0, spont=0.0, regrow_pI=0.0)
+    assert infos[0]["deaths"] == 1 and infos[0]["eaten"] == 0
+    assert ow.grid()[0, 5] == 1
+    # the same cell with a staying agent: it eats the resource
+    ow, infos = run_alone(oracle_lib, 1, R, pos=(0, 5), forced=4, spont=0.0, regrow_pI=0.0)
+    assert infos[0]["eaten"] == 1 and ow.grid()[0, 5] == 0
+
+
+def test_climate_thresholds_high_precision(oracle_lib):
+    # floor(2^32 p), p = p_I c(x) + c, c(x) = (alpha^x + 1) / (alpha + 1),
+    # x = row / (H - 1), for one resource neighbour (p_I on) and for two (off),
+    # recomputed in 50-digit decimal arithmetic from the same doubles; the
+    # double computation may differ by one only where 2^32 p lies within a
+    # hair of the integer between the two results
+    from decimal import Decimal, getcontext
+    getcontext().prec = 50
+    for H, pI, alpha, spont in ((200, 0.002, 200.0, 5e-5), (7, 0.9, 3.5, 0.01), (33, 0.25, 1000.0, 0.0)):
+        cfg = paper_cfg(oracle_lib, H=H, regrow_pI=pI, regrow_alpha=alpha, spont=spont)
+        tab = oracle_lib.threshold_table(cfg)
+        a, c, p1 = Decimal(alpha), Decimal(spont), Decimal(pI)
+        for row in range(H):
+            x = Decimal(row) / Decimal(H - 1)
+            cx = (a ** x + 1) / (a + 1)
+            for n, pin in ((1, p1), (2, Decimal(0))):
+                real = (pin * cx + c) * Decimal(2 ** 32)
+                ex = min(int(real), 2 ** 32) if real > 0 else 0
+                got = int(tab[row, n])
+                if got != ex:
+                    assert abs(got - ex) == 1 and abs(real - max(got, ex)) < Decimal("1e-4"), (H, row, n, got, ex)
+
+
 def test_stacked_agents_one_eater(oracle_lib):
     # three agents step onto one resource cell: they stack, the smallest
     # (EAT draw, uid) eats (EAT = stream 9 of the pinned Philox)
