@@ -100,6 +100,22 @@ def test_first_birth_after_t_repr(oracle_lib):
     assert w.next_uid == 2
 
 
+def test_streak_counts_energy_at_the_threshold(oracle_lib):
+    """The minimal criterion counts steps with energy at or above E_repr: an
+    agent held exactly at E_repr has its first child after T_repr steps, one
+    held a unit below never has one."""
+    for e0, first in ((40, 4), (39, None)):
+        cfg = tiny_cfg(oracle_lib, H=7, W=7, n_init=1, cap=4, E0=e0, E_repr=40, T_repr=5)
+        w = oracle_lib.OracleWorld(cfg, 2)
+        w.set_forced(None, default=4)
+        births = [w.step()["births"] for _ in range(12)]
+        assert w.agents()["energy"][0] == e0
+        if first is None:
+            assert not any(births)
+        else:
+            assert births.index(1) == first and not any(births[:first])
+
+
 def test_child_direction_uniform(oracle_lib):
     """A lone interior parent's child lands on each of its four neighbours
     equally often over seeds (the start of the neighbour scan is random)."""

@@ -29,6 +29,13 @@ MUTANTS = {
     # random primitives
     "philox_nine_rounds": ("round < 10; ++round", "round < 9; ++round", 1, (GOLD, RNG)),
     "philox_weyl_constant": ("k1 += 0xBB67AE85u;", "k1 += 0xBB67AE87u;", 1, (GOLD, RNG)),
+    "counter_entity_step_swapped": ("philox_block(entity, step, stream, block, (uint32_t)seed, (uint32_t)(seed >> 32), out);",
+                                    "philox_block(step, entity, stream, block, (uint32_t)seed, (uint32_t)(seed >> 32), out);",
+                                    1, (DYN,)),
+    "ln_series_coefficient": ("p = fmaf(p, s2, 1.0f / 5.0f);", "p = fmaf(p, s2, 1.0f / 6.0f);", 1, (RNG,)),
+    "cos_series_sign": ("p = fmaf(p, x2, -1.0f / 720.0f);", "p = fmaf(p, x2, 1.0f / 720.0f);", 1, (RNG,)),
+    "quadrant_rotation_sign": ("    case 1: *s_out = cf;  *c_out = -sf; break;", "    case 1: *s_out = cf;  *c_out = sf; break;",
+                               1, (RNG,)),
     "gauss_radius_without_2": ("sqrtf(-2.0f * ln_unit(u1))", "sqrtf(-ln_unit(u1))", 1, (RNG,)),
     "gauss_sin_cos_swapped": ("*z0 = r * c;\n    *z1 = r * s;", "*z0 = r * s;\n    *z1 = r * c;", 1, (RNG,)),
     "gumbel_sign": ("    return -ln_unit(e);", "    return ln_unit(e);", 1, (CNN,)),
@@ -37,6 +44,7 @@ MUTANTS = {
     "gru_reset_dropped": ("tanh(gi[2] + r * gh[2])", "tanh(gi[2] + gh[2])", 1, (GRU,)),
     "gru_update_convention": ("(1.0 - z) * n + z * (double)h[k]", "z * n + (1.0 - z) * (double)h[k]", 1, (GRU,)),
     "gru_w_hh_transposed": ("th[L.hh + (j * hd + k) * 3 + g]", "th[L.hh + (k * hd + j) * 3 + g]", 1, (GRU,)),
+    "gru_update_gate_copy": ("double z = sigmoid(gi[1] + gh[1]);", "double z = sigmoid(gi[0] + gh[0]);", 1, (GRU,)),
     "gru_head_bias_dropped": ("double s = (double)th[L.bo + a];", "double s = 0.0;", 1, (GRU,)),
     "init_biases_random": ("else if (p < L->wo) std = 0.0f;", "else if (p < L->wo) std = std_hd;", 1, (GRU,)),
     "init_std_over_fan_in": ("float std_ih = (float)(w->cfg.w_init_gain / sqrt((double)L->n_in));",
@@ -55,6 +63,12 @@ MUTANTS = {
                               "th[L.c1w + ((kx * CNN_K + ky) * CNN_CH + ci) * CNN_F1 + co]", 1, (CNN,)),
     "cnn_padding_dropped": ("int iy = oy * CNN_S + ky - L.pad1, ix = ox * CNN_S + kx - L.pad1;",
                             "int iy = oy * CNN_S + ky, ix = ox * CNN_S + kx;", 1, (CNN,)),
+    "cnn_conv2_padding_dropped": ("int iy = oy * CNN_S + ky - L.pad2, ix = ox * CNN_S + kx - L.pad2;",
+                                  "int iy = oy * CNN_S + ky, ix = ox * CNN_S + kx;", 1, (CNN,)),
+    "observe_cnn_channels_swapped": ("px[0] = w->R[r * W + c] ? 1.0 : 0.0;", "px[1] = w->R[r * W + c] ? 1.0 : 0.0;", 1,
+                                     (CNN,)),
+    "sampling_fifth_word_reused": ("float g = gumbel_of_word(a < 4 ? r0[a] : r1[a - 4]);",
+                                   "float g = gumbel_of_word(r0[a % 4]);", 1, (CNN,)),
     "cnn_pool_sum": ("q1[(y * L.p1 + x) * CNN_F1 + ch] = s / (double)(CNN_POOL * CNN_POOL);",
                      "q1[(y * L.p1 + x) * CNN_F1 + ch] = s;", 1, (CNN,)),
     "lstm_input_forget_swapped": ("c_out[k] = fg * (double)c[k] + ig * gg;", "c_out[k] = ig * (double)c[k] + fg * gg;",
@@ -72,6 +86,9 @@ MUTANTS = {
     "death_energy_bound": ("(w->e[a] <= 0)", "(w->e[a] < 0)", 1, (DYN,)),
     "streak_not_reset": ("            w->streak[a] = 0;\n            w->occ[w->claim[a]] = c;",
                          "            w->occ[w->claim[a]] = c;", 1, (DYN,)),
+    "streak_strict_threshold": ("w->streak[a] = (w->e[a] >= cfg->E_repr) ? w->streak[a] + 1 : 0;",
+                                "w->streak[a] = (w->e[a] > cfg->E_repr) ? w->streak[a] + 1 : 0;", 1, (DYN,)),
+    "child_in_current_window": ("w->wvalid[c] = 0;   /* not alive", "w->wvalid[c] = 1;   /* not alive", 1, (MET,)),
     "birth_start_direction": ("int d0 = (int)(rr[0] & 3u);", "int d0 = 0;", 1, (DYN,)),
     "move_draw_stream": ("draw(w->seed, w->uid[a], t, ORACLE_S_MOVE, 0, rr);",
                          "draw(w->seed, w->uid[a], t, ORACLE_S_BIRTH, 0, rr);", 1, (DYN,)),
@@ -108,6 +125,11 @@ MUTANTS = {
                               "draw(w->seed, w->uid[a], t, ORACLE_S_MOVE, 0, rr);", 1, (PAP,)),
     "paper_wall_dead_eats": ("        if (w->walldead[a]) continue;\n", "", 1, (PAP,)),
     "paper_dead_age_off_by_one": ("inf->dead_age += w->age[a];", "inf->dead_age += w->age[a] - 1;", 1, (PAP, MET)),
+    "paper_streak_at_threshold": ("if (e > cfg->E_repr) s = (s > 0 ? s : 0) + 1;",
+                                  "if (e >= cfg->E_repr) s = (s > 0 ? s : 0) + 1;", 1, (PAP,)),
+    "paper_death_at_threshold": ("else if (e < cfg->E_repr) s = (s < 0 ? s : 0) - 1;",
+                                 "else if (e <= cfg->E_repr) s = (s < 0 ? s : 0) - 1;", 1, (PAP,)),
+    "paper_age_bound": ("(w->age[a] > cfg->L_max)", "(w->age[a] >= cfg->L_max)", 1, (PAP,)),
     "paper_parent_streak_kept": ("        w->streak[a] = 0;\n        w->n++;", "        w->n++;", 1, (PAP,)),
     # ecology metrics and the lab's greediness
     "move_metric_chebyshev": ("int dist = abs(w->row[a] - w->wrow[a]) + abs(w->col[a] - w->wcol[a]);",

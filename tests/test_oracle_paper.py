@@ -148,6 +148,22 @@ def test_wall_kills(oracle_lib):
     assert infos[0]["deaths"] == 0 and ow.agents()["row"][0] == 4
 
 
+def test_energy_at_the_threshold_counts_neither_way(oracle_lib):
+    # an agent held exactly at E_min = 0 (no decay, no food) neither progresses
+    # towards reproduction nor towards death: no child and no death however long
+    cfg = paper_cfg(oracle_lib, H=20, W=20, n_init=0, cap=8, decay=0, T_repr=3, T_death=3, spont=0.0,
+                    regrow_pI=0.0)
+    ow = oracle_lib.OracleWorld(cfg, 3)
+    im = image(ow, np.zeros((20, 20), np.uint8), [(10, 10)])
+    im["energy"][:] = 0
+    ow.load(im)
+    ow.set_forced(None, default=4)
+    infos = [ow.step() for _ in range(20)]
+    assert not any(i["births"] for i in infos) and not any(i["deaths"] for i in infos)
+    a = ow.agents()
+    assert a["energy"][0] == 0 and a["streak"][0] == 0
+
+
 def test_wall_death_eats_nothing(oracle_lib):
     # an agent on a resource cell that walks into the wall dies where it stood
     # and eats nothing: the resource stays (regrowth off)
