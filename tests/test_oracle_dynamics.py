@@ -116,6 +116,61 @@ def test_streak_counts_energy_at_the_threshold(oracle_lib):
             assert births.index(1) == first and not any(births[:first])
 
 
+@pytest.mark.parametrize("seed", [0, 11, 2**33 + 7])
+def test_initial_world_recomputed(oracle_lib, seed):
+    """The initial world from the pinned generator (streams as the simulator
+    numbers them: 1 initial resources, 2 placement): cell i holds a resource iff
+    its stream-1 word is below floor(p 2^32); the agents take the n_init cells of
+    smallest (stream-2 word, cell index), uids in that order."""
+    from oracle_ref import exact_threshold
+    H, W, n = 9, 13, 20
+    cfg = tiny_cfg(oracle_lib, H=H, W=W, n_init=n, cap=n, res_init_p=0.3)
+    w = oracle_lib.OracleWorld(cfg, seed)
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    ctr = np.zeros((H * W, 4), np.uint32)
+    ctr[:, 0] = np.arange(H * W)
+    ctr[:, 2] = 1
+    res = oracle_lib.philox(ctr, key)[:, 0]
+    thr = exact_threshold(dict(rate_bottom=0.0, rate_top=0.0, rate_scale=1.0, spont=0.3, H=2), 0, 0)
+    assert np.array_equal(w.grid().ravel(), (res.astype(np.uint64) < thr).astype(np.uint8))
+    ctr[:, 2] = 2
+    place = oracle_lib.philox(ctr, key)[:, 0]
+    order = sorted(range(H * W), key=lambda i: (int(place[i]), i))[:n]
+    a = w.agents()
+    assert list(a["uid"]) == list(range(n))
+    assert [int(r) * W + int(c) for r, c in zip(a["row"], a["col"])] == order
+
+
+def test_birth_claim_resolution(oracle_lib):
+    """Two eligible parents whose only free neighbour is the same cell: the
+    smaller (second word of the birth draw, uid) wins it (birth draw = stream 5
+    of the pinned generator at counter (uid, step, 5, 0)); the other keeps its
+    streak."""
+    wins = set()
+    for seed in range(30):
+        cfg = tiny_cfg(oracle_lib, H=3, W=3, n_init=8, cap=9, E_repr=40, T_repr=1)
+        w = oracle_lib.OracleWorld(cfg, seed)
+        w.set_forced(None, default=4)
+        s = w.state(with_hidden=True, with_theta=True)
+        cells = [(1, 0), (1, 2), (0, 0), (0, 1), (0, 2), (2, 0), (2, 1), (2, 2)]   # parents first
+        s["row"] = np.array([r for r, _ in cells], np.int32)
+        s["col"] = np.array([c for _, c in cells], np.int32)
+        s["energy"] = np.array([50, 50] + [10] * 6, np.int32)
+        s["streak"] = np.zeros(8, np.int32)
+        w.load(s)
+        info = w.step()
+        ctr = np.array([[0, 0, 5, 0], [1, 0, 5, 0]], np.uint32)
+        words = oracle_lib.philox(ctr, [seed, 0])[:, 1]
+        winner = int(np.argmin([(int(words[u]) << 32) | u for u in range(2)]))
+        wins.add(winner)
+        a = w.agents()
+        assert info["births"] == 1 and info["claim_wins"] == 1
+        assert (int(a["row"][8]), int(a["col"][8])) == (1, 1)
+        assert a["streak"][winner] == 0 and a["streak"][1 - winner] == 1
+        w.close()
+    assert wins == {0, 1}
+
+
 def test_child_direction_uniform(oracle_lib):
     """A lone interior parent's child lands on each of its four neighbours
     equally often over seeds (the start of the neighbour scan is random)."""

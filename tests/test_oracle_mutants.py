@@ -97,6 +97,13 @@ MUTANTS = {
                                  2, (DYN,)),
     "mutation_sigma_doubled": ("float sigma = (float)cfg->sigma_mut;", "float sigma = 2.0f * (float)cfg->sigma_mut;", 2,
                                (DYN,)),
+    # the initial world
+    "placement_highest_draws": ("uint32_t cell = (uint32_t)(keys[a] & 0xFFFFFFFFu);",
+                                "uint32_t cell = (uint32_t)(keys[HW - 1 - (size_t)a] & 0xFFFFFFFFu);", 1, (DYN, REG)),
+    "resources_from_placement_stream": ("draw(seed, (uint32_t)i, 0, ORACLE_S_INIT_RES, 0, r);",
+                                        "draw(seed, (uint32_t)i, 0, ORACLE_S_INIT_PLACE, 0, r);", 1, (DYN, REG)),
+    "birth_claim_same_word": ("uint64_t key = claim_key(rr[1], w->uid[a]);", "uint64_t key = claim_key(rr[0], w->uid[a]);",
+                              1, (DYN,)),
     # regrowth
     "regrowth_latitude_flipped": ("double a = d * (double)row;", "double a = d * (double)(cfg->H - 1 - row);", 1,
                                   (REG,)),
