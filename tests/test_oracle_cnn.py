@@ -90,6 +90,23 @@ def test_param_count_matches_paper(oracle_lib):
     assert (3 * 3 * 3 * 4 + 4) + (3 * 3 * 4 * 8 + 8) + (78 * 16 + 4 * 16 + 16) + (82 * 8 + 8) + (8 * 5 + 5) == P_PAPER
 
 
+def test_initial_genome_spread(oracle_lib):
+    """The initial genome of the paper's network: each weight layer N(0, gain^2
+    / fan_in) with fan_in 27 and 36 (the convolutions), 78 and 4 (the LSTM's
+    input and hidden kernels), 82 and 8 (the dense layers); every bias zero."""
+    from scipy import stats
+    gain = 0.7
+    w = oracle_lib.OracleWorld(cnn_cfg(oracle_lib, n_init=300, w_init_gain=gain), 9)
+    th = w.theta()
+    layers = [split_genome(t) for t in th]
+    for name, fan in (("c1w", 27), ("c2w", 36), ("wi", 78), ("wh", 4), ("d8w", 82), ("d5w", 8)):
+        v = np.concatenate([g[name].ravel() for g in layers]) / (gain / np.sqrt(fan))
+        assert stats.kstest(v, "norm").pvalue > 1e-3, name
+    for name in ("c1b", "c2b", "lb", "d8b", "d5b"):
+        assert not any(g[name].any() for g in layers), name
+    w.close()
+
+
 @pytest.mark.parametrize("trial", range(8))
 def test_forward_matches_torch(oracle_lib, trial):
     rng = np.random.default_rng(100 + trial)

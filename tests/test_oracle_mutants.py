@@ -45,6 +45,8 @@ MUTANTS = {
     "gru_update_convention": ("(1.0 - z) * n + z * (double)h[k]", "z * n + (1.0 - z) * (double)h[k]", 1, (GRU,)),
     "gru_w_hh_transposed": ("th[L.hh + (j * hd + k) * 3 + g]", "th[L.hh + (k * hd + j) * 3 + g]", 1, (GRU,)),
     "gru_update_gate_copy": ("double z = sigmoid(gi[1] + gh[1]);", "double z = sigmoid(gi[0] + gh[0]);", 1, (GRU,)),
+    "gru_head_transposed": ("s += (double)th[L.wo + a * hd + k] * h_out[k];", "s += (double)th[L.wo + k * 5 + a] * h_out[k];",
+                            1, (GRU,)),
     "gru_head_bias_dropped": ("double s = (double)th[L.bo + a];", "double s = 0.0;", 1, (GRU,)),
     "init_biases_random": ("else if (p < L->wo) std = 0.0f;", "else if (p < L->wo) std = std_hd;", 1, (GRU,)),
     "init_std_over_fan_in": ("float std_ih = (float)(w->cfg.w_init_gain / sqrt((double)L->n_in));",
@@ -76,6 +78,14 @@ MUTANTS = {
     "lstm_bias_dropped": ("double s = (double)th[L.lb + g * CNN_HD + k];", "double s = 0.0;", 1, (CNN,)),
     "dense8_reads_cell_state": ("cat[L.emb + k] = h_out[k];", "cat[L.emb + k] = c_out[k];", 1, (CNN,)),
     "ate_bit_dropped": ("emb[L.flat + CNN_NA] = ate ? 1.0 : 0.0;", "emb[L.flat + CNN_NA] = 0.0;", 1, (CNN,)),
+    "cnn_init_lstm_fan": ("else if (p < L.lb) fan = CNN_HD;", "else if (p < L.lb) fan = L.emb;", 1, (CNN,)),
+    "cnn_init_dense_fan": ("else if (p < L.d8b) fan = L.cat;", "else if (p < L.d8b) fan = CNN_D;", 1, (CNN,)),
+    "dense5_transposed": ("s += (double)th[L.d5w + o * CNN_NA + a] * y8[o];", "s += (double)th[L.d5w + a * CNN_D + o] * y8[o];",
+                          1, (CNN,)),
+    "dense8_without_tanh": ("y8[o] = tanh(s);", "y8[o] = s;", 1, (CNN,)),
+    "prev_action_one_hot_shifted": ("emb[L.flat + a] = (prev_action == a) ? 1.0 : 0.0;",
+                                    "emb[L.flat + a] = (prev_action == a + 1) ? 1.0 : 0.0;", 1, (CNN,)),
+    "prev_action_before_resync": ("w->pact[a] = act;", "w->pact[a] = best;", 1, (CNN,)),
     "temperature_inverted": ("float sc = 50.0f * lf[a];", "float sc = lf[a] / 50.0f;", 1, (CNN,)),
     "observe_cnn_wall_channel": ("                px[2] = 1.0;", "                px[2] = 0.0;", 1, (CNN,)),
     # benchmark dynamics
