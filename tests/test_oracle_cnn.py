@@ -243,12 +243,23 @@ def test_recurrent_inputs_and_state(oracle_lib):
     ri = ow.recurrent_inputs()
     assert np.all(ri["last_action"] == oracle_lib.NO_ACTION) and np.all(ri["ate"] == 0)
     assert np.all(ow.hidden() == 0) and ow.hidden().shape == (cfg.n_init, 8)
-    births = 0
-    for s in range(40):
+    births = deaths = 0
+    # 100 steps: births from step 8, deaths by starvation and age from step 50,
+    # so the survivors are compacted many times; each survivor's previous
+    # action, ate bit, streak and recurrent state must stay its own
+    for s in range(100):
         before = ow.agents()
         e0 = {int(u): int(e) for u, e in zip(before["uid"], before["energy"])}
+        k0 = {int(u): int(k) for u, k in zip(before["uid"], before["streak"])}
+        if s % 10 == 9:
+            ri0 = ow.recurrent_inputs()
+            hs0 = ow.hidden()
+            sample = {int(before["uid"][i]): (ow.obs_cnn(i), int(ri0["last_action"][i]), int(ri0["ate"][i]), hs0[i])
+                      for i in range(0, len(before["uid"]), 17)}
+            thetas = dict(zip((int(u) for u in before["uid"]), ow.theta()))
         info = ow.step()
         births += info["births"]
+        deaths += info["deaths"]
         last = ow.last_controller()
         acted = {int(u): int(x) for u, x in zip(last["uid"], last["action"])}
         after = ow.agents()
@@ -260,9 +271,20 @@ def test_recurrent_inputs_and_state(oracle_lib):
                 assert ri["last_action"][i] == acted[u]
                 ate = after["energy"][i] - e0[u] == cfg.gain - cfg.decay
                 assert ri["ate"][i] == int(ate)
+                # at or above E_repr the count goes on (or restarts at 0 with a
+                # birth, possible only once it has reached T_repr); below, 0
+                k = int(after["streak"][i])
+                if after["energy"][i] >= cfg.E_repr:
+                    assert k == k0[u] + 1 or (k == 0 and k0[u] + 1 >= cfg.T_repr), (s, u)
+                else:
+                    assert k == 0, (s, u)
+                if s % 10 == 9 and u in sample:
+                    obs, pa, at, h0 = sample[u]
+                    _, h1, c1, _ = torch_forward(thetas[u], obs, pa, at, h0[:4], h0[4:])
+                    assert np.abs(hs[i][:4] - h1).max() < 1e-6 and np.abs(hs[i][4:] - c1).max() < 1e-6, (s, u)
             else:   # born in this step
                 assert ri["last_action"][i] == oracle_lib.NO_ACTION and ri["ate"][i] == 0
                 assert np.all(hs[i] == 0)
-    assert births > 5
+    assert births > 5 and deaths > 50
     # sampled actions are not all the same
     assert len(set(acted.values())) > 1

@@ -114,6 +114,14 @@ MUTANTS = {
                                         "draw(seed, (uint32_t)i, 0, ORACLE_S_INIT_PLACE, 0, r);", 1, (DYN, REG)),
     "birth_claim_same_word": ("uint64_t key = claim_key(rr[1], w->uid[a]);", "uint64_t key = claim_key(rr[0], w->uid[a]);",
                               1, (DYN,)),
+    # compaction of the survivors (both rule sets)
+    "compaction_drops_previous_action": ("            w->pact[n_surv] = w->pact[a];\n", "", 2, (CNN, DYN, PAP)),
+    "compaction_drops_streak": ("            w->streak[n_surv] = w->streak[a];\n", "", 2, (CNN, DYN, PAP)),
+    "compaction_drops_window_start": ("            w->wrow[n_surv] = w->wrow[a];\n", "", 2, (MET,)),
+    "compaction_drops_ate_bit": ("            w->pate[n_surv] = w->pate[a];\n", "", 2, (CNN, DYN, PAP)),
+    "compaction_drops_hidden_state": (
+        "            memmove(w->h + (size_t)n_surv * hd, w->h + (size_t)a * hd, (size_t)hd * sizeof(float));\n", "", 2,
+        (GRU, CNN, DYN, PAP)),
     # regrowth
     "regrowth_latitude_flipped": ("double a = d * (double)row;", "double a = d * (double)(cfg->H - 1 - row);", 1,
                                   (REG,)),
