@@ -122,6 +122,11 @@ MUTANTS = {
     "compaction_drops_hidden_state": (
         "            memmove(w->h + (size_t)n_surv * hd, w->h + (size_t)a * hd, (size_t)hd * sizeof(float));\n", "", 2,
         (GRU, CNN, DYN, PAP)),
+    "compaction_drops_genome": (
+        "            memmove(w->theta + (size_t)n_surv * P, w->theta + (size_t)a * P, P * sizeof(float));\n", "", 2,
+        (GRU, CNN, DYN, PAP)),
+    "compaction_drops_age": ("            w->age[n_surv] = w->age[a];\n", "", 2, (CNN, DYN, PAP, MET)),
+    "compaction_drops_window_flag": ("            w->wvalid[n_surv] = w->wvalid[a];\n", "", 2, (MET,)),
     # regrowth
     "regrowth_latitude_flipped": ("double a = d * (double)row;", "double a = d * (double)(cfg->H - 1 - row);", 1,
                                   (REG,)),
