@@ -195,7 +195,7 @@ def results(tmp_path_factory):
     if shutil.which("gcc") is None:
         pytest.skip("no host C compiler")
     tmp = str(tmp_path_factory.mktemp("mutants"))
-    with ThreadPoolExecutor(max_workers=min(6, os.cpu_count() or 1)) as ex:
+    with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
         futs = {n: ex.submit(run_mutant, n, tmp) for n in MUTANTS}
         return {n: f.result() for n, f in futs.items()}
 
