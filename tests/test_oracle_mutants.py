@@ -127,6 +127,7 @@ MUTANTS = {
         (GRU, CNN, DYN, PAP)),
     "compaction_drops_age": ("            w->age[n_surv] = w->age[a];\n", "", 2, (CNN, DYN, PAP, MET)),
     "compaction_drops_window_flag": ("            w->wvalid[n_surv] = w->wvalid[a];\n", "", 2, (MET,)),
+    "slots_one_short": ("int free_slots = cfg->cap - w->n;", "int free_slots = cfg->cap - w->n - 1;", 2, (DYN, PAP)),
     # regrowth
     "regrowth_latitude_flipped": ("double a = d * (double)row;", "double a = d * (double)(cfg->H - 1 - row);", 1,
                                   (REG,)),
@@ -160,6 +161,8 @@ MUTANTS = {
     "paper_death_at_threshold": ("else if (e < cfg->E_repr) s = (s < 0 ? s : 0) - 1;",
                                  "else if (e <= cfg->E_repr) s = (s < 0 ? s : 0) - 1;", 1, (PAP,)),
     "paper_age_bound": ("(w->age[a] > cfg->L_max)", "(w->age[a] >= cfg->L_max)", 1, (PAP,)),
+    "paper_slots_one_short": ("    inf->claim_wins = n_elig;\n    int free_slots = cfg->cap - w->n;",
+                              "    inf->claim_wins = n_elig;\n    int free_slots = cfg->cap - w->n - 1;", 1, (PAP,)),
     "paper_parent_streak_kept": ("        w->streak[a] = 0;\n        w->n++;", "        w->n++;", 1, (PAP,)),
     # ecology metrics and the lab's greediness
     "move_metric_chebyshev": ("int dist = abs(w->row[a] - w->wrow[a]) + abs(w->col[a] - w->wcol[a]);",

@@ -164,6 +164,24 @@ def test_energy_at_the_threshold_counts_neither_way(oracle_lib):
     assert a["energy"][0] == 0 and a["streak"][0] == 0
 
 
+def test_births_fill_the_free_slots_in_uid_order(oracle_lib):
+    # three eligible agents stacked on one cell, two free slots: the first two
+    # (uid order) have a child on that cell, the third keeps its streak; with
+    # the table full, nobody has one
+    cfg = paper_cfg(oracle_lib, H=20, W=20, n_init=0, cap=5, decay=0, T_repr=1, spont=0.0, regrow_pI=0.0)
+    ow = oracle_lib.OracleWorld(cfg, 3)
+    ow.load(image(ow, np.zeros((20, 20), np.uint8), [(10, 10)] * 3))
+    ow.set_forced(None, default=4)
+    info = ow.step()
+    a = ow.agents()
+    assert info["births"] == 2 and ow.n_live == 5
+    assert list(a["uid"]) == [0, 1, 2, 3, 4]
+    assert all(a["row"] == 10) and all(a["col"] == 10)
+    assert list(a["streak"]) == [0, 0, 1, 0, 0]
+    info = ow.step()
+    assert info["births"] == 0 and ow.agents()["streak"][2] == 2
+
+
 def test_wall_death_eats_nothing(oracle_lib):
     # an agent on a resource cell that walks into the wall dies where it stood
     # and eats nothing: the resource stays (regrowth off)
