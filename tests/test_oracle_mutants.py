@@ -90,6 +90,11 @@ MUTANTS = {
     "observe_cnn_wall_channel": ("                px[2] = 1.0;", "                px[2] = 0.0;", 1, (CNN,)),
     # benchmark dynamics
     "move_into_occupied": ("            if (w->occ[cell] != -1) continue;\n", "", 1, (DYN,)),
+    "east_west_swapped": ("static const int DC[5] = {0, 0, 1, -1, 0};", "static const int DC[5] = {0, 0, -1, 1, 0};", 1,
+                          (DYN,)),
+    "moves_see_earlier_moves": ("            if (w->occ[cell] != -1) continue;\n            uint32_t rr[4];",
+                                "            if (w->occ[cell] != -1 || w->who[cell] != -1) continue;\n            uint32_t rr[4];",
+                                1, (DYN,)),
     "energy_decay_only_unfed": ("w->e[a] = w->e[a] - cfg->decay + cfg->gain * (int32_t)w->ate[a];",
                                 "w->e[a] = w->e[a] + (w->ate[a] ? cfg->gain : -cfg->decay);", 1, (DYN,)),
     "death_age_bound": ("(w->age[a] >= cfg->L_max)", "(w->age[a] > cfg->L_max)", 1, (DYN,)),
@@ -163,6 +168,7 @@ MUTANTS = {
     "paper_age_bound": ("(w->age[a] > cfg->L_max)", "(w->age[a] >= cfg->L_max)", 1, (PAP,)),
     "paper_slots_one_short": ("    inf->claim_wins = n_elig;\n    int free_slots = cfg->cap - w->n;",
                               "    inf->claim_wins = n_elig;\n    int free_slots = cfg->cap - w->n - 1;", 1, (PAP,)),
+    "paper_eat_without_resource": ("        if (!w->R[cell]) continue;\n", "", 1, (PAP,)),
     "paper_parent_streak_kept": ("        w->streak[a] = 0;\n        w->n++;", "        w->n++;", 1, (PAP,)),
     # ecology metrics and the lab's greediness
     "move_metric_chebyshev": ("int dist = abs(w->row[a] - w->wrow[a]) + abs(w->col[a] - w->wcol[a]);",
