@@ -141,6 +141,62 @@ CLAIM_BYTES_PER_AGENT = 32 + 8 + 4
 CLAIM_BYTES_PER_ELIGIBLE = 96 + 64
 
 
+def step_algorithmic_bytes(cfg: dict, P: int, acting, rows_read, births):
+    """Bytes one step must move (per step of a window; numpy arrays in, an
+    array out), counted as the benchmark definition's sparse-input form: per
+    acting agent the recurrent weights W_hh, both bias vectors, the head (W_o,
+    b_o), the hidden state in and out with about 40 bytes of scalars (8 hd +
+    40) and the energy input's row; the input rows the act phase actually read
+    (the device counts them: per binary window the rows of its ones, or its
+    column total and the rows of its zeros); the parent's genome read and the
+    child's written per birth; the grid (resource byte and occupancy word, in
+    and out)."""
+    hd = cfg["hidden"]
+    rw = 3 * hd * 4
+    per_agent = 3 * hd * hd * 4 + 2 * rw + (5 * hd + 5) * 4 + 8 * hd + 40 + rw
+    return (np.asarray(acting, np.float64) * per_agent + np.asarray(rows_read, np.float64) * rw
+            + np.asarray(births, np.float64) * 8 * P + cfg["H"] * cfg["W"] * 10)
+
+
+def kernel_window_bytes(cfg: dict, P: int, acting, rows_read, births_prev, deaths, claim_wins) -> dict:
+    """Algorithmic bytes per launch of each phase kernel, averaged over a
+    window (arrays per step): act = the children of the previous step (parent
+    genome in, child genome out) + per acting agent act_bytes_per_agent with
+    the rows it read + the grid once; move = its per-agent records + its share
+    of the recurrent projection; claim = the rest of the projection (the
+    survivors among those positions), its per-agent records, the
+    neighbourhood of each birth-claim winner, the grid's resource bytes."""
+    acting = np.asarray(acting, np.float64)
+    hd = cfg["hidden"]
+    rw = 3 * hd * 4
+    act = (acting * act_bytes_per_agent(cfg, 0.0) + np.asarray(rows_read, np.float64) * rw
+           + np.asarray(births_prev, np.float64) * 8 * P + cfg["H"] * cfg["W"] * 5)
+    pb = proj_bytes_per_agent(cfg)
+    move = acting * (MOVE_BYTES_PER_AGENT + PROJ_MOVE_SHARE * pb)
+    claim = ((1 - PROJ_MOVE_SHARE) * (acting - np.asarray(deaths, np.float64)) * pb + acting * CLAIM_BYTES_PER_AGENT
+             + np.asarray(claim_wins, np.float64) * CLAIM_BYTES_PER_ELIGIBLE + 2 * cfg["H"] * cfg["W"])
+    return {"act": float(act.mean()), "move": float(move.mean()), "claim": float(claim.mean())}
+
+
+def read_traffic_per_agent(src_hash: str, rows, path: str = TRAFFIC_FILE):
+    """HBM bytes per acting agent of the act kernel compiled for `rows` input
+    rows per round trip, from the committed counter summary (measured on the
+    same bench window), or None when the kernel sources changed since."""
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != src_hash:
+        return None
+    try:
+        return float(kv[f"hbm_bytes_per_acting_agent_rows{rows}"])
+    except (KeyError, ValueError):
+        return None
+
+
 def read_traffic(src_hash: str, rows, path: str = TRAFFIC_FILE):
     """HBM bytes per launch of the act kernel compiled for `rows` input rows
     per round trip (None: the network's act kernel), from the committed
@@ -333,21 +389,38 @@ def batched_run(args) -> dict:
     entries = workloads.batch_manifest(args.batch_worlds, seed=0)
     log(f"[bench] batched: {len(entries)} worlds, warm-up {args.batch_warmup}, timed {args.batch_steps}")
     b = batch.WorldBatch(entries, mode="graph")
-    b.step(args.batch_warmup)
+    if args.batch_warmup > 0:
+        b.step(args.batch_warmup)
     b.sync()
-    tuned = tune.autotune(b, trial_steps=100)
+    tuned = tune.autotune(b, trial_steps=100)   # restores the state it started from
     best = tuned["best"]
     log(f"[bench] batched autotune: {best}")
     K = best["K"]
     wall, chunk_ms = batch.time_chunks(b.step, args.batch_steps, K, b.stream)
     b.sync()
     agent_steps = b.acting_agents(args.batch_warmup, args.batch_steps)
+    # the batched launch against the HBM roofline: every world's step bytes
+    # over the window (its own counters), over the batch's wall time
+    from paper_2302_09334_amd import world as wmod
+    step_bytes = 0.0
+    for wd in b.worlds:
+        first = args.batch_warmup
+        c = wd.counters(first, args.batch_steps)
+        n0 = wd.counters(first - 1, 1)["n_live"][0] if first > 0 else wd.cfg["n_init"]
+        acting = np.concatenate([[n0], c["n_live"][:-1]])
+        step_bytes += float(step_algorithmic_bytes(wd.cfg, wmod.dims(wd.cfg)[1], acting, c["rows_read"],
+                                                   c["births"]).sum())
     n_agents = sum(w.snapshot()["n_live"] for w in b.worlds)
     b.close()
     seq = batch.run_sequential(entries, args.batch_warmup, args.batch_steps, 100, mode="graph")
+    gbps = step_bytes / wall / 1e9
     out = {"worlds": len(entries), "steps": args.batch_steps, "warmup": args.batch_warmup,
            "agent_steps_per_s": agent_steps / wall, "ms_per_step": wall / args.batch_steps * 1e3,
            "step_ms_p50": float(np.percentile(chunk_ms / K, 50)), "step_ms_p99": float(np.percentile(chunk_ms / K, 99)),
+           "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": gbps / HBM_PEAK_GBS,
+                        "basis": "all worlds' step algorithmic bytes (same formula as the headline's step_frac, "
+                                 "from each world's counters) over the batch's wall time"},
            "live_agents_end": int(n_agents), "tuned": best,
            "sequential_plain": {"agent_steps_per_s": seq["agent_steps_per_s"], "wall_s": seq["wall_s"]},
            "speedup_vs_sequential": (agent_steps / wall) / seq["agent_steps_per_s"]}
@@ -507,65 +580,31 @@ def copy_calibration(torch, world):
     log("[bench] copy calibration: 3 x 1 GiB device copies done")
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=1000)
-    ap.add_argument("--workload", default="m1_4k")
-    ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--mode", default="auto", choices=["auto", "kernels", "graph"])
-    ap.add_argument("--chunk", type=int, default=100, help="steps per world_step call")
-    ap.add_argument("--phase-steps", type=int, default=200, help="steps of the per-phase event pass")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--calib-copy", action="store_true",
-                    help="also run the plain copy kernel on 1 GiB (memory-counter calibration)")
-    ap.add_argument("--m2-steps", type=int, default=60, help="steps of the cache-exceeding cfg2 run (0 = skip)")
-    ap.add_argument("--batch-worlds", type=int, default=64, help="uneven worlds of the batched run (0 = skip)")
-    ap.add_argument("--batch-steps", type=int, default=400)
-    ap.add_argument("--batch-warmup", type=int, default=100)
-    ap.add_argument("--serve-seconds", type=float, default=20.0, help="arrival window of the served run (0 = skip)")
-    ap.add_argument("--serve-budget-gb", type=float, default=200.0)
-    ap.add_argument("--net-steps", type=int, default=500, help="timed steps of the paper-network world (0 = skip)")
-    ap.add_argument("--net-warmup", type=int, default=300)
-    ap.add_argument("--net-phase-steps", type=int, default=100)
-    ap.add_argument("--only", choices=["net", "paper", "lab", "m2"], help="run only this leg and print it")
-    ap.add_argument("--paper-steps", type=int, default=2000, help="timed steps of the paper-dynamics world (0 = skip)")
-    ap.add_argument("--paper-warmup", type=int, default=1000)
-    ap.add_argument("--lab-agents", type=int, default=50, help="evolved agents of the lab leg (0 = skip)")
-    ap.add_argument("--lab-trials", type=int, default=10)
-    ap.add_argument("--lab-evolve-steps", type=int, default=20000)
-    ap.add_argument("--lab-seq-sample", type=int, default=20)
-    args = ap.parse_args()
+# Steps from the seed that prepare the headline fixture's state (the M1-4k
+# workload: steps 0..999 are its warm-up, so that the population has turned
+# over, with births and deaths every step) before --warmup and --steps.
+FIXTURE_STEPS = 1000
+# The committed GPU parity tests compare m1_4k with the oracle over steps
+# 0..PARITY_STEPS_M1_4K - 1 in the timed launch configuration.
+PARITY_STEPS_M1_4K = 2200
 
-    world_size = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world_size != 1:
-        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1",
-                          "n_gpus": args.gpus}))
-        sys.exit(2)
-    if args.steps < 1 or args.steps > 8000:
-        sys.exit("--steps must be in 1..8000 (the per-step counter ring holds 8192 steps)")
 
+def headline_run(args) -> dict:
+    """The headline: m1_4k prepared by its 1000 fixture steps, --warmup more
+    untimed steps, then exactly --steps timed steps (graph launches of
+    --chunk steps, or per-phase kernels, whichever the calibration picked)
+    between two synchronisations; then the same steps again from the same
+    state as per-phase kernels with dispatch-stamped events (kernel times);
+    bytes from the window's own device counters."""
     import torch
     from paper_2302_09334_amd import workloads, world
-
-    if args.only:
-        leg = {"net": ("paper_network", net_run), "paper": ("paper_dynamics", paper_run), "lab": ("lab", lab_run),
-               "m2": ("cache_exceeding", lambda a: hbm_honest_run(a, ONLY_M2_ROWS))}
-        name, fn = leg[args.only]
-        out = fn(args)
-        if args.calib_copy:
-            copy_calibration(torch, world)
-        print(json.dumps({name: out}))
-        return
-
     cfg = workloads.WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(device=dev)
     w = world.World(cfg, args.seed, stream=stream, mode="graph")
+    P = w.n_params
     log(f"[bench] {args.workload}: H={cfg['H']} W={cfg['W']} cap={cfg['cap']} n_init={cfg['n_init']} "
-        f"hidden={cfg['hidden']} P={w.n_params}")
+        f"hidden={cfg['hidden']} P={P}")
 
     def run(nsteps, mode):
         w.set_mode(mode)
@@ -575,37 +614,39 @@ def main():
             w.step(k)
             done += k
 
-    # warm-up (graph mode; every mode reaches the same state)
-    run(args.warmup, "graph")
+    run(args.fixture_steps, "graph")
     w.sync()
-    start = w.snapshot(hidden=True, theta=True)
-    log(f"[bench] warm-up done: t={start['t']} n_live={start['n_live']}")
-
+    prep = w.snapshot(hidden=True, theta=True)
     # pick the launch mode and the act kernel's rows per round trip (both
-    # leave every result unchanged) on a short calibration from the same state
+    # leave every result unchanged) on 200 steps from the prepared state
     modes = ["graph", "kernels"] if args.mode == "auto" else [args.mode]
     calib = {}
     for m in modes:
-        for rows in (8, 16, 32):
+        for rows in ((8, 16, 32) if args.rows == 0 else (args.rows,)):
             w.set_tuning(rows)
-            w.load(start)
-            run(min(args.chunk, args.steps), m)   # capture / first launch
+            w.load(prep)
+            run(args.chunk, m)   # capture / first launch
             w.sync()
-            w.load(start)
-            n_cal = min(2 * args.chunk, args.steps)
+            w.load(prep)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            run(n_cal, m)
+            run(200, m)
             w.sync()
-            calib[f"{m}/rows{rows}"] = (time.perf_counter() - t0) / n_cal * 1e3
+            calib[f"{m}/rows{rows}"] = (time.perf_counter() - t0) / 200 * 1e3
             log(f"[bench] {m} rows {rows}: {calib[f'{m}/rows{rows}'] * 1e3:.1f} us/step")
     best_key = min(calib, key=calib.get)
     best, best_rows = best_key.split("/rows")[0], int(best_key.split("/rows")[1])
     w.set_tuning(best_rows)
+    w.load(prep)
+    run(args.warmup, "graph")
+    w.sync()
+    start = w.snapshot(hidden=True, theta=True)
+    t_first = start["t"]
+    log(f"[bench] fixture {args.fixture_steps} + warm-up {args.warmup} steps done: t={t_first} "
+        f"n_live={start['n_live']}")
 
     # the timed region: exactly K steps from the warmed-up state
-    w.load(start)
-    run(min(args.chunk, args.steps), best)
+    run(min(args.chunk, args.steps), best)   # graph capture outside the timed region
     w.sync()
     w.load(start)
     w.set_mode(best)
@@ -628,14 +669,13 @@ def main():
     chunk_ms = np.array([ev[j].elapsed_time(ev[j + 1]) for j in range(i)])
     chunk_steps = np.array([min(args.chunk, args.steps - j * args.chunk) for j in range(i)])
     per_step_ms = chunk_ms / chunk_steps
-    t_first = start["t"]
-    ctr_prev = w.counters(t_first - 1, 1)["n_live"][0] if t_first > 0 else start["n_live"]
+    prev = w.counters(t_first - 1, 1) if t_first > 0 else None
     ctr = w.counters(t_first, args.steps)
-    acting = np.concatenate([[ctr_prev], ctr["n_live"][:-1]])
+    n0 = int(prev["n_live"][0]) if prev is not None else int(start["n_live"])
+    acting = np.concatenate([[n0], ctr["n_live"][:-1]])
+    births_prev = np.concatenate([[int(prev["births"][0]) if prev is not None else 0], ctr["births"][:-1]])
     agent_steps = int(acting.sum())
-    value = agent_steps / wall
-    end = w.snapshot()
-    # ecology metrics of App. C over the timed steps (computed inside them)
+    end = w.snapshot(hidden=True, theta=True)
     deaths = int(ctr["deaths"].sum())
     win0 = (t_first + 49) // 50
     win1 = (t_first + args.steps) // 50
@@ -648,108 +688,57 @@ def main():
             "window": int(win1 - 1), "counted": int(mh[-1]),
             "percent_by_bin": [round(100.0 * float(x) / max(int(mh[-1]), 1), 2) for x in mh[:-1]]},
     }
-    log(f"[bench] timed {args.steps} steps in {wall * 1e3:.2f} ms ({best}); agent-steps {agent_steps}; "
-        f"N_live mean {acting.mean():.1f} min {acting.min()} max {acting.max()}; births {int(ctr['births'].sum())} "
-        f"deaths {int(ctr['deaths'].sum())}")
+    log(f"[bench] timed steps {t_first}..{t_first + args.steps - 1} in {wall * 1e3:.2f} ms ({best}); agent-steps "
+        f"{agent_steps}; N_live mean {acting.mean():.1f} min {acting.min()} max {acting.max()}; births "
+        f"{int(ctr['births'].sum())} deaths {deaths}")
 
-    # roofline of the dominant kernel: act phase in per-phase mode with events
+    # the same steps again from the same state as per-phase kernels, each
+    # launch between events its own dispatch stamps (kernel execution time)
     w.load(start)
-    nnz0, rows0 = observed_inputs(start, cfg)
-    ph_ms = w.phase_times(args.phase_steps)
-    mid = w.snapshot()
-    nnz1, rows1 = observed_inputs(mid, cfg)
-    nnz_mean = float(np.concatenate([nnz0, nnz1]).mean())
-    rows_mean = float(np.concatenate([rows0, rows1]).mean())
-    pc = w.counters(t_first, args.phase_steps)
-    n_act = float(np.concatenate([[start["n_live"]], pc["n_live"][:-1]]).mean())
-    per_agent = act_bytes_per_agent(cfg, rows_mean)
-    grid_bytes = cfg["H"] * cfg["W"] * 5
-    elig = float(np.mean([(s["streak"] >= cfg["T_repr"]).sum() for s in (start, mid)]))
-    kbytes = {
-        "act": n_act * per_agent + grid_bytes,
-        "move": n_act * (MOVE_BYTES_PER_AGENT + PROJ_MOVE_SHARE * proj_bytes_per_agent(cfg)),
-        "claim": (1 - PROJ_MOVE_SHARE) * (n_act - float(pc["deaths"].mean())) * proj_bytes_per_agent(cfg)
-                 + n_act * CLAIM_BYTES_PER_AGENT + elig * CLAIM_BYTES_PER_ELIGIBLE + 2 * cfg["H"] * cfg["W"],
-    }
+    ph_ms = w.phase_times(args.steps)
+    again = w.snapshot(hidden=True, theta=True)
+    same_state = all(np.array_equal(end[k], again[k]) for k in ("uid", "row", "col", "energy", "age", "streak", "R"))
     kms = {"act": float(ph_ms[0]), "move": float(ph_ms[1]), "claim": float(ph_ms[2])}
+    rows_read = ctr["rows_read"]
+    kbytes = kernel_window_bytes(cfg, P, acting, rows_read, births_prev, ctr["deaths"], ctr["claim_wins"])
+    step_b = step_algorithmic_bytes(cfg, P, acting, rows_read, ctr["births"])
     dominant = max(kms, key=kms.get)
-    act_bytes = kbytes["act"]
-    step_bytes = sum(kbytes.values())
     achieved = kbytes[dominant] / (kms[dominant] * 1e-3) / 1e9
+    step_gbps = float(step_b.sum()) / wall / 1e9
     src_hash = kernel_source_hash()
-    traffic = read_traffic(src_hash, best_rows) if dominant == "act" else None
-    dense_per_agent = 4 * w.n_params + 2 * cfg["hidden"] * 4 + 21
+    per_agent_traffic = read_traffic_per_agent(src_hash, best_rows) if dominant == "act" else None
+    n_act = float(acting.mean())
+    traffic = per_agent_traffic * n_act if per_agent_traffic is not None else None
+    w.close()
     log(f"[bench] kernel us act {kms['act'] * 1e3:.2f} move {kms['move'] * 1e3:.2f} claim {kms['claim'] * 1e3:.2f}; "
-        f"nnz mean {nnz_mean:.2f} rows read {rows_mean:.2f}; MB act {kbytes['act'] / 1e6:.2f} move {kbytes['move'] / 1e6:.2f} "
-        f"claim {kbytes['claim'] / 1e6:.2f}; dominant {dominant}")
-
-    if args.calib_copy:
-        copy_calibration(torch, world)
-
-    net = None
-    if args.net_steps > 0:
-        net = net_run(args)
-    paper = None
-    if args.paper_steps > 0:
-        paper = paper_run(args)
-    labs = None
-    if args.lab_agents > 0:
-        labs = lab_run(args)
-
-    m2 = None
-    if args.m2_steps > 0:
-        m2 = hbm_honest_run(args, best_rows)
-
-    batched = None
-    if args.batch_worlds > 0:
-        batched = batched_run(args)
-    served = None
-    if args.serve_seconds > 0:
-        served = served_run(args)
-
-    cpu = None
-    if not args.no_cpu:
-        log("[bench] oracle CPU baseline ...")
-        cpu = cpu_baseline(cfg, args.seed, args.cpu_seconds)
-        log(f"[bench] oracle: {cpu['value']:.0f} agent-steps/s")
-
-    # every weight read once per acting agent, h in and out, ~20 B of scalars in
-    # and out, parent genome in and child genome out per birth, grid as u8 +
-    # i32 in and out: what a step would move with no input skipped
-    P = w.n_params
-    dense_step = (acting.mean() * (4 * P + 8 * cfg["hidden"] + 40) + ctr["births"].mean() * 8 * P
-                  + cfg["H"] * cfg["W"] * (2 * 1 + 2 * 4))
-    ms_per_step = wall / args.steps * 1e3
-    out = {
-        "metric": "agent-steps/s @200x400, ~4k agents; batched/served p50/p99 step latency",
-        "value": value,
-        "unit": "agent-steps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic (seeded counter-based generator: resources, placement, genomes)",
+        f"rows read per agent {float(rows_read.sum()) / agent_steps:.2f}; MB act {kbytes['act'] / 1e6:.2f} move "
+        f"{kbytes['move'] / 1e6:.2f} claim {kbytes['claim'] / 1e6:.2f}; step {float(step_b.mean()) / 1e6:.1f} MB at "
+        f"{step_gbps:.0f} GB/s; dominant {dominant}")
+    return {
+        "value": agent_steps / wall, "wall": wall, "ms_per_step": wall / args.steps * 1e3,
         "config": {
             "workload": f"{args.workload}: {cfg['H']}x{cfg['W']} grid, cap {cfg['cap']}, {cfg['n_init']} initial "
                         f"agents, resources Bernoulli({cfg['res_init_p']}), regrowth x{cfg['rate_scale']}, "
                         f"obs {2 * cfg['obs_radius'] + 1}x{2 * cfg['obs_radius'] + 1}x2+1, GRU {cfg['hidden']}, "
-                        f"seed {args.seed}",
+                        f"seed {args.seed}; timed steps {t_first}..{t_first + args.steps - 1} after "
+                        f"{args.fixture_steps} fixture steps and {args.warmup} warm-up steps",
             "launch_mode": best,
             "act_rows_per_round_trip": best_rows,
             "steps_per_launch": args.chunk,
-            "n_live_mean": float(acting.mean()),
+            "first_timed_step": t_first,
+            "n_live_mean": n_act,
             "n_live_min": int(acting.min()),
             "n_live_max": int(acting.max()),
             "births": int(ctr["births"].sum()),
-            "deaths": int(ctr["deaths"].sum()),
+            "deaths": deaths,
+            "oracle_parity_tested_steps": f"0..{PARITY_STEPS_M1_4K - 1}"
+                                          + ("" if t_first + args.steps <= PARITY_STEPS_M1_4K
+                                             else " (this window goes beyond them)"),
             "parallelism": "single GPU",
         },
         "latency_ms_per_step": {"p50": float(np.percentile(per_step_ms, 50)),
                                 "p99": float(np.percentile(per_step_ms, 99)),
+                                "samples": int(len(per_step_ms)),
                                 "window": f"per {args.chunk}-step launch"},
         "calibration_us_per_step": {m: v * 1e3 for m, v in calib.items()},
         "kernels": {k: {"ms_per_launch": kms[k], "algorithmic_bytes": kbytes[k],
@@ -764,20 +753,237 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
+            "traffic_basis": None if traffic is None else
+                "rocprofv3 FETCH_SIZE + WRITE_SIZE of this kernel per acting agent on the same bench window "
+                "(profiles/act_m1_4k_traffic.txt), times this window's mean acting agents",
             "algorithmic_bytes_per_launch": kbytes[dominant],
             "launch_ms": kms[dominant],
-            "act_per_agent_bytes": per_agent,
+            "kernel_pass_same_steps": same_state,
             "agents_per_launch": n_act,
-            "nnz_binary_inputs_mean": nnz_mean,
-            "act_input_rows_read_mean": rows_mean,
-            "act_dense_equivalent_bytes_per_launch": n_act * dense_per_agent + grid_bytes,
-            "step_algorithmic_bytes": step_bytes,
-            "step_achieved_GBps": step_bytes / (wall / args.steps) / 1e9,
-            "step_dense_equivalent_bytes": dense_step,
-            "step_dense_equivalent_GBps": dense_step / (wall / args.steps) / 1e9,
+            "act_input_rows_read_per_agent": float(rows_read.sum()) / agent_steps,
+            "step_algorithmic_bytes": float(step_b.mean()),
+            "step_achieved_GBps": step_gbps,
+            "step_frac": step_gbps / HBM_PEAK_GBS,
+            "step_bytes_formula": "per acting agent 4*(3hd*hd + 6hd + 5hd + 5) + 8hd + 40 + 12hd (energy row); "
+                                  "+ 12hd per input row read (device counter); + 8P per birth; + 10 H W",
             "kernel_source_sha256_16": src_hash,
         },
         "ecology_metrics": metrics,
+        "_cfg": cfg,
+        "_start_t": t_first,
+    }
+
+
+def m0_run(args) -> dict:
+    """M0: the 32 x 64 world (cfg0) for its 1000 steps from the seed: one
+    launch per step (per-phase kernels, the launch-bound latency of a tiny
+    world) with an event per step, then the same 1000 steps as graphs of 100;
+    the oracle's rate on the same steps beside it."""
+    import torch
+    from paper_2302_09334_amd import batch, workloads, world
+    cfg = workloads.WORKLOADS["cfg0"]
+    steps = workloads.STEPS["cfg0"]
+    out = {"workload": "cfg0: 32x64 grid, cap 256, 32 initial agents, Bernoulli(0.1), obs 5x5x2+1, GRU 16, "
+                       f"seed {args.seed}, steps 0..{steps - 1}"}
+    for mode, K in (("kernels", 1), ("graph", 100)):
+        w = world.World(cfg, args.seed, mode=mode)
+        s0 = w.snapshot(hidden=True, theta=True)
+        w.step(K)    # graph capture / first launch, outside the timed region
+        w.sync()
+        w.load(s0)
+        wall, ms = batch.time_chunks(w.step, steps, K, w.stream)
+        c = w.counters(0, steps)
+        acting = int(cfg["n_init"]) + int(c["n_live"][:-1].sum())
+        out[f"{mode}_K{K}"] = {"steps_per_s": steps / wall, "agent_steps_per_s": acting / wall,
+                               "step_ms_p50": float(np.percentile(ms / K, 50)),
+                               "step_ms_p99": float(np.percentile(ms / K, 99))}
+        out["n_live_mean"] = float(np.concatenate([[cfg["n_init"]], c["n_live"][:-1]]).mean())
+        w.close()
+    import oracle
+    ow = oracle.OracleWorld(oracle.OracleConfig.from_dict(cfg), args.seed)
+    t0 = time.perf_counter()
+    acted = 0
+    for _ in range(steps):
+        acted += ow.n_live
+        ow.step()
+    el = time.perf_counter() - t0
+    ow.close()
+    out["oracle"] = {"steps_per_s": steps / el, "agent_steps_per_s": acted / el, "cores": 1}
+    out["gpu_vs_oracle_steps"] = out["graph_K100"]["steps_per_s"] / out["oracle"]["steps_per_s"]
+    log(f"[bench] M0 cfg0: {out['kernels_K1']['steps_per_s']:.0f} steps/s one launch per step (p50 "
+        f"{out['kernels_K1']['step_ms_p50'] * 1e3:.1f} us), {out['graph_K100']['steps_per_s']:.0f} steps/s in graphs; "
+        f"oracle {out['oracle']['steps_per_s']:.0f} steps/s")
+    return out
+
+
+def m1_run(args) -> dict:
+    """M1: the paper-scale world (cfg1: 200 x 400, 8192 slots, 1000 initial
+    agents, Bernoulli(0.05)) for its 10,000 steps from the seed as 100
+    graphs of 100 steps, with the mean live population."""
+    import torch
+    from paper_2302_09334_amd import batch, workloads, world
+    cfg = workloads.WORKLOADS["cfg1"]
+    steps = workloads.STEPS["cfg1"]
+    w2 = world.World(cfg, args.seed, mode="graph")
+    s0 = w2.snapshot(hidden=True, theta=True)
+    w2.step(100)    # graph capture, outside the timed region
+    w2.sync()
+    w2.load(s0)
+    # two timed halves (the counter ring holds 8192 steps: each half's
+    # counters are read between them, outside the timed regions)
+    wall = 0.0
+    ms_all, n_live = [], []
+    for h0 in range(0, steps, steps // 2):
+        wh, ms = batch.time_chunks(w2.step, steps // 2, 100, w2.stream)
+        wall += wh
+        ms_all.append(ms)
+        n_live.append(w2.counters(h0, steps // 2)["n_live"])
+    ms = np.concatenate(ms_all)
+    n_live = np.concatenate(n_live)
+    acting = np.concatenate([[cfg["n_init"]], n_live[:-1]])
+    w2.close()
+    out = {"workload": "cfg1: 200x400 grid, cap 8192, 1000 initial agents, Bernoulli(0.05), obs 7x7x2+1, GRU 32, "
+                       f"seed {args.seed}, steps 0..{steps - 1} as {steps // 100} graphs of 100 steps (timed in "
+                       "two halves; the counters are read between them)",
+           "agent_steps_per_s": float(acting.sum()) / wall, "steps_per_s": steps / wall,
+           "ms_per_step": wall / steps * 1e3, "n_live_mean": float(acting.mean()), "n_live_min": int(acting.min()),
+           "n_live_max": int(acting.max()), "step_ms_p50": float(np.percentile(ms / 100, 50)),
+           "step_ms_p99": float(np.percentile(ms / 100, 99))}
+    log(f"[bench] M1 cfg1: {out['agent_steps_per_s'] / 1e6:.1f} M agent-steps/s, {out['steps_per_s']:.0f} steps/s, "
+        f"mean N_live {out['n_live_mean']:.0f}")
+    return out
+
+
+def m2_run(args) -> dict:
+    """M2: the dense-population stress world (cfg2) for its 5000 steps from
+    the seed as graphs of 100 steps."""
+    from paper_2302_09334_amd import batch, workloads, world
+    cfg = workloads.WORKLOADS["cfg2"]
+    steps = workloads.STEPS["cfg2"]
+    w2 = world.World(cfg, args.seed, mode="graph")
+    s0 = w2.snapshot(hidden=True, theta=True)
+    w2.step(100)    # graph capture, outside the timed region
+    w2.sync()
+    w2.load(s0)
+    wall, ms = batch.time_chunks(w2.step, steps, 100, w2.stream)
+    c = w2.counters(0, steps)
+    acting = np.concatenate([[cfg["n_init"]], c["n_live"][:-1]])
+    w2.close()
+    out = {"workload": "cfg2: 200x400 grid, cap 16384, 12000 initial agents, Bernoulli(0.3), regrowth x5, obs "
+                       f"7x7x2+1, GRU 32, seed {args.seed}, steps 0..{steps - 1} as graphs of 100 steps",
+           "agent_steps_per_s": float(acting.sum()) / wall, "steps_per_s": steps / wall,
+           "ms_per_step": wall / steps * 1e3, "n_live_mean": float(acting.mean()), "n_live_min": int(acting.min()),
+           "n_live_max": int(acting.max()), "births": int(c["births"].sum()), "deaths": int(c["deaths"].sum()),
+           "step_ms_p50": float(np.percentile(ms / 100, 50)), "step_ms_p99": float(np.percentile(ms / 100, 99))}
+    log(f"[bench] M2 cfg2 5000 steps: {out['agent_steps_per_s'] / 1e6:.1f} M agent-steps/s, mean N_live "
+        f"{out['n_live_mean']:.0f}, births {out['births']}, deaths {out['deaths']}")
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--fixture-steps", type=int, default=FIXTURE_STEPS,
+                    help="steps from the seed that prepare the workload before --warmup (the M1-4k fixture: 1000)")
+    ap.add_argument("--workload", default="m1_4k")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--mode", default="auto", choices=["auto", "kernels", "graph"])
+    ap.add_argument("--chunk", type=int, default=100, help="steps per world_step call")
+    ap.add_argument("--rows", type=int, default=0, choices=[0, 8, 16, 32],
+                    help="act rows per round trip (0 = calibrate among 8, 16, 32)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run the plain copy kernel on 1 GiB (memory-counter calibration)")
+    ap.add_argument("--m2-steps", type=int, default=60, help="steps of the cache-exceeding cfg2 run (0 = skip)")
+    ap.add_argument("--fixtures", type=int, default=1, help="run the M0, M1 and M2 fixtures (0 = skip)")
+    ap.add_argument("--batch-worlds", type=int, default=64, help="uneven worlds of the batched run (0 = skip)")
+    ap.add_argument("--batch-steps", type=int, default=2000)
+    ap.add_argument("--batch-warmup", type=int, default=0)
+    ap.add_argument("--serve-seconds", type=float, default=20.0, help="arrival window of the served run (0 = skip)")
+    ap.add_argument("--serve-budget-gb", type=float, default=200.0)
+    ap.add_argument("--net-steps", type=int, default=500, help="timed steps of the paper-network world (0 = skip)")
+    ap.add_argument("--net-warmup", type=int, default=300)
+    ap.add_argument("--net-phase-steps", type=int, default=100)
+    ap.add_argument("--only", choices=["net", "paper", "lab", "m2", "headline", "served", "batched", "fixtures"],
+                    help="run only this leg and print it")
+    ap.add_argument("--paper-steps", type=int, default=2000, help="timed steps of the paper-dynamics world (0 = skip)")
+    ap.add_argument("--paper-warmup", type=int, default=1000)
+    ap.add_argument("--lab-agents", type=int, default=50, help="evolved agents of the lab leg (0 = skip)")
+    ap.add_argument("--lab-trials", type=int, default=10)
+    ap.add_argument("--lab-evolve-steps", type=int, default=20000)
+    ap.add_argument("--lab-seq-sample", type=int, default=20)
+    args = ap.parse_args()
+
+    world_size = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world_size != 1:
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    if args.steps < 1 or args.steps > 8000:
+        sys.exit("--steps must be in 1..8000 (the per-step counter ring holds 8192 steps)")
+
+    import torch
+    from paper_2302_09334_amd import world
+
+    if args.only and args.only != "headline":
+        leg = {"net": ("paper_network", net_run), "paper": ("paper_dynamics", paper_run), "lab": ("lab", lab_run),
+               "m2": ("cache_exceeding", lambda a: hbm_honest_run(a, ONLY_M2_ROWS)),
+               "served": ("served", served_run), "batched": ("batched", batched_run),
+               "fixtures": ("fixtures", lambda a: {"M0": m0_run(a), "M1": m1_run(a), "M2": m2_run(a)})}
+        name, fn = leg[args.only]
+        out = fn(args)
+        if args.calib_copy:
+            copy_calibration(torch, world)
+        print(json.dumps({name: out}))
+        return
+
+    head = headline_run(args)
+    cfg = head.pop("_cfg")
+    head.pop("_start_t")
+    if args.calib_copy:
+        copy_calibration(torch, world)
+    if args.only == "headline":
+        print(json.dumps({"headline": head}))
+        return
+
+    net = net_run(args) if args.net_steps > 0 else None
+    paper = paper_run(args) if args.paper_steps > 0 else None
+    labs = lab_run(args) if args.lab_agents > 0 else None
+    m2 = hbm_honest_run(args, head["config"]["act_rows_per_round_trip"]) if args.m2_steps > 0 else None
+    fixtures = None
+    if args.fixtures:
+        fixtures = {"M0": m0_run(args), "M1": m1_run(args), "M2": m2_run(args)}
+    batched = batched_run(args) if args.batch_worlds > 0 else None
+    served = served_run(args) if args.serve_seconds > 0 else None
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] oracle CPU baseline ...")
+        cpu = cpu_baseline(cfg, args.seed, args.cpu_seconds)
+        log(f"[bench] oracle: {cpu['value']:.0f} agent-steps/s")
+
+    out = {
+        "metric": "agent-steps/s @200x400, ~4k agents; batched/served p50/p99 step latency",
+        "value": head["value"],
+        "unit": "agent-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded counter-based generator: resources, placement, genomes)",
+        "config": head["config"],
+        "latency_ms_per_step": head["latency_ms_per_step"],
+        "calibration_us_per_step": head["calibration_us_per_step"],
+        "kernels": head["kernels"],
+        "roofline": head["roofline"],
+        "ecology_metrics": head["ecology_metrics"],
+        "fixtures": fixtures,
         "paper_network": net,
         "paper_dynamics": paper,
         "lab": labs,
@@ -786,7 +992,6 @@ def main():
         "batched": batched,
         "served": served,
     }
-    w.close()
     print(json.dumps(out))
 
 

@@ -128,7 +128,11 @@ typedef struct world_counters {
     int32_t seen_resource;/* acting agents with a resource in their field of
                             view at the step start (greediness of the lab
                             environments, Sec. 2.2)                         */
-    int32_t reserved;
+    int32_t rows_read;   /* GRU controller: input-weight rows (3 x hidden
+                            floats each) the act phase read in the step --
+                            per binary window the rows of its ones, or its
+                            column total and the rows of its zeros; 0 for the
+                            paper's network.  The bytes a step really reads. */
 } world_counters;
 
 /* Movement metric (App. C).  Window k covers steps [k * WORLD_MOVE_WINDOW,
@@ -173,54 +177,98 @@ typedef struct world_image {
     uint8_t *ate;
 } world_image;
 
-/* Device bytes a world with this configuration needs.  Pure host function. */
-int world_required_bytes(const world_config *cfg, size_t *device_bytes);
+/* Sizes for a configuration (pure host function, no device access):
+ * *device_bytes = the arena world_create needs (the whole state of App. B:
+ * grid, agents, genomes, lists, counters); *snapshot_bytes = the host bytes
+ * of a complete world_image with agent_capacity = cap (R, the six int32
+ * agent arrays, h, theta, last_action, ate).  Either pointer may be NULL, not
+ * both.  Errors: WORLD_E_INVALID_ARG, WORLD_E_INVALID_CONFIG. */
+int world_required_bytes(const world_config *cfg, size_t *device_bytes, size_t *snapshot_bytes);
 
 /* Inputs and parameters per agent for this configuration (GRU: window cells
- * x 2 + energy; paper's network: 15 x 15 x 3 observation values).  Pure host. */
+ * x 2 + energy; paper's network: 15 x 15 x 3 observation values, 2445
+ * parameters as App. B.5 counts them).  Pure host; either pointer may be
+ * NULL.  Errors: WORLD_E_INVALID_CONFIG. */
 int world_dims(const world_config *cfg, int32_t *n_inputs, int32_t *n_params);
 
-/* Lay out a world in `device_arena` (>= world_required_bytes, 256-byte aligned,
- * owned by the caller and kept alive until world_destroy), initialise it from
- * `seed` (resources, placement and genomes from the counter-based generator)
- * on `hip_stream` (a hipStream_t; NULL = default stream).  Synchronises the
- * stream before returning.  *out receives the handle. */
+/* Lay out a world in `device_arena` (device memory, >= world_required_bytes,
+ * 256-byte aligned, owned by the caller and kept alive until world_destroy),
+ * initialise it from `seed` on `hip_stream` (a hipStream_t owned by the
+ * caller; NULL = default stream) and synchronise the stream.  The initial
+ * world is App. B.4's: agents at distinct random cells with energy E0, i.i.d.
+ * random resources; the genomes are random (App. B.2: the population starts
+ * from random controllers), drawn from the counter-based generator.  *out
+ * receives the host handle (owned by the library until world_destroy).
+ * Errors: WORLD_E_INVALID_ARG (NULL, misaligned), WORLD_E_INVALID_CONFIG,
+ * WORLD_E_BUFFER_TOO_SMALL (arena), WORLD_E_HIP (nothing is created). */
 int world_create(const world_config *cfg, uint64_t seed, void *device_arena, size_t arena_bytes,
                  void *hip_stream, world_t **out);
 
-/* Enqueue K >= 1 steps of the world step on the world's stream. */
+/* Enqueue K >= 1 world steps on the world's stream and return.  One step is
+ * App. B in order: observation and controller of every agent (B.2, B.5),
+ * moves, eating and energy (B.2), death and minimal-criterion reproduction
+ * with mutation (B.3), resource regrowth (B.1, Eq. (1)); the K steps run
+ * without a host round trip (App. B.4: one long run, no resets).  Device
+ * failures surface at the next synchronising call.  Errors:
+ * WORLD_E_INVALID_ARG (K < 1), WORLD_E_POISONED, WORLD_E_HIP. */
 int world_step(world_t *w, int32_t K);
 
-/* Enqueue K steps of n worlds in shared launches.  All worlds must use the
- * same stream and the same controller; the result of every world is
- * bit-identical to stepping it alone. */
+/* Enqueue K steps (the step of world_step, App. B) of n worlds in shared
+ * launches.  All worlds must use the same stream, controller and dynamics,
+ * and no world may be listed twice; the result of every world is
+ * bit-identical to stepping it alone.  The library keeps a small device
+ * launch table per distinct list (allocated on first use, released by
+ * world_destroy of any listed world or by LRU eviction).  Errors:
+ * WORLD_E_INVALID_ARG, WORLD_E_POISONED, WORLD_E_HIP. */
 int world_step_many(world_t *const *ws, int32_t n, int32_t K);
 
-/* Select WORLD_MODE_* for later steps. */
+/* Select WORLD_MODE_* for later steps (how the App. B step is launched:
+ * per-phase kernels, or K steps captured once into a HIP graph and replayed;
+ * results are identical).  Errors: WORLD_E_INVALID_ARG. */
 int world_set_mode(world_t *w, int32_t mode);
 
-/* Move the world to another HIP stream (the old stream is synchronised
- * first).  Lets a world be created on one stream and then join a batch. */
+/* Move the world to another HIP stream (caller-owned; the old stream is
+ * synchronised first).  Lets a world be created on one stream and then join
+ * a batch of world_step_many.  Errors: WORLD_E_INVALID_ARG, WORLD_E_HIP. */
 int world_set_stream(world_t *w, void *hip_stream);
 
-/* Tuning knob of the act kernel: input rows fetched per wave per round trip
- * (8, 16 or 32; default 16).  Results are identical for every value.  A
- * batched step uses the first world's setting. */
+/* Tuning knob of the act kernel (the controller of App. B.2): input rows
+ * fetched per wave per round trip (8, 16 or 32; default 16).  Results are
+ * identical for every value.  A batched step uses the first world's setting.
+ * Errors: WORLD_E_INVALID_ARG. */
 int world_set_tuning(world_t *w, int32_t act_rows);
 
-/* Wait for the world's stream; report device-side failures. */
+/* Wait for the world's stream; report device-side failures (WORLD_E_HIP
+ * poisons the handle). */
 int world_sync(world_t *w);
 
-/* Synchronise and copy the canonical state into caller buffers.  If
- * agent_capacity < n_live, returns WORLD_E_BUFFER_TOO_SMALL with n_live set. */
+/* Synchronise and copy the canonical state (the state App. B's step acts on:
+ * grid resources, agents with position, energy, age, reproduction streak,
+ * recurrent state and genome) into caller-owned host buffers; any array
+ * pointer may be NULL to skip it.  Agents are listed by increasing uid.  If
+ * agent_capacity < n_live, returns WORLD_E_BUFFER_TOO_SMALL with n_live set.
+ * Errors: WORLD_E_INVALID_ARG, WORLD_E_POISONED, WORLD_E_HIP. */
 int world_snapshot(world_t *w, world_image *out);
 
-/* Overwrite the world's state from a canonical image (both WORLD_SNAP_HIDDEN
- * and WORLD_SNAP_THETA must be set, every array present).  Validates
- * positions, uids, actions and sizes. */
+/* Overwrite the world's state from a canonical image (resume or resync of a
+ * long run, App. B.4; both WORLD_SNAP_HIDDEN and WORLD_SNAP_THETA must be set,
+ * every array present; the caller keeps `in`).  Validates positions, uids,
+ * actions and sizes before touching the device.  Synchronises.  Errors:
+ * WORLD_E_INVALID_ARG, WORLD_E_POISONED, WORLD_E_HIP. */
 int world_load(world_t *w, const world_image *in);
 
-/* Synchronise and copy counters of steps [first_step, first_step + n). */
+/* Check, on the host only, that world_load would accept `in` for a world of
+ * configuration `cfg`: the full state present, agents inside the grid (one
+ * per cell under WORLD_DYN_BENCH), uids increasing and below next_uid, ages
+ * >= 0, resource bytes 0 or 1, previous actions 0..5, ate bits 0 or 1.  No
+ * device access.  Returns WORLD_OK, WORLD_E_INVALID_CONFIG or
+ * WORLD_E_INVALID_ARG (world_last_error(NULL) names the problem). */
+int world_validate_image(const world_config *cfg, const world_image *in);
+
+/* Synchronise and copy counters of steps [first_step, first_step + n) into
+ * out (caller-owned, n entries): population, births, deaths, resources (the
+ * App. C population and resource series) and the per-step sums behind its
+ * life expectancy.  The last 8192 steps are held (WORLD_E_STATE otherwise). */
 int world_counters_get(world_t *w, int64_t first_step, int32_t n, world_counters *out);
 
 /* Synchronise and copy the movement histograms of windows [first_window,
@@ -229,7 +277,9 @@ int world_counters_get(world_t *w, int64_t first_step, int32_t n, world_counters
  * ended and be among the last 64 (WORLD_E_STATE otherwise).  App. C. */
 int world_move_hist(world_t *w, int64_t first_window, int32_t n, int32_t *out);
 
-/* Synchronise and release the handle.  The arena is not freed. */
+/* Synchronise and release the handle, its graphs and every batch launch table
+ * that lists it.  The arena and the stream are not freed (the caller owns
+ * them).  NULL is accepted. */
 int world_destroy(world_t *w);
 
 /* Message of the last failure of `w` (or of the calling thread if w is NULL). */
@@ -237,9 +287,19 @@ const char *world_last_error(const world_t *w);
 
 /* ---- test hooks ----------------------------------------------------------- */
 
-/* Force every agent's action (0 = N, 1 = S, 2 = E, 3 = W, 4 = stay); -1
- * returns control to the controller. */
+/* Force every agent's action (0 = N, 1 = S, 2 = E, 3 = W, 4 = stay; the
+ * actions of App. B.2); -1 returns control to the controller.  Clears the
+ * by-uid table of world_set_forced_actions.  Synchronises. */
 int world_set_forced_action(world_t *w, int32_t action);
+
+/* Scripted policy by agent (test hook): the agent with uid u takes
+ * act_by_uid[u] (0..4) when u < n and that entry is >= 0, otherwise
+ * default_action (-1 = its controller's choice).  act_by_uid is a host array
+ * of n int32 read during the call; n may be 0 (then act_by_uid may be NULL)
+ * and at most max(4 * cap, 4096).  The controller still runs and is logged;
+ * only the action taken changes.  Synchronises.  Errors: WORLD_E_INVALID_ARG
+ * (n out of range, an action outside -1..4), WORLD_E_POISONED, WORLD_E_HIP. */
+int world_set_forced_actions(world_t *w, const int32_t *act_by_uid, int32_t n, int32_t default_action);
 
 /* Failure injection for the look-back scans: from the next step on, move
  * tile `tile` (0 <= tile < ceil(cap / 64); -1 = none) publishes no look-back
@@ -251,22 +311,33 @@ int world_set_forced_action(world_t *w, int32_t action);
 int world_test_stall_lookback(world_t *w, int32_t tile, uint32_t spin_ticks);
 
 /* Synchronise and copy the controller log of `step` (needs log_steps > 0 and
- * the step among the last log_steps): per acting agent in uid order its uid,
- * action and 5 logits.  *n receives the number of agents. */
+ * the step among the last log_steps) into caller-owned host arrays of
+ * `capacity` entries (any may be NULL): per acting agent in uid order its
+ * uid, the action taken and the 5 logits of its controller (App. B.2, B.5),
+ * and in margin the device's top-2 margin of its decision values (the
+ * logits for the GRU's arg-max; the sampling scores 50 l + g of the paper's
+ * network), which a checker uses to recognise near ties.  *n receives the
+ * number of agents; WORLD_E_BUFFER_TOO_SMALL if capacity < *n. */
 int world_action_log(world_t *w, int64_t step, int32_t capacity, uint32_t *uid, uint8_t *action,
-                     float *logits, int32_t *n);
+                     float *logits, float *margin, int32_t *n);
 
-/* Philox4x32-10 on the device: n counters (device, n x 4 words) under key
- * (k0, k1) into out (device, n x 4 words), on hip_stream. */
+/* Philox4x32-10 (Salmon et al., SC'11: the counter-based generator behind
+ * every random choice of the step) on the device: n counters (device, n x 4
+ * words) under key (k0, k1) into out (device, n x 4 words), on hip_stream.
+ * Synchronises hip_stream.  Errors: WORLD_E_INVALID_ARG, WORLD_E_HIP. */
 int world_test_philox(const uint32_t *d_ctr, size_t n, uint32_t k0, uint32_t k1, uint32_t *d_out,
                       void *hip_stream);
 
-/* Box-Muller normals on the device from n word pairs (device buffers). */
+/* Box-Muller normals on the device from n word pairs (device buffers): the
+ * Gaussian of the mutation (App. B.3) and of the initial genomes.
+ * Synchronises hip_stream. */
 int world_test_gauss(const uint32_t *d_a, const uint32_t *d_b, size_t n, float *d_z0, float *d_z1,
                      void *hip_stream);
 
-/* Gumbel deviates of the paper's action sampling on the device: one per
- * 32-bit word, n words (device) into d_g (device floats), on hip_stream. */
+/* Gumbel deviates of the paper's action sampling (App. B.2: softmax at
+ * temperature 1/50, sampled as the arg-max of 50 l + g) on the device: one
+ * per 32-bit word, n words (device) into d_g (device floats), on hip_stream.
+ * Synchronises hip_stream. */
 int world_test_gumbel(const uint32_t *d_words, size_t n, float *d_g, void *hip_stream);
 
 /* Run K steps as per-phase kernels on the world's stream and return the mean
@@ -280,11 +351,15 @@ int world_test_gumbel(const uint32_t *d_words, size_t n, float *d_g, void *hip_s
 int world_phase_times(world_t *w, int32_t K, float *ms);
 
 /* Plain device-to-device copy kernel (16-byte vector loads/stores) of `bytes`
- * (multiple of 16) on hip_stream; a known-size reference for memory counters. */
+ * (multiple of 16) between caller-owned device buffers on hip_stream; a
+ * known-size reference for memory counters (not part of the method).
+ * Synchronises hip_stream. */
 int world_test_copy(const void *d_src, void *d_dst, size_t bytes, void *hip_stream);
 
 /* Regrowth threshold table of a configuration, as the library builds it
- * (host memory, H x 25 entries; grow iff draw < entry). */
+ * (App. B.1, Eq. (1); out = caller-owned host memory, H x 25 entries indexed
+ * [row][resource neighbours]; a cell grows iff its 32-bit draw < entry).
+ * Pure host.  Errors: WORLD_E_INVALID_ARG, WORLD_E_INVALID_CONFIG. */
 int world_threshold_table(const world_config *cfg, uint64_t *out);
 
 #ifdef __cplusplus

@@ -444,7 +444,7 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
             best = a;
         }
     }
-    if (d.forced >= 0) best = d.forced;
+    if (d.forced_on) best = forced_of(d, u, best);
 
     // ---- outputs ----------------------------------------------------------------
     if (lane < 16 && gq == 0) {

@@ -44,6 +44,18 @@ __device__ __forceinline__ uint64_t claim_key(uint32_t draw_word, uint32_t u) {
 
 __device__ __forceinline__ float sigmoidf_(float v) { return 1.0f / (1.0f + expf(-v)); }
 
+// Test hook (scripted policies): the action forced on the agent with uid
+// `u` -- its entry of the by-uid table if it has one >= 0, else the world's
+// default -- or the controller's choice `best` when neither forces one.
+__device__ __forceinline__ int forced_of(DevRef d, uint32_t u, int best) {
+    int fa = d.forced;
+    if (u < uint32_t(d.n_forced)) {
+        const int v = d.forced_tab[u];
+        if (v >= 0) fa = v;
+    }
+    return fa >= 0 ? fa : best;
+}
+
 // The act phase's claim on the cell the chosen action leads to (one lane per
 // agent).  Benchmark rules: a move claims its target when it lies inside the
 // grid and is empty at the step start; the smallest (MOVE draw, uid) moves.
@@ -258,6 +270,7 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
     if (cR) mR = ~mR & wmask;
     if (cO) mO = ~mO & wmask;
     int pend = (cR ? 1 : 0) | (cO ? 2 : 0);   // window totals still to add
+    const int nrows = __popcll(mR) + __popcll(mO) + (cR ? 1 : 0) + (cO ? 1 : 0);   // input rows read
     constexpr int kNeg = 1 << 16;
     const int tot_row = d.tot_row;
     float ar = 0.f, az = 0.f, an = 0.f;
@@ -332,7 +345,7 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
 #pragma unroll
     for (int a = 1; a < 5; ++a)
         if (lg[a] > lg[best]) best = a;
-    if (d.forced >= 0) best = d.forced;
+    if (d.forced_on) best = forced_of(d, u, best);
 
     if (g == 0) d.h[size_t(slot) * HD + k] = hnew;
     if (lane == 0 && t % kMoveWin == 0) {   // a movement window starts with this step
@@ -341,7 +354,7 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
     }
     if (lane == 0) {
         d.action[slot] = uint8_t(best);
-        recp->action = best | (seen ? kSeenBit : 0);
+        recp->action = best | (seen ? kSeenBit : 0) | (nrows << kRowsShift);
         // the claim on the target cell (resolved by the next phase); the
         // target's window bits (outside cells read occupied, no resource)
         const int q = (rho + act_dr(best)) * win + (rho + act_dc(best));
@@ -465,7 +478,8 @@ __device__ __forceinline__ WaveRank wave_rank2(bool a, bool b, int lane) {
 // resource of the final cell, energy += gain * ate - decay, age += 1, death
 // at energy <= 0 or age >= L_max, streak of survivors.  occB receives the
 // moves and deaths; occA (read by every agent in this phase) is untouched.
-// Returns bit 0 = ate, bit 1 = died, bit 2 = had a resource in view.
+// Returns bit 0 = ate, bit 1 = died, bit 2 = had a resource in view, bits
+// 3.. = input rows its act phase read.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int move_agent(DevRef d, const AgentRec& a, int64_t t, PostRec* post,
                                           AgentRec* next_rec_src) {
@@ -546,7 +560,7 @@ __device__ __forceinline__ int move_agent(DevRef d, const AgentRec& a, int64_t t
     nr.action = act;   // the previous action and ate bit of the next step
     nr.ate = ate;
     *next_rec_src = nr;
-    return ate | (dead ? 2 : 0) | ((a.action & kSeenBit) ? 4 : 0);
+    return ate | (dead ? 2 : 0) | ((a.action & kSeenBit) ? 4 : 0) | (((a.action >> kRowsShift) & kRowsMask) << 3);
 }
 
 // P2 under the paper's dynamics (App. B.2, B.3): the move always happens,
@@ -613,7 +627,7 @@ __device__ __forceinline__ int move_agent_paper(DevRef d, const AgentRec& a, int
     nr.action = act;
     nr.ate = ate;
     *next_rec_src = nr;
-    return ate | (dead ? 2 : 0) | ((a.action & kSeenBit) ? 4 : 0);
+    return ate | (dead ? 2 : 0) | ((a.action & kSeenBit) ? 4 : 0) | (((a.action >> kRowsShift) & kRowsMask) << 3);
 }
 
 // The world scalars a block works with, read once at its start.
@@ -662,7 +676,7 @@ __device__ __forceinline__ StepScal read_step(const WorldScal* S) {
 }
 
 struct StepShared {
-    int sw[3 * (kBlock / 64)];
+    int sw[4 * (kBlock / 64)];
     long long sw64[kBlock / 64];
 };
 
@@ -686,6 +700,9 @@ __device__ __forceinline__ void move_block(DevRef d, PosRec* P, int j, int lane,
     const bool dead = i < n && (res & 2);
     const int cnt = __popcll(__ballot((res & 1) != 0));
     const int cnt_seen = __popcll(__ballot((res & 4) != 0));
+    int rows = res >> 3;   // input rows read by the act phase
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) rows += __shfl_xor(rows, off);
     int dage = dead ? nr.age : 0;   // age at death (life expectancy, App. C)
     if (__ballot(dead)) {            // deaths are rare: most tiles skip the sum
 #pragma unroll
@@ -694,6 +711,7 @@ __device__ __forceinline__ void move_block(DevRef d, PosRec* P, int j, int lane,
     if (lane == 0) {
         d.eat_part[j] = cnt | (cnt_seen << 16);
         d.dage_part[j] = dage;
+        d.rows_part[j] = rows;
     }
     // Movement metric (App. C): the window ends with this step; every
     // survivor whose slot recorded it at the window start counts, in bin
@@ -1082,13 +1100,14 @@ __device__ __forceinline__ void close_counters(DevRef d, int tid, StepShared& sh
     WorldScal* S = d.scal;
     if (!S->ctr_open) return;
     const int nwv = (S->n_prev + 63) / 64;
-    int pe = 0, pr = 0, ps = 0;
+    int pe = 0, pr = 0, ps = 0, pw = 0;
     long long pa = 0;
     for (int i = tid; i < nwv; i += kBlock) {
         const int ep = d.eat_part[i];
         pe += ep & 0xFFFF;
         ps += ep >> 16;
         pa += d.dage_part[i];
+        pw += d.rows_part[i];
     }
     for (int i = tid; i < d.ntiles; i += kBlock) pr += d.res_part[i];
 #pragma unroll
@@ -1097,21 +1116,24 @@ __device__ __forceinline__ void close_counters(DevRef d, int tid, StepShared& sh
         pr += __shfl_xor(pr, off);
         ps += __shfl_xor(ps, off);
         pa += __shfl_xor(pa, off);
+        pw += __shfl_xor(pw, off);
     }
     if ((tid & 63) == 0) {
         sh.sw[tid >> 6] = pe;
         sh.sw[(kBlock / 64) + (tid >> 6)] = pr;
         sh.sw[2 * (kBlock / 64) + (tid >> 6)] = ps;
+        sh.sw[3 * (kBlock / 64) + (tid >> 6)] = pw;
         sh.sw64[tid >> 6] = pa;
     }
     __syncthreads();
     if (tid == 0) {
-        int te = 0, tr = 0, ts = 0;
+        int te = 0, tr = 0, ts = 0, tw = 0;
         long long ta = 0;
         for (int w = 0; w < kBlock / 64; ++w) {
             te += sh.sw[w];
             tr += sh.sw[(kBlock / 64) + w];
             ts += sh.sw[2 * (kBlock / 64) + w];
+            tw += sh.sw[3 * (kBlock / 64) + w];
             ta += sh.sw64[w];
         }
         int32_t* rec = d.ring + (S->spawn_t % kRing) * kCtrWords;
@@ -1120,6 +1142,7 @@ __device__ __forceinline__ void close_counters(DevRef d, int tid, StepShared& sh
         rec[kCtrDeadAgeLo] = int32_t(uint64_t(ta) & 0xFFFFFFFFu);
         rec[kCtrDeadAgeHi] = int32_t(uint64_t(ta) >> 32);
         rec[kCtrSeen] = ts;
+        rec[kCtrRows] = tw;
     }
     __syncthreads();
 }

@@ -102,13 +102,23 @@ const char* check_config(const world_config* c) {
     return nullptr;
 }
 
+// Entries of the forced-action table by uid (a test hook for scripted
+// policies): uids at or beyond it take the world's default.
+int32_t forced_capacity(const world_config& c) { return std::max(4 * c.cap, 4096); }
+
+// Host bytes of a complete canonical image with agent_capacity = cap.
+size_t snapshot_bytes_of(const world_config& c, const Dims& dm) {
+    const size_t cap = size_t(c.cap);
+    return size_t(c.H) * c.W + cap * (6 * 4 + 4 * size_t(state_of(c)) + 4 * size_t(dm.P) + 2);
+}
+
 // Byte offsets of every array inside the arena.
 struct Layout {
     size_t desc, scal, ring, batch, thr, R0, R1, occA, occB, mclaim;
     size_t uid, cell, prev_cell, energy, age, streak, action, alive, ate, claim, bkey;
     size_t live0, live1, pos, freeq, child, h, gh, theta;
-    size_t log_uid, log_act, log_logits, log_n, eat_part, dage_part, wcell, wuid, mhist, res_part, deadlist, lb_move,
-        lb_claim;
+    size_t log_uid, log_act, log_logits, log_n, eat_part, dage_part, rows_part, wcell, wuid, mhist, res_part, deadlist,
+        lb_move, lb_claim, forced;
     size_t total;
 };
 
@@ -159,6 +169,7 @@ Layout layout_of(const world_config& c) {
     l.log_n = take(4 * L);
     l.eat_part = take(4 * (cap / 64 + 1));
     l.dage_part = take(4 * (cap / 64 + 1));
+    l.rows_part = take(4 * (cap / 64 + 1));
     l.wcell = take(4 * cap);
     l.wuid = take(4 * cap);
     l.mhist = take(4 * size_t(kMoveRing) * (kMoveBins + 1));
@@ -166,6 +177,7 @@ Layout layout_of(const world_config& c) {
     l.lb_move = take(8 * ((cap + kTileN - 1) / kTileN));
     l.lb_claim = take(8 * ((cap + kTileN - 1) / kTileN));
     l.res_part = take(4 * size_t(((c.H + kTile - 1) / kTile) * ((c.W + kTile - 1) / kTile)));
+    l.forced = take(size_t(forced_capacity(c)));
     l.total = o;
     static_assert(kArenaAlign == kAlign, "arena alignment");
     assert(l.scal == kScalOff && l.pos == kPosOff);
@@ -433,16 +445,50 @@ int run_steps(world* w0, int mode, const TableView& tv, const std::vector<int>& 
 
 }  // namespace
 
+// Why a canonical image cannot be loaded into a world of configuration `c`
+// (nullptr if it can): the full state must be present; positions inside the
+// grid (one agent per cell under the benchmark rules); uids increasing and
+// below next_uid; resource bytes, previous actions and ate bits in range.
+static const char* image_problem(const world_config& c, const world_image* in) {
+    if (in->struct_size != sizeof(world_image)) return "world_image.struct_size mismatch";
+    const int n = in->n_live;
+    if (n < 0 || n > c.cap) return "n_live out of range";
+    if (!(in->flags & WORLD_SNAP_HIDDEN) || !(in->flags & WORLD_SNAP_THETA) || !in->R || !in->uid || !in->row ||
+        !in->col || !in->energy || !in->age || !in->streak ||
+        (n > 0 && (!in->h || !in->theta || !in->last_action || !in->ate)))
+        return "loading needs the full state";
+    if (in->step < 0) return "negative step";
+    const size_t HW = size_t(c.H) * c.W;
+    for (size_t i = 0; i < HW; ++i)
+        if (in->R[i] > 1) return "resource bytes must be 0 or 1";
+    std::vector<uint8_t> held(c.dynamics == WORLD_DYN_PAPER ? 0 : HW, 0);
+    for (int i = 0; i < n; ++i) {
+        if (in->row[i] < 0 || in->row[i] >= c.H || in->col[i] < 0 || in->col[i] >= c.W) return "agent outside the grid";
+        if (i > 0 && in->uid[i] <= in->uid[i - 1]) return "uids must increase";
+        if (in->uid[i] >= in->next_uid) return "uid >= next_uid";
+        if (in->age[i] < 0) return "negative age";
+        if (in->last_action[i] > kNoAction || in->ate[i] > 1) return "last_action must be 0..5 and ate 0 or 1";
+        if (c.dynamics != WORLD_DYN_PAPER) {
+            const size_t cell = size_t(in->row[i]) * c.W + in->col[i];
+            if (held[cell]) return "two agents in one cell";
+            held[cell] = 1;
+        }
+    }
+    return nullptr;
+}
+
 // =========================================================================
 // C-ABI
 // =========================================================================
 
 extern "C" {
 
-int world_required_bytes(const world_config* cfg, size_t* device_bytes) {
-    if (!device_bytes) return fail(nullptr, WORLD_E_INVALID_ARG, "device_bytes is NULL");
+int world_required_bytes(const world_config* cfg, size_t* device_bytes, size_t* snapshot_bytes) {
+    if (!device_bytes && !snapshot_bytes)
+        return fail(nullptr, WORLD_E_INVALID_ARG, "device_bytes and snapshot_bytes are both NULL");
     if (const char* m = check_config(cfg)) return fail(nullptr, WORLD_E_INVALID_CONFIG, m);
-    *device_bytes = layout_of(*cfg).total;
+    if (device_bytes) *device_bytes = layout_of(*cfg).total;
+    if (snapshot_bytes) *snapshot_bytes = snapshot_bytes_of(*cfg, dims_of(*cfg));
     return WORLD_OK;
 }
 
@@ -541,6 +587,10 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
     d.lb_move = reinterpret_cast<uint64_t*>(b + lay.lb_move);
     d.lb_claim = reinterpret_cast<uint64_t*>(b + lay.lb_claim);
     d.res_part = reinterpret_cast<int32_t*>(b + lay.res_part);
+    d.rows_part = reinterpret_cast<int32_t*>(b + lay.rows_part);
+    d.forced_tab = reinterpret_cast<const int8_t*>(b + lay.forced);
+    d.n_forced = 0;
+    d.forced_on = 0;
     d.ntiles = ((c.H + kTile - 1) / kTile) * ((c.W + kTile - 1) / kTile);
     w->d_dev = reinterpret_cast<WorldDev*>(b + lay.desc);
 
@@ -706,6 +756,8 @@ static std::mutex g_batch_mu;
 static std::map<std::vector<uintptr_t>, BatchEntry*> g_batches;
 static uint64_t g_batch_clock = 0;
 
+constexpr size_t kBatchKeyWords = 7;   // key words per world (the handle first)
+
 static std::vector<uintptr_t> batch_key(world_t* const* ws, int n) {
     std::vector<uintptr_t> key;
     for (int i = 0; i < n; ++i) {
@@ -857,31 +909,15 @@ int world_snapshot(world_t* w, world_image* out) {
 int world_load(world_t* w, const world_image* in) {
     if (!w || !in) return fail(w, WORLD_E_INVALID_ARG, "NULL argument");
     if (w->poisoned) return WORLD_E_POISONED;
-    if (in->struct_size != sizeof(world_image)) return fail(w, WORLD_E_INVALID_ARG, "world_image.struct_size mismatch");
     const world_config& c = w->cfg;
+    if (const char* m = image_problem(c, in)) return fail(w, WORLD_E_INVALID_ARG, m);
     const int n = in->n_live;
-    if (n < 0 || n > c.cap) return fail(w, WORLD_E_INVALID_ARG, "n_live out of range");
-    if (!(in->flags & WORLD_SNAP_HIDDEN) || !(in->flags & WORLD_SNAP_THETA) || !in->R || !in->uid || !in->row ||
-        !in->col || !in->energy || !in->age || !in->streak ||
-        (n > 0 && (!in->h || !in->theta || !in->last_action || !in->ate)))
-        return fail(w, WORLD_E_INVALID_ARG, "world_load needs the full state");
-    if (in->step < 0) return fail(w, WORLD_E_INVALID_ARG, "negative step");
     const size_t HW = size_t(c.H) * c.W;
     std::vector<int32_t> occ(HW, -1), cells(c.cap, 0), live(c.cap, 0), freeq(c.cap, 0);
     for (int i = 0; i < n; ++i) {
-        if (in->row[i] < 0 || in->row[i] >= c.H || in->col[i] < 0 || in->col[i] >= c.W)
-            return fail(w, WORLD_E_INVALID_ARG, "agent outside the grid");
-        if (i > 0 && in->uid[i] <= in->uid[i - 1]) return fail(w, WORLD_E_INVALID_ARG, "uids must increase");
-        if (in->uid[i] >= in->next_uid) return fail(w, WORLD_E_INVALID_ARG, "uid >= next_uid");
         const int cell = in->row[i] * c.W + in->col[i];
-        if (in->last_action[i] > kNoAction || in->ate[i] > 1)
-            return fail(w, WORLD_E_INVALID_ARG, "last_action must be 0..5 and ate 0 or 1");
-        if (c.dynamics == WORLD_DYN_PAPER) {
-            occ[cell] += 1;   // agents on the cell minus one (-1 = empty)
-        } else {
-            if (occ[cell] != -1) return fail(w, WORLD_E_INVALID_ARG, "two agents in one cell");
-            occ[cell] = i;
-        }
+        if (c.dynamics == WORLD_DYN_PAPER) occ[cell] += 1;   // agents on the cell minus one (-1 = empty)
+        else occ[cell] = i;
         cells[i] = cell;
         live[i] = i;
     }
@@ -957,6 +993,13 @@ int world_load(world_t* w, const world_image* in) {
     return WORLD_OK;
 }
 
+int world_validate_image(const world_config* cfg, const world_image* in) {
+    if (!in) return fail(nullptr, WORLD_E_INVALID_ARG, "image is NULL");
+    if (const char* m = check_config(cfg)) return fail(nullptr, WORLD_E_INVALID_CONFIG, m);
+    if (const char* m = image_problem(*cfg, in)) return fail(nullptr, WORLD_E_INVALID_ARG, m);
+    return WORLD_OK;
+}
+
 int world_counters_get(world_t* w, int64_t first, int32_t n, world_counters* out) {
     if (!w || (!out && n > 0)) return fail(w, WORLD_E_INVALID_ARG, "NULL argument");
     if (w->poisoned) return WORLD_E_POISONED;
@@ -981,7 +1024,7 @@ int world_counters_get(world_t* w, int64_t first, int32_t n, world_counters* out
         out[i].claim_wins = r[kCtrWins];
         out[i].dead_age_sum = int64_t((uint64_t(uint32_t(r[kCtrDeadAgeHi])) << 32) | uint32_t(r[kCtrDeadAgeLo]));
         out[i].seen_resource = r[kCtrSeen];
-        out[i].reserved = 0;
+        out[i].rows_read = r[kCtrRows];
     }
     return WORLD_OK;
 }
@@ -1008,6 +1051,22 @@ int world_move_hist(world_t* w, int64_t first, int32_t n, int32_t* out) {
 int world_destroy(world_t* w) {
     if (!w) return WORLD_OK;
     (void)hipStreamSynchronize(w->stream);
+    {
+        // launch tables and graphs of batches that list this world go with it
+        // (their streams are synchronised before anything is released)
+        std::lock_guard<std::mutex> lk(g_batch_mu);
+        const uintptr_t key = reinterpret_cast<uintptr_t>(w);
+        for (auto it = g_batches.begin(); it != g_batches.end();) {
+            bool has = false;
+            for (size_t i = 0; i < it->first.size(); i += kBatchKeyWords) has = has || it->first[i] == key;
+            if (has) {
+                release_entry(it->second);
+                it = g_batches.erase(it);
+            } else {
+                ++it;
+            }
+        }
+    }
     for (auto& kv : w->graphs) (void)hipGraphExecDestroy(kv.second);
     for (auto& kv : w->graph_defs) (void)hipGraphDestroy(kv.second);
     delete w;
@@ -1019,15 +1078,42 @@ const char* world_last_error(const world_t* w) {
     return g_thread_err.c_str();
 }
 
+// Writes the forced-action fields of the descriptor (forced, n_forced,
+// forced_on are contiguous) after the table, once the stream is idle.
+static int write_forced(world* w, const int8_t* tab, int32_t n, int32_t dflt) {
+    HIP_TRY(w, hipStreamSynchronize(w->stream));
+    if (n > 0) HIP_TRY(w, hipMemcpy(w->base + w->lay.forced, tab, size_t(n), hipMemcpyHostToDevice));
+    w->dev.forced = dflt;
+    w->dev.n_forced = n;
+    w->dev.forced_on = (dflt >= 0 || n > 0) ? 1 : 0;
+    static_assert(offsetof(WorldDev, n_forced) == offsetof(WorldDev, forced) + 4 &&
+                      offsetof(WorldDev, forced_on) == offsetof(WorldDev, forced) + 8,
+                  "forced fields must be contiguous");
+    HIP_TRY(w, hipMemcpy(w->base + w->lay.desc + offsetof(WorldDev, forced), &w->dev.forced, 12,
+                         hipMemcpyHostToDevice));
+    return WORLD_OK;
+}
+
 int world_set_forced_action(world_t* w, int32_t action) {
     if (!w) return fail(nullptr, WORLD_E_INVALID_ARG, "world is NULL");
     if (w->poisoned) return WORLD_E_POISONED;
     if (action < -1 || action > 4) return fail(w, WORLD_E_INVALID_ARG, "action must be -1..4");
-    w->dev.forced = action;
-    HIP_TRY(w, hipStreamSynchronize(w->stream));
-    HIP_TRY(w, hipMemcpy(w->base + w->lay.desc + offsetof(WorldDev, forced), &action, sizeof(action),
-                         hipMemcpyHostToDevice));
-    return WORLD_OK;
+    return write_forced(w, nullptr, 0, action);
+}
+
+int world_set_forced_actions(world_t* w, const int32_t* act_by_uid, int32_t n, int32_t default_action) {
+    if (!w) return fail(nullptr, WORLD_E_INVALID_ARG, "world is NULL");
+    if (w->poisoned) return WORLD_E_POISONED;
+    if (n < 0 || (n > 0 && !act_by_uid)) return fail(w, WORLD_E_INVALID_ARG, "n < 0 or a NULL table");
+    if (n > forced_capacity(w->cfg))
+        return fail(w, WORLD_E_INVALID_ARG, "table longer than max(4 * cap, 4096) uids");
+    if (default_action < -1 || default_action > 4) return fail(w, WORLD_E_INVALID_ARG, "default must be -1..4");
+    std::vector<int8_t> tab(size_t(std::max(n, 1)));
+    for (int i = 0; i < n; ++i) {
+        if (act_by_uid[i] < -1 || act_by_uid[i] > 4) return fail(w, WORLD_E_INVALID_ARG, "actions must be -1..4");
+        tab[size_t(i)] = int8_t(act_by_uid[i]);
+    }
+    return write_forced(w, tab.data(), n, default_action);
 }
 
 int world_test_stall_lookback(world_t* w, int32_t tile, uint32_t spin_ticks) {
@@ -1046,7 +1132,7 @@ int world_test_stall_lookback(world_t* w, int32_t tile, uint32_t spin_ticks) {
 }
 
 int world_action_log(world_t* w, int64_t step, int32_t capacity, uint32_t* uid, uint8_t* action, float* logits,
-                     int32_t* n) {
+                     float* margin, int32_t* n) {
     if (!w || !n) return fail(w, WORLD_E_INVALID_ARG, "NULL argument");
     if (w->poisoned) return WORLD_E_POISONED;
     const world_config& c = w->cfg;
@@ -1065,6 +1151,33 @@ int world_action_log(world_t* w, int64_t step, int32_t capacity, uint32_t* uid, 
     if (action) HIP_TRY(w, hipMemcpy(action, w->base + w->lay.log_act + base, size_t(cnt), hipMemcpyDeviceToHost));
     if (logits)
         HIP_TRY(w, hipMemcpy(logits, w->base + w->lay.log_logits + 4 * 5 * base, 4 * 5 * size_t(cnt), hipMemcpyDeviceToHost));
+    if (margin && cnt > 0) {
+        // the device's decision values: the logits (GRU, arg-max) or the
+        // sampling scores 50 l + g of the paper's network, whose Gumbel terms
+        // g the same counter-based draws give on the host bit for bit
+        std::vector<float> lg(size_t(cnt) * 5);
+        std::vector<uint32_t> us(static_cast<size_t>(cnt));
+        HIP_TRY(w, hipMemcpy(lg.data(), w->base + w->lay.log_logits + 4 * 5 * base, 4 * lg.size(), hipMemcpyDeviceToHost));
+        HIP_TRY(w, hipMemcpy(us.data(), w->base + w->lay.log_uid + 4 * base, 4 * us.size(), hipMemcpyDeviceToHost));
+        const bool net_ctrl = is_net(c);
+        for (int i = 0; i < cnt; ++i) {
+            float sc[5];
+            for (int a = 0; a < 5; ++a) sc[a] = lg[size_t(i) * 5 + a];
+            if (net_ctrl) {
+                const Draw4 d0 = philox(us[size_t(i)], uint32_t(step), kAct, 0u, w->dev.seed_lo, w->dev.seed_hi);
+                const Draw4 d1 = philox(us[size_t(i)], uint32_t(step), kAct, 1u, w->dev.seed_lo, w->dev.seed_hi);
+                const uint32_t words[5] = {d0.x, d0.y, d0.z, d0.w, d1.x};
+                for (int a = 0; a < 5; ++a) sc[a] = 50.0f * sc[a] + gumbel_of_word(words[a]);
+            }
+            int best = 0;
+            for (int a = 1; a < 5; ++a)
+                if (sc[a] > sc[best]) best = a;
+            float second = -INFINITY;
+            for (int a = 0; a < 5; ++a)
+                if (a != best && sc[a] > second) second = sc[a];
+            margin[i] = sc[best] - second;
+        }
+    }
     return WORLD_OK;
 }
 
@@ -1150,7 +1263,9 @@ int world_test_copy(const void* src, void* dst, size_t bytes, void* stream) {
     return WORLD_OK;
 }
 
-int world_step_many(world_t* const* ws, int32_t n, int32_t K) {
+// Checks shared by the batched entry points: a non-empty list of distinct,
+// healthy worlds on one stream with one controller and one rule set.
+static int check_batch(world_t* const* ws, int32_t n, int32_t K) {
     if (!ws || n < 1) return fail(nullptr, WORLD_E_INVALID_ARG, "empty world list");
     if (K < 1) return fail(nullptr, WORLD_E_INVALID_ARG, "K must be >= 1");
     for (int i = 0; i < n; ++i) {
@@ -1160,6 +1275,18 @@ int world_step_many(world_t* const* ws, int32_t n, int32_t K) {
         if (ws[i]->cfg.controller != ws[0]->cfg.controller || ws[i]->cfg.dynamics != ws[0]->cfg.dynamics)
             return fail(nullptr, WORLD_E_INVALID_ARG, "worlds of one batch must use the same controller and dynamics");
     }
+    {
+        // a world listed twice would be stepped by two block ranges at once
+        std::vector<const world*> sorted(ws, ws + n);
+        std::sort(sorted.begin(), sorted.end());
+        if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+            return fail(nullptr, WORLD_E_INVALID_ARG, "a world is listed twice");
+    }
+    return WORLD_OK;
+}
+
+int world_step_many(world_t* const* ws, int32_t n, int32_t K) {
+    if (int rc = check_batch(ws, n, K)) return rc;
     return batch_step(ws, n, K);
 }
 

@@ -38,13 +38,18 @@ constexpr uint32_t kSpinTicks = 200000000u;   // look-back wait bound: 2 s at th
 
 // Counter record fields (match world_counters in world.h).
 enum : int { kCtrLive = 0, kCtrBirths, kCtrDeaths, kCtrEaten, kCtrRes, kCtrWins, kCtrDeadAgeLo, kCtrDeadAgeHi,
-             kCtrSeen };
+             kCtrSeen, kCtrRows };
 
 // The act phase marks in the agent record's action word whether the agent had
 // a resource in its field of view (greediness of the lab environments, Sec.
 // 2.2); the move phase counts and strips the mark.
 constexpr int kSeenBit = 1 << 8;
 constexpr int kActMask = 0xFF;
+// The GRU act phase also stores there how many input rows of W_ih it read
+// (window rows and window totals, at most 2 * 25); the move phase sums them
+// per step into the counter ring (the bytes the step really read).
+constexpr int kRowsShift = 9;
+constexpr int kRowsMask = 0x7F;
 
 // Movement metric (App. C): windows of kMoveWin steps (window k covers steps
 // [k * kMoveWin, (k + 1) * kMoveWin)), distances binned by 3 into kMoveBins
@@ -118,7 +123,9 @@ struct WorldDev {
     int32_t E0, decay, gain, E_repr, T_repr, L_max;
     float sigma;
     uint32_t seed_lo, seed_hi;
-    int32_t forced;     // forced action or -1
+    int32_t forced;     // forced action of every agent not in forced_tab, or -1 (the controller decides)
+    int32_t n_forced;   // entries of forced_tab (forced action by uid, -1 = use `forced`)
+    int32_t forced_on;  // forced >= 0 || n_forced > 0
     int32_t log_steps;
     int32_t off_hh, off_bih, off_bhh, off_wo, off_bo;  // genome offsets (floats)
     int32_t nblk;       // float4 blocks per genome, ceil(P / 4)
@@ -171,6 +178,8 @@ struct WorldDev {
     uint32_t* wuid;       // per slot: uid of the agent the window start was recorded for
     int32_t* mhist;       // kMoveRing x (kMoveBins + 1) movement histograms
     int32_t* res_part;    // per-tile resource counts of the regrowth phase
+    int32_t* rows_part;   // per-wave sums of the input rows read by the act phase (cap / 64)
+    const int8_t* forced_tab;   // test hook: forced action by uid (n_forced entries)
     int32_t ntiles;       // regrowth tiles
     int32_t pad1;
 };

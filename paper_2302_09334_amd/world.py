@@ -54,7 +54,7 @@ class Config(C.Structure):
 class Counters(C.Structure):
     _fields_ = [("n_live", C.c_int32), ("births", C.c_int32), ("deaths", C.c_int32),
                 ("eaten", C.c_int32), ("resources", C.c_int32), ("claim_wins", C.c_int32),
-                ("dead_age_sum", C.c_int64), ("seen_resource", C.c_int32), ("reserved", C.c_int32)]
+                ("dead_age_sum", C.c_int64), ("seen_resource", C.c_int32), ("rows_read", C.c_int32)]
 
 MOVE_WINDOW = 50   # steps per movement window (App. C)
 MOVE_BINS = 17     # distance bins of a movement window
@@ -78,6 +78,7 @@ EXPORTS = [
     "world_destroy", "world_last_error", "world_set_forced_action", "world_action_log",
     "world_test_philox", "world_test_gauss", "world_threshold_table", "world_phase_times",
     "world_test_copy", "world_move_hist", "world_test_gumbel", "world_test_stall_lookback",
+    "world_set_forced_actions", "world_validate_image",
 ]
 
 _lib = None
@@ -91,7 +92,7 @@ def lib():
                                "g.build()'` (there is no CPU fallback)")
         L = C.CDLL(LIB_PATH)
         P = C.c_void_p
-        L.world_required_bytes.argtypes = [C.POINTER(Config), C.POINTER(C.c_size_t)]
+        L.world_required_bytes.argtypes = [C.POINTER(Config), C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
         L.world_dims.argtypes = [C.POINTER(Config), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.world_create.argtypes = [C.POINTER(Config), C.c_uint64, P, C.c_size_t, P, C.POINTER(P)]
         L.world_step.argtypes = [P, C.c_int32]
@@ -107,7 +108,9 @@ def lib():
         L.world_last_error.argtypes = [P]
         L.world_last_error.restype = C.c_char_p
         L.world_set_forced_action.argtypes = [P, C.c_int32]
-        L.world_action_log.argtypes = [P, C.c_int64, C.c_int32, P, P, P, C.POINTER(C.c_int32)]
+        L.world_action_log.argtypes = [P, C.c_int64, C.c_int32, P, P, P, P, C.POINTER(C.c_int32)]
+        L.world_set_forced_actions.argtypes = [P, P, C.c_int32, C.c_int32]
+        L.world_validate_image.argtypes = [C.POINTER(Config), C.POINTER(Image)]
         L.world_test_philox.argtypes = [P, C.c_size_t, C.c_uint32, C.c_uint32, P, P]
         L.world_test_gauss.argtypes = [P, P, C.c_size_t, P, P, P]
         L.world_threshold_table.argtypes = [C.POINTER(Config), P]
@@ -152,7 +155,15 @@ def state_size(cfg: dict) -> int:
 def required_bytes(cfg: dict) -> int:
     n = C.c_size_t()
     c = make_config(cfg)
-    _check(lib().world_required_bytes(C.byref(c), C.byref(n)))
+    _check(lib().world_required_bytes(C.byref(c), C.byref(n), None))
+    return int(n.value)
+
+
+def snapshot_bytes(cfg: dict) -> int:
+    """Host bytes of a complete image of a world of this configuration."""
+    n = C.c_size_t()
+    c = make_config(cfg)
+    _check(lib().world_required_bytes(C.byref(c), None, C.byref(n)))
     return int(n.value)
 
 
@@ -174,6 +185,40 @@ def _np_ptr(a: np.ndarray):
     return a.ctypes.data_as(C.c_void_p)
 
 
+def image_of(cfg: dict, s: dict):
+    """A world_image over the arrays of a canonical state dict (the keys of
+    World.snapshot(hidden=True, theta=True)); returns (image, arrays to keep
+    alive while the image is used)."""
+    n = int(s["n_live"])
+    P = dims(cfg)[1]
+    arrs = {"R": np.ascontiguousarray(s["R"], np.uint8).ravel(), "uid": np.ascontiguousarray(s["uid"], np.uint32)}
+    for k in ("row", "col", "energy", "age", "streak"):
+        arrs[k] = np.ascontiguousarray(s[k], np.int32)
+    arrs["h"] = np.ascontiguousarray(s["h"], np.float32).reshape(n, state_size(cfg))
+    arrs["last_action"] = np.ascontiguousarray(s["last_action"], np.uint8)
+    arrs["ate"] = np.ascontiguousarray(s["ate"], np.uint8)
+    arrs["theta"] = np.ascontiguousarray(s["theta"], np.float32).reshape(n, P)
+    img = Image()
+    img.struct_size = C.sizeof(Image)
+    img.flags = SNAP_HIDDEN | SNAP_THETA
+    img.step = int(s["t"])
+    img.n_live = n
+    img.next_uid = int(s["next_uid"])
+    img.agent_capacity = n
+    for k, a in arrs.items():
+        setattr(img, k, _np_ptr(a))
+    return img, arrs
+
+
+def validate_image(cfg: dict, s: dict):
+    """Raise WorldError unless world_load would accept the state dict `s` for
+    a world of configuration `cfg` (host only, no device)."""
+    img, keep = image_of(cfg, s)
+    c = make_config(cfg)
+    _check(lib().world_validate_image(C.byref(c), C.byref(img)))
+    del keep
+
+
 class World:
     """One world resident in a torch-allocated device arena."""
 
@@ -185,7 +230,7 @@ class World:
         self._c = make_config(cfg, log_steps)
         self.log_steps = int(self._c.log_steps)
         nbytes = C.c_size_t()
-        _check(lib().world_required_bytes(C.byref(self._c), C.byref(nbytes)))
+        _check(lib().world_required_bytes(C.byref(self._c), C.byref(nbytes), None))
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
         # torch's caching allocator returns 512-byte aligned blocks
@@ -237,6 +282,13 @@ class World:
     def set_forced_action(self, a: int):
         _check(lib().world_set_forced_action(self._h, int(a)), self._h)
 
+    def set_forced_actions(self, act_by_uid, default: int = -1):
+        """Scripted policy: uid u takes act_by_uid[u] when >= 0, else `default`
+        (-1 = the controller)."""
+        a = np.ascontiguousarray(act_by_uid if act_by_uid is not None else [], np.int32)
+        _check(lib().world_set_forced_actions(self._h, _np_ptr(a) if a.size else None, int(a.size), int(default)),
+               self._h)
+
     def test_stall_lookback(self, tile: int, spin_ticks: int = 0):
         """Failure injection: move tile `tile` withholds its look-back word and
         waits end after `spin_ticks` wall-clock ticks (include/world.h)."""
@@ -285,25 +337,9 @@ class World:
         return res
 
     def load(self, s: dict):
-        n = int(s["n_live"])
-        arrs = {"R": np.ascontiguousarray(s["R"], np.uint8).ravel(),
-                "uid": np.ascontiguousarray(s["uid"], np.uint32)}
-        for k in ("row", "col", "energy", "age", "streak"):
-            arrs[k] = np.ascontiguousarray(s[k], np.int32)
-        arrs["h"] = np.ascontiguousarray(s["h"], np.float32).reshape(n, state_size(self.cfg))
-        arrs["last_action"] = np.ascontiguousarray(s["last_action"], np.uint8)
-        arrs["ate"] = np.ascontiguousarray(s["ate"], np.uint8)
-        arrs["theta"] = np.ascontiguousarray(s["theta"], np.float32).reshape(n, self.n_params)
-        img = Image()
-        img.struct_size = C.sizeof(Image)
-        img.flags = SNAP_HIDDEN | SNAP_THETA
-        img.step = int(s["t"])
-        img.n_live = n
-        img.next_uid = int(s["next_uid"])
-        img.agent_capacity = n
-        for k, a in arrs.items():
-            setattr(img, k, _np_ptr(a))
+        img, keep = image_of(self.cfg, s)
         _check(lib().world_load(self._h, C.byref(img)), self._h)
+        del keep
 
     def counters(self, first: int, n: int) -> dict:
         buf = (Counters * max(n, 1))()
@@ -312,6 +348,7 @@ class World:
         out = {k: np.array([getattr(buf[i], k) for i in range(n)], np.int64) for k in keys}
         out["dead_age"] = np.array([buf[i].dead_age_sum for i in range(n)], np.int64)
         out["seen"] = np.array([buf[i].seen_resource for i in range(n)], np.int64)
+        out["rows_read"] = np.array([buf[i].rows_read for i in range(n)], np.int64)
         return out
 
     def move_hist(self, first: int, n: int) -> np.ndarray:
@@ -333,11 +370,13 @@ class World:
         uid = np.empty(cap, np.uint32)
         act = np.empty(cap, np.uint8)
         logits = np.empty((cap, 5), np.float32)
+        margin = np.empty(cap, np.float32)
         n = C.c_int32()
         _check(lib().world_action_log(self._h, int(step), cap, _np_ptr(uid), _np_ptr(act), _np_ptr(logits),
-                                      C.byref(n)), self._h)
+                                      _np_ptr(margin), C.byref(n)), self._h)
         k = int(n.value)
-        return {"uid": uid[:k].copy(), "action": act[:k].copy(), "logits": logits[:k].copy()}
+        return {"uid": uid[:k].copy(), "action": act[:k].copy(), "logits": logits[:k].copy(),
+                "margin": margin[:k].copy()}
 
 
 def step_many(worlds: list[World], K: int = 1):

@@ -89,3 +89,52 @@ def test_network_config_accepted(wlib):
     cfg = dict(workloads.WORKLOADS["cfg0"], controller=1, obs_radius=7, hidden=4)
     assert wlib.dims(cfg) == (675, 2445)
     assert wlib.required_bytes(cfg) > 0
+
+
+def header_prototypes():
+    """name -> parameter list of every call include/world.h declares."""
+    text = open(os.path.join(ROOT, "include", "world.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    out = {}
+    for m in re.finditer(r"\b(world_[a-z_]+)\s*\(([^)]*)\)\s*;", text):
+        params = [p.strip() for p in m.group(2).split(",") if p.strip() and p.strip() != "void"]
+        out[m.group(1)] = params
+    return out
+
+
+def test_binding_signatures_match_header(wlib):
+    """The binding marshals exactly the parameters the header declares."""
+    protos = header_prototypes()
+    L = wlib.lib()
+    assert set(protos) == set(wlib.EXPORTS)
+    for name, params in protos.items():
+        assert len(getattr(L, name).argtypes) == len(params), (name, params)
+    assert protos["world_required_bytes"][-1].endswith("*snapshot_bytes")
+    assert "float *margin" in protos["world_action_log"]
+    assert protos["world_set_forced_actions"] == ["world_t *w", "const int32_t *act_by_uid", "int32_t n",
+                                                  "int32_t default_action"]
+
+
+def test_snapshot_bytes(wlib):
+    """world_required_bytes reports the host bytes of a full image at capacity:
+    the grid, six int32 agent arrays, the recurrent state, the genome and two
+    byte arrays per slot."""
+    from paper_2302_09334_amd import workloads
+    for name in ("cfg0", "m1_4k", "net_m1_4k", "paper1k"):
+        cfg = workloads.WORKLOADS[name]
+        _, P = wlib.dims(cfg)
+        want = cfg["H"] * cfg["W"] + cfg["cap"] * (6 * 4 + 4 * wlib.state_size(cfg) + 4 * P + 2)
+        assert wlib.snapshot_bytes(cfg) == want, name
+    c = wlib.make_config(workloads.WORKLOADS["cfg0"])
+    assert wlib.lib().world_required_bytes(ctypes.byref(c), None, None) == -1
+
+
+def test_null_handles_rejected(wlib):
+    """Every call that takes a world rejects NULL with WORLD_E_INVALID_ARG."""
+    L = wlib.lib()
+    assert L.world_step(None, 1) == -1
+    assert L.world_set_forced_actions(None, None, 0, -1) == -1
+    assert L.world_set_forced_action(None, 0) == -1
+    assert L.world_step_many(None, 0, 1) == -1
+    assert L.world_sync(None) == -1
+    assert L.world_destroy(None) == 0

@@ -78,3 +78,41 @@ def test_cpu_baseline_fields(bench, oracle_lib):
     assert out["kind"] == "oracle" and out["cores"] == 1 and out["unit"] == "agent-steps/s"
     assert out["value"] > 0 and 1 <= out["host_cores"] <= os.cpu_count()
     assert "steps 0.." in out["sample"]
+
+
+def test_step_bytes_closed_form(bench):
+    """Step bytes of the sparse-input count: per acting agent W_hh, both
+    biases, the head, h in and out with 40 bytes of scalars, the energy row;
+    per input row read 3*hd floats; per birth two genomes; the grid."""
+    cfg = {"hidden": 32, "H": 200, "W": 400}
+    P = 12933
+    hd = 32
+    per_agent = 4 * (3 * hd * hd + 3 * hd + 3 * hd + 5 * hd + 5) + 8 * hd + 40 + 4 * 3 * hd
+    got = bench.step_algorithmic_bytes(cfg, P, np.array([4608, 4600]), np.array([100000, 0]), np.array([5, 0]))
+    want = np.array([4608 * per_agent + 100000 * 384 + 5 * 8 * P, 4600 * per_agent]) + 200 * 400 * 10
+    assert np.allclose(got, want)
+
+
+def test_kernel_window_bytes(bench):
+    """The act kernel's bytes are its per-agent bytes without input rows,
+    plus the rows the device counted, the children's genomes and the grid;
+    the projection splits 3/8 (move) and 5/8 of the survivors (claim)."""
+    cfg = {"hidden": 16, "H": 10, "W": 20}
+    P = 1000
+    kb = bench.kernel_window_bytes(cfg, P, np.array([100, 100]), np.array([1000, 3000]), np.array([2, 0]),
+                                   np.array([8, 0]), np.array([1, 3]))
+    rw = 3 * 16 * 4
+    act = 100 * bench.act_bytes_per_agent(cfg, 0.0) + 2000 * rw + 1 * 8 * P + 200 * 5
+    assert kb["act"] == pytest.approx(act)
+    pb = bench.proj_bytes_per_agent(cfg)
+    assert kb["move"] == pytest.approx(100 * (bench.MOVE_BYTES_PER_AGENT + 3 / 8 * pb))
+    claim = 5 / 8 * 96 * pb + 100 * bench.CLAIM_BYTES_PER_AGENT + 2 * bench.CLAIM_BYTES_PER_ELIGIBLE + 2 * 200
+    assert kb["claim"] == pytest.approx(claim)
+
+
+def test_traffic_per_agent_tied_to_sources(bench, tmp_path):
+    p = tmp_path / "t.txt"
+    p.write_text("hbm_bytes_per_acting_agent_rows8: 12345.5\nkernel_source_sha256_16: abc\n")
+    assert bench.read_traffic_per_agent("abc", 8, str(p)) == 12345.5
+    assert bench.read_traffic_per_agent("abc", 16, str(p)) is None
+    assert bench.read_traffic_per_agent("xyz", 8, str(p)) is None
