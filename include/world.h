@@ -222,6 +222,20 @@ int world_step(world_t *w, int32_t K);
  * WORLD_E_INVALID_ARG, WORLD_E_POISONED, WORLD_E_HIP. */
 int world_step_many(world_t *const *ws, int32_t n, int32_t K);
 
+/* world_step_many for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same steps and results (bit-identical to stepping each world alone),
+ * launched as per-phase kernels whatever the worlds' mode, with the batch's
+ * launch table written into a fixed device array of the library (48 KB per
+ * GPU, held until the process ends) by small kernels whose arguments carry
+ * it -- no hipMalloc, hipFree, host-to-device copy or graph instantiation.
+ * At most 2048 worlds per call (WORLD_E_INVALID_ARG beyond).  Call it with
+ * the worlds' device current.  Every call on one GPU shares the array and
+ * rewrites all of it before its kernels read it: calls that overlap on one
+ * GPU (other streams or threads) race and must not be issued.  Errors as
+ * world_step_many. */
+int world_step_many_noalloc(world_t *const *ws, int32_t n, int32_t K);
+
 /* Select WORLD_MODE_* for later steps (how the App. B step is launched:
  * per-phase kernels, or K steps captured once into a HIP graph and replayed;
  * results are identical).  Errors: WORLD_E_INVALID_ARG. */

@@ -1290,4 +1290,94 @@ int world_step_many(world_t* const* ws, int32_t n, int32_t K) {
     return batch_step(ws, n, K);
 }
 
+// ---- batched steps without allocation -----------------------------------
+// world_step_many keeps each batch's launch table in device memory it
+// allocates (and caches).  For callers that cannot allocate (graph capture,
+// tight serving loops), world_step_many_noalloc writes the table into a
+// fixed device array instead, with small fill kernels whose arguments carry
+// the table (no copy from host memory), and launches the per-phase kernels
+// (no graph instantiation).  Each GPU holds its own copy of the array for the
+// life of the process; its device address comes from hipGetSymbolAddress,
+// once per device.  Every call rewrites the whole table before its step
+// kernels read it; calls that overlap on one GPU (other streams or threads)
+// race on it.
+constexpr int kNoAllocMaxWorlds = 2048;
+constexpr size_t kScratchBytes = 49152;
+static_assert(kScratchBytes >= (sizeof(void*) * kNoAllocMaxWorlds + 15) / 16 * 16 +
+                                   sizeof(int) * size_t(kPreKinds) * (kNoAllocMaxWorlds + 1),
+              "scratch holds the launch table of the largest batch");
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+constexpr int kFillChunk = 96;   // worlds per fill launch (arguments stay under 4 KB)
+struct TableChunk {
+    int n_total;                          // worlds in the table
+    int first;                            // first world of this chunk
+    int count;                            // worlds in this chunk
+    const WorldDev* w[kFillChunk];        // their descriptors
+    int pre[kPreKinds][kFillChunk + 1];   // prefix entries first .. first + count
+};
+static_assert(sizeof(TableChunk) < 4000, "kernel arguments");
+
+__global__ void k_fill_table(char* table, TableChunk c) {
+    const int i = threadIdx.x;
+    const size_t ptr_bytes = (sizeof(void*) * size_t(c.n_total) + 15) / 16 * 16;
+    const WorldDev** wp = reinterpret_cast<const WorldDev**>(table);
+    int* pre = reinterpret_cast<int*>(table + ptr_bytes);
+    if (i < c.count) wp[c.first + i] = c.w[i];
+    if (i <= c.count)
+        for (int k = 0; k < kPreKinds; ++k) pre[k * (c.n_total + 1) + c.first + i] = c.pre[k][i];
+}
+
+static std::mutex g_scratch_mu;
+static std::map<int, char*> g_scratch_addr;   // device -> address of its `scratch`
+
+// Device address of the current device's `scratch` (looked up once per device).
+static int scratch_address(char** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(nullptr, WORLD_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_addr.find(dev);
+    if (it == g_scratch_addr.end()) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr)
+            return fail(nullptr, WORLD_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        it = g_scratch_addr.emplace(dev, static_cast<char*>(p)).first;
+    }
+    *out = it->second;
+    return WORLD_OK;
+}
+
+int world_step_many_noalloc(world_t* const* ws, int32_t n, int32_t K) {
+    if (int rc = check_batch(ws, n, K)) return rc;
+    if (n > kNoAllocMaxWorlds) return fail(nullptr, WORLD_E_INVALID_ARG, "more than 2048 worlds in one batch");
+    char* table = nullptr;
+    if (int rc = scratch_address(&table)) return rc;
+    world* w0 = ws[0];
+    hipStream_t s = w0->stream;
+    std::vector<const world*> list(ws, ws + n);
+    const std::vector<int> bp = batch_prefix(list);
+    int slots = 0;
+    for (const world* x : list) slots += x->cfg.cap;
+    for (int first = 0; first < n; first += kFillChunk) {
+        TableChunk c;
+        std::memset(&c, 0, sizeof(c));
+        c.n_total = n;
+        c.first = first;
+        c.count = std::min(kFillChunk, n - first);
+        for (int i = 0; i < c.count; ++i) c.w[i] = list[size_t(first + i)]->d_dev;
+        for (int k = 0; k < kPreKinds; ++k)
+            for (int i = 0; i <= c.count; ++i) c.pre[k][i] = bp[size_t(k) * (n + 1) + first + i];
+        hipLaunchKernelGGL(k_fill_table, dim3(1), dim3(128), 0, s, table, c);
+    }
+    HIP_TRY(w0, hipGetLastError());
+    const size_t ptr_bytes = align_up(sizeof(void*) * size_t(n), 16);
+    Batch b{reinterpret_cast<const WorldDev* const*>(table), reinterpret_cast<const int*>(table + ptr_bytes), n,
+            w0->act_rows, n == 1 ? static_cast<const WorldDev*>(w0->d_dev) : nullptr, w0->cfg.cap, w0->dev.ctrl,
+            w0->dev.dyn, net_wide(slots)};
+    for (int k = 0; k < K; ++k) HIP_TRY(w0, launch_step(b, bp.data(), n, s));
+    return WORLD_OK;
+}
+
 }  // extern "C"

@@ -78,7 +78,7 @@ EXPORTS = [
     "world_destroy", "world_last_error", "world_set_forced_action", "world_action_log",
     "world_test_philox", "world_test_gauss", "world_threshold_table", "world_phase_times",
     "world_test_copy", "world_move_hist", "world_test_gumbel", "world_test_stall_lookback",
-    "world_set_forced_actions", "world_validate_image",
+    "world_set_forced_actions", "world_validate_image", "world_step_many_noalloc",
 ]
 
 _lib = None
@@ -97,6 +97,7 @@ def lib():
         L.world_create.argtypes = [C.POINTER(Config), C.c_uint64, P, C.c_size_t, P, C.POINTER(P)]
         L.world_step.argtypes = [P, C.c_int32]
         L.world_step_many.argtypes = [C.POINTER(P), C.c_int32, C.c_int32]
+        L.world_step_many_noalloc.argtypes = [C.POINTER(P), C.c_int32, C.c_int32]
         L.world_set_mode.argtypes = [P, C.c_int32]
         L.world_set_tuning.argtypes = [P, C.c_int32]
         L.world_set_stream.argtypes = [P, P]
@@ -383,6 +384,16 @@ def step_many(worlds: list[World], K: int = 1):
     """Advance several worlds (same stream) by K steps in shared launches."""
     arr = (C.c_void_p * len(worlds))(*[w.handle for w in worlds])
     rc = lib().world_step_many(arr, len(worlds), int(K))
+    if rc != WORLD_OK:
+        _check(rc, worlds[0].handle if rc != -1 else None)
+
+
+def step_many_noalloc(worlds: list[World], K: int = 1):
+    """world_step_many without device allocation (per-phase launches; the
+    launch table in the library's fixed device array): for code under graph
+    capture or serving loops that must not allocate."""
+    arr = (C.c_void_p * len(worlds))(*[w.handle for w in worlds])
+    rc = lib().world_step_many_noalloc(arr, len(worlds), int(K))
     if rc != WORLD_OK:
         _check(rc, worlds[0].handle if rc != -1 else None)
 
