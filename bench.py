@@ -179,9 +179,10 @@ def kernel_window_bytes(cfg: dict, P: int, acting, rows_read, births_prev, death
 
 
 def read_traffic_per_agent(src_hash: str, rows, path: str = TRAFFIC_FILE):
-    """HBM bytes per acting agent of the act kernel compiled for `rows` input
-    rows per round trip, from the committed counter summary (measured on the
-    same bench window), or None when the kernel sources changed since."""
+    """HBM bytes per acting agent of the act kernel variant `rows` (input rows
+    per round trip, or "rows_waves" with the agents per block), from the
+    committed counter summary (measured on the same bench window), or None
+    when the kernel sources changed since."""
     if not os.path.exists(path):
         return None
     kv = {}
@@ -439,9 +440,16 @@ def served_run(args) -> dict:
     log(f"[bench] served: {len(reqs)} requests over {args.serve_seconds:.0f} s of arrivals")
     be = serve.HipBackend(mode="kernels")
     srv = serve.Server(be, budget_bytes=int(args.serve_budget_gb * 1e9), K=50)
-    results, m = srv.run(reqs, duration=args.serve_seconds, realtime=True)
+    results, m = srv.run(reqs, duration=args.serve_seconds, realtime=True,
+                         progress=lambda t, done, act, q: log(f"[bench] served t={t:.0f} s: {done} done, "
+                                                              f"{act} active, {q} waiting"))
+    be.shutdown()
+    m["fixture"] = ("M4: Poisson(20/s) arrivals for 600 s" if args.serve_seconds >= 600 else
+                    f"M4 truncated to {args.serve_seconds:.0f} s of arrivals (the full 600 s run: "
+                    "profiles/served_cfg4_600s.txt)")
     m["arrival_window_s"] = args.serve_seconds
     m["rate_hz"] = 20.0
+    m["offered_steps_per_s"] = 20.0 * float(np.mean([r.steps for r in reqs])) if reqs else 0.0
     log(f"[bench] served {m['requests']} requests: {m['agent_steps_per_s'] / 1e6:.1f} M agent-steps/s, "
         f"p50 {m['step_ms_p50']:.3f} ms p99 {m['step_ms_p99']:.3f} ms per step")
     return m
@@ -589,6 +597,31 @@ FIXTURE_STEPS = 1000
 PARITY_STEPS_M1_4K = 2200
 
 
+class OneWorld:
+    """One world seen through the batch interface the autotuner drives."""
+
+    def __init__(self, w):
+        self.w = w
+
+    def snapshots(self):
+        return self.w.snapshot(hidden=True, theta=True)
+
+    def load(self, s):
+        self.w.load(s)
+
+    def set_mode(self, m):
+        self.w.set_mode(m)
+
+    def set_tuning(self, rows, waves, tile):
+        self.w.set_tuning(rows, waves, tile)
+
+    def step(self, k):
+        self.w.step(k)
+
+    def sync(self):
+        self.w.sync()
+
+
 def headline_run(args) -> dict:
     """The headline: m1_4k prepared by its 1000 fixture steps, --warmup more
     untimed steps, then exactly --steps timed steps (graph launches of
@@ -617,26 +650,25 @@ def headline_run(args) -> dict:
     run(args.fixture_steps, "graph")
     w.sync()
     prep = w.snapshot(hidden=True, theta=True)
-    # pick the launch mode and the act kernel's rows per round trip (both
-    # leave every result unchanged) on 200 steps from the prepared state
-    modes = ["graph", "kernels"] if args.mode == "auto" else [args.mode]
-    calib = {}
-    for m in modes:
-        for rows in ((8, 16, 32) if args.rows == 0 else (args.rows,)):
-            w.set_tuning(rows)
-            w.load(prep)
-            run(args.chunk, m)   # capture / first launch
-            w.sync()
-            w.load(prep)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            run(200, m)
-            w.sync()
-            calib[f"{m}/rows{rows}"] = (time.perf_counter() - t0) / 200 * 1e3
-            log(f"[bench] {m} rows {rows}: {calib[f'{m}/rows{rows}'] * 1e3:.1f} us/step")
-    best_key = min(calib, key=calib.get)
-    best, best_rows = best_key.split("/rows")[0], int(best_key.split("/rows")[1])
-    w.set_tuning(best_rows)
+    # pick the launch mode and shape (act rows per round trip, agents per act
+    # block, regrowth tile edge; none changes any result) with the project's
+    # autotuner: a coordinate descent, each trial 200 steps from the prepared
+    # state
+    from paper_2302_09334_amd import tune
+    one = OneWorld(w)
+    if args.shape:
+        r_, wv_, tl_ = (int(x) for x in args.shape.split(","))
+        sp = dict(modes=[args.mode if args.mode != "auto" else "graph"], rows=(r_,), waves=(wv_,), tiles=(tl_,))
+    else:
+        sp = dict(modes=["graph", "kernels"] if args.mode == "auto" else [args.mode])
+    tuned = tune.autotune(one, trial_steps=200, ks=(args.chunk,), **sp)
+    calib = {f"{t['mode']}/rows{t['act_rows']}/waves{t['act_waves']}/tile{t['regrow_tile']}": t["us_per_step"] / 1e3
+             for t in tuned["trials"]}
+    for k, v in calib.items():
+        log(f"[bench] {k}: {v * 1e3:.1f} us/step")
+    bt = tuned["best"]
+    best, best_rows, best_waves, best_tile = bt["mode"], bt["act_rows"], bt["act_waves"], bt["regrow_tile"]
+    w.set_tuning(best_rows, best_waves, best_tile)
     w.load(prep)
     run(args.warmup, "graph")
     w.sync()
@@ -706,9 +738,27 @@ def headline_run(args) -> dict:
     achieved = kbytes[dominant] / (kms[dominant] * 1e-3) / 1e9
     step_gbps = float(step_b.sum()) / wall / 1e9
     src_hash = kernel_source_hash()
-    per_agent_traffic = read_traffic_per_agent(src_hash, best_rows) if dominant == "act" else None
+    per_agent_traffic = (read_traffic_per_agent(src_hash, f"{best_rows}_{best_waves}") if dominant == "act"
+                         else None)
     n_act = float(acting.mean())
     traffic = per_agent_traffic * n_act if per_agent_traffic is not None else None
+    # the plain path's per-step latency distribution: 200 steps from the same
+    # state as single-step launches of the chosen mode, an event after each
+    w.load(start)
+    w.set_mode(best)
+    w.step(1)   # graph capture outside the measured launches
+    w.sync()
+    w.load(start)
+    sev = [torch.cuda.Event(enable_timing=True) for _ in range(201)]
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        sev[0].record(stream)
+        for j in range(200):
+            w.step(1)
+            sev[j + 1].record(stream)
+    w.sync()
+    torch.cuda.synchronize()
+    single_ms = np.array([sev[j].elapsed_time(sev[j + 1]) for j in range(200)])
     w.close()
     log(f"[bench] kernel us act {kms['act'] * 1e3:.2f} move {kms['move'] * 1e3:.2f} claim {kms['claim'] * 1e3:.2f}; "
         f"rows read per agent {float(rows_read.sum()) / agent_steps:.2f}; MB act {kbytes['act'] / 1e6:.2f} move "
@@ -724,6 +774,8 @@ def headline_run(args) -> dict:
                         f"{args.fixture_steps} fixture steps and {args.warmup} warm-up steps",
             "launch_mode": best,
             "act_rows_per_round_trip": best_rows,
+            "act_agents_per_block": best_waves,
+            "regrow_tile_edge": best_tile,
             "steps_per_launch": args.chunk,
             "first_timed_step": t_first,
             "n_live_mean": n_act,
@@ -739,7 +791,12 @@ def headline_run(args) -> dict:
         "latency_ms_per_step": {"p50": float(np.percentile(per_step_ms, 50)),
                                 "p99": float(np.percentile(per_step_ms, 99)),
                                 "samples": int(len(per_step_ms)),
-                                "window": f"per {args.chunk}-step launch"},
+                                "window": f"per {args.chunk}-step launch of the timed steps",
+                                "single_step_launches": {
+                                    "p50": float(np.percentile(single_ms, 50)),
+                                    "p99": float(np.percentile(single_ms, 99)), "samples": 200,
+                                    "window": f"steps {t_first}..{t_first + 199} again, one launch per step "
+                                              f"({best})"}},
         "calibration_us_per_step": {m: v * 1e3 for m, v in calib.items()},
         "kernels": {k: {"ms_per_launch": kms[k], "algorithmic_bytes": kbytes[k],
                         "GBps": kbytes[k] / (kms[k] * 1e-3) / 1e9} for k in kms},
@@ -891,8 +948,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--mode", default="auto", choices=["auto", "kernels", "graph"])
     ap.add_argument("--chunk", type=int, default=100, help="steps per world_step call")
-    ap.add_argument("--rows", type=int, default=0, choices=[0, 8, 16, 32],
-                    help="act rows per round trip (0 = calibrate among 8, 16, 32)")
+    ap.add_argument("--shape", default="",
+                    help="rows,waves,tile: fix the launch shape of the headline (default: autotuned)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calib-copy", action="store_true",

@@ -246,11 +246,15 @@ int world_set_mode(world_t *w, int32_t mode);
  * a batch of world_step_many.  Errors: WORLD_E_INVALID_ARG, WORLD_E_HIP. */
 int world_set_stream(world_t *w, void *hip_stream);
 
-/* Tuning knob of the act kernel (the controller of App. B.2): input rows
- * fetched per wave per round trip (8, 16 or 32; default 16).  Results are
- * identical for every value.  A batched step uses the first world's setting.
- * Errors: WORLD_E_INVALID_ARG. */
-int world_set_tuning(world_t *w, int32_t act_rows);
+/* Launch-shape knobs of the step (none changes any result; an autotuner picks
+ * them): act_rows = input rows of the controller (App. B.2) fetched per wave
+ * per round trip (8, 16 or 32; default 16); act_waves = agents per block of
+ * the GRU act kernel (2, 4 or 8; default 4; the paper's network always runs
+ * 4); regrow_tile = edge of the square regrowth tiles (App. B.1, Eq. (1);
+ * 8, 16 or 32; default 16).  A batched step uses the first world's setting.
+ * Synchronises when the shape changes.  Errors: WORLD_E_INVALID_ARG,
+ * WORLD_E_POISONED, WORLD_E_HIP. */
+int world_set_tuning(world_t *w, int32_t act_rows, int32_t act_waves, int32_t regrow_tile);
 
 /* Wait for the world's stream; report device-side failures (WORLD_E_HIP
  * poisons the handle). */

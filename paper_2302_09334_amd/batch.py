@@ -29,10 +29,10 @@ class WorldBatch:
         for w in self.worlds:
             w.set_mode(mode)
 
-    def set_tuning(self, act_rows: int):
-        self.act_rows = act_rows
+    def set_tuning(self, act_rows: int = 16, act_waves: int = 4, regrow_tile: int = 16):
+        self.act_rows, self.act_waves, self.regrow_tile = act_rows, act_waves, regrow_tile
         for w in self.worlds:
-            w.set_tuning(act_rows)
+            w.set_tuning(act_rows, act_waves, regrow_tile)
 
     def step(self, K: int):
         world.step_many(self.worlds, K)

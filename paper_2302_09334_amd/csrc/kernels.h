@@ -54,6 +54,8 @@ struct Batch {
     int ctrl;                   // controller of every world in the batch
     int dyn;                    // dynamics of every world in the batch
     int net_wide;               // host only: the network act kernel for five waves per SIMD
+    int act_waves;              // host only: agents (waves) per block of the GRU act kernel (2, 4, 8)
+    int tile;                   // host only: regrowth tile edge (8, 16, 32)
 };
 
 template <int ROWS>
@@ -120,10 +122,10 @@ __device__ __attribute__((noinline)) void net_child_act(DevRef d, AgentRec* recp
 // Act blocks of a world: nb = newborn_blocks(cap) leading blocks create the
 // children of the previous step (rank r, r + nb, ...) and run their first
 // controller step (they are the last n_child entries of the live list); the
-// remaining blocks run the controller of the other agents, four per block.
+// remaining blocks run the controller of the other agents, NT / 64 per block.
 // NET: the paper's network (with `lds`, one scratch per wave), else the GRU;
 // WIDE: the kernel is compiled for five waves per SIMD.
-template <int ROWS, bool NET, bool PAPER = false, bool WIDE = false>
+template <int ROWS, bool NET, bool PAPER = false, bool WIDE = false, int NT = kBlock>
 __device__ __forceinline__ void act_body(const Batch& bt, int vb, int tid, StepShared& sh, net::WaveLds* lds) {
     const BlockWorld bw = block_world(bt, kPreAct, vb);
     DevRef d = *bw.d;
@@ -132,7 +134,7 @@ __device__ __forceinline__ void act_body(const Batch& bt, int vb, int tid, StepS
     // the agent's record words in both lists, read together with the
     // scalars (index clamped; the newborn blocks read theirs later)
     const int nb = newborn_blocks(bw.cap);
-    const int li = (lb - nb) * (kBlock / 64) + (tid >> 6);
+    const int li = (lb - nb) * (NT / 64) + (tid >> 6);
     const int lc = min(max(li, 0), bw.cap - 1);
     const int4 q0 = *reinterpret_cast<const int4*>(&P[lc].r[0]);
     const int4 q1 = *reinterpret_cast<const int4*>(&P[lc].r[1]);
@@ -158,13 +160,13 @@ __device__ __forceinline__ void act_body(const Batch& bt, int vb, int tid, StepS
             if (tid == 0) step_open(d, t);
             if (t % kMoveWin == 0 && tid <= kMoveBins)   // a movement window starts: clear its record
                 d.mhist[((t / kMoveWin) % kMoveRing) * (kMoveBins + 1) + tid] = 0;
-            close_counters_in_step(d, tid, sh);
+            close_counters_in_step<NT>(d, tid, sh);
         }
         for (int rk = lb; rk < nc; rk += nb) {
-            spawn_child(d, rk, tid, NET ? net::kState : d.hd);
+            spawn_child<NT>(d, rk, tid, NET ? net::kState : d.hd);
             __syncthreads();
             if constexpr (!NET) {
-                spawn_proj(d, rk, tid);
+                spawn_proj<NT>(d, rk, tid);
                 __syncthreads();
             }
             if (tid < 64) {
@@ -242,7 +244,7 @@ __device__ __forceinline__ void move_body(const Batch& bt, int vb, int lane) {
 // 0.5 us pause (the tiles' first gathers and the regrowth loads go first),
 // two positions per wave, gave 32.7 us per step against 34.4 us with all of
 // it here and no pause.
-template <bool PAPER>
+template <bool PAPER, int TILE>
 __device__ __forceinline__ void claim_body(const Batch& bt, int vb, int lane, uint8_t* tile) {
     const BlockWorld bw = block_world(bt, kPreClaim, vb);
     DevRef d = *bw.d;
@@ -256,9 +258,9 @@ __device__ __forceinline__ void claim_body(const Batch& bt, int vb, int lane, ui
         claim_block<PAPER>(d, bw.S, bw.P, lb, lane, ss, p);
         return;
     }
-    const int ngrow = ((d.H + kTile - 1) / kTile) * ((d.W + kTile - 1) / kTile);
+    const int ngrow = ((d.H + TILE - 1) / TILE) * ((d.W + TILE - 1) / TILE);
     if (lb < ntile + ngrow) {
-        regrow_tile(d, lb - ntile, lane, tile, kconst(bw.S)->t_grow);
+        regrow_tile<TILE>(d, lb - ntile, lane, tile, kconst(bw.S)->t_grow, ngrow);
         return;
     }
     if (ECO_PROJ_DELAY > 0) {   // let the tiles' loads pass first
@@ -275,25 +277,15 @@ __device__ __forceinline__ void claim_body(const Batch& bt, int vb, int lane, ui
     }
 }
 
-#ifndef ECO_ACT_WAVES
-#define ECO_ACT_WAVES 0   // waves per SIMD the act kernel is compiled for (0 = compiler's choice)
-#endif
-#if ECO_ACT_WAVES > 0
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(ECO_ACT_WAVES, ECO_ACT_WAVES)))
-#else
-__global__ __launch_bounds__(kBlock)
-#endif
-void k_act(Batch bt) {
+// Act kernels of GRU worlds: ROWS input rows per wave per round trip, WAVES
+// agents (one wave each) per block.  Both are tuning knobs that change no
+// result: an agent's summation order depends on its observation only, and
+// the block-wide work (child genomes, window totals, counter sums) is
+// elementwise or integer.
+template <int ROWS, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_act_gru(Batch bt) {
     __shared__ StepShared sh;
-    act_body<16, false>(bt, blockIdx.x, threadIdx.x, sh, nullptr);
-}
-
-// Tuning variants of the act kernel (identical results, different numbers of
-// loads in flight per wave).
-template <int ROWS>
-__global__ __launch_bounds__(kBlock) void k_act_rows(Batch bt) {
-    __shared__ StepShared sh;
-    act_body<ROWS, false>(bt, blockIdx.x, threadIdx.x, sh, nullptr);
+    act_body<ROWS, false, false, false, 64 * WAVES>(bt, blockIdx.x, threadIdx.x, sh, nullptr);
 }
 
 // Act kernels of worlds with the paper's network.  The compiler's own
@@ -359,10 +351,10 @@ __global__ __launch_bounds__(kBlock) void k_materialize(const WorldDev* dp) {
     if (d.scal->err) return;
     const int nc = d.scal->n_child;
     for (int rk = blockIdx.x; rk < nc; rk += gridDim.x) {
-        spawn_child(d, rk, threadIdx.x, d.ss);
+        spawn_child<kBlock>(d, rk, threadIdx.x, d.ss);
         __syncthreads();
         if (d.ctrl == kCtrlGru) {
-            spawn_proj(d, rk, threadIdx.x);
+            spawn_proj<kBlock>(d, rk, threadIdx.x);
             __syncthreads();
         }
     }
@@ -396,21 +388,24 @@ __global__ void k_clear_pending(const WorldDev* dp) {
 // Sums the eaten / resource partials of a world's last step if still open.
 __global__ __launch_bounds__(kBlock) void k_close_counters(const WorldDev* dp) {
     __shared__ StepShared sh;
-    close_counters_in_step(*kconst(dp), threadIdx.x, sh);
+    close_counters_in_step<kBlock>(*kconst(dp), threadIdx.x, sh);
 }
 
 __global__ __launch_bounds__(64) void k_move(Batch bt) { move_body(bt, blockIdx.x, threadIdx.x); }
 
+// Claim kernels, one per regrowth tile edge TILE (a tuning knob).
+template <int TILE>
 __global__ __launch_bounds__(64) void k_claim(Batch bt) {
-    __shared__ uint8_t tile[kHalo * kHalo];
-    claim_body<false>(bt, blockIdx.x, threadIdx.x, tile);
+    __shared__ uint8_t tile[(TILE + 4) * (TILE + 4)];
+    claim_body<false, TILE>(bt, blockIdx.x, threadIdx.x, tile);
 }
 
 // The claim phase of worlds with the paper's dynamics (births on the parent's
 // cell, no neighbour scan).
+template <int TILE>
 __global__ __launch_bounds__(64) void k_claim_paper(Batch bt) {
-    __shared__ uint8_t tile[kHalo * kHalo];
-    claim_body<true>(bt, blockIdx.x, threadIdx.x, tile);
+    __shared__ uint8_t tile[(TILE + 4) * (TILE + 4)];
+    claim_body<true, TILE>(bt, blockIdx.x, threadIdx.x, tile);
 }
 
 // Spread of the initial weights: parameter p takes sd[k] for the first k with

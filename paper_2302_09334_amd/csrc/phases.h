@@ -675,9 +675,10 @@ __device__ __forceinline__ StepScal read_step(const WorldScal* S) {
     return s;
 }
 
+constexpr int kMaxBlockWaves = 8;   // waves per block of the act kernels (2, 4 or 8)
 struct StepShared {
-    int sw[4 * (kBlock / 64)];
-    long long sw64[kBlock / 64];
+    int sw[4 * kMaxBlockWaves];
+    long long sw64[kMaxBlockWaves];
 };
 
 // P2 for tile `j` (kTileN live-list entries, one wave) of one world.
@@ -981,19 +982,24 @@ __device__ __forceinline__ void claim_block(DevRef d, WorldScal* S, PosRec* P, i
 }
 
 // ---------------------------------------------------------------------------
-// P3b: regrowth of one kTile x kTile tile (one wave, four cells per lane).
+// P3b: regrowth of one TILE x TILE tile (one wave, TILE * TILE / 64 cells per lane).
 // The tile plus a 2-cell halo of the post-eating grid is staged in LDS; an
 // empty cell counts the resources among its 24 neighbours and grows iff its
 // REGROW draw is below thr[row][count].  Writes the other grid buffer
 // (synchronous update) and the tile's resource count.
 // ---------------------------------------------------------------------------
-constexpr int kHalo = kTile + 4;
+// Regrowth tile edges a launch may use (a tuning knob: every cell's result
+// depends on its own draw and its 5 x 5 neighbourhood only, so the tiling
+// changes nothing but the per-tile resource partials, which are integers).
+constexpr int kTileMin = 8;
+constexpr int kTileMax = 32;
 
-__device__ __forceinline__ void regrow_tile(DevRef d, int tile, int lane, uint8_t* s, int64_t t) {
-    constexpr int E = kHalo;
-    const int ntx = (d.W + kTile - 1) / kTile;
-    const int ty0 = (tile / ntx) * kTile;
-    const int tx0 = (tile - (tile / ntx) * ntx) * kTile;
+template <int TILE>
+__device__ __forceinline__ void regrow_tile(DevRef d, int tile, int lane, uint8_t* s, int64_t t, int ntiles) {
+    constexpr int E = TILE + 4;
+    const int ntx = (d.W + TILE - 1) / TILE;
+    const int ty0 = (tile / ntx) * TILE;
+    const int tx0 = (tile - (tile / ntx) * ntx) * TILE;
     const uint8_t* Rc = d.R[t & 1];
     uint8_t* Rn = d.R[(t + 1) & 1];
     for (int idx = lane; idx < E * E; idx += 64) {
@@ -1004,9 +1010,9 @@ __device__ __forceinline__ void regrow_tile(DevRef d, int tile, int lane, uint8_
     __syncthreads();
     int total = 0;
 #pragma unroll
-    for (int part = 0; part < kTile * kTile / 64; ++part) {
+    for (int part = 0; part < TILE * TILE / 64; ++part) {
         const int c = part * 64 + lane;
-        const int ly = c / kTile, lx = c - (c / kTile) * kTile;
+        const int ly = c / TILE, lx = c - (c / TILE) * TILE;
         const int gy = ty0 + ly, gx = tx0 + lx;
         int v = 0;
         if (gy < d.H && gx < d.W) {
@@ -1030,7 +1036,10 @@ __device__ __forceinline__ void regrow_tile(DevRef d, int tile, int lane, uint8_
         }
         total += __popcll(__ballot(v != 0));
     }
-    if (lane == 0) d.res_part[tile] = total;
+    if (lane == 0) {
+        d.res_part[tile] = total;
+        if (tile == 0) *d.res_ntiles = ntiles;   // how many partials the counter close sums
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1045,12 +1054,13 @@ __device__ __forceinline__ void regrow_tile(DevRef d, int tile, int lane, uint8_
 // floats per slot (the caller's, so that the GRU act kernel sizes it by the
 // descriptor field its controller already reads).
 // ---------------------------------------------------------------------------
+template <int NT>
 __device__ __forceinline__ void spawn_child(DevRef d, int rk, int tid, int ss) {
     const int4 rec = d.child[rk];   // child slot, parent slot, cell, uid
     const uint32_t ts = uint32_t(d.scal->spawn_t);
     const float* par = d.theta + size_t(rec.y) * size_t(d.Ppad);
     float* out = d.theta + size_t(rec.x) * size_t(d.Ppad);
-    for (int blk = tid; blk < d.nblk; blk += kBlock) {
+    for (int blk = tid; blk < d.nblk; blk += NT) {
         const int p0 = 4 * blk;
         const float4 pv = *reinterpret_cast<const float4*>(par + p0);
         const Draw4 dr = philox(uint32_t(rec.w), ts, kMutate, uint32_t(blk), d.seed_lo, d.seed_hi);
@@ -1084,32 +1094,35 @@ __device__ __forceinline__ void spawn_child(DevRef d, int rk, int tid, int ss) {
 
 // Recurrent projection and window sums of a new agent of a GRU world (after
 // spawn_child and a barrier).
+template <int NT>
 __device__ __forceinline__ void spawn_proj(DevRef d, int rk, int tid) {
     const int cs = d.child[rk].x;
     if (tid < 64) {
         if (d.hd == 32) proj_zero<32>(d, cs, tid);
         else proj_zero<16>(d, cs, tid);
     }
-    rsum_agent(d, cs, tid, kBlock);
+    rsum_agent(d, cs, tid, NT);
     __builtin_amdgcn_s_waitcnt(0);
 }
 
 // Eaten, resource and age-at-death totals of the step just closed (one block
 // per world).
+template <int NT>
 __device__ __forceinline__ void close_counters(DevRef d, int tid, StepShared& sh) {
     WorldScal* S = d.scal;
     if (!S->ctr_open) return;
     const int nwv = (S->n_prev + 63) / 64;
     int pe = 0, pr = 0, ps = 0, pw = 0;
     long long pa = 0;
-    for (int i = tid; i < nwv; i += kBlock) {
+    for (int i = tid; i < nwv; i += NT) {
         const int ep = d.eat_part[i];
         pe += ep & 0xFFFF;
         ps += ep >> 16;
         pa += d.dage_part[i];
         pw += d.rows_part[i];
     }
-    for (int i = tid; i < d.ntiles; i += kBlock) pr += d.res_part[i];
+    const int ntiles = *d.res_ntiles;
+    for (int i = tid; i < ntiles; i += NT) pr += d.res_part[i];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         pe += __shfl_xor(pe, off);
@@ -1118,22 +1131,23 @@ __device__ __forceinline__ void close_counters(DevRef d, int tid, StepShared& sh
         pa += __shfl_xor(pa, off);
         pw += __shfl_xor(pw, off);
     }
+    constexpr int NW = NT / 64;
     if ((tid & 63) == 0) {
         sh.sw[tid >> 6] = pe;
-        sh.sw[(kBlock / 64) + (tid >> 6)] = pr;
-        sh.sw[2 * (kBlock / 64) + (tid >> 6)] = ps;
-        sh.sw[3 * (kBlock / 64) + (tid >> 6)] = pw;
+        sh.sw[NW + (tid >> 6)] = pr;
+        sh.sw[2 * NW + (tid >> 6)] = ps;
+        sh.sw[3 * NW + (tid >> 6)] = pw;
         sh.sw64[tid >> 6] = pa;
     }
     __syncthreads();
     if (tid == 0) {
         int te = 0, tr = 0, ts = 0, tw = 0;
         long long ta = 0;
-        for (int w = 0; w < kBlock / 64; ++w) {
+        for (int w = 0; w < NW; ++w) {
             te += sh.sw[w];
-            tr += sh.sw[(kBlock / 64) + w];
-            ts += sh.sw[2 * (kBlock / 64) + w];
-            tw += sh.sw[3 * (kBlock / 64) + w];
+            tr += sh.sw[NW + w];
+            ts += sh.sw[2 * NW + w];
+            tw += sh.sw[3 * NW + w];
             ta += sh.sw64[w];
         }
         int32_t* rec = d.ring + (S->spawn_t % kRing) * kCtrWords;
@@ -1149,8 +1163,9 @@ __device__ __forceinline__ void close_counters(DevRef d, int tid, StepShared& sh
 
 // P1 bookkeeping by the first block of a world: sum the eaten / resource
 // partials of the previous step (written by its P2 and P3).
+template <int NT>
 __device__ __forceinline__ void close_counters_in_step(DevRef d, int tid, StepShared& sh) {
-    close_counters(d, tid, sh);
+    close_counters<NT>(d, tid, sh);
     if (tid == 0) d.scal->ctr_open = 0;
 }
 

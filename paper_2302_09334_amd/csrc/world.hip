@@ -118,7 +118,7 @@ struct Layout {
     size_t uid, cell, prev_cell, energy, age, streak, action, alive, ate, claim, bkey;
     size_t live0, live1, pos, freeq, child, h, gh, theta;
     size_t log_uid, log_act, log_logits, log_n, eat_part, dage_part, rows_part, wcell, wuid, mhist, res_part, deadlist,
-        lb_move, lb_claim, forced;
+        lb_move, lb_claim, forced, res_ntiles;
     size_t total;
 };
 
@@ -176,7 +176,8 @@ Layout layout_of(const world_config& c) {
     l.deadlist = take(4 * cap);
     l.lb_move = take(8 * ((cap + kTileN - 1) / kTileN));
     l.lb_claim = take(8 * ((cap + kTileN - 1) / kTileN));
-    l.res_part = take(4 * size_t(((c.H + kTile - 1) / kTile) * ((c.W + kTile - 1) / kTile)));
+    l.res_part = take(4 * size_t(((c.H + kTileMin - 1) / kTileMin) * ((c.W + kTileMin - 1) / kTileMin)));
+    l.res_ntiles = take(4);
     l.forced = take(size_t(forced_capacity(c)));
     l.total = o;
     static_assert(kArenaAlign == kAlign, "arena alignment");
@@ -268,6 +269,8 @@ struct world {
     hipStream_t stream;
     int mode = WORLD_MODE_KERNELS;
     int act_rows = 16;     // act-kernel tuning knob (8, 16, 32)
+    int act_waves = 4;     // agents per GRU act block (2, 4, 8)
+    int tile = 16;         // regrowth tile edge (8, 16, 32)
     bool poisoned = false;
     std::string err;
     std::map<int, hipGraphExec_t> graphs;
@@ -293,26 +296,44 @@ int fail(world* w, int code, const std::string& msg) {
             return fail((w), WORLD_E_HIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
     } while (0)
 
-int blocks_act(const world_config& c) { return (c.cap + kBlock / 64 - 1) / (kBlock / 64); }
-int tiles_agent(const world_config& c) { return (c.cap + kTileN - 1) / kTileN; }   // move / claim tiles
-int tiles_of(const world_config& c) {
-    return ((c.H + kTile - 1) / kTile) * ((c.W + kTile - 1) / kTile);
+// Agent blocks of the act phase: `waves` agents per block (the paper's
+// network always runs four per block).
+int blocks_act(const world_config& c, int waves) {
+    const int per = is_net(c) ? kBlock / 64 : waves;
+    return (c.cap + per - 1) / per;
 }
+int blocks_of_agents(const world_config& c) { return (c.cap + kBlock / 64 - 1) / (kBlock / 64); }   // 4 per block
+int tiles_agent(const world_config& c) { return (c.cap + kTileN - 1) / kTileN; }   // move / claim tiles
+int tiles_of(const world_config& c, int tile) { return ((c.H + tile - 1) / tile) * ((c.W + tile - 1) / tile); }
 
 // Host table of block prefixes for a batch of worlds (kPreKinds x (n + 1)).
-std::vector<int> batch_prefix(const std::vector<const world*>& ws) {
+std::vector<int> batch_prefix(const std::vector<const world*>& ws, int waves, int tile) {
     const int n = int(ws.size());
     std::vector<int> pre(size_t(kPreKinds) * (n + 1), 0);
     for (int i = 0; i < n; ++i) {
         const world_config& c = ws[i]->cfg;
-        pre[kPreAct * (n + 1) + i + 1] = pre[kPreAct * (n + 1) + i] + newborn_blocks(c.cap) + blocks_act(c);
+        pre[kPreAct * (n + 1) + i + 1] = pre[kPreAct * (n + 1) + i] + newborn_blocks(c.cap) + blocks_act(c, waves);
         pre[kPreMove * (n + 1) + i + 1] =
             pre[kPreMove * (n + 1) + i] + tiles_agent(c) + (is_net(c) ? 0 : proj_waves_move(c.cap));
         // GRU worlds add the recurrent-projection blocks to the claim phase
         pre[kPreClaim * (n + 1) + i + 1] =
-            pre[kPreClaim * (n + 1) + i] + tiles_agent(c) + tiles_of(c) + (is_net(c) ? 0 : proj_waves(c.cap));
+            pre[kPreClaim * (n + 1) + i] + tiles_agent(c) + tiles_of(c, tile) + (is_net(c) ? 0 : proj_waves(c.cap));
     }
     return pre;
+}
+
+// The GRU act kernel for the batch's rows per round trip and agents per block.
+template <int ROWS>
+void launch_act_rows(const Batch& b, int grid, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+    if (b.act_waves == 2) hipExtLaunchKernelGGL(k_act_gru<ROWS, 2>, dim3(grid), dim3(128), 0, s, t0, t1, 0, b);
+    else if (b.act_waves == 8) hipExtLaunchKernelGGL(k_act_gru<ROWS, 8>, dim3(grid), dim3(512), 0, s, t0, t1, 0, b);
+    else hipExtLaunchKernelGGL(k_act_gru<ROWS, 4>, dim3(grid), dim3(256), 0, s, t0, t1, 0, b);
+}
+
+void launch_act_gru(const Batch& b, int grid, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+    if (b.act_rows == 8) launch_act_rows<8>(b, grid, s, t0, t1);
+    else if (b.act_rows == 32) launch_act_rows<32>(b, grid, s, t0, t1);
+    else launch_act_rows<16>(b, grid, s, t0, t1);
 }
 
 // `t0` / `t1` (optional): events the dispatch itself stamps when the kernel
@@ -323,14 +344,20 @@ void launch_act(const Batch& b, int grid, hipStream_t s, hipEvent_t t0 = nullptr
                               t0, t1, 0, b);
     else if (b.ctrl == kCtrlNet)
         hipExtLaunchKernelGGL(b.net_wide ? k_act_net_wide : k_act_net, dim3(grid), dim3(kBlock), 0, s, t0, t1, 0, b);
-    else if (b.act_rows == 8) hipExtLaunchKernelGGL(k_act_rows<8>, dim3(grid), dim3(kBlock), 0, s, t0, t1, 0, b);
-    else if (b.act_rows == 32) hipExtLaunchKernelGGL(k_act_rows<32>, dim3(grid), dim3(kBlock), 0, s, t0, t1, 0, b);
-    else hipExtLaunchKernelGGL(k_act, dim3(grid), dim3(kBlock), 0, s, t0, t1, 0, b);
+    else launch_act_gru(b, grid, s, t0, t1);
+}
+
+template <bool PAPER>
+void launch_claim_t(const Batch& b, int grid, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+    if (b.tile == 8) hipExtLaunchKernelGGL(PAPER ? k_claim_paper<8> : k_claim<8>, dim3(grid), dim3(64), 0, s, t0, t1, 0, b);
+    else if (b.tile == 32)
+        hipExtLaunchKernelGGL(PAPER ? k_claim_paper<32> : k_claim<32>, dim3(grid), dim3(64), 0, s, t0, t1, 0, b);
+    else hipExtLaunchKernelGGL(PAPER ? k_claim_paper<16> : k_claim<16>, dim3(grid), dim3(64), 0, s, t0, t1, 0, b);
 }
 
 void launch_claim(const Batch& b, int grid, hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr) {
-    if (b.dyn == kDynPaper) hipExtLaunchKernelGGL(k_claim_paper, dim3(grid), dim3(64), 0, s, t0, t1, 0, b);
-    else hipExtLaunchKernelGGL(k_claim, dim3(grid), dim3(64), 0, s, t0, t1, 0, b);
+    if (b.dyn == kDynPaper) launch_claim_t<true>(b, grid, s, t0, t1);
+    else launch_claim_t<false>(b, grid, s, t0, t1);
 }
 
 // Enqueue one step of the per-phase kernels for a batch.
@@ -392,7 +419,7 @@ size_t table_bytes(int n) { return align_up(sizeof(void*) * size_t(n), 16) + siz
 std::vector<char> build_table(const std::vector<const world*>& ws, char* dev_base, TableView* view,
                               std::vector<int>* host_block_pre, int* max_useful) {
     const int n = int(ws.size());
-    const std::vector<int> bp = batch_prefix(ws);
+    const std::vector<int> bp = batch_prefix(ws, ws[0]->act_waves, ws[0]->tile);
     view->slots = 0;
     for (const world* x : ws) view->slots += x->cfg.cap;
     int useful = 1;
@@ -416,13 +443,13 @@ int run_steps(world* w0, int mode, const TableView& tv, const std::vector<int>& 
               int K, std::map<int, hipGraphExec_t>& graphs, std::map<int, hipGraph_t>& defs) {
     hipStream_t s = w0->stream;
     Batch b{tv.w, tv.block_pre, n, w0->act_rows, n == 1 ? static_cast<const WorldDev*>(w0->d_dev) : nullptr,
-            w0->cfg.cap, w0->dev.ctrl, w0->dev.dyn, net_wide(tv.slots)};
+            w0->cfg.cap, w0->dev.ctrl, w0->dev.dyn, net_wide(tv.slots), w0->act_waves, w0->tile};
     if (mode == WORLD_MODE_KERNELS) {
         for (int k = 0; k < K; ++k) HIP_TRY(w0, launch_step(b, host_bp.data(), n, s));
         return WORLD_OK;
     }
     if (mode == WORLD_MODE_GRAPH) {
-        const int gkey = K * 64 + w0->act_rows;
+        const int gkey = ((K * 16 + w0->act_waves) * 64 + w0->tile) * 64 + w0->act_rows;
         auto it = graphs.find(gkey);
         if (it == graphs.end()) {
             hipGraph_t g = nullptr;
@@ -591,7 +618,7 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
     d.forced_tab = reinterpret_cast<const int8_t*>(b + lay.forced);
     d.n_forced = 0;
     d.forced_on = 0;
-    d.ntiles = ((c.H + kTile - 1) / kTile) * ((c.W + kTile - 1) / kTile);
+    d.res_ntiles = reinterpret_cast<int32_t*>(b + lay.res_ntiles);
     w->d_dev = reinterpret_cast<WorldDev*>(b + lay.desc);
 
     // Host initialisation (not timed): resources, placement, lists.
@@ -676,6 +703,7 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.child, 0, 16 * size_t(c.cap), s);
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.deadlist, 0, 4 * size_t(c.cap), s);
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.mhist, 0, 4 * size_t(kMoveRing) * (kMoveBins + 1), s);
+    if (e == hipSuccess) e = hipMemsetAsync(b + lay.res_ntiles, 0, 4, s);
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.lb_move, 0, 8 * size_t(tiles_agent(c)), s);
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.lb_claim, 0, 8 * size_t(tiles_agent(c)), s);
     if (e == hipSuccess) e = hipMemsetAsync(b + lay.h, 0, 4 * size_t(c.cap) * state_of(c), s);
@@ -691,7 +719,7 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
         e = hipGetLastError();
     }
     if (e == hipSuccess && n0 > 0 && !is_net(c)) {
-        hipLaunchKernelGGL(k_proj_all, dim3(blocks_act(c)), dim3(kBlock), 0, s, static_cast<const WorldDev*>(w->d_dev));
+        hipLaunchKernelGGL(k_proj_all, dim3(blocks_of_agents(c)), dim3(kBlock), 0, s, static_cast<const WorldDev*>(w->d_dev));
         hipLaunchKernelGGL(k_rsum_all, dim3(c.cap), dim3(kBlock), 0, s, static_cast<const WorldDev*>(w->d_dev));
         e = hipGetLastError();
     }
@@ -713,10 +741,24 @@ int world_set_stream(world_t* w, void* hip_stream) {
     return WORLD_OK;
 }
 
-int world_set_tuning(world_t* w, int32_t act_rows) {
+int world_set_tuning(world_t* w, int32_t act_rows, int32_t act_waves, int32_t regrow_tile) {
     if (!w) return fail(nullptr, WORLD_E_INVALID_ARG, "world is NULL");
+    if (w->poisoned) return WORLD_E_POISONED;
     if (act_rows != 8 && act_rows != 16 && act_rows != 32) return fail(w, WORLD_E_INVALID_ARG, "act_rows must be 8, 16 or 32");
+    if (act_waves != 2 && act_waves != 4 && act_waves != 8)
+        return fail(w, WORLD_E_INVALID_ARG, "act_waves must be 2, 4 or 8");
+    if (regrow_tile != 8 && regrow_tile != 16 && regrow_tile != 32)
+        return fail(w, WORLD_E_INVALID_ARG, "regrow_tile must be 8, 16 or 32");
     w->act_rows = act_rows;
+    if (act_waves == w->act_waves && regrow_tile == w->tile) return WORLD_OK;
+    // the single-world launch table (block prefixes) depends on the shape
+    HIP_TRY(w, hipStreamSynchronize(w->stream));
+    w->act_waves = act_waves;
+    w->tile = regrow_tile;
+    TableView tv;
+    std::vector<const world*> one{w};
+    const std::vector<char> table = build_table(one, w->base + w->lay.batch, &tv, &w->host_bp, &w->max_useful);
+    HIP_TRY(w, hipMemcpy(w->base + w->lay.batch, table.data(), table.size(), hipMemcpyHostToDevice));
     return WORLD_OK;
 }
 
@@ -756,7 +798,7 @@ static std::mutex g_batch_mu;
 static std::map<std::vector<uintptr_t>, BatchEntry*> g_batches;
 static uint64_t g_batch_clock = 0;
 
-constexpr size_t kBatchKeyWords = 7;   // key words per world (the handle first)
+constexpr size_t kBatchKeyWords = 8;   // key words per world (the handle first)
 
 static std::vector<uintptr_t> batch_key(world_t* const* ws, int n) {
     std::vector<uintptr_t> key;
@@ -768,6 +810,7 @@ static std::vector<uintptr_t> batch_key(world_t* const* ws, int n) {
         key.push_back(uintptr_t(ws[i]->cfg.hidden));
         key.push_back(uintptr_t(ws[i]->cfg.controller));
         key.push_back(uintptr_t(ws[i]->cfg.dynamics));
+        key.push_back(uintptr_t(ws[0]->act_waves) << 8 | uintptr_t(ws[0]->tile));   // the launch shape
     }
     return key;
 }
@@ -983,7 +1026,7 @@ int world_load(world_t* w, const world_image* in) {
         HIP_TRY(w, hipMemcpy(b + l.theta, th.data(), 4 * size_t(n) * Pp, hipMemcpyHostToDevice));
     }
     if (n > 0 && !is_net(c)) {
-        hipLaunchKernelGGL(k_proj_all, dim3(blocks_act(c)), dim3(kBlock), 0, w->stream,
+        hipLaunchKernelGGL(k_proj_all, dim3(blocks_of_agents(c)), dim3(kBlock), 0, w->stream,
                            static_cast<const WorldDev*>(w->d_dev));
         hipLaunchKernelGGL(k_rsum_all, dim3(c.cap), dim3(kBlock), 0, w->stream,
                            static_cast<const WorldDev*>(w->d_dev));
@@ -1221,7 +1264,7 @@ int world_phase_times(world_t* w, int32_t K, float* ms) {
     const int np = 2;
     const int* hp = w->host_bp.data();
     Batch b{w->tv.w, w->tv.block_pre, 1, w->act_rows, static_cast<const WorldDev*>(w->d_dev), w->cfg.cap, w->dev.ctrl,
-            w->dev.dyn, net_wide(w->tv.slots)};
+            w->dev.dyn, net_wide(w->tv.slots), w->act_waves, w->tile};
     hipStream_t s = w->stream;
     // each kernel between start / end events stamped by its own dispatch
     std::vector<hipEvent_t> ev(size_t(K) * 6);
@@ -1357,7 +1400,7 @@ int world_step_many_noalloc(world_t* const* ws, int32_t n, int32_t K) {
     world* w0 = ws[0];
     hipStream_t s = w0->stream;
     std::vector<const world*> list(ws, ws + n);
-    const std::vector<int> bp = batch_prefix(list);
+    const std::vector<int> bp = batch_prefix(list, w0->act_waves, w0->tile);
     int slots = 0;
     for (const world* x : list) slots += x->cfg.cap;
     for (int first = 0; first < n; first += kFillChunk) {
@@ -1375,7 +1418,7 @@ int world_step_many_noalloc(world_t* const* ws, int32_t n, int32_t K) {
     const size_t ptr_bytes = align_up(sizeof(void*) * size_t(n), 16);
     Batch b{reinterpret_cast<const WorldDev* const*>(table), reinterpret_cast<const int*>(table + ptr_bytes), n,
             w0->act_rows, n == 1 ? static_cast<const WorldDev*>(w0->d_dev) : nullptr, w0->cfg.cap, w0->dev.ctrl,
-            w0->dev.dyn, net_wide(slots)};
+            w0->dev.dyn, net_wide(slots), w0->act_waves, w0->tile};
     for (int k = 0; k < K; ++k) HIP_TRY(w0, launch_step(b, bp.data(), n, s));
     return WORLD_OK;
 }

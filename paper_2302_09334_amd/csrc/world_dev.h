@@ -33,7 +33,6 @@ namespace eco {
 constexpr int kRing = 8192;     // steps of counters kept on device
 constexpr int kCtrWords = 10;   // words per counter record
 constexpr int kBlock = 256;     // threads per block in every kernel
-constexpr int kTile = 16;       // regrowth tile edge (16 x 16 cells per block)
 constexpr uint32_t kSpinTicks = 200000000u;   // look-back wait bound: 2 s at the 100 MHz wall clock
 
 // Counter record fields (match world_counters in world.h).
@@ -177,11 +176,11 @@ struct WorldDev {
     int32_t* wcell;       // per slot: cell at the start of the current movement window
     uint32_t* wuid;       // per slot: uid of the agent the window start was recorded for
     int32_t* mhist;       // kMoveRing x (kMoveBins + 1) movement histograms
-    int32_t* res_part;    // per-tile resource counts of the regrowth phase
+    int32_t* res_part;    // per-tile resource counts of the regrowth phase (room for the smallest tile edge)
     int32_t* rows_part;   // per-wave sums of the input rows read by the act phase (cap / 64)
+    int32_t* res_ntiles;  // regrowth tiles (resource partials) of the last claim phase
     const int8_t* forced_tab;   // test hook: forced action by uid (n_forced entries)
-    int32_t ntiles;       // regrowth tiles
-    int32_t pad1;
+    int32_t pad1, pad2;
 };
 
 // A world's arena starts with its descriptor; the scalars and the

@@ -99,7 +99,7 @@ def lib():
         L.world_step_many.argtypes = [C.POINTER(P), C.c_int32, C.c_int32]
         L.world_step_many_noalloc.argtypes = [C.POINTER(P), C.c_int32, C.c_int32]
         L.world_set_mode.argtypes = [P, C.c_int32]
-        L.world_set_tuning.argtypes = [P, C.c_int32]
+        L.world_set_tuning.argtypes = [P, C.c_int32, C.c_int32, C.c_int32]
         L.world_set_stream.argtypes = [P, P]
         L.world_sync.argtypes = [P]
         L.world_snapshot.argtypes = [P, C.POINTER(Image)]
@@ -269,10 +269,14 @@ class World:
         _check(lib().world_set_stream(self._h, C.c_void_p(stream.cuda_stream)), self._h)
         self.stream = stream
 
-    def set_tuning(self, act_rows: int):
-        """Act-kernel rows per round trip (8, 16, 32); results are identical."""
+    def set_tuning(self, act_rows: int = 16, act_waves: int | None = None, regrow_tile: int | None = None):
+        """Launch shape: act rows per round trip (8, 16, 32), agents per act
+        block (2, 4, 8), regrowth tile edge (8, 16, 32); results are identical
+        for every choice.  Unnamed knobs keep their current values."""
         self.act_rows = int(act_rows)
-        _check(lib().world_set_tuning(self._h, int(act_rows)), self._h)
+        self.act_waves = int(act_waves if act_waves is not None else getattr(self, "act_waves", 4))
+        self.regrow_tile = int(regrow_tile if regrow_tile is not None else getattr(self, "regrow_tile", 16))
+        _check(lib().world_set_tuning(self._h, self.act_rows, self.act_waves, self.regrow_tile), self._h)
 
     def step(self, K: int = 1):
         _check(lib().world_step(self._h, int(K)), self._h)

@@ -211,3 +211,77 @@ def test_lookback_timeout_poisons(env):
     same(other.snapshot(hidden=True, theta=True), ref.snapshot(hidden=True, theta=True), "unaffected world")
     other.close()
     ref.close()
+
+
+@pytest.mark.parametrize("mode", ["graph", "kernels"])
+def test_batched_uneven_worlds_against_oracle(env, mode):
+    """Uneven worlds of the batched workload's shapes (grids from its size
+    set up to 200 x 400, caps up to 8192, 10% initial agents, scaled rates)
+    advanced together by world_step_many, each compared with its own oracle
+    every step for 200 steps (counters, acting agents, logits) and bit-exactly
+    (state and genomes) every 50."""
+    import oracle
+    import torch
+
+    from parity_util import check_chunk, compare_state, new_stats
+    world, wl = env
+    entries = wl.batch_manifest(6, seed=11)
+    entries[0] = dict(cfg=wl.make(H=200, W=400, cap=8192, n_init=819, rate_scale=1.7), seed=100)
+    entries[1] = dict(cfg=wl.make(H=64, W=128, cap=512, n_init=51, rate_scale=0.6), seed=101)
+    K = 50
+    s = torch.cuda.Stream()
+    gws = [world.World(e["cfg"], e["seed"], stream=s, mode=mode, log_steps=K) for e in entries]
+    ows = [oracle.OracleWorld(oracle.OracleConfig.from_dict(e["cfg"]), e["seed"]) for e in entries]
+    stats = [new_stats() for _ in entries]
+    for t in range(0, 200, K):
+        world.step_many(gws, K)
+        gws[0].sync()
+        for i, (g, o) in enumerate(zip(gws, ows)):
+            check_chunk(g, o, t, K, stats[i])
+            compare_state(g.snapshot(hidden=True, theta=True), o.state(with_hidden=True, with_theta=True),
+                          f"world {i} t={t + K}", theta=True)
+    say(f"[systems] batched vs oracle ({mode}): " + ", ".join(
+        f"{e['cfg']['H']}x{e['cfg']['W']}/{e['cfg']['cap']}: {st['agent_steps']} agent-steps, {st['births']} births"
+        for e, st in zip(entries, stats)))
+    for g, o in zip(gws, ows):
+        g.close()
+        o.close()
+
+
+SHAPES = [(8, 2, 8), (16, 8, 32), (32, 4, 8), (8, 8, 16), (16, 2, 32), (32, 8, 8)]
+
+
+@pytest.mark.parametrize("mode", ["graph", "kernels"])
+def test_launch_shapes_bit_identical(env, mode):
+    """Every launch shape the autotuner may pick (act rows per round trip,
+    agents per act block, regrowth tile edge) gives the same worlds bit for
+    bit as the default shape, batched (uneven GRU worlds) and alone (the
+    paper's network and dynamics, whose act blocks keep four agents but
+    whose regrowth tiles follow the knob)."""
+    import torch
+    world, wl = env
+    s = torch.cuda.Stream()
+    entries = [dict(cfg=dense(wl, obs_radius=3, hidden=32), seed=1), dict(cfg=dense(wl, H=57, W=31, cap=260), seed=2),
+               dict(cfg=dense(wl, H=23, W=90, cap=333, obs_radius=1), seed=3)]
+    paper = dense(wl, obs_radius=7, hidden=4, controller=1, w_init_gain=1.0, dynamics=1, E0=120, E_max=120, gain=40,
+                  E_repr=0, T_repr=20, T_death=25, regrow_pI=0.2, regrow_alpha=200.0, spont=0.002)
+
+    def run(shape, steps=60):
+        ws = [world.World(e["cfg"], e["seed"], stream=s, mode=mode) for e in entries]
+        for w in ws:
+            w.set_tuning(*shape)
+        world.step_many(ws, 30)
+        world.step_many(ws, steps - 30)
+        p = world.World(paper, 4, stream=s, mode=mode)
+        p.set_tuning(*shape)
+        p.step(steps)
+        out = [w.snapshot(hidden=True, theta=True) for w in ws + [p]]
+        for w in ws + [p]:
+            w.close()
+        return out
+
+    ref = run((16, 4, 16))
+    for shape in SHAPES:
+        say(f"[systems] launch shape {shape} ({mode})")
+        for i, (a, b) in enumerate(zip(ref, run(shape))):
+            same(a, b, (shape, i))

@@ -78,7 +78,11 @@ def test_ln_unit_exhaustive(oracle_lib):
     ulp = np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64)
     assert got[-1] == 0.0  # ln 1
     ulp[-1] = 1.0
-    assert (np.abs(got - ref) / ulp).max() <= 3.0
+    # measured: 2.51 ulp at most, 4893 of the 2^24 inputs above 2 ulp (the
+    # division s = (m - 1) / (m + 1) rounds before the series); the device
+    # computes the same bits, so the bound only limits the Gaussian's error
+    e = np.abs(got - ref) / ulp
+    assert e.max() <= 2.6 and (e > 2.0).sum() < 10000
 
 
 def test_sincos_2pi_exhaustive(oracle_lib):
@@ -91,7 +95,7 @@ def test_sincos_2pi_exhaustive(oracle_lib):
         assert err.max() <= 2.0 * 2.0**-24
         m = np.abs(ref) > 2.0**-10
         ulp = np.spacing(np.abs(ref[m]).astype(np.float32)).astype(np.float64)
-        assert (err[m] / ulp).max() <= 3.0
+        assert (err[m] / ulp).max() <= 2.0   # measured 1.93
     # exact special angles
     assert s[0] == 0 and c[0] == 1
     q = 2**22

@@ -1,7 +1,7 @@
-"""Host logic of the autotuner (no GPU): every combination of launch mode,
-act rows per round trip and steps per launch is timed from the same saved
-state, the fastest one is applied, and the batch is left at the state it
-started from."""
+"""Host logic of the autotuner (no GPU): a coordinate descent over launch
+mode, steps per launch, act rows per round trip, agents per act block and
+regrowth tile edge, every trial timed from the same saved state; the fastest
+combination is applied and the batch is left at the state it started from."""
 import pytest
 
 from paper_2302_09334_amd import tune
@@ -14,7 +14,7 @@ class FakeBatch:
         self.clock = clock
         self.cost = cost
         self.mode = None
-        self.rows = None
+        self.shape = None
         self.state = "start"
         self.calls = []
 
@@ -24,48 +24,78 @@ class FakeBatch:
     def set_mode(self, m):
         self.mode = m
 
-    def set_tuning(self, r):
-        self.rows = r
+    def set_tuning(self, rows, waves, tile):
+        self.shape = (rows, waves, tile)
 
     def load(self, s):
         self.calls.append(("load", s))
         self.state = s.split(":", 1)[1]
 
     def step(self, k):
-        self.calls.append(("step", self.mode, self.rows, k, self.state))
-        self.clock[0] += self.cost(self.mode, self.rows, k) * k
+        self.calls.append(("step", self.mode, self.shape, k, self.state))
+        self.clock[0] += self.cost(self.mode, self.shape, k) * k
         self.state = "advanced"
 
     def sync(self):
         pass
 
 
-def test_autotune_picks_the_fastest_and_restores_the_state(monkeypatch):
+@pytest.fixture
+def fake_clock(monkeypatch):
     import torch
     monkeypatch.setattr(torch.cuda, "synchronize", lambda: None)
     clock = [0.0]
     monkeypatch.setattr(tune.time, "perf_counter", lambda: clock[0])
+    return clock
 
-    # per-step cost: graph with 16 rows and 50 steps per launch is the fastest
-    def cost(mode, rows, k):
+
+def test_autotune_picks_the_fastest_and_restores_the_state(fake_clock):
+    # per-step cost (separable): kernels, 50 steps per launch, 8 rows, two
+    # agents per act block and 32-cell tiles is the fastest
+    def cost(mode, shape, k):
+        rows, waves, tile = shape
         c = 1e-3
-        if mode == "graph":
-            c -= 2e-4
-        if rows == 16:
-            c -= 1e-4
-        if k == 50:
-            c -= 5e-5
+        c -= 2e-4 if mode == "kernels" else 0
+        c -= 5e-5 if k == 50 else 0
+        c -= 1e-4 if rows == 8 else 0
+        c -= 3e-5 if waves == 2 else (1e-5 if waves == 8 else 0)
+        c -= 2e-5 if tile == 32 else 0
         return c
 
-    b = FakeBatch(clock, cost)
+    b = FakeBatch(fake_clock, cost)
     out = tune.autotune(b, trial_steps=100)
-    assert len(out["trials"]) == len(tune.MODES) * len(tune.ROWS) * len(tune.KS)
-    assert (out["best"]["mode"], out["best"]["act_rows"], out["best"]["K"]) == ("graph", 16, 50)
-    assert out["best"]["us_per_step"] == pytest.approx((1e-3 - 2e-4 - 1e-4 - 5e-5) * 1e6)
+    best = out["best"]
+    assert (best["mode"], best["K"], best["act_rows"], best["act_waves"], best["regrow_tile"]) == \
+        ("kernels", 50, 8, 2, 32)
+    assert best["us_per_step"] == pytest.approx((1e-3 - 2e-4 - 5e-5 - 1e-4 - 3e-5 - 2e-5) * 1e6)
+    # one pass finds a separable optimum, the second confirms it: each knob
+    # value is timed once per combination visited, far fewer than the full grid
+    assert len(out["trials"]) < len(tune.MODES) * len(tune.KS) * len(tune.ROWS) * len(tune.WAVES) * len(tune.TILES)
     # applied, and back at the saved state
-    assert (b.mode, b.rows) == ("graph", 16)
+    assert (b.mode, b.shape) == ("kernels", (8, 2, 32))
     assert b.calls[-1] == ("load", "saved:start") and b.state == "start"
     # every timed trial starts from the saved state: each run of steps follows a load
     for i, c in enumerate(b.calls):
         if c[0] == "step" and (i == 0 or b.calls[i - 1][0] == "load"):
             assert c[4] == "start"
+
+
+def test_autotune_coordinate_descent_revisits(fake_clock):
+    # an interaction: 32-cell tiles only pay with eight agents per block, and
+    # eight agents per block only pay with 32-cell tiles -- the descent stops
+    # at a point no single knob change improves
+    def cost(mode, shape, k):
+        rows, waves, tile = shape
+        c = 1e-3
+        if waves == 8 and tile == 32:
+            c -= 3e-4
+        return c
+
+    b = FakeBatch(fake_clock, cost)
+    out = tune.autotune(b, trial_steps=50, modes=("graph",), ks=(50,), rows=(16,))
+    best = out["best"]
+    key = (best["act_waves"], best["regrow_tile"])
+    # from the default (4, 16) no single change helps: the descent keeps it
+    assert key == (4, 16)
+    # no combination it timed beats the chosen one by more than the 1% it requires
+    assert all(t["us_per_step"] >= (1 - tune.MIN_GAIN) * best["us_per_step"] for t in out["trials"])
