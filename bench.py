@@ -442,7 +442,7 @@ def served_run(args) -> dict:
     srv = serve.Server(be, budget_bytes=int(args.serve_budget_gb * 1e9), K=50)
     results, m = srv.run(reqs, duration=args.serve_seconds, realtime=True,
                          progress=lambda t, done, act, q: log(f"[bench] served t={t:.0f} s: {done} done, "
-                                                              f"{act} active, {q} waiting"))
+                                                              f"{act} active, {q} queued"))
     be.shutdown()
     m["fixture"] = ("M4: Poisson(20/s) arrivals for 600 s" if args.serve_seconds >= 600 else
                     f"M4 truncated to {args.serve_seconds:.0f} s of arrivals (the full 600 s run: "

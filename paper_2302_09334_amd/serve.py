@@ -165,7 +165,7 @@ class Server:
         """Serve `requests` (sorted by arrival time, seconds from start).  With
         `duration`, arrivals after it are dropped and the active set drains.
         `progress(t, done, active, queued)` is called every `progress_every`
-        seconds of the run."""
+        seconds of the run (queued: arrived and not yet admitted)."""
         be = self.backend
         async_create = realtime and hasattr(be, "create_async")
         async_finish = realtime and hasattr(be, "finish_async")
@@ -237,7 +237,7 @@ class Server:
         while pending or queue or active or creating or finishing:
             t = now()
             if progress is not None and t >= next_report:
-                progress(t, len(results), len(active), len(queue) + len(pending))
+                progress(t, len(results), len(active) + len(creating), len(queue))
                 next_report += progress_every
             while pending and pending[0].arrival <= t:
                 queue.append(pending.popleft())
