@@ -121,7 +121,7 @@ typedef struct world_counters {
     int32_t deaths;      /* agents that died in the step        */
     int32_t eaten;       /* resources eaten in the step         */
     int32_t resources;   /* resources on the grid after regrowth*/
-    int32_t claim_wins;  /* birth claims won before the slot cap */
+    int32_t claim_wins;  /* birth claims won before the slot cap (0 when the survivors fill the cap) */
     int64_t dead_age_sum;/* sum of the ages of the agents that died in the step
                             (life expectancy over a window, App. C: the sum of
                             this field over the window / the sum of deaths) */

@@ -961,11 +961,12 @@ static void step_paper(world *w, uint32_t t, oracle_stepinfo *inf)
         n_surv++;
     }
     w->n = n_surv;
-    /* S8 births on the parent's cell */
+    /* S8 births on the parent's cell (with no free slot nobody can be born and
+     * no claim is counted) */
     int n_elig = 0;
     for (int a = 0; a < w->n; ++a) n_elig += w->streak[a] >= cfg->T_repr;
-    inf->claim_wins = n_elig;
     int free_slots = cfg->cap - w->n;
+    inf->claim_wins = free_slots > 0 ? n_elig : 0;
     int n_born = n_elig < free_slots ? n_elig : free_slots;
     int rank = 0;
     int n_before = w->n;
@@ -1193,7 +1194,10 @@ int oracle_step(void *vw, const uint32_t *hint_uid, const uint8_t *hint_act, int
          * cell; the benchmark forbids sharing): an eligible parent scans its four
          * neighbours in the order N, S, E, W cyclically from a random start and
          * claims the first free in-grid cell; claims resolve like moves with the
-         * BIRTH draw; winners are born in uid order while slots remain. */
+         * BIRTH draw; winners are born in uid order while slots remain.  With no
+         * free slot (the survivors fill the cap) nobody can be born: no claim is
+         * made or resolved, and no winner is counted. */
+        int free_slots = cfg->cap - w->n;
         for (size_t i = 0; i < HW; ++i) {
             w->best[i] = UINT64_MAX;
             w->who[i] = -1;
@@ -1201,7 +1205,7 @@ int oracle_step(void *vw, const uint32_t *hint_uid, const uint8_t *hint_act, int
         for (int a = 0; a < w->n; ++a) {
             w->claim[a] = -1;
             w->won[a] = 0;
-            if (w->streak[a] < cfg->T_repr) continue;
+            if (free_slots <= 0 || w->streak[a] < cfg->T_repr) continue;
             uint32_t rr[4];
             draw(w->seed, w->uid[a], t, ORACLE_S_BIRTH, 0, rr);
             int d0 = (int)(rr[0] & 3u);
@@ -1228,7 +1232,6 @@ int oracle_step(void *vw, const uint32_t *hint_uid, const uint8_t *hint_act, int
                 n_win++;
             }
         inf.claim_wins = n_win;
-        int free_slots = cfg->cap - w->n;
         int n_born = n_win < free_slots ? n_win : free_slots;
         int rank = 0;
         int n_before = w->n;

@@ -80,7 +80,8 @@ typedef struct oracle_stepinfo {
     int32_t resources;   /* resources on the grid after regrowth               */
     int32_t resyncs;     /* near-tie actions adopted from the supplied hints   */
     int32_t mismatches;  /* hints that disagreed outside the near-tie band     */
-    int32_t claim_wins;  /* birth-claim winners before the slot cap            */
+    int32_t claim_wins;  /* birth-claim winners before the slot cap (0 when no
+                            slot is free: no claim is made)                   */
     int64_t dead_age;    /* sum of the ages of the agents that died (App. C)   */
     int32_t seen;        /* acting agents with a resource in their field of view
                             at the step start (greediness, Sec. 2.2)          */

@@ -453,11 +453,6 @@ __device__ __forceinline__ uint64_t lookback(DevRef d, uint64_t* st, int tile, u
     return excl;
 }
 
-// Inclusive total of the last tile of a completed look-back.
-__device__ __forceinline__ uint64_t lookback_total(const uint64_t* st, int ntile) {
-    return __hip_atomic_load(st + ntile - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kValMask;
-}
-
 // Exclusive ranks of two predicates within the wave and the wave totals.
 struct WaveRank {
     int ra, rb;   // this lane's exclusive rank among the wave's a / b
@@ -634,6 +629,7 @@ __device__ __forceinline__ int move_agent_paper(DevRef d, const AgentRec& a, int
 struct StepScal {
     int64_t t;
     int n, sel, nc;
+    int n_surv;   // survivors of this step's move phase (valid in its claim phase)
     int err;   // nonzero after a device failure: the world no longer steps
     uint32_t next_uid;
     int free_head, free_tail;
@@ -644,6 +640,7 @@ __device__ __forceinline__ StepScal read_step_from(P S) {
     StepScal s;
     s.t = S->t;
     s.n = S->n_live;
+    s.n_surv = S->n_surv;
     s.sel = S->live_sel;
     s.nc = S->n_child;
     s.next_uid = S->next_uid;
@@ -665,7 +662,8 @@ __device__ __forceinline__ void pin64(uint64_t v) { asm volatile("" ::"v"(v)); }
 // block of the same kernel that reads them has done so (the last claim tile
 // rewrites them once its look-back has seen every other claim tile publish,
 // which each does after reading them; the regrowth tiles read t_grow, which
-// it does not write).
+// it does not write; the last move tile writes n_surv, which only the next
+// kernel, the claim phase, uses).
 __device__ __forceinline__ StepScal read_step(const WorldScal* S) {
     const StepScal s = read_step_from(kconst(S));
     pin_s(int(s.t));
@@ -740,6 +738,9 @@ __device__ __forceinline__ void move_block(DevRef d, PosRec* P, int j, int lane,
     }
     const WaveRank wr = wave_rank2(alive, dead, lane);
     const uint64_t ex = lookback(d, d.lb_move, j, uint32_t(t), pack2(wr.ta, wr.tb), lane, j == d.stall_tile);
+    // the last tile's inclusive prefix is the step's survivor count, which the
+    // claim phase reads with its other scalars
+    if (lane == 0 && j == (d.cap + kTileN - 1) / kTileN - 1) d.scal->n_surv = int(unpack_a(ex)) + wr.ta;
     if (alive) {
         const int pos = int(unpack_a(ex)) + wr.ra;
         d.live[sel ^ 1][pos] = nr.slot;
@@ -784,14 +785,16 @@ __device__ __forceinline__ bool rival_claims(const bool (&fr)[7][7], int v) {
 // a rival claiming the same cell sits two steps away and its own claim
 // depends on cells up to three steps away, so the occB words of the whole
 // radius-3 diamond (24 cells) and the birth keys of the 8 cells at distance
-// 2 are loaded together, and the resolution is computed from them.
+// 2 are loaded together, and the resolution is computed from them.  With
+// no free slot (`room` false: the survivors fill the cap) no birth can
+// follow, and no claim is made.
 // Returns the claimed cell of a claim winner, -1 otherwise.
 // ---------------------------------------------------------------------------
 template <bool PAPER>
-__device__ __forceinline__ int claim_agent(DevRef d, const PostRec& p, int64_t t) {
+__device__ __forceinline__ int claim_agent(DevRef d, const PostRec& p, int64_t t, bool room) {
     const int X = p.prev_cell;
     const int X2 = p.cell;
-    const bool alive = p.alive != 0;
+    const bool alive = p.alive != 0 && room;
     constexpr bool paper = PAPER;
     {
         // clear the claim word this agent may have written in P1 (its move
@@ -898,18 +901,18 @@ __device__ __forceinline__ void claim_block(DevRef d, WorldScal* S, PosRec* P, i
     const int n = ss.n;
     const int sel = ss.sel;
     const int64_t t = ss.t;
+    const int surv = ss.n_surv;
     const int ntile = (cap + kTileN - 1) / kTileN;
     int slot = -1, cell = -1, pos = -1;
     bool win = false;
     if (i < n) {
         slot = p.slot;
         pos = p.next_pos;
-        cell = claim_agent<PAPER>(d, p, t);
+        cell = claim_agent<PAPER>(d, p, t, surv < cap);
         win = cell >= 0;
     }
     const WaveRank wr = wave_rank2(win, false, lane);
     const uint64_t ex = lookback(d, d.lb_claim, j, uint32_t(t), pack2(wr.ta, 0), lane);
-    const int surv = int(unpack_a(lookback_total(d.lb_move, ntile)));
     const int nfree = cap - n;
     if (win) {
         const int rk = int(unpack_a(ex)) + wr.ra;

@@ -114,6 +114,8 @@ struct WorldScal {
     int32_t ctr_open;   // 1: eaten/resource totals of step spawn_t not yet summed
     int32_t n_grow;     // live agents of the running claim phase's step (written by its move phase)
     int64_t t_grow;     // step of the running claim phase (written by its move phase)
+    int32_t n_surv;     // survivors of the running step's move phase (written by its last tile)
+    int32_t pad_surv;
 };
 
 struct WorldDev {

@@ -227,7 +227,8 @@ def test_full_world_keeps_streak(oracle_lib):
         info = w.step()
         assert info["births"] == 0 and w.n_live == 1
     assert w.agents()["streak"][0] == 30
-    assert info["claim_wins"] == 1
+    # with no free slot no birth claim is resolved or counted
+    assert info["claim_wins"] == 0
 
 
 def test_frozen_dynamics_conserve(oracle_lib):

@@ -166,8 +166,8 @@ MUTANTS = {
     "paper_death_at_threshold": ("else if (e < cfg->E_repr) s = (s < 0 ? s : 0) - 1;",
                                  "else if (e <= cfg->E_repr) s = (s < 0 ? s : 0) - 1;", 1, (PAP,)),
     "paper_age_bound": ("(w->age[a] > cfg->L_max)", "(w->age[a] >= cfg->L_max)", 1, (PAP,)),
-    "paper_slots_one_short": ("    inf->claim_wins = n_elig;\n    int free_slots = cfg->cap - w->n;",
-                              "    inf->claim_wins = n_elig;\n    int free_slots = cfg->cap - w->n - 1;", 1, (PAP,)),
+    "paper_slots_one_short": ("    int free_slots = cfg->cap - w->n;\n    inf->claim_wins",
+                              "    int free_slots = cfg->cap - w->n - 1;\n    inf->claim_wins", 1, (PAP,)),
     "paper_eat_without_resource": ("        if (!w->R[cell]) continue;\n", "", 1, (PAP,)),
     "paper_parent_streak_kept": ("        w->streak[a] = 0;\n        w->n++;", "        w->n++;", 1, (PAP,)),
     # ecology metrics and the lab's greediness
