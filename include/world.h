@@ -25,7 +25,10 @@
  *    the next synchronising call (world_sync, world_snapshot, ...).
  *  - After a HIP error the handle is poisoned: every later call except
  *    world_destroy returns WORLD_E_POISONED.
- *  - A handle is not thread-safe; distinct handles are.
+ *  - A handle is not thread-safe; distinct handles are, also when they share
+ *    a stream: copies and fills run on the world's own stream (never the
+ *    legacy default stream), and waits for other threads' launches are
+ *    ordered against this library's graph captures (world_set_stream).
  */
 #ifndef ECO_WORLD_H
 #define ECO_WORLD_H
@@ -241,9 +244,15 @@ int world_step_many_noalloc(world_t *const *ws, int32_t n, int32_t K);
  * results are identical).  Errors: WORLD_E_INVALID_ARG. */
 int world_set_mode(world_t *w, int32_t mode);
 
-/* Move the world to another HIP stream (caller-owned; the old stream is
- * synchronised first).  Lets a world be created on one stream and then join
- * a batch of world_step_many.  Errors: WORLD_E_INVALID_ARG, WORLD_E_HIP. */
+/* Move the world to another HIP stream (caller-owned).  First waits on the
+ * host for the last launch that included the world (an event the library
+ * records after each launch, polled while no graph capture of this library
+ * is in progress), not for other work on the old stream, and enqueues
+ * nothing on either stream: another thread may meanwhile launch other worlds
+ * on the old stream, capturing graphs through this library (a capture on it
+ * by other code must not overlap this call).  Lets a world be created on one
+ * stream and then join a batch of world_step_many, and leave it again.
+ * Errors: WORLD_E_INVALID_ARG, WORLD_E_POISONED, WORLD_E_HIP. */
 int world_set_stream(world_t *w, void *hip_stream);
 
 /* Launch-shape knobs of the step (none changes any result; an autotuner picks
@@ -295,9 +304,10 @@ int world_counters_get(world_t *w, int64_t first_step, int32_t n, world_counters
  * ended and be among the last 64 (WORLD_E_STATE otherwise).  App. C. */
 int world_move_hist(world_t *w, int64_t first_window, int32_t n, int32_t *out);
 
-/* Synchronise and release the handle, its graphs and every batch launch table
- * that lists it.  The arena and the stream are not freed (the caller owns
- * them).  NULL is accepted. */
+/* Wait for the world's last launch (as world_set_stream does: no stream is
+ * synchronised) and release the handle, its graphs and every batch launch
+ * table that lists it (after that batch's last launch).  The arena and the
+ * stream are not freed (the caller owns them).  NULL is accepted. */
 int world_destroy(world_t *w);
 
 /* Message of the last failure of `w` (or of the calling thread if w is NULL). */

@@ -17,6 +17,7 @@ LIB = os.path.join(HERE, "libworld.so")
 SOURCES = [os.path.join(HERE, "csrc", "world.hip")]
 DEPS = [os.path.join(HERE, "csrc", f) for f in ("rng.h", "world_dev.h", "phases.h", "net.h", "kernels.h")]
 ARCH = os.environ.get("ECO_OFFLOAD_ARCH", "gfx950")
+LIBS = ["-lrocprofiler-sdk-roctx"]   # roctx ranges around the C-ABI calls
 
 
 def hipcc() -> str:
@@ -38,10 +39,11 @@ def flags() -> list[str]:
 
 def build(verbose: bool = False, out: str = LIB, defines: dict | None = None) -> str:
     """Compile the library to `out`; `defines` are extra -D tuning macros
-    (ECO_ACT_ROWS, ECO_ACT_WAVES)."""
+    (ECO_PROJ_MOVE_EIGHTHS, ECO_PROJ_DELAY, ECO_PROJ_PER, ECO_NET_WAVES,
+    ECO_NET_WAVES_WIDE, ECO_NEWBORN_BLOCKS; none changes a result)."""
     tmp = out + ".tmp"
     extra = [f"-D{k}={v}" for k, v in (defines or {}).items()]
-    cmd = [hipcc()] + flags() + extra + SOURCES + ["-o", tmp]
+    cmd = [hipcc()] + flags() + extra + SOURCES + ["-o", tmp] + LIBS
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)

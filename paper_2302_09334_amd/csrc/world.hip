@@ -5,14 +5,19 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cassert>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
+
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include "world.h"
 #include "kernels.h"
@@ -22,6 +27,20 @@ using namespace eco;
 namespace {
 
 thread_local std::string g_thread_err;
+
+// A roctx range around one call of the C-ABI (rocprofv3 --marker-trace shows
+// them beside the kernels: one range per K-step chunk, snapshot or load).
+struct TraceRange {
+    explicit TraceRange(const char* what) { roctxRangePushA(what); }
+    TraceRange(const char* fmt, int a, int b = 0) {
+        char msg[96];
+        std::snprintf(msg, sizeof(msg), fmt, a, b);
+        roctxRangePushA(msg);
+    }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
+};
 
 constexpr size_t kAlign = 256;
 
@@ -251,6 +270,15 @@ InitSegs init_segments(const world_config& c, const Dims& dm) {
 
 }  // namespace
 
+// The end of a launch: an event recorded on the launch stream right after
+// it.  Released with its last holder.
+struct WorkEvent {
+    hipEvent_t ev = nullptr;
+    ~WorkEvent() {
+        if (ev) (void)hipEventDestroy(ev);
+    }
+};
+
 struct world {
     world_config cfg;
     Dims dm;
@@ -275,6 +303,14 @@ struct world {
     std::string err;
     std::map<int, hipGraphExec_t> graphs;
     std::map<int, hipGraph_t> graph_defs;
+    // Completion of this world's launches: `own` is recorded after each
+    // launch the world leads (alone, or first of a batch); `last` is the
+    // event recorded after the last launch that included the world (a batch
+    // leader's `own`), null when nothing is pending.  Moving or releasing a
+    // world waits for `last` (wait_launch) instead of synchronising a stream
+    // that another thread may be launching on.
+    std::shared_ptr<WorkEvent> own;
+    std::shared_ptr<WorkEvent> last;
 };
 
 namespace {
@@ -385,6 +421,58 @@ int device_cus() {
 // kernels compiled for five waves per SIMD: at four, a CU holds 16 agent waves.
 int net_wide(int slots) { return slots > 16 * device_cus() ? 1 : 0; }
 
+// Records the end of a launch of ws[0..n) (all on ws[0]'s stream, after
+// any capture has ended) as the last launch of each.
+int mark_launch(world* const* ws, int n) {
+    world* w0 = ws[0];
+    HIP_TRY(w0, hipEventRecord(w0->own->ev, w0->stream));
+    for (int i = 0; i < n; ++i) ws[i]->last = w0->own;
+    return WORLD_OK;
+}
+
+// Held while the library captures a graph.  HIP invalidates a capture in
+// progress on a stream (and fails the call) when another thread
+// synchronises with, queries or waits for an event last recorded on that
+// stream, so a thread that waits for a launch polls its event under this
+// lock: the library's own captures never overlap the query.
+std::mutex g_capture_mu;
+
+hipError_t wait_launch(hipEvent_t launch) {
+    for (;;) {
+        hipError_t q;
+        {
+            std::lock_guard<std::mutex> lk(g_capture_mu);
+            q = hipEventQuery(launch);
+        }
+        if (q != hipErrorNotReady) return q;
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+}
+
+// Waits on the host for the last launch that included `w`; nothing is
+// pending afterwards.
+int wait_world(world* w) {
+    if (w->last) {
+        HIP_TRY(w, wait_launch(w->last->ev));
+        w->last.reset();
+    }
+    return WORLD_OK;
+}
+
+// A copy or fill on the world's own stream, complete when it returns.  Never
+// the synchronous hipMemcpy / hipMemset: they run on the legacy default
+// stream, which HIP makes depend on the other streams, and they fail (and
+// invalidate the capture) while another thread captures a graph on one.
+hipError_t copy_now(world* w, void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, kind, w->stream);
+    return e == hipSuccess ? hipStreamSynchronize(w->stream) : e;
+}
+
+hipError_t fill_now(world* w, void* dst, int value, size_t bytes) {
+    hipError_t e = hipMemsetAsync(dst, value, bytes, w->stream);
+    return e == hipSuccess ? hipStreamSynchronize(w->stream) : e;
+}
+
 int check_device_error(world* w) {
     WorldScal sc;
     HIP_TRY(w, hipMemcpyAsync(&sc, w->base + w->lay.scal, sizeof(sc), hipMemcpyDeviceToHost, w->stream));
@@ -454,10 +542,13 @@ int run_steps(world* w0, int mode, const TableView& tv, const std::vector<int>& 
         if (it == graphs.end()) {
             hipGraph_t g = nullptr;
             hipGraphExec_t ge = nullptr;
-            HIP_TRY(w0, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            hipError_t le = hipSuccess;
-            for (int k = 0; k < K && le == hipSuccess; ++k) le = launch_step(b, host_bp.data(), n, s);
-            const hipError_t ce = hipStreamEndCapture(s, &g);
+            hipError_t le = hipSuccess, ce = hipSuccess;
+            {
+                std::lock_guard<std::mutex> lk(g_capture_mu);
+                HIP_TRY(w0, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                for (int k = 0; k < K && le == hipSuccess; ++k) le = launch_step(b, host_bp.data(), n, s);
+                ce = hipStreamEndCapture(s, &g);
+            }
             if (le != hipSuccess) return fail(w0, WORLD_E_HIP, std::string("graph capture: ") + hipGetErrorString(le));
             if (ce != hipSuccess) return fail(w0, WORLD_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
             HIP_TRY(w0, hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
@@ -536,6 +627,7 @@ int world_threshold_table(const world_config* cfg, uint64_t* out) {
 
 int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t arena_bytes, void* hip_stream,
                  world_t** out) {
+    TraceRange trace("world_create");
     if (!out || !arena) return fail(nullptr, WORLD_E_INVALID_ARG, "arena and out must be non-NULL");
     *out = nullptr;
     if (const char* m = check_config(cfg)) return fail(nullptr, WORLD_E_INVALID_CONFIG, m);
@@ -545,6 +637,14 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
     if (arena_bytes < lay.total) return fail(nullptr, WORLD_E_BUFFER_TOO_SMALL, "arena smaller than world_required_bytes");
 
     world* w = new world();
+    w->own = std::make_shared<WorkEvent>();
+    {
+        const hipError_t e = hipEventCreateWithFlags(&w->own->ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            delete w;
+            return fail(nullptr, WORLD_E_HIP, std::string("world_create: ") + hipGetErrorString(e));
+        }
+    }
     w->cfg = *cfg;
     w->dm = dims_of(*cfg);
     w->lay = lay;
@@ -736,7 +836,7 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
 int world_set_stream(world_t* w, void* hip_stream) {
     if (!w) return fail(nullptr, WORLD_E_INVALID_ARG, "world is NULL");
     if (w->poisoned) return WORLD_E_POISONED;
-    HIP_TRY(w, hipStreamSynchronize(w->stream));
+    if (int rc = wait_world(w)) return rc;
     w->stream = static_cast<hipStream_t>(hip_stream);
     return WORLD_OK;
 }
@@ -758,7 +858,7 @@ int world_set_tuning(world_t* w, int32_t act_rows, int32_t act_waves, int32_t re
     TableView tv;
     std::vector<const world*> one{w};
     const std::vector<char> table = build_table(one, w->base + w->lay.batch, &tv, &w->host_bp, &w->max_useful);
-    HIP_TRY(w, hipMemcpy(w->base + w->lay.batch, table.data(), table.size(), hipMemcpyHostToDevice));
+    HIP_TRY(w, copy_now(w, w->base + w->lay.batch, table.data(), table.size(), hipMemcpyHostToDevice));
     return WORLD_OK;
 }
 
@@ -775,7 +875,8 @@ static int step_single(world* w, int K) {
     tv.w = w->tv.w;
     tv.block_pre = w->tv.block_pre;
     tv.slots = w->tv.slots;
-    return run_steps(w, w->mode, tv, w->host_bp, 1, w->max_useful, K, w->graphs, w->graph_defs);
+    if (int rc = run_steps(w, w->mode, tv, w->host_bp, 1, w->max_useful, K, w->graphs, w->graph_defs)) return rc;
+    return mark_launch(&w, 1);
 }
 
 // Launch tables of batches (device memory owned by the library, one per
@@ -788,7 +889,8 @@ struct BatchEntry {
     std::vector<int> host_bp;
     int max_useful = 1;
     uint64_t last_use = 0;
-    hipStream_t stream = nullptr;
+    std::shared_ptr<WorkEvent> done;   // recorded after the entry's last launch
+    std::vector<char> host_table;      // source of the table's upload
     std::map<int, hipGraphExec_t> graphs;
     std::map<int, hipGraph_t> defs;
 };
@@ -816,7 +918,7 @@ static std::vector<uintptr_t> batch_key(world_t* const* ws, int n) {
 }
 
 static void release_entry(BatchEntry* be) {
-    if (be->stream) (void)hipStreamSynchronize(be->stream);
+    if (be->done) (void)wait_launch(be->done->ev);
     for (auto& kv : be->graphs) (void)hipGraphExecDestroy(kv.second);
     for (auto& kv : be->defs) (void)hipGraphDestroy(kv.second);
     if (be->dev) (void)hipFree(be->dev);
@@ -839,7 +941,6 @@ static int batch_step(world_t* const* ws, int n, int K) {
                 g_batches.erase(lru);
             }
             be = new BatchEntry();
-            be->stream = w0->stream;
             hipError_t e = hipMalloc(&be->dev, table_bytes(n));
             if (e != hipSuccess) {
                 delete be;
@@ -848,7 +949,10 @@ static int batch_step(world_t* const* ws, int n, int K) {
             std::vector<const world*> list(ws, ws + n);
             const std::vector<char> host = build_table(list, static_cast<char*>(be->dev), &be->tv, &be->host_bp,
                                                        &be->max_useful);
-            e = hipMemcpy(be->dev, host.data(), host.size(), hipMemcpyHostToDevice);
+            // on the launch stream, ahead of the launches that read it; the
+            // host copy lives with the entry, so nothing waits for the copy
+            be->host_table = host;
+            e = hipMemcpyAsync(be->dev, be->host_table.data(), be->host_table.size(), hipMemcpyHostToDevice, w0->stream);
             if (e != hipSuccess) {
                 (void)hipFree(be->dev);
                 delete be;
@@ -859,10 +963,15 @@ static int batch_step(world_t* const* ws, int n, int K) {
         be = it->second;
         be->last_use = ++g_batch_clock;
     }
-    return run_steps(w0, w0->mode, be->tv, be->host_bp, n, be->max_useful, K, be->graphs, be->defs);
+    if (int rc = run_steps(w0, w0->mode, be->tv, be->host_bp, n, be->max_useful, K, be->graphs, be->defs)) return rc;
+    if (int rc = mark_launch(ws, n)) return rc;
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    be->done = w0->own;
+    return WORLD_OK;
 }
 
 int world_step(world_t* w, int32_t K) {
+    TraceRange trace("world_step K=%d", K);
     if (!w) return fail(nullptr, WORLD_E_INVALID_ARG, "world is NULL");
     if (w->poisoned) return WORLD_E_POISONED;
     if (K < 1) return fail(w, WORLD_E_INVALID_ARG, "K must be >= 1");
@@ -877,6 +986,7 @@ int world_sync(world_t* w) {
 }
 
 int world_snapshot(world_t* w, world_image* out) {
+    TraceRange trace("world_snapshot");
     if (!w || !out) return fail(w, WORLD_E_INVALID_ARG, "NULL argument");
     if (w->poisoned) return WORLD_E_POISONED;
     if (out->struct_size != sizeof(world_image)) return fail(w, WORLD_E_INVALID_ARG, "world_image.struct_size mismatch");
@@ -884,7 +994,7 @@ int world_snapshot(world_t* w, world_image* out) {
     const world_config& c = w->cfg;
     const Layout& l = w->lay;
     WorldScal sc;
-    HIP_TRY(w, hipMemcpy(&sc, w->base + l.scal, sizeof(sc), hipMemcpyDeviceToHost));
+    HIP_TRY(w, copy_now(w, &sc, w->base + l.scal, sizeof(sc), hipMemcpyDeviceToHost));
     if (sc.n_child > 0) {
         // children of the last step are created at the start of the next
         // one; create them now so that the image is complete
@@ -893,21 +1003,21 @@ int world_snapshot(world_t* w, world_image* out) {
         hipLaunchKernelGGL(k_clear_pending, dim3(1), dim3(64), 0, w->stream, dp);
         HIP_TRY(w, hipGetLastError());
         HIP_TRY(w, hipStreamSynchronize(w->stream));
-        HIP_TRY(w, hipMemcpy(&sc, w->base + l.scal, sizeof(sc), hipMemcpyDeviceToHost));
+        HIP_TRY(w, copy_now(w, &sc, w->base + l.scal, sizeof(sc), hipMemcpyDeviceToHost));
     }
     out->step = sc.t;
     out->n_live = sc.n_live;
     out->next_uid = sc.next_uid;
     if (out->agent_capacity < sc.n_live) return fail(w, WORLD_E_BUFFER_TOO_SMALL, "agent_capacity < n_live");
     const size_t HW = size_t(c.H) * c.W;
-    if (out->R) HIP_TRY(w, hipMemcpy(out->R, w->base + (sc.t & 1 ? l.R1 : l.R0), HW, hipMemcpyDeviceToHost));
+    if (out->R) HIP_TRY(w, copy_now(w, out->R, w->base + (sc.t & 1 ? l.R1 : l.R0), HW, hipMemcpyDeviceToHost));
     const int n = sc.n_live;
     std::vector<int32_t> live(std::max(n, 1));
-    HIP_TRY(w, hipMemcpy(live.data(), w->base + (sc.live_sel ? l.live1 : l.live0), 4 * size_t(n), hipMemcpyDeviceToHost));
+    HIP_TRY(w, copy_now(w, live.data(), w->base + (sc.live_sel ? l.live1 : l.live0), 4 * size_t(n), hipMemcpyDeviceToHost));
     auto gather_i32 = [&](size_t off, int32_t* dst) -> int {
         if (!dst) return WORLD_OK;
         std::vector<int32_t> all(c.cap);
-        HIP_TRY(w, hipMemcpy(all.data(), w->base + off, 4 * size_t(c.cap), hipMemcpyDeviceToHost));
+        HIP_TRY(w, copy_now(w, all.data(), w->base + off, 4 * size_t(c.cap), hipMemcpyDeviceToHost));
         for (int i = 0; i < n; ++i) dst[i] = all[live[i]];
         return WORLD_OK;
     };
@@ -926,13 +1036,13 @@ int world_snapshot(world_t* w, world_image* out) {
     const size_t ss = size_t(state_of(c));
     if ((out->flags & WORLD_SNAP_HIDDEN) && out->h) {
         std::vector<float> hs(size_t(c.cap) * ss);
-        HIP_TRY(w, hipMemcpy(hs.data(), w->base + l.h, 4 * hs.size(), hipMemcpyDeviceToHost));
+        HIP_TRY(w, copy_now(w, hs.data(), w->base + l.h, 4 * hs.size(), hipMemcpyDeviceToHost));
         for (int i = 0; i < n; ++i) std::memcpy(out->h + size_t(i) * ss, hs.data() + size_t(live[i]) * ss, 4 * ss);
     }
     auto gather_u8 = [&](size_t off, uint8_t* dst) -> int {
         if (!dst) return WORLD_OK;
         std::vector<uint8_t> all(c.cap);
-        HIP_TRY(w, hipMemcpy(all.data(), w->base + off, size_t(c.cap), hipMemcpyDeviceToHost));
+        HIP_TRY(w, copy_now(w, all.data(), w->base + off, size_t(c.cap), hipMemcpyDeviceToHost));
         for (int i = 0; i < n; ++i) dst[i] = all[live[i]];
         return WORLD_OK;
     };
@@ -941,15 +1051,30 @@ int world_snapshot(world_t* w, world_image* out) {
         if (int rc = gather_u8(l.ate, out->ate)) return rc;
     }
     if ((out->flags & WORLD_SNAP_THETA) && out->theta) {
+        // whole slot ranges of at most 64 MB, one copy each, then the rows of
+        // the live agents in them (in uid order in the image)
         const size_t P = size_t(w->dm.P), Pp = size_t(w->dm.Ppad);
-        for (int i = 0; i < n; ++i)
-            HIP_TRY(w, hipMemcpy(out->theta + size_t(i) * P, w->base + l.theta + 4 * Pp * size_t(live[i]), 4 * P,
+        std::vector<int> by_slot(static_cast<size_t>(n));
+        for (int i = 0; i < n; ++i) by_slot[size_t(i)] = i;
+        std::sort(by_slot.begin(), by_slot.end(), [&](int a, int b) { return live[a] < live[b]; });
+        const size_t chunk = std::max<size_t>(1, (size_t(64) << 20) / (4 * Pp));
+        std::vector<float> buf(std::min(chunk, size_t(c.cap)) * Pp);
+        size_t k = 0;
+        for (size_t s0 = 0; s0 < size_t(c.cap) && k < by_slot.size(); s0 += chunk) {
+            const size_t s1 = std::min(size_t(c.cap), s0 + chunk);
+            if (size_t(live[by_slot[k]]) >= s1) continue;   // no live agent in these slots
+            HIP_TRY(w, copy_now(w, buf.data(), w->base + l.theta + 4 * Pp * s0, 4 * Pp * (s1 - s0),
                                  hipMemcpyDeviceToHost));
+            for (; k < by_slot.size() && size_t(live[by_slot[k]]) < s1; ++k)
+                std::memcpy(out->theta + size_t(by_slot[k]) * P, buf.data() + (size_t(live[by_slot[k]]) - s0) * Pp,
+                            4 * P);
+        }
     }
     return WORLD_OK;
 }
 
 int world_load(world_t* w, const world_image* in) {
+    TraceRange trace("world_load");
     if (!w || !in) return fail(w, WORLD_E_INVALID_ARG, "NULL argument");
     if (w->poisoned) return WORLD_E_POISONED;
     const world_config& c = w->cfg;
@@ -990,40 +1115,40 @@ int world_load(world_t* w, const world_image* in) {
         ates[i] = in->ate[i];
     }
     HIP_TRY(w, hipStreamSynchronize(w->stream));
-    HIP_TRY(w, hipMemcpy(b + l.scal, &sc, sizeof(sc), hipMemcpyHostToDevice));
-    HIP_TRY(w, hipMemcpy(b + (in->step & 1 ? l.R1 : l.R0), in->R, HW, hipMemcpyHostToDevice));
-    HIP_TRY(w, hipMemcpy(b + l.occA, occ.data(), 4 * HW, hipMemcpyHostToDevice));
-    HIP_TRY(w, hipMemcpy(b + l.occB, occ.data(), 4 * HW, hipMemcpyHostToDevice));
-    HIP_TRY(w, hipMemcpy(b + l.uid, uids.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
-    HIP_TRY(w, hipMemcpy(b + l.cell, cells.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
-    HIP_TRY(w, hipMemcpy(b + l.prev_cell, cells.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
-    HIP_TRY(w, hipMemcpy(b + l.energy, energies.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
-    HIP_TRY(w, hipMemcpy(b + l.age, ages.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
-    HIP_TRY(w, hipMemcpy(b + l.streak, streaks.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
-    HIP_TRY(w, hipMemcpy(b + l.alive, alive.data(), size_t(c.cap), hipMemcpyHostToDevice));
-    HIP_TRY(w, hipMemcpy(b + l.action, acts.data(), size_t(c.cap), hipMemcpyHostToDevice));
-    HIP_TRY(w, hipMemcpy(b + l.ate, ates.data(), size_t(c.cap), hipMemcpyHostToDevice));
-    HIP_TRY(w, hipMemcpy(b + l.live0, live.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
+    HIP_TRY(w, copy_now(w, b + l.scal, &sc, sizeof(sc), hipMemcpyHostToDevice));
+    HIP_TRY(w, copy_now(w, b + (in->step & 1 ? l.R1 : l.R0), in->R, HW, hipMemcpyHostToDevice));
+    HIP_TRY(w, copy_now(w, b + l.occA, occ.data(), 4 * HW, hipMemcpyHostToDevice));
+    HIP_TRY(w, copy_now(w, b + l.occB, occ.data(), 4 * HW, hipMemcpyHostToDevice));
+    HIP_TRY(w, copy_now(w, b + l.uid, uids.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
+    HIP_TRY(w, copy_now(w, b + l.cell, cells.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
+    HIP_TRY(w, copy_now(w, b + l.prev_cell, cells.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
+    HIP_TRY(w, copy_now(w, b + l.energy, energies.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
+    HIP_TRY(w, copy_now(w, b + l.age, ages.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
+    HIP_TRY(w, copy_now(w, b + l.streak, streaks.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
+    HIP_TRY(w, copy_now(w, b + l.alive, alive.data(), size_t(c.cap), hipMemcpyHostToDevice));
+    HIP_TRY(w, copy_now(w, b + l.action, acts.data(), size_t(c.cap), hipMemcpyHostToDevice));
+    HIP_TRY(w, copy_now(w, b + l.ate, ates.data(), size_t(c.cap), hipMemcpyHostToDevice));
+    HIP_TRY(w, copy_now(w, b + l.live0, live.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
     {
         std::vector<PosRec> recs(c.cap);
         std::memset(recs.data(), 0, sizeof(PosRec) * recs.size());
         for (int i = 0; i < n; ++i)
             recs[i].r[0] = AgentRec{i, cells[i], energies[i], uids[i], ages[i], streaks[i], int32_t(acts[i]),
                                     int32_t(ates[i])};
-        HIP_TRY(w, hipMemcpy(b + l.pos, recs.data(), sizeof(PosRec) * size_t(c.cap), hipMemcpyHostToDevice));
+        HIP_TRY(w, copy_now(w, b + l.pos, recs.data(), sizeof(PosRec) * size_t(c.cap), hipMemcpyHostToDevice));
     }
-    HIP_TRY(w, hipMemcpy(b + l.freeq, freeq.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
-    HIP_TRY(w, hipMemset(b + l.lb_move, 0, 8 * size_t(tiles_agent(c))));
-    HIP_TRY(w, hipMemset(b + l.lb_claim, 0, 8 * size_t(tiles_agent(c))));
-    HIP_TRY(w, hipMemset(b + l.mclaim, 0xFF, 8 * HW));
-    HIP_TRY(w, hipMemset(b + l.wuid, 0xFF, 4 * size_t(c.cap)));   // no agent counts in the window in progress
-    HIP_TRY(w, hipMemset(b + l.mhist, 0, 4 * size_t(kMoveRing) * (kMoveBins + 1)));
+    HIP_TRY(w, copy_now(w, b + l.freeq, freeq.data(), 4 * size_t(c.cap), hipMemcpyHostToDevice));
+    HIP_TRY(w, fill_now(w, b + l.lb_move, 0, 8 * size_t(tiles_agent(c))));
+    HIP_TRY(w, fill_now(w, b + l.lb_claim, 0, 8 * size_t(tiles_agent(c))));
+    HIP_TRY(w, fill_now(w, b + l.mclaim, 0xFF, 8 * HW));
+    HIP_TRY(w, fill_now(w, b + l.wuid, 0xFF, 4 * size_t(c.cap)));   // no agent counts in the window in progress
+    HIP_TRY(w, fill_now(w, b + l.mhist, 0, 4 * size_t(kMoveRing) * (kMoveBins + 1)));
     if (n > 0) {
         const size_t ss = size_t(state_of(c));
         std::vector<float> hs(size_t(c.cap) * ss, 0.f);
         std::memcpy(hs.data(), in->h, 4 * size_t(n) * ss);
-        HIP_TRY(w, hipMemcpy(b + l.h, hs.data(), 4 * hs.size(), hipMemcpyHostToDevice));
-        HIP_TRY(w, hipMemcpy(b + l.theta, th.data(), 4 * size_t(n) * Pp, hipMemcpyHostToDevice));
+        HIP_TRY(w, copy_now(w, b + l.h, hs.data(), 4 * hs.size(), hipMemcpyHostToDevice));
+        HIP_TRY(w, copy_now(w, b + l.theta, th.data(), 4 * size_t(n) * Pp, hipMemcpyHostToDevice));
     }
     if (n > 0 && !is_net(c)) {
         hipLaunchKernelGGL(k_proj_all, dim3(blocks_of_agents(c)), dim3(kBlock), 0, w->stream,
@@ -1052,11 +1177,11 @@ int world_counters_get(world_t* w, int64_t first, int32_t n, world_counters* out
     HIP_TRY(w, hipGetLastError());
     if (int rc = world_sync(w)) return rc;
     WorldScal sc;
-    HIP_TRY(w, hipMemcpy(&sc, w->base + w->lay.scal, sizeof(sc), hipMemcpyDeviceToHost));
+    HIP_TRY(w, copy_now(w, &sc, w->base + w->lay.scal, sizeof(sc), hipMemcpyDeviceToHost));
     if (n < 0 || first < 0 || first + n > sc.t || first < sc.t - kRing)
         return fail(w, WORLD_E_STATE, "requested steps are not held in the counter ring");
     std::vector<int32_t> ring(size_t(kRing) * kCtrWords);
-    HIP_TRY(w, hipMemcpy(ring.data(), w->base + w->lay.ring, 4 * ring.size(), hipMemcpyDeviceToHost));
+    HIP_TRY(w, copy_now(w, ring.data(), w->base + w->lay.ring, 4 * ring.size(), hipMemcpyDeviceToHost));
     for (int i = 0; i < n; ++i) {
         const int32_t* r = ring.data() + ((first + i) % kRing) * kCtrWords;
         out[i].n_live = r[kCtrLive];
@@ -1077,14 +1202,14 @@ int world_move_hist(world_t* w, int64_t first, int32_t n, int32_t* out) {
     if (w->poisoned) return WORLD_E_POISONED;
     if (int rc = world_sync(w)) return rc;
     WorldScal sc;
-    HIP_TRY(w, hipMemcpy(&sc, w->base + w->lay.scal, sizeof(sc), hipMemcpyDeviceToHost));
+    HIP_TRY(w, copy_now(w, &sc, w->base + w->lay.scal, sizeof(sc), hipMemcpyDeviceToHost));
     // window k has ended once (k + 1) * kMoveWin steps are done; its record is
     // overwritten when window k + kMoveRing starts
     const int64_t started = sc.t > 0 ? (sc.t - 1) / kMoveWin : -1;   // last window begun
     if (n < 0 || first < 0 || (first + n) * kMoveWin > sc.t || (n > 0 && first <= started - kMoveRing))
         return fail(w, WORLD_E_STATE, "requested windows have not ended or are no longer held");
     std::vector<int32_t> ring(size_t(kMoveRing) * (kMoveBins + 1));
-    HIP_TRY(w, hipMemcpy(ring.data(), w->base + w->lay.mhist, 4 * ring.size(), hipMemcpyDeviceToHost));
+    HIP_TRY(w, copy_now(w, ring.data(), w->base + w->lay.mhist, 4 * ring.size(), hipMemcpyDeviceToHost));
     for (int i = 0; i < n; ++i)
         std::memcpy(out + size_t(i) * (kMoveBins + 1), ring.data() + ((first + i) % kMoveRing) * (kMoveBins + 1),
                     4 * (kMoveBins + 1));
@@ -1093,7 +1218,7 @@ int world_move_hist(world_t* w, int64_t first, int32_t n, int32_t* out) {
 
 int world_destroy(world_t* w) {
     if (!w) return WORLD_OK;
-    (void)hipStreamSynchronize(w->stream);
+    if (w->last) (void)wait_launch(w->last->ev);
     {
         // launch tables and graphs of batches that list this world go with it
         // (their streams are synchronised before anything is released)
@@ -1125,14 +1250,14 @@ const char* world_last_error(const world_t* w) {
 // forced_on are contiguous) after the table, once the stream is idle.
 static int write_forced(world* w, const int8_t* tab, int32_t n, int32_t dflt) {
     HIP_TRY(w, hipStreamSynchronize(w->stream));
-    if (n > 0) HIP_TRY(w, hipMemcpy(w->base + w->lay.forced, tab, size_t(n), hipMemcpyHostToDevice));
+    if (n > 0) HIP_TRY(w, copy_now(w, w->base + w->lay.forced, tab, size_t(n), hipMemcpyHostToDevice));
     w->dev.forced = dflt;
     w->dev.n_forced = n;
     w->dev.forced_on = (dflt >= 0 || n > 0) ? 1 : 0;
     static_assert(offsetof(WorldDev, n_forced) == offsetof(WorldDev, forced) + 4 &&
                       offsetof(WorldDev, forced_on) == offsetof(WorldDev, forced) + 8,
                   "forced fields must be contiguous");
-    HIP_TRY(w, hipMemcpy(w->base + w->lay.desc + offsetof(WorldDev, forced), &w->dev.forced, 12,
+    HIP_TRY(w, copy_now(w, w->base + w->lay.desc + offsetof(WorldDev, forced), &w->dev.forced, 12,
                          hipMemcpyHostToDevice));
     return WORLD_OK;
 }
@@ -1167,9 +1292,9 @@ int world_test_stall_lookback(world_t* w, int32_t tile, uint32_t spin_ticks) {
     w->dev.stall_tile = tile;
     w->dev.spin_ticks = ticks;
     HIP_TRY(w, hipStreamSynchronize(w->stream));
-    HIP_TRY(w, hipMemcpy(w->base + w->lay.desc + offsetof(WorldDev, stall_tile), &tile, sizeof(tile),
+    HIP_TRY(w, copy_now(w, w->base + w->lay.desc + offsetof(WorldDev, stall_tile), &tile, sizeof(tile),
                          hipMemcpyHostToDevice));
-    HIP_TRY(w, hipMemcpy(w->base + w->lay.desc + offsetof(WorldDev, spin_ticks), &ticks, sizeof(ticks),
+    HIP_TRY(w, copy_now(w, w->base + w->lay.desc + offsetof(WorldDev, spin_ticks), &ticks, sizeof(ticks),
                          hipMemcpyHostToDevice));
     return WORLD_OK;
 }
@@ -1182,26 +1307,26 @@ int world_action_log(world_t* w, int64_t step, int32_t capacity, uint32_t* uid, 
     if (c.log_steps <= 0) return fail(w, WORLD_E_STATE, "world created without a controller log");
     if (int rc = world_sync(w)) return rc;
     WorldScal sc;
-    HIP_TRY(w, hipMemcpy(&sc, w->base + w->lay.scal, sizeof(sc), hipMemcpyDeviceToHost));
+    HIP_TRY(w, copy_now(w, &sc, w->base + w->lay.scal, sizeof(sc), hipMemcpyDeviceToHost));
     if (step < 0 || step >= sc.t || step < sc.t - c.log_steps) return fail(w, WORLD_E_STATE, "step not held in the log");
     const size_t row = size_t(step % c.log_steps);
     int32_t cnt = 0;
-    HIP_TRY(w, hipMemcpy(&cnt, w->base + w->lay.log_n + 4 * row, 4, hipMemcpyDeviceToHost));
+    HIP_TRY(w, copy_now(w, &cnt, w->base + w->lay.log_n + 4 * row, 4, hipMemcpyDeviceToHost));
     *n = cnt;
     if (capacity < cnt) return fail(w, WORLD_E_BUFFER_TOO_SMALL, "capacity < agents in the step");
     const size_t base = row * size_t(c.cap);
-    if (uid) HIP_TRY(w, hipMemcpy(uid, w->base + w->lay.log_uid + 4 * base, 4 * size_t(cnt), hipMemcpyDeviceToHost));
-    if (action) HIP_TRY(w, hipMemcpy(action, w->base + w->lay.log_act + base, size_t(cnt), hipMemcpyDeviceToHost));
+    if (uid) HIP_TRY(w, copy_now(w, uid, w->base + w->lay.log_uid + 4 * base, 4 * size_t(cnt), hipMemcpyDeviceToHost));
+    if (action) HIP_TRY(w, copy_now(w, action, w->base + w->lay.log_act + base, size_t(cnt), hipMemcpyDeviceToHost));
     if (logits)
-        HIP_TRY(w, hipMemcpy(logits, w->base + w->lay.log_logits + 4 * 5 * base, 4 * 5 * size_t(cnt), hipMemcpyDeviceToHost));
+        HIP_TRY(w, copy_now(w, logits, w->base + w->lay.log_logits + 4 * 5 * base, 4 * 5 * size_t(cnt), hipMemcpyDeviceToHost));
     if (margin && cnt > 0) {
         // the device's decision values: the logits (GRU, arg-max) or the
         // sampling scores 50 l + g of the paper's network, whose Gumbel terms
         // g the same counter-based draws give on the host bit for bit
         std::vector<float> lg(size_t(cnt) * 5);
         std::vector<uint32_t> us(static_cast<size_t>(cnt));
-        HIP_TRY(w, hipMemcpy(lg.data(), w->base + w->lay.log_logits + 4 * 5 * base, 4 * lg.size(), hipMemcpyDeviceToHost));
-        HIP_TRY(w, hipMemcpy(us.data(), w->base + w->lay.log_uid + 4 * base, 4 * us.size(), hipMemcpyDeviceToHost));
+        HIP_TRY(w, copy_now(w, lg.data(), w->base + w->lay.log_logits + 4 * 5 * base, 4 * lg.size(), hipMemcpyDeviceToHost));
+        HIP_TRY(w, copy_now(w, us.data(), w->base + w->lay.log_uid + 4 * base, 4 * us.size(), hipMemcpyDeviceToHost));
         const bool net_ctrl = is_net(c);
         for (int i = 0; i < cnt; ++i) {
             float sc[5];
@@ -1258,6 +1383,7 @@ int world_test_gumbel(const uint32_t* d_words, size_t n, float* d_g, void* strea
 }
 
 int world_phase_times(world_t* w, int32_t K, float* ms) {
+    TraceRange trace("world_phase_times K=%d", K);
     if (!w || !ms) return fail(w, WORLD_E_INVALID_ARG, "NULL argument");
     if (w->poisoned) return WORLD_E_POISONED;
     if (K < 1) return fail(w, WORLD_E_INVALID_ARG, "K must be >= 1");
@@ -1329,6 +1455,7 @@ static int check_batch(world_t* const* ws, int32_t n, int32_t K) {
 }
 
 int world_step_many(world_t* const* ws, int32_t n, int32_t K) {
+    TraceRange trace("world_step_many n=%d K=%d", n, K);
     if (int rc = check_batch(ws, n, K)) return rc;
     return batch_step(ws, n, K);
 }
@@ -1393,6 +1520,7 @@ static int scratch_address(char** out) {
 }
 
 int world_step_many_noalloc(world_t* const* ws, int32_t n, int32_t K) {
+    TraceRange trace("world_step_many_noalloc n=%d K=%d", n, K);
     if (int rc = check_batch(ws, n, K)) return rc;
     if (n > kNoAllocMaxWorlds) return fail(nullptr, WORLD_E_INVALID_ARG, "more than 2048 worlds in one batch");
     char* table = nullptr;
@@ -1420,7 +1548,7 @@ int world_step_many_noalloc(world_t* const* ws, int32_t n, int32_t K) {
             w0->act_rows, n == 1 ? static_cast<const WorldDev*>(w0->d_dev) : nullptr, w0->cfg.cap, w0->dev.ctrl,
             w0->dev.dyn, net_wide(slots), w0->act_waves, w0->tile};
     for (int k = 0; k < K; ++k) HIP_TRY(w0, launch_step(b, bp.data(), n, s));
-    return WORLD_OK;
+    return mark_launch(ws, n);
 }
 
 }  // extern "C"

@@ -88,3 +88,64 @@ def test_served_mixed_kinds_equal_alone(env):
         alone = serve.state_digest(w.snapshot(hidden=True, theta=True))
         w.close()
         assert results[r.rid]["digest"] == alone, r.rid
+
+
+def test_finish_while_loop_captures(env):
+    """What the serving loop's helper threads do while the loop launches on
+    the shared stream, capturing a new graph for every launch: create a world
+    on a side stream, move finished worlds off the shared stream, read their
+    images and counters, and release them (with the batch launch tables that
+    list them).  None of these calls may synchronise with the shared stream
+    or the legacy default stream (HIP makes that one depend on it) while a
+    capture is in progress there; every result must equal the same world
+    stepped alone."""
+    import threading
+
+    import torch
+    world, serve, batch, tune, wl = env
+    cfg = wl.make(H=64, W=128, cap=512, n_init=51, hidden=16, rate_scale=1.0, res_init_p=0.3)
+    S, side = torch.cuda.Stream(), torch.cuda.Stream()
+    runners = [world.World(cfg, 20 + i, stream=S, mode="graph") for i in range(2)]
+    leaving = [world.World(cfg, 30 + i, stream=S, mode="graph") for i in range(6)]
+    world.step_many(leaving[:3], 4)   # batch tables listing the leaving worlds
+    world.step_many(leaving[3:], 4)
+    for w in leaving:
+        w.step(2)
+    errors, images, created = [], {}, []
+
+    def finisher():
+        try:
+            for i, w in enumerate(leaving):
+                created.append(world.World(cfg, 90 + i, stream=side, mode="graph"))
+                w.set_stream(side)
+                img = w.snapshot(hidden=True, theta=True)
+                ctr = w.counters(0, 6)
+                w.close()
+                images[i] = (serve.state_digest(img), int(ctr["n_live"][-1]) == img["n_live"])
+        except Exception as e:
+            errors.append(repr(e))
+
+    say("[serve] a helper thread finishes worlds while the loop captures a graph per launch")
+    th = threading.Thread(target=finisher)
+    th.start()
+    steps, K = 0, 1
+    while (th.is_alive() or K <= 8) and K <= 40:
+        world.step_many(runners, K)   # a new K: a new capture
+        steps += K
+        K += 1
+    th.join()
+    torch.cuda.synchronize()
+    assert not errors, errors
+    assert len(created) == len(leaving)
+    for i in range(len(leaving)):
+        alone = world.World(cfg, 30 + i, mode="graph")
+        alone.step(6)
+        assert images[i][0] == serve.state_digest(alone.snapshot(hidden=True, theta=True)), i
+        assert images[i][1], i
+        alone.close()
+    for i, w in enumerate(runners):
+        w.sync()
+        alone = world.World(cfg, 20 + i, mode="graph")
+        alone.step(steps)
+        assert serve.state_digest(w.snapshot(hidden=True, theta=True)) == \
+            serve.state_digest(alone.snapshot(hidden=True, theta=True)), i

@@ -56,7 +56,7 @@ def test_library_host_code_under_asan_ubsan(tmp_path):
              "-Xarch_host", "-fno-sanitize-recover=all",
              "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-I", os.path.join(ROOT, "include"), os.path.join(ROOT, "paper_2302_09334_amd", "csrc", "world.hip"),
-             os.path.join(HELPERS, "world_host_sanitize_main.cpp"), "-o", exe])
+             os.path.join(HELPERS, "world_host_sanitize_main.cpp"), "-o", exe, "-lrocprofiler-sdk-roctx"])
     assert b.returncode == 0, b.stderr[-3000:]
     r = run([exe], env=dict(os.environ, ASAN_OPTIONS="detect_leaks=1", UBSAN_OPTIONS="print_stacktrace=1"),
             timeout=300)
