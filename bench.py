@@ -115,9 +115,9 @@ def act_bytes_per_agent(cfg: dict, rows_mean: float) -> float:
 
 
 # Share of the live list whose recurrent projection runs in the move kernel
-# (the library's build default, ECO_PROJ_MOVE_EIGHTHS = 3); the rest, minus
+# (the library's build default, ECO_PROJ_MOVE_EIGHTHS = 4); the rest, minus
 # the agents that died in the move phase, runs in the claim kernel.
-PROJ_MOVE_SHARE = 3 / 8
+PROJ_MOVE_SHARE = 4 / 8
 
 
 def proj_bytes_per_agent(cfg: dict) -> float:

@@ -25,12 +25,9 @@ constexpr int kNewbornBlocks = ECO_NEWBORN_BLOCKS;  // leading act blocks that c
 #endif
 constexpr int kProjPer = ECO_PROJ_PER;
 #ifndef ECO_PROJ_MOVE_EIGHTHS
-#define ECO_PROJ_MOVE_EIGHTHS 3   // eighths of the live list whose projection runs in the move phase
+#define ECO_PROJ_MOVE_EIGHTHS 4   // eighths of the live list whose projection runs in the move phase
 #endif
 constexpr int kProjMove8 = ECO_PROJ_MOVE_EIGHTHS;
-#ifndef ECO_PROJ_DELAY
-#define ECO_PROJ_DELAY 50   // wall-clock ticks (10 ns) a claim-phase projection wave waits before its loads
-#endif
 
 // Live-list positions [0, proj_split(n)) are projected in the move phase, the
 // rest in the claim phase.
@@ -237,13 +234,13 @@ __device__ __forceinline__ void move_body(const Batch& bt, int vb, int lane) {
 // and a child taking over a dead agent's slot is projected when the next act
 // phase creates it.
 //
-// The projection (about 40% of a step's bytes) streams while the move and
-// claim tiles, which are latency-bound, wait on their round trips; but every
-// tile load then queues behind the projection's loads.  Measured at 4608
-// agents: three eighths of the list in the move phase, the rest here after a
-// 0.5 us pause (the tiles' first gathers and the regrowth loads go first),
-// two positions per wave, gave 32.7 us per step against 34.4 us with all of
-// it here and no pause.
+// The projection (about half of a step's bytes) streams while the move and
+// claim tiles, which are latency-bound, wait on their round trips; every tile
+// load then queues behind the projection's loads, so it is split between the
+// two phases.  Measured at 4608 agents, two positions per wave: half of the
+// list in each phase 31.4 us per step, three eighths in the move phase 31.9
+// (all of it here: 34.4 before the claim tiles skipped their gathers in steps
+// without a free slot).
 template <bool PAPER, int TILE>
 __device__ __forceinline__ void claim_body(const Batch& bt, int vb, int lane, uint8_t* tile) {
     const BlockWorld bw = block_world(bt, kPreClaim, vb);
@@ -262,10 +259,6 @@ __device__ __forceinline__ void claim_body(const Batch& bt, int vb, int lane, ui
     if (lb < ntile + ngrow) {
         regrow_tile<TILE>(d, lb - ntile, lane, tile, kconst(bw.S)->t_grow, ngrow);
         return;
-    }
-    if (ECO_PROJ_DELAY > 0) {   // let the tiles' loads pass first
-        const uint64_t t0 = wall_clock64();
-        while (wall_clock64() - t0 < uint64_t(ECO_PROJ_DELAY)) __builtin_amdgcn_s_sleep(4);
     }
     const int nw = proj_waves(bw.cap);
     const int n = kconst(bw.S)->n_grow;

@@ -96,7 +96,7 @@ def test_step_bytes_closed_form(bench):
 def test_kernel_window_bytes(bench):
     """The act kernel's bytes are its per-agent bytes without input rows,
     plus the rows the device counted, the children's genomes and the grid;
-    the projection splits 3/8 (move) and 5/8 of the survivors (claim)."""
+    the projection splits 4/8 (move) and 4/8 of the survivors (claim)."""
     cfg = {"hidden": 16, "H": 10, "W": 20}
     P = 1000
     kb = bench.kernel_window_bytes(cfg, P, np.array([100, 100]), np.array([1000, 3000]), np.array([2, 0]),
@@ -105,8 +105,8 @@ def test_kernel_window_bytes(bench):
     act = 100 * bench.act_bytes_per_agent(cfg, 0.0) + 2000 * rw + 1 * 8 * P + 200 * 5
     assert kb["act"] == pytest.approx(act)
     pb = bench.proj_bytes_per_agent(cfg)
-    assert kb["move"] == pytest.approx(100 * (bench.MOVE_BYTES_PER_AGENT + 3 / 8 * pb))
-    claim = 5 / 8 * 96 * pb + 100 * bench.CLAIM_BYTES_PER_AGENT + 2 * bench.CLAIM_BYTES_PER_ELIGIBLE + 2 * 200
+    assert kb["move"] == pytest.approx(100 * (bench.MOVE_BYTES_PER_AGENT + 4 / 8 * pb))
+    claim = 4 / 8 * 96 * pb + 100 * bench.CLAIM_BYTES_PER_AGENT + 2 * bench.CLAIM_BYTES_PER_ELIGIBLE + 2 * 200
     assert kb["claim"] == pytest.approx(claim)
 
 
@@ -116,3 +116,13 @@ def test_traffic_per_agent_tied_to_sources(bench, tmp_path):
     assert bench.read_traffic_per_agent("abc", 8, str(p)) == 12345.5
     assert bench.read_traffic_per_agent("abc", 16, str(p)) is None
     assert bench.read_traffic_per_agent("xyz", 8, str(p)) is None
+
+
+def test_projection_share_matches_library_default(bench):
+    """The bench's split of the projection bytes between the move and claim
+    kernels is the library's build default."""
+    import re
+    src = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2302_09334_amd",
+                            "csrc", "kernels.h")).read()
+    eighths = int(re.search(r"#define ECO_PROJ_MOVE_EIGHTHS (\d+)", src).group(1))
+    assert bench.PROJ_MOVE_SHARE == eighths / 8
