@@ -80,8 +80,14 @@ static void draw(uint64_t seed, uint32_t entity, uint32_t step, uint32_t stream,
 /* any implementation performing the same IEEE operations gets the same bits.*/
 /* ========================================================================= */
 
-/* ln(u) for u in (0, 1].  u = m * 2^e with m in [sqrt(1/2), sqrt(2));
- * ln m = 2 atanh(s), s = (m - 1) / (m + 1), atanh(s) = sum s^(2k+1)/(2k+1). */
+/* ln(u) for a positive normal float u (the uniforms of Box-Muller, and the
+ * exponential deviate inside a Gumbel draw).  u = m * 2^e with m in
+ * [sqrt(1/2), sqrt(2)) and f = m - 1, which is exact.  For s = f / (2 + f),
+ * ln m = ln((1 + s) / (1 - s)) = 2 (s + s^3/3 + s^5/5 + ...).  Because
+ * s (2 + f) = f, the leading 2s equals f - s f, and
+ *     ln m = f - (f^2/2 - s (f^2/2 + R)),  R = 2 s^2/3 + 2 s^4/5 + ... + 2 s^10/11,
+ * which keeps the large term f free of rounding.  ln 2 is split into a head
+ * whose products with e are exact and a tail. */
 static float ln_unit(float u)
 {
     int e;
@@ -91,19 +97,19 @@ static float ln_unit(float u)
         e = e - 1;
     }
     float f = m - 1.0f;
-    float d = m + 1.0f;
-    float s = f / d;
+    float s = f / (2.0f + f);
     float s2 = s * s;
-    float p = 1.0f / 11.0f;
-    p = fmaf(p, s2, 1.0f / 9.0f);
-    p = fmaf(p, s2, 1.0f / 7.0f);
-    p = fmaf(p, s2, 1.0f / 5.0f);
-    p = fmaf(p, s2, 1.0f / 3.0f);
-    p = fmaf(p, s2, 1.0f);
-    float lnm = 2.0f * (s * p);
+    float r = 2.0f / 11.0f;                  /* R / s^2 by Horner in s^2 */
+    r = fmaf(r, s2, 2.0f / 9.0f);
+    r = fmaf(r, s2, 2.0f / 7.0f);
+    r = fmaf(r, s2, 2.0f / 5.0f);
+    r = fmaf(r, s2, 2.0f / 3.0f);
+    float R = r * s2;
+    float half_f2 = (0.5f * f) * f;
     float ef = (float)e;
-    /* ln 2 split into a short head (exact products with e) and a tail. */
-    return fmaf(ef, 0x1.62e4p-1f, fmaf(ef, 0x1.7f7d1cp-20f, lnm));
+    float small = fmaf(s, half_f2 + R, ef * 0x1.7f7d1cp-20f);   /* + e * (ln 2 tail) */
+    float corr = half_f2 - small;
+    return fmaf(ef, 0x1.62e4p-1f, f - corr);
 }
 
 /* sin and cos of (pi/2) * g for g in [0, 1/2], from the Taylor series. */

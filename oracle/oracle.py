@@ -23,13 +23,14 @@ LIB_PATH = os.environ.get("ORACLE_LIB", os.path.join(HERE, "liboracle.so"))
 
 def build(quiet: bool = True) -> str:
     """Compile liboracle.so with the host C compiler (no contraction, no fast-math)."""
+    tmp = f"{LIB_PATH}.{os.getpid()}.tmp"   # per process: parallel test workers build at once
     cmd = [
         "gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
         "-Wall", "-Wextra", "-Wno-unused-parameter",
-        SRC_PATH, "-o", LIB_PATH + ".tmp", "-lm",
+        SRC_PATH, "-o", tmp, "-lm",
     ]
     subprocess.run(cmd, check=True, capture_output=quiet)
-    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    os.replace(tmp, LIB_PATH)
     return LIB_PATH
 
 

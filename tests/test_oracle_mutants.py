@@ -32,7 +32,9 @@ MUTANTS = {
     "counter_entity_step_swapped": ("philox_block(entity, step, stream, block, (uint32_t)seed, (uint32_t)(seed >> 32), out);",
                                     "philox_block(step, entity, stream, block, (uint32_t)seed, (uint32_t)(seed >> 32), out);",
                                     1, (DYN,)),
-    "ln_series_coefficient": ("p = fmaf(p, s2, 1.0f / 5.0f);", "p = fmaf(p, s2, 1.0f / 6.0f);", 1, (RNG,)),
+    "ln_series_coefficient": ("r = fmaf(r, s2, 2.0f / 5.0f);", "r = fmaf(r, s2, 2.0f / 6.0f);", 1, (RNG,)),
+    "ln_correction_sign": ("return fmaf(ef, 0x1.62e4p-1f, f - corr);", "return fmaf(ef, 0x1.62e4p-1f, f + corr);", 1,
+                           (RNG,)),
     "cos_series_sign": ("p = fmaf(p, x2, -1.0f / 720.0f);", "p = fmaf(p, x2, 1.0f / 720.0f);", 1, (RNG,)),
     "quadrant_rotation_sign": ("    case 1: *s_out = cf;  *c_out = -sf; break;", "    case 1: *s_out = cf;  *c_out = sf; break;",
                                1, (RNG,)),
