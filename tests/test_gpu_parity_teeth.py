@@ -67,6 +67,7 @@ CASES = {
     "death_age_bound": gru_world,
     "regrowth_latitude_flipped": gru_world,
     "mutation_sigma_doubled": gru_world,
+    "claims_when_full": gru_world,   # the world fills its 300 slots by step 8
     "paper_any_neighbour": paper_world,
     "lstm_input_forget_swapped": paper_world,
     "temperature_inverted": paper_world,

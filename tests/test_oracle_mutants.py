@@ -135,6 +135,8 @@ MUTANTS = {
     "compaction_drops_age": ("            w->age[n_surv] = w->age[a];\n", "", 2, (CNN, DYN, PAP, MET)),
     "compaction_drops_window_flag": ("            w->wvalid[n_surv] = w->wvalid[a];\n", "", 2, (MET,)),
     "slots_one_short": ("int free_slots = cfg->cap - w->n;", "int free_slots = cfg->cap - w->n - 1;", 2, (DYN, PAP)),
+    "claims_when_full": ("if (free_slots <= 0 || w->streak[a] < cfg->T_repr) continue;",
+                         "if (w->streak[a] < cfg->T_repr) continue;", 1, (DYN,)),
     # regrowth
     "regrowth_latitude_flipped": ("double a = d * (double)row;", "double a = d * (double)(cfg->H - 1 - row);", 1,
                                   (REG,)),
