@@ -881,8 +881,9 @@ static int step_single(world* w, int K) {
 
 // Launch tables of batches (device memory owned by the library, one per
 // distinct list of worlds), with their captured graphs.  At most kBatchCache
-// tables are kept; the least recently used one is released (after its stream
-// has drained) when a new list needs a table.
+// tables are kept (more only while every one is being launched from); the
+// least recently used idle one is released (after its last launch) when a new
+// list needs a table.
 struct BatchEntry {
     void* dev = nullptr;
     TableView tv;
@@ -891,6 +892,7 @@ struct BatchEntry {
     uint64_t last_use = 0;
     std::shared_ptr<WorkEvent> done;   // recorded after the entry's last launch
     std::vector<char> host_table;      // source of the table's upload
+    int busy = 0;                      // calls launching from the entry (guarded by g_batch_mu)
     std::map<int, hipGraphExec_t> graphs;
     std::map<int, hipGraph_t> defs;
 };
@@ -934,11 +936,16 @@ static int batch_step(world_t* const* ws, int n, int K) {
         auto it = g_batches.find(key);
         if (it == g_batches.end()) {
             if (g_batches.size() >= kBatchCache) {
-                auto lru = g_batches.begin();
+                // the least recently used entry that no other thread is
+                // launching from (the cache overflows while all are busy)
+                auto lru = g_batches.end();
                 for (auto jt = g_batches.begin(); jt != g_batches.end(); ++jt)
-                    if (jt->second->last_use < lru->second->last_use) lru = jt;
-                release_entry(lru->second);
-                g_batches.erase(lru);
+                    if (jt->second->busy == 0 && (lru == g_batches.end() || jt->second->last_use < lru->second->last_use))
+                        lru = jt;
+                if (lru != g_batches.end()) {
+                    release_entry(lru->second);
+                    g_batches.erase(lru);
+                }
             }
             be = new BatchEntry();
             hipError_t e = hipMalloc(&be->dev, table_bytes(n));
@@ -962,12 +969,14 @@ static int batch_step(world_t* const* ws, int n, int K) {
         }
         be = it->second;
         be->last_use = ++g_batch_clock;
+        be->busy += 1;   // not evicted while this call launches from it
     }
-    if (int rc = run_steps(w0, w0->mode, be->tv, be->host_bp, n, be->max_useful, K, be->graphs, be->defs)) return rc;
-    if (int rc = mark_launch(ws, n)) return rc;
+    int rc = run_steps(w0, w0->mode, be->tv, be->host_bp, n, be->max_useful, K, be->graphs, be->defs);
+    if (rc == WORLD_OK) rc = mark_launch(ws, n);
     std::lock_guard<std::mutex> lk(g_batch_mu);
-    be->done = w0->own;
-    return WORLD_OK;
+    if (rc == WORLD_OK) be->done = w0->own;
+    be->busy -= 1;
+    return rc;
 }
 
 int world_step(world_t* w, int32_t K) {

@@ -285,3 +285,53 @@ def test_launch_shapes_bit_identical(env, mode):
         say(f"[systems] launch shape {shape} ({mode})")
         for i, (a, b) in enumerate(zip(ref, run(shape))):
             same(a, b, (shape, i))
+
+
+def test_batch_tables_shared_by_threads(env):
+    """Two threads, each with its own stream and eight worlds, step them
+    through 40 distinct batch lists apiece (80 in all, more than the 64 launch
+    tables the library caches), so one thread's new tables evict the other's
+    least recently used ones while it launches (an entry in use is never
+    evicted); every world ends bit-identical to the same world stepped alone."""
+    import threading
+
+    import torch
+
+    from paper_2302_09334_amd import serve
+    world, wl = env
+    cfg = wl.make(H=32, W=64, cap=256, n_init=40, hidden=16, rate_scale=2.0, res_init_p=0.3)
+    K = 2
+    results, errors = {}, []
+
+    def run(base):
+        try:
+            s = torch.cuda.Stream()
+            ws = [world.World(cfg, base + i, stream=s, mode="graph") for i in range(8)]
+            steps = [0] * 8
+            for it in range(40):   # (start, length) pairs: 8 starts x 5 lengths, all distinct
+                start, length = it % 8, 1 + it // 8
+                idx = [(start + j) % 8 for j in range(length)]
+                world.step_many([ws[i] for i in idx], K)
+                for i in idx:
+                    steps[i] += K
+            ws[0].sync()
+            for i, w in enumerate(ws):
+                results[base + i] = (steps[i], serve.state_digest(w.snapshot(hidden=True, theta=True)))
+                w.close()
+        except Exception as e:
+            errors.append(repr(e))
+
+    say("[systems] two threads, 80 batch lists against a cache of 64 launch tables")
+    threads = [threading.Thread(target=run, args=(b,)) for b in (500, 600)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    torch.cuda.synchronize()
+    assert not errors, errors
+    assert len(results) == 16
+    for seed, (steps, digest) in results.items():
+        alone = world.World(cfg, seed, mode="graph")
+        alone.step(steps)
+        assert digest == serve.state_digest(alone.snapshot(hidden=True, theta=True)), seed
+        alone.close()
