@@ -235,8 +235,11 @@ int world_step_many(world_t *const *ws, int32_t n, int32_t K);
  * At most 2048 worlds per call (WORLD_E_INVALID_ARG beyond).  Call it with
  * the worlds' device current.  Every call on one GPU shares the array and
  * rewrites all of it before its kernels read it: calls that overlap on one
- * GPU (other streams or threads) race and must not be issued.  Errors as
- * world_step_many. */
+ * GPU (other streams or threads) race and must not be issued.  When the
+ * stream is being captured into a caller's graph, the launches are recorded
+ * into it (each replay then advances the worlds as one such call does) and
+ * the caller waits for its replays before moving or releasing the worlds.
+ * Errors as world_step_many. */
 int world_step_many_noalloc(world_t *const *ws, int32_t n, int32_t K);
 
 /* Select WORLD_MODE_* for later steps (how the App. B step is launched:

@@ -422,9 +422,15 @@ int device_cus() {
 int net_wide(int slots) { return slots > 16 * device_cus() ? 1 : 0; }
 
 // Records the end of a launch of ws[0..n) (all on ws[0]'s stream, after
-// any capture has ended) as the last launch of each.
+// the library's own capture has ended) as the last launch of each.  Launches
+// that a caller records into a graph of its own (the stream is capturing)
+// are the caller's to wait for: no event is recorded into its graph, and the
+// worlds keep their last eager launch.
 int mark_launch(world* const* ws, int n) {
     world* w0 = ws[0];
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(w0, hipStreamIsCapturing(w0->stream, &cs));
+    if (cs != hipStreamCaptureStatusNone) return WORLD_OK;
     HIP_TRY(w0, hipEventRecord(w0->own->ev, w0->stream));
     for (int i = 0; i < n; ++i) ws[i]->last = w0->own;
     return WORLD_OK;

@@ -2,7 +2,7 @@
 launch table lives in a fixed device array) against world_step_many on
 identical worlds, through the C-ABI: two calls in a row, the second with a
 smaller batch, then a single world; every world's complete state bit-exact
-after each call."""
+after each call.  Also recorded into a caller's own HIP graph and replayed."""
 import ctypes as C
 
 import numpy as np
@@ -54,3 +54,36 @@ def test_noalloc_equals_step_many(env):
             same(a.snapshot(hidden=True, theta=True), b.snapshot(hidden=True, theta=True), (sub.start, K, i))
     for w in A + B:
         w.close()
+
+
+def test_noalloc_replayed_from_a_captured_graph(env):
+    """A caller that cannot allocate records world_step_many_noalloc into a
+    HIP graph of its own (torch.cuda.graph) and replays it: each of three
+    replays advances the worlds exactly as the same call made eagerly on
+    twin worlds, with the program's own reads (complete images) between the
+    replays; afterwards the worlds can be moved to another stream and
+    released."""
+    world, wl, torch = env
+    entries = wl.batch_manifest(3, seed=5)
+    S, T = torch.cuda.Stream(), torch.cuda.Stream()
+    A = [world.World(e["cfg"], e["seed"], stream=S) for e in entries]
+    B = [world.World(e["cfg"], e["seed"], stream=T) for e in entries]
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    say("[noalloc] capture into a caller's graph")
+    with torch.cuda.graph(g, stream=S, capture_error_mode="thread_local"):
+        step_noalloc(world, A, 4)
+    for r in range(3):
+        say(f"[noalloc] replay {r}")
+        g.replay()
+        torch.cuda.synchronize()
+        step_noalloc(world, B, 4)
+        for i, (a, b) in enumerate(zip(A, B)):
+            same(a.snapshot(hidden=True, theta=True), b.snapshot(hidden=True, theta=True), ("replay", r, i))
+    side = torch.cuda.Stream()
+    for w in A:
+        w.set_stream(side)
+        w.sync()
+    for w in A + B:
+        w.close()
+    del g
