@@ -25,10 +25,14 @@
  *    the next synchronising call (world_sync, world_snapshot, ...).
  *  - After a HIP error the handle is poisoned: every later call except
  *    world_destroy returns WORLD_E_POISONED.
- *  - A handle is not thread-safe; distinct handles are, also when they share
- *    a stream: copies and fills run on the world's own stream (never the
- *    legacy default stream), and waits for other threads' launches are
- *    ordered against this library's graph captures (world_set_stream).
+ *  - A handle is not thread-safe; distinct handles may be used from
+ *    different threads.  Copies and fills run on the world's own stream
+ *    (never the legacy default stream, which HIP makes depend on the other
+ *    streams).  While another thread launches on a world's stream (and may
+ *    capture graphs there), only world_set_stream and world_destroy may be
+ *    called for that world: they enqueue nothing and wait for its last launch
+ *    in step with this library's graph captures.  Move a world to a stream of
+ *    its own before reading it (world_snapshot, world_counters_get, ...).
  */
 #ifndef ECO_WORLD_H
 #define ECO_WORLD_H
