@@ -68,6 +68,7 @@ CASES = {
     "regrowth_latitude_flipped": gru_world,
     "mutation_sigma_doubled": gru_world,
     "claims_when_full": gru_world,   # the world fills its 300 slots by step 8
+    "ln_correction_sign": gru_world,   # every child's mutation noise goes through ln
     "paper_any_neighbour": paper_world,
     "lstm_input_forget_swapped": paper_world,
     "temperature_inverted": paper_world,
