@@ -21,9 +21,13 @@ enum : int { kPreAct = 0, kPreMove = 1, kPreClaim = 2, kPreKinds = 3 };
 constexpr int kNewbornBlocks = ECO_NEWBORN_BLOCKS;  // leading act blocks that create children (idle ones exit at once)
 
 #ifndef ECO_PROJ_PER
-#define ECO_PROJ_PER 2   // live-list positions per recurrent-projection wave
+#define ECO_PROJ_PER 2   // live-list positions per recurrent-projection wave of the move phase
 #endif
 constexpr int kProjPer = ECO_PROJ_PER;
+#ifndef ECO_PROJ_PER_CLAIM
+#define ECO_PROJ_PER_CLAIM 1   // ... and of the claim phase
+#endif
+constexpr int kProjPerClaim = ECO_PROJ_PER_CLAIM;
 #ifndef ECO_PROJ_MOVE_EIGHTHS
 #define ECO_PROJ_MOVE_EIGHTHS 4   // eighths of the live list whose projection runs in the move phase
 #endif
@@ -35,7 +39,7 @@ __host__ __device__ constexpr int proj_split(int n) { return n * kProjMove8 / 8;
 // Recurrent-projection waves of a GRU world with `cap` slots in the move and
 // in the claim phase (n - proj_split(n) grows with n, so cap bounds both).
 __host__ __device__ constexpr int proj_waves_move(int cap) { return (proj_split(cap) + kProjPer - 1) / kProjPer; }
-__host__ __device__ constexpr int proj_waves(int cap) { return (cap - proj_split(cap) + kProjPer - 1) / kProjPer; }
+__host__ __device__ constexpr int proj_waves(int cap) { return (cap - proj_split(cap) + kProjPerClaim - 1) / kProjPerClaim; }
 
 // Newborn blocks of a world with `cap` slots (a world never has more children
 // per step than slots).
@@ -240,7 +244,10 @@ __device__ __forceinline__ void move_body(const Batch& bt, int vb, int lane) {
 // two phases.  Measured at 4608 agents, two positions per wave: half of the
 // list in each phase 31.4 us per step, three eighths in the move phase 31.9
 // (all of it here: 34.4 before the claim tiles skipped their gathers in steps
-// without a free slot).
+// without a free slot).  Here one position per wave: the chain of a wave that
+// projects two agents in turn outlasts the claim tiles (31.6 -> 31.25 us per
+// step; three per wave 32.2), while the move phase keeps two (one there was
+// slower).
 template <bool PAPER, int TILE>
 __device__ __forceinline__ void claim_body(const Batch& bt, int vb, int lane, uint8_t* tile) {
     const BlockWorld bw = block_world(bt, kPreClaim, vb);
