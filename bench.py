@@ -802,8 +802,8 @@ def headline_run(args) -> dict:
                         "GBps": kbytes[k] / (kms[k] * 1e-3) / 1e9} for k in kms},
         "roofline": {
             "kernel": {"act": "k_act (observation + sparse input rows + GRU + head, one wave per agent)",
-                       "move": "k_move (moves, energy, death, survivor scan; 3/8 of the recurrent projection)",
-                       "claim": "k_claim (birth claims, birth scan, regrowth; 5/8 of the recurrent projection)"}[dominant],
+                       "move": "k_move (moves, energy, death, survivor scan; half of the recurrent projection)",
+                       "claim": "k_claim (birth claims, birth scan, regrowth; the other half of the recurrent projection)"}[dominant],
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
