@@ -8,6 +8,7 @@ at least one of them.  A mutant that passes them all marks a gap in the pins.
 The committed oracle is never touched: the copies exist only in the test's
 temporary directory.
 """
+import json
 import os
 import shutil
 import subprocess
@@ -203,14 +204,30 @@ def run_mutant(name, tmp):
     return r.returncode, failed, r.stdout[-2000:] + r.stderr[-2000:]
 
 
+def run_all(tmp):
+    with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        futs = {n: ex.submit(run_mutant, n, tmp) for n in MUTANTS}
+        return {n: f.result() for n, f in futs.items()}
+
+
 @pytest.fixture(scope="module")
 def results(tmp_path_factory):
     if shutil.which("gcc") is None:
         pytest.skip("no host C compiler")
-    tmp = str(tmp_path_factory.mktemp("mutants"))
-    with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
-        futs = {n: ex.submit(run_mutant, n, tmp) for n in MUTANTS}
-        return {n: f.result() for n, f in futs.items()}
+    run_uid = os.environ.get("PYTEST_XDIST_TESTRUNUID")
+    if not run_uid:
+        return run_all(str(tmp_path_factory.mktemp("mutants")))
+    # Under pytest-xdist each worker that draws one of these tests would run
+    # every mutant again: the first worker runs them and the others of the
+    # same test run read its results.
+    from filelock import FileLock
+    out = tmp_path_factory.getbasetemp().parent / f"mutants-{run_uid}.json"
+    with FileLock(str(out) + ".lock"):
+        if out.exists():
+            return {n: tuple(v) for n, v in json.loads(out.read_text()).items()}
+        res = run_all(str(tmp_path_factory.mktemp("mutants")))
+        out.write_text(json.dumps(res))
+        return res
 
 
 @pytest.mark.parametrize("name", list(MUTANTS))
