@@ -734,6 +734,27 @@ def headline_run(args) -> dict:
     rows_read = ctr["rows_read"]
     kbytes = kernel_window_bytes(cfg, P, acting, rows_read, births_prev, ctr["deaths"], ctr["claim_wins"])
     step_b = step_algorithmic_bytes(cfg, P, acting, rows_read, ctr["births"])
+    # nnz(x), the binary inputs that are 1, of every timed step: the same
+    # steps once more, one launch each, recounted on the host from each step's
+    # starting state.  The rows the act kernel reads and the acting agents,
+    # recounted from the same states, must equal the device counters at every
+    # step, else the recount is not reported.
+    w.load(start)
+    w.set_mode("kernels")
+    nnz_host = np.zeros(args.steps, np.float64)
+    rows_host = np.zeros(args.steps, np.int64)
+    live_host = np.zeros(args.steps, np.int64)
+    for j in range(args.steps):
+        s = w.snapshot()
+        on, rd = observed_inputs(s, cfg)
+        nnz_host[j], rows_host[j], live_host[j] = float(on.sum()), int(rd.sum()), s["n_live"]
+        w.step(1)
+    w.sync()
+    recount_ok = bool(np.array_equal(rows_host, np.asarray(rows_read, np.int64))
+                      and np.array_equal(live_host, np.asarray(acting, np.int64)))
+    step_b_nnz = step_algorithmic_bytes(cfg, P, acting, nnz_host, ctr["births"]) if recount_ok else None
+    log(f"[bench] host recount of the timed steps' inputs: nnz per agent {nnz_host.sum() / agent_steps:.2f}, "
+        f"rows per agent {rows_host.sum() / agent_steps:.2f}; equal to the device counters: {recount_ok}")
     dominant = max(kms, key=kms.get)
     achieved = kbytes[dominant] / (kms[dominant] * 1e-3) / 1e9
     step_gbps = float(step_b.sum()) / wall / 1e9
@@ -823,6 +844,15 @@ def headline_run(args) -> dict:
             "step_frac": step_gbps / HBM_PEAK_GBS,
             "step_bytes_formula": "per acting agent 4*(3hd*hd + 6hd + 5hd + 5) + 8hd + 40 + 12hd (energy row); "
                                   "+ 12hd per input row read (device counter); + 8P per birth; + 10 H W",
+            "nnz_inputs_per_agent": float(nnz_host.sum()) / agent_steps if recount_ok else None,
+            "step_algorithmic_bytes_nnz": float(step_b_nnz.mean()) if recount_ok else None,
+            "step_frac_nnz": float(step_b_nnz.sum()) / wall / 1e9 / HBM_PEAK_GBS if recount_ok else None,
+            "step_nnz_basis": "the same step bytes with the input term counted as nnz(x) rows of 12hd bytes (the "
+                              "binary inputs that are 1, recounted on the host from every timed step's starting "
+                              "state; the rows read and the acting agents recounted from the same states equal the "
+                              "device counters at every step); the act kernel reads fewer rows than nnz (a window "
+                              "with more ones than zeros is read as its column total and the rows of its zeros), "
+                              "so step_frac, counting the rows read, is the figure of the bytes moved",
             "kernel_source_sha256_16": src_hash,
         },
         "ecology_metrics": metrics,
