@@ -349,31 +349,37 @@ def hbm_honest_run(args, rows: int) -> dict:
     w.sync()
     wall = time.perf_counter() - t0
     c = w.counters(0, steps)
-    acting = int(s0["n_live"]) + int(c["n_live"][:-1].sum())
-    s1 = w.snapshot()
+    P = w.n_params
     w.close()
     w2 = world.World(cfg, args.seed, stream=stream, mode="kernels")
     w2.set_tuning(rows)
     ph = w2.phase_times(steps)
     w2.close()
-    rows_read = float(np.concatenate([observed_inputs(s, cfg)[1] for s in (s0, s1)]).mean())
+    # bytes from the window's own device counters, as for the headline (the
+    # world starts from its seed: no children are pending at step 0)
+    acting_v = np.concatenate([[int(s0["n_live"])], c["n_live"][:-1]]).astype(np.float64)
+    acting = int(acting_v.sum())
     n = acting / steps
-    act_b = n * act_bytes_per_agent(cfg, rows_read) + cfg["H"] * cfg["W"] * 5
-    pb = proj_bytes_per_agent(cfg)
-    move_b = n * (MOVE_BYTES_PER_AGENT + PROJ_MOVE_SHARE * pb)
-    claim_b = ((1 - PROJ_MOVE_SHARE) * (n - float(c["deaths"].mean())) * pb + n * CLAIM_BYTES_PER_AGENT
-               + 2 * cfg["H"] * cfg["W"])
+    births_prev = np.concatenate([[0], c["births"][:-1]])
+    kb = kernel_window_bytes(cfg, P, acting_v, c["rows_read"], births_prev, c["deaths"], c["claim_wins"])
+    step_b = step_algorithmic_bytes(cfg, P, acting_v, c["rows_read"], c["births"])
     out = {"workload": "cfg2: 200x400 grid, cap 16384, 12000 initial agents, resources Bernoulli(0.3), "
                        "regrowth x5.0, obs 7x7x2+1, GRU 32, seed %d, steps 0..%d" % (args.seed, steps - 1),
            "steps": steps, "agent_steps_per_s": acting / wall, "ms_per_step": wall / steps * 1e3,
            "n_live_mean": n, "births_mean": float(c["births"].mean()),
            "kernel_ms": {"act": float(ph[0]), "move": float(ph[1]), "claim": float(ph[2])},
-           "act_GBps": act_b / (float(ph[0]) * 1e-3) / 1e9, "move_GBps": move_b / (float(ph[1]) * 1e-3) / 1e9,
-           "claim_GBps": claim_b / (float(ph[2]) * 1e-3) / 1e9,
-           "act_algorithmic_MB_per_launch": act_b / 1e6, "step_algorithmic_MB": (act_b + move_b + claim_b) / 1e6}
+           "act_GBps": kb["act"] / (float(ph[0]) * 1e-3) / 1e9, "move_GBps": kb["move"] / (float(ph[1]) * 1e-3) / 1e9,
+           "claim_GBps": kb["claim"] / (float(ph[2]) * 1e-3) / 1e9,
+           "act_frac": kb["act"] / (float(ph[0]) * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "act_input_rows_read_per_agent": float(np.sum(c["rows_read"])) / acting,
+           "act_algorithmic_MB_per_launch": kb["act"] / 1e6,
+           "step_algorithmic_MB": float(step_b.mean()) / 1e6,
+           "step_frac": float(step_b.sum()) / wall / 1e9 / HBM_PEAK_GBS,
+           "bytes_basis": "the headline's formulas (kernel bytes per launch, step bytes) over this window's device "
+                          "counters; the rate and step_frac are per-phase launches timed by the wall clock"}
     log(f"[bench] cfg2 (cache-exceeding, {n:.0f} agents): {out['agent_steps_per_s'] / 1e6:.1f} M agent-steps/s, "
         f"{out['ms_per_step'] * 1e3:.1f} us/step, act {out['act_GBps']:.0f} GB/s, move {out['move_GBps']:.0f} GB/s, "
-        f"claim {out['claim_GBps']:.0f} GB/s")
+        f"claim {out['claim_GBps']:.0f} GB/s; step {out['step_algorithmic_MB']:.1f} MB, frac {out['step_frac']:.3f}")
     return out
 
 
