@@ -730,6 +730,29 @@ def headline_run(args) -> dict:
         f"{agent_steps}; N_live mean {acting.mean():.1f} min {acting.min()} max {acting.max()}; births "
         f"{int(ctr['births'].sum())} deaths {deaths}")
 
+    # nnz(x), the binary inputs that are 1, of every timed step (GRU worlds
+    # with the benchmark's rules): the same steps once more, one launch each,
+    # recounted on the host from each step's starting state.  The rows the act
+    # kernel reads and the acting agents, recounted from the same states, must
+    # equal the device counters at every step, else the recount is not reported.
+    recount_ok, nnz_host = False, None
+    if not cfg.get("controller", 0) and not cfg.get("dynamics", 0):
+        w.load(start)
+        w.set_mode("kernels")
+        nnz_host = np.zeros(args.steps, np.float64)
+        rows_host = np.zeros(args.steps, np.int64)
+        live_host = np.zeros(args.steps, np.int64)
+        for j in range(args.steps):
+            s = w.snapshot()
+            on, rd = observed_inputs(s, cfg)
+            nnz_host[j], rows_host[j], live_host[j] = float(on.sum()), int(rd.sum()), s["n_live"]
+            w.step(1)
+        w.sync()
+        recount_ok = bool(np.array_equal(rows_host, np.asarray(ctr["rows_read"], np.int64))
+                          and np.array_equal(live_host, np.asarray(acting, np.int64)))
+        log(f"[bench] host recount of the timed steps' inputs: nnz per agent {nnz_host.sum() / agent_steps:.2f}, "
+            f"rows per agent {rows_host.sum() / agent_steps:.2f}; equal to the device counters: {recount_ok}")
+
     # the same steps again from the same state as per-phase kernels, each
     # launch between events its own dispatch stamps (kernel execution time)
     w.load(start)
@@ -740,27 +763,7 @@ def headline_run(args) -> dict:
     rows_read = ctr["rows_read"]
     kbytes = kernel_window_bytes(cfg, P, acting, rows_read, births_prev, ctr["deaths"], ctr["claim_wins"])
     step_b = step_algorithmic_bytes(cfg, P, acting, rows_read, ctr["births"])
-    # nnz(x), the binary inputs that are 1, of every timed step: the same
-    # steps once more, one launch each, recounted on the host from each step's
-    # starting state.  The rows the act kernel reads and the acting agents,
-    # recounted from the same states, must equal the device counters at every
-    # step, else the recount is not reported.
-    w.load(start)
-    w.set_mode("kernels")
-    nnz_host = np.zeros(args.steps, np.float64)
-    rows_host = np.zeros(args.steps, np.int64)
-    live_host = np.zeros(args.steps, np.int64)
-    for j in range(args.steps):
-        s = w.snapshot()
-        on, rd = observed_inputs(s, cfg)
-        nnz_host[j], rows_host[j], live_host[j] = float(on.sum()), int(rd.sum()), s["n_live"]
-        w.step(1)
-    w.sync()
-    recount_ok = bool(np.array_equal(rows_host, np.asarray(rows_read, np.int64))
-                      and np.array_equal(live_host, np.asarray(acting, np.int64)))
     step_b_nnz = step_algorithmic_bytes(cfg, P, acting, nnz_host, ctr["births"]) if recount_ok else None
-    log(f"[bench] host recount of the timed steps' inputs: nnz per agent {nnz_host.sum() / agent_steps:.2f}, "
-        f"rows per agent {rows_host.sum() / agent_steps:.2f}; equal to the device counters: {recount_ok}")
     dominant = max(kms, key=kms.get)
     achieved = kbytes[dominant] / (kms[dominant] * 1e-3) / 1e9
     step_gbps = float(step_b.sum()) / wall / 1e9
