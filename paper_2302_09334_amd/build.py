@@ -40,7 +40,8 @@ def flags() -> list[str]:
 def build(verbose: bool = False, out: str = LIB, defines: dict | None = None) -> str:
     """Compile the library to `out`; `defines` are extra -D tuning macros
     (ECO_PROJ_MOVE_EIGHTHS, ECO_PROJ_PER, ECO_PROJ_PER_CLAIM, ECO_NET_WAVES,
-    ECO_NET_WAVES_WIDE, ECO_NEWBORN_BLOCKS; none changes a result)."""
+    ECO_NET_WAVES_WIDE, ECO_NEWBORN_BLOCKS, ECO_ROWS_STREAM_MIB; none changes a
+    result)."""
     tmp = f"{out}.{os.getpid()}.tmp"   # per process
     extra = [f"-D{k}={v}" for k, v in (defines or {}).items()]
     cmd = [hipcc()] + flags() + extra + SOURCES + ["-o", tmp] + LIBS

@@ -57,12 +57,35 @@ struct Batch {
     int net_wide;               // host only: the network act kernel for five waves per SIMD
     int act_waves;              // host only: agents (waves) per block of the GRU act kernel (2, 4, 8)
     int tile;                   // host only: regrowth tile edge (8, 16, 32)
+    int may_stream;             // host only: the GRU act kernel holding the streaming copy of the rows
 };
 
-template <int ROWS>
-__device__ __forceinline__ void act_dispatch(DevRef d, AgentRec* rec, int4 rv, int li, int64_t t, int lane) {
-    if (d.hd == 32) act_agent<32, ROWS>(d, rec, rv, li, t, lane);
-    else act_agent<16, ROWS>(d, rec, rv, li, t, lane);
+// Live-genome bytes of a world above which its act phase streams the input
+// rows (non-temporal loads): the last-level cache (Infinity Cache, 256 MiB).
+// Measured at 4608 agents (genomes 228 MiB) plain loads are faster (30.9
+// against 32.7 us per step: rows kept from earlier steps hit), at 15k agents
+// streaming is (77.1 against 83.4 us per step).
+#ifndef ECO_ROWS_STREAM_MIB
+#define ECO_ROWS_STREAM_MIB 256
+#endif
+constexpr size_t kRowsStreamBytes = size_t(ECO_ROWS_STREAM_MIB) << 20;
+
+// The streaming copy exists only in the act kernels compiled with
+// STREAMABLE (launched for worlds whose genomes can exceed the cache), and
+// there only for the wide (hd 32) agents of the act blocks: it costs code
+// size, and the act kernel's code is close to the size of the instruction
+// cache.  Children acting in their first step (a few per step) and hd 16
+// worlds (whose genomes stay below the cache up to about 11k agents) load as
+// usual.
+template <int ROWS, bool STREAMABLE>
+__device__ __forceinline__ void act_dispatch(DevRef d, AgentRec* rec, int4 rv, int li, int64_t t, int lane,
+                                             bool stream) {
+    if (d.hd == 32) {
+        if (STREAMABLE && stream) act_agent<32, ROWS, STREAMABLE>(d, rec, rv, li, t, lane);
+        else act_agent<32, ROWS, false>(d, rec, rv, li, t, lane);
+    } else {
+        act_agent<16, ROWS, false>(d, rec, rv, li, t, lane);
+    }
 }
 
 // A block's world and its index among that world's blocks of one phase.  The
@@ -126,7 +149,7 @@ __device__ __attribute__((noinline)) void net_child_act(DevRef d, AgentRec* recp
 // remaining blocks run the controller of the other agents, NT / 64 per block.
 // NET: the paper's network (with `lds`, one scratch per wave), else the GRU;
 // WIDE: the kernel is compiled for five waves per SIMD.
-template <int ROWS, bool NET, bool PAPER = false, bool WIDE = false, int NT = kBlock>
+template <int ROWS, bool NET, bool PAPER = false, bool WIDE = false, int NT = kBlock, bool STREAMABLE = false>
 __device__ __forceinline__ void act_body(const Batch& bt, int vb, int tid, StepShared& sh, net::WaveLds* lds) {
     const BlockWorld bw = block_world(bt, kPreAct, vb);
     DevRef d = *bw.d;
@@ -156,6 +179,8 @@ __device__ __forceinline__ void act_body(const Batch& bt, int vb, int tid, StepS
     const int n = ss.n;
     const int nc = ss.nc;
     const int sel = ss.sel;
+    // the same choice for every wave of the world in this step
+    const bool stream = STREAMABLE && size_t(n) * size_t(d.Ppad) * sizeof(float) > kRowsStreamBytes;
     if (lb < nb) {
         if (lb == 0) {
             if (tid == 0) step_open(d, t);
@@ -177,7 +202,7 @@ __device__ __forceinline__ void act_body(const Batch& bt, int vb, int tid, StepS
                     const int4 rv2 = *(reinterpret_cast<const int4*>(&P[lj].r[sel]) + 1);
                     net_child_act<PAPER, WIDE>(d, &P[lj].r[sel], rv, rv2, lj, t, tid, lds[0]);
                 } else {
-                    act_dispatch<ROWS>(d, &P[lj].r[sel], rv, lj, t, tid);
+                    act_dispatch<ROWS, false>(d, &P[lj].r[sel], rv, lj, t, tid, false);
                 }
             }
             __syncthreads();
@@ -187,7 +212,7 @@ __device__ __forceinline__ void act_body(const Batch& bt, int vb, int tid, StepS
     if (li >= n - nc) return;
     if constexpr (NET)
         net::act_agent<PAPER>(d, &P[li].r[sel], sel ? q1 : q0, sel ? q1b : q0b, li, t, tid & 63, lds[tid >> 6]);
-    else act_dispatch<ROWS>(d, &P[li].r[sel], sel ? q1 : q0, li, t, tid & 63);
+    else act_dispatch<ROWS, STREAMABLE>(d, &P[li].r[sel], sel ? q1 : q0, li, t, tid & 63, stream);
 }
 
 // Move blocks of a world (one wave each): the move tiles, in look-back
@@ -282,10 +307,10 @@ __device__ __forceinline__ void claim_body(const Batch& bt, int vb, int lane, ui
 // result: an agent's summation order depends on its observation only, and
 // the block-wide work (child genomes, window totals, counter sums) is
 // elementwise or integer.
-template <int ROWS, int WAVES>
+template <int ROWS, int WAVES, bool STREAMABLE>
 __global__ __launch_bounds__(64 * WAVES) void k_act_gru(Batch bt) {
     __shared__ StepShared sh;
-    act_body<ROWS, false, false, false, 64 * WAVES>(bt, blockIdx.x, threadIdx.x, sh, nullptr);
+    act_body<ROWS, false, false, false, 64 * WAVES, STREAMABLE>(bt, blockIdx.x, threadIdx.x, sh, nullptr);
 }
 
 // Act kernels of worlds with the paper's network.  The compiler's own

@@ -203,8 +203,12 @@ __device__ __forceinline__ void proj_zero(DevRef d, int slot, int lane) {
 // how many loads are in flight, since item q of the enumeration always goes
 // to group q % G and each group adds its items in increasing q.
 // The recurrent projection comes precomputed from gh[slot].
+// STREAM: the input rows are read with non-temporal loads (chosen per world
+// and step by the caller when the live genomes exceed the last-level cache:
+// then they cannot be held there from one step to the next, and streaming
+// them leaves the cache to the data the step's later phases read again).
 // ---------------------------------------------------------------------------
-template <int HD, int ROWS>
+template <int HD, int ROWS, bool STREAM>
 __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int li, int64_t t, int lane) {
     constexpr int G = 64 / HD;
     constexpr int RW = 3 * HD;   // floats per input row
@@ -304,7 +308,16 @@ __device__ __forceinline__ void act_agent(DevRef d, AgentRec* recp, int4 rv, int
             for (int gg = 1; gg < G; ++gg)
                 if (g == gg) it = items[b * G + gg];
             const float* p = th + (it & (kNeg - 1)) * RW + 3 * k;
-            const float x0 = p[0], x1 = p[1], x2 = p[2];
+            float x0, x1, x2;
+            if constexpr (STREAM) {
+                x0 = __builtin_nontemporal_load(p);
+                x1 = __builtin_nontemporal_load(p + 1);
+                x2 = __builtin_nontemporal_load(p + 2);
+            } else {
+                x0 = p[0];
+                x1 = p[1];
+                x2 = p[2];
+            }
             const bool neg = (it & kNeg) != 0;
             vr[b] = neg ? -x0 : x0;
             vz[b] = neg ? -x1 : x1;

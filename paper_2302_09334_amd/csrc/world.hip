@@ -291,6 +291,7 @@ struct world {
         const WorldDev* const* w;
         const int* block_pre;
         int slots;
+        int may_stream;
     } tv;                  // single-world launch table (inside the arena)
     std::vector<int> host_bp;
     int max_useful = 1;
@@ -361,9 +362,15 @@ std::vector<int> batch_prefix(const std::vector<const world*>& ws, int waves, in
 // The GRU act kernel for the batch's rows per round trip and agents per block.
 template <int ROWS>
 void launch_act_rows(const Batch& b, int grid, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
-    if (b.act_waves == 2) hipExtLaunchKernelGGL(k_act_gru<ROWS, 2>, dim3(grid), dim3(128), 0, s, t0, t1, 0, b);
-    else if (b.act_waves == 8) hipExtLaunchKernelGGL(k_act_gru<ROWS, 8>, dim3(grid), dim3(512), 0, s, t0, t1, 0, b);
-    else hipExtLaunchKernelGGL(k_act_gru<ROWS, 4>, dim3(grid), dim3(256), 0, s, t0, t1, 0, b);
+    if (b.act_waves == 2)
+        hipExtLaunchKernelGGL(b.may_stream ? k_act_gru<ROWS, 2, true> : k_act_gru<ROWS, 2, false>, dim3(grid), dim3(128),
+                              0, s, t0, t1, 0, b);
+    else if (b.act_waves == 8)
+        hipExtLaunchKernelGGL(b.may_stream ? k_act_gru<ROWS, 8, true> : k_act_gru<ROWS, 8, false>, dim3(grid), dim3(512),
+                              0, s, t0, t1, 0, b);
+    else
+        hipExtLaunchKernelGGL(b.may_stream ? k_act_gru<ROWS, 4, true> : k_act_gru<ROWS, 4, false>, dim3(grid), dim3(256),
+                              0, s, t0, t1, 0, b);
 }
 
 void launch_act_gru(const Batch& b, int grid, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
@@ -505,8 +512,18 @@ int wall_rate_khz() {
 struct TableView {
     const WorldDev* const* w;
     const int* block_pre;
-    int slots = 0;   // agent slots of all worlds of the batch
+    int slots = 0;        // agent slots of all worlds of the batch
+    int may_stream = 0;   // some world's live genomes can exceed the last-level cache
 };
+
+// A GRU world whose genomes, with every slot live, exceed the last-level
+// cache: its act phase may stream the input rows (decided on the device from
+// the live count of each step), so its launches use the act kernel that holds
+// the streaming copy; every other launch uses the kernel without it (smaller
+// code, about 0.5% faster per step).
+static int may_stream(const world* x) {
+    return x->dev.ctrl == kCtrlGru && size_t(x->cfg.cap) * size_t(x->dev.Ppad) * sizeof(float) > kRowsStreamBytes;
+}
 
 size_t table_bytes(int n) { return align_up(sizeof(void*) * size_t(n), 16) + sizeof(int) * size_t(kPreKinds) * (n + 1); }
 
@@ -515,7 +532,11 @@ std::vector<char> build_table(const std::vector<const world*>& ws, char* dev_bas
     const int n = int(ws.size());
     const std::vector<int> bp = batch_prefix(ws, ws[0]->act_waves, ws[0]->tile);
     view->slots = 0;
-    for (const world* x : ws) view->slots += x->cfg.cap;
+    view->may_stream = 0;
+    for (const world* x : ws) {
+        view->slots += x->cfg.cap;
+        view->may_stream |= may_stream(x);
+    }
     int useful = 1;
     for (int k = 0; k < kPreKinds; ++k) useful = std::max(useful, bp[size_t(k) * (n + 1) + n]);
     const size_t ptr_bytes = align_up(sizeof(void*) * size_t(n), 16);
@@ -537,7 +558,7 @@ int run_steps(world* w0, int mode, const TableView& tv, const std::vector<int>& 
               int K, std::map<int, hipGraphExec_t>& graphs, std::map<int, hipGraph_t>& defs) {
     hipStream_t s = w0->stream;
     Batch b{tv.w, tv.block_pre, n, w0->act_rows, n == 1 ? static_cast<const WorldDev*>(w0->d_dev) : nullptr,
-            w0->cfg.cap, w0->dev.ctrl, w0->dev.dyn, net_wide(tv.slots), w0->act_waves, w0->tile};
+            w0->cfg.cap, w0->dev.ctrl, w0->dev.dyn, net_wide(tv.slots), w0->act_waves, w0->tile, tv.may_stream};
     if (mode == WORLD_MODE_KERNELS) {
         for (int k = 0; k < K; ++k) HIP_TRY(w0, launch_step(b, host_bp.data(), n, s));
         return WORLD_OK;
@@ -772,6 +793,7 @@ int world_create(const world_config* cfg, uint64_t seed, void* arena, size_t are
     w->tv.w = tv.w;
     w->tv.block_pre = tv.block_pre;
     w->tv.slots = tv.slots;
+    w->tv.may_stream = tv.may_stream;
 
     hipStream_t s = w->stream;
     auto up = [&](size_t off, const void* src, size_t bytes) {
@@ -881,6 +903,7 @@ static int step_single(world* w, int K) {
     tv.w = w->tv.w;
     tv.block_pre = w->tv.block_pre;
     tv.slots = w->tv.slots;
+    tv.may_stream = w->tv.may_stream;
     if (int rc = run_steps(w, w->mode, tv, w->host_bp, 1, w->max_useful, K, w->graphs, w->graph_defs)) return rc;
     return mark_launch(&w, 1);
 }
@@ -1405,7 +1428,7 @@ int world_phase_times(world_t* w, int32_t K, float* ms) {
     const int np = 2;
     const int* hp = w->host_bp.data();
     Batch b{w->tv.w, w->tv.block_pre, 1, w->act_rows, static_cast<const WorldDev*>(w->d_dev), w->cfg.cap, w->dev.ctrl,
-            w->dev.dyn, net_wide(w->tv.slots), w->act_waves, w->tile};
+            w->dev.dyn, net_wide(w->tv.slots), w->act_waves, w->tile, w->tv.may_stream};
     hipStream_t s = w->stream;
     // each kernel between start / end events stamped by its own dispatch
     std::vector<hipEvent_t> ev(size_t(K) * 6);
@@ -1544,8 +1567,11 @@ int world_step_many_noalloc(world_t* const* ws, int32_t n, int32_t K) {
     hipStream_t s = w0->stream;
     std::vector<const world*> list(ws, ws + n);
     const std::vector<int> bp = batch_prefix(list, w0->act_waves, w0->tile);
-    int slots = 0;
-    for (const world* x : list) slots += x->cfg.cap;
+    int slots = 0, streams = 0;
+    for (const world* x : list) {
+        slots += x->cfg.cap;
+        streams |= may_stream(x);
+    }
     for (int first = 0; first < n; first += kFillChunk) {
         TableChunk c;
         std::memset(&c, 0, sizeof(c));
@@ -1561,7 +1587,7 @@ int world_step_many_noalloc(world_t* const* ws, int32_t n, int32_t K) {
     const size_t ptr_bytes = align_up(sizeof(void*) * size_t(n), 16);
     Batch b{reinterpret_cast<const WorldDev* const*>(table), reinterpret_cast<const int*>(table + ptr_bytes), n,
             w0->act_rows, n == 1 ? static_cast<const WorldDev*>(w0->d_dev) : nullptr, w0->cfg.cap, w0->dev.ctrl,
-            w0->dev.dyn, net_wide(slots), w0->act_waves, w0->tile};
+            w0->dev.dyn, net_wide(slots), w0->act_waves, w0->tile, streams};
     for (int k = 0; k < K; ++k) HIP_TRY(w0, launch_step(b, bp.data(), n, s));
     return mark_launch(ws, n);
 }
