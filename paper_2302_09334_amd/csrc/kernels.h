@@ -62,7 +62,7 @@ struct Batch {
 
 // Live-genome bytes of a world above which its act phase streams the input
 // rows (non-temporal loads): the last-level cache (Infinity Cache, 256 MiB).
-// Measured at 4608 agents (genomes 228 MiB) plain loads are faster (30.9
+// Measured at 4608 agents (genomes 233 MiB) plain loads are faster (30.9
 // against 32.7 us per step: rows kept from earlier steps hit), at 15k agents
 // streaming is (77.1 against 83.4 us per step).
 #ifndef ECO_ROWS_STREAM_MIB
