@@ -287,6 +287,36 @@ def test_launch_shapes_bit_identical(env, mode):
             same(a, b, (shape, i))
 
 
+def test_streaming_world_launch_shapes_bit_identical(env):
+    """A world whose live genomes exceed the last-level cache (cfg2: 12,000
+    agents of 12,933 parameters, over 600 MB) is stepped by the act kernels
+    that read the input rows with non-temporal loads; every act shape (rows
+    per round trip, agents per block) gives it the same state bit for bit as
+    the default shape, genomes and hidden states included.  The default shape
+    itself is compared with the oracle by the cfg2 parity tests."""
+    import torch
+    world, wl = env
+    cfg = wl.WORKLOADS["cfg2"]
+    assert cfg["n_init"] * world.dims(cfg)[1] * 4 > 256 << 20   # the act phase streams from step 0
+    s = torch.cuda.Stream()
+
+    def run(rows, waves, steps=6):
+        w = world.World(cfg, 0, stream=s, mode="kernels")
+        w.set_tuning(rows, waves, 16)
+        w.step(steps)
+        out = w.snapshot(hidden=True, theta=True)
+        w.close()
+        return out
+
+    ref = run(16, 4)
+    for rows in (8, 16, 32):
+        for waves in (2, 4, 8):
+            if (rows, waves) == (16, 4):
+                continue
+            say(f"[systems] streaming world, act shape rows {rows} waves {waves}")
+            same(ref, run(rows, waves), (rows, waves))
+
+
 def test_batch_tables_shared_by_threads(env):
     """Two threads, each with its own stream and eight worlds, step them
     through 40 distinct batch lists apiece (80 in all, more than the 64 launch
